@@ -1,0 +1,232 @@
+"""Benchmark of the well-balanced 2D Saint-Venant step on one MI355X.
+
+Workload (default): the 8192 x 8192 overland-flow hillslope (1 m cells,
+initially dry, 50 mm/h rain, Green-Ampt infiltration, Darcy-Weisbach
+friction), i.e. every step of the method is active.  A step is one full
+Heun step of the whole grid (both stage kernels).  W warmup steps run first
+(default 300: the dry start ends with ponding after about 223 s of simulated
+time, so the timed steps see thin films and wet/dry fronts), then K timed
+steps.  The metric counts nx*ny cell updates per step, dry cells included.
+
+Prints one JSON line with the throughput, the roofline of the dominant
+kernel (HIP events on the library's stream) and the CPU oracle timed on a
+bounded sample of the same workload.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "cell-updates/s (FP64) + % HBM roofline; ensemble & adjoint vs plain, same GPU"
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+KERNEL_SRC = os.path.join(ROOT, "paper_1307_4839_amd", "csrc", "swe_step.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_hillslope_8192.json")
+
+
+def algorithmic_bytes(wl):
+    """Bytes per cell each stage kernel must move at least once.
+
+    stage 1 (rate): read h, qx, qy, z; write Phi (3 values).
+    stage 2 (update): read h, qx, qy, Phi (3), z [+ friction field]
+    [+ V_inf]; write h, qx, qy [+ V_inf].
+    """
+    rate = 8 * (4 + 3)
+    upd = 8 * (3 + 3 + 1 + 3)
+    if wl.fric is not None:
+        upd += 8
+    if wl.infil_on:
+        upd += 16
+    return rate, upd
+
+
+def kernel_hash():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def load_traffic(kernel_name):
+    """Measured HBM bytes per launch from the committed PMC summary, if it was
+    taken on the current kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_sha256_16") != kernel_hash():
+        return None
+    k = rec.get("kernels", {}).get(kernel_name)
+    if not k:
+        return None
+    return k.get("bytes_per_launch")
+
+
+def cpu_baseline(wl, rows, steps):
+    import numpy as np
+
+    import oracle
+    sub = wl.copy()
+    sub.ny = rows
+    for f in ("z", "h", "qx", "qy", "vinf", "fric"):
+        a = getattr(sub, f)
+        if a is not None:
+            setattr(sub, f, np.ascontiguousarray(a[:rows]))
+    s = oracle.State(sub)
+    t0 = time.perf_counter()
+    rc = s.run(steps)
+    el = time.perf_counter() - t0
+    assert rc in (0, 1), rc
+    cells = sub.nx * sub.ny * s.steps
+    return {"value": cells / el, "unit": "cell-updates/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"rows 0..{rows - 1} of the {wl.nx}x{wl.ny} {wl.name} workload, "
+                      f"{s.steps} steps from its initial state ({cells:.3g} cell-updates "
+                      f"in {el:.1f} s)"}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=300)
+    ap.add_argument("--workload", default="hillslope_8192",
+                    choices=["hillslope_8192", "valley_2048", "dam_break_200",
+                             "calibration_1024"])
+    ap.add_argument("--size", type=int, default=0, help="override nx = ny (testing)")
+    ap.add_argument("--profile-steps", type=int, default=50)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-rows", type=int, default=2048)
+    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--probe-copy-mib", type=int, default=0,
+                    help="after the run, copy a float64 tensor of this many MiB once "
+                         "(a plain copy of known size that calibrates byte counters)")
+    args = ap.parse_args(argv)
+
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); "
+              "the multi-GPU decomposition is a design, not an implementation",
+              file=sys.stderr, flush=True)
+        return 2
+
+    import torch
+
+    from paper_1307_4839_amd import inputs as I
+    from paper_1307_4839_amd.solver import Solver
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        return 1
+
+    t0 = time.perf_counter()
+    gen = I.WORKLOADS[args.workload]
+    wl = gen(args.size, args.size) if args.size else gen()
+    print(f"[bench] workload {wl.name} {wl.nx}x{wl.ny} generated in "
+          f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+
+    g = Solver(wl, device="cuda:0")
+    stream = g.stream
+    g.step(args.warmup)
+    torch.cuda.synchronize()
+    print(f"[bench] warmup {args.warmup} steps done, t = {g.time()[0]:.2f} s",
+          file=sys.stderr, flush=True)
+
+    # timed region: K steps bracketed by synchronizations
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    e0.record(stream)
+    g.step(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms = e0.elapsed_time(e1)
+    rc, flags = g.status()
+    t_sim, last_dt, nsteps_done = g.time()
+    if rc != 0:
+        print(f"[bench] status flags {flags} (code {rc})", file=sys.stderr, flush=True)
+    cells = wl.nx * wl.ny
+    value = cells * args.steps / (ms / 1e3)
+    print(f"[bench] timed {args.steps} steps: {ms:.2f} ms (wall {wall * 1e3:.2f} ms), "
+          f"t = {t_sim:.2f} s", file=sys.stderr, flush=True)
+
+    # per-kernel durations on the library's stream (HIP events)
+    g.profile_begin(args.profile_steps)
+    g.step(args.profile_steps)
+    ms_rate, ms_upd, np_ = g.profile_end()
+    avg_rate, avg_upd = ms_rate / np_, ms_upd / np_
+    b_rate, b_upd = algorithmic_bytes(wl)
+    kern = {
+        "rate": {"avg_ms": avg_rate, "bytes_per_cell": b_rate,
+                 "GBps": b_rate * cells / (avg_rate / 1e3) / 1e9},
+        "update": {"avg_ms": avg_upd, "bytes_per_cell": b_upd,
+                   "GBps": b_upd * cells / (avg_upd / 1e3) / 1e9},
+    }
+    dom = "update" if avg_upd >= avg_rate else "rate"
+    kname = "stage_kernel<2>" if dom == "update" else "stage_kernel<1>"
+    ach = kern[dom]["GBps"]
+    traffic = load_traffic(kname)
+    roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "kernel": kname,
+                "algorithmic_bytes_per_launch": kern[dom]["bytes_per_cell"] * cells}
+    step_bytes = (b_rate + b_upd) * cells
+    print(f"[bench] kernels: {json.dumps(kern)}", file=sys.stderr, flush=True)
+
+    if args.probe_copy_mib:
+        n = args.probe_copy_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] probe copy of {args.probe_copy_mib} MiB done", file=sys.stderr,
+              flush=True)
+        del src, dst
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(wl, min(args.cpu_rows, wl.ny), args.cpu_steps)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded fBm terrain; inputs.py recipe)",
+        "config": {"workload": wl.name, "nx": wl.nx, "ny": wl.ny, "dx": wl.dx,
+                   "cells": cells, "physics": {
+                       "friction": ["none", "manning", "darcy"][wl.fric_law],
+                       "rain_m_per_s": wl.rain, "green_ampt": bool(wl.infil_on)},
+                   "parallelism": "single GPU"},
+        "step_hbm_frac": round(value * (b_rate + b_upd) / (HBM_PEAK_GBS * 1e9), 4),
+        "step_algorithmic_bytes": step_bytes,
+        "kernels": kern,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "sim_time_s": t_sim,
+        "status_flags": flags,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,170 @@
+/*
+ * swe.h -- C ABI of the MI355X (gfx950) library for the well-balanced
+ * finite-volume step of the 2D Saint-Venant (shallow-water) system.
+ *
+ * Method (arXiv:1307.4839, "FullSWOF_Paral", Sections 2-3):
+ *   model SW2D (Section 2.1) with rain R, Green-Ampt infiltration
+ *   (Section 3.5) and Manning or Darcy-Weisbach friction (Section 2.1);
+ *   second-order MUSCL/minmod reconstruction of h, h+z and u (Section 3.4),
+ *   hydrostatic reconstruction with the S and Fc source corrections
+ *   (Section 3.1, eq. SW1Dscheme), HLL flux (Section 3.3), semi-implicit
+ *   friction and Heun's RK2 (Section 3.2), CFL time step on the
+ *   reconstructed states (Section 3.3, eq. cfl), ghost-cell boundary
+ *   conditions (Section 2.2) with two ghost layers (Section 6.1), and the
+ *   per-stage order of Algorithm 1 (Section 6.2).
+ *
+ * Conventions
+ *   - Every array is FP64, [ny][nx] row-major with x fastest, no padding.
+ *     Cell (i, j) has centre ((i + 1/2) dx, (j + 1/2) dy).
+ *   - Device pointers are owned by the caller; the library never frees them
+ *     and keeps them only for the life of the context.  Host pointers are
+ *     never retained past the call.
+ *   - All work is enqueued on the caller's HIP stream given at creation;
+ *     calls documented as "synchronizes" wait for that stream.
+ *   - Every function returns 0 on success or a negative SWE_E* code.
+ *   - A context is not thread-safe.  Contexts on the same device are
+ *     independent (each has its own workspace).
+ *   - Water depth is never clamped: a negative or non-finite value is
+ *     reported through sticky status flags.
+ */
+#ifndef SWE_H
+#define SWE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* error codes */
+#define SWE_OK 0
+#define SWE_EINVAL (-1)     /* invalid argument or parameter */
+#define SWE_EHIP (-2)       /* a HIP runtime call failed */
+#define SWE_ENEGDEPTH (-3)  /* a negative water depth was produced */
+#define SWE_ENONFINITE (-4) /* a non-finite value was produced */
+#define SWE_EDT (-5)        /* the time step was not finite */
+#define SWE_ENOMEM (-6)     /* workspace too small */
+
+/* sticky status flags (swe_get_status) */
+#define SWE_FLAG_NEGDEPTH 1u
+#define SWE_FLAG_NONFINITE 2u
+#define SWE_FLAG_DT 4u
+
+/* boundary types, Section 2.2: ghost cells.  WALL mirrors the boundary
+ * cells (normal discharge negated); OUTFLOW copies the boundary cell (free,
+ * zero-gradient outflow). */
+#define SWE_BC_WALL 0
+#define SWE_BC_OUTFLOW 1
+
+/* friction laws, Section 2.1 */
+#define SWE_FRIC_NONE 0
+#define SWE_FRIC_MANNING 1 /* coefficient n:  S_f = n^2 |u| u / h^(4/3) */
+#define SWE_FRIC_DARCY 2   /* coefficient f:  S_f = f/(8g) |u| u / h    */
+
+typedef struct swe_params {
+    int32_t nx, ny;      /* cells, >= 2 each */
+    double dx, dy;       /* cell sizes [m], > 0 */
+    double g;            /* gravity [m/s^2] (9.81) */
+    double cfl;          /* n_CFL (0.5 at second order, eq. cfl) */
+    double dt_max;       /* upper bound on dt [s] (INFINITY for none) */
+    double h_eps;        /* dry threshold [m]: velocity is 0 at or below it */
+    int32_t bc[4];       /* west, east, south, north: SWE_BC_* */
+    int32_t fric_law;    /* SWE_FRIC_* */
+    double fric_coef;    /* n or f, used when the friction field is NULL */
+    double rain;         /* rain intensity R [m/s] (uniform) */
+    int32_t infil_on;    /* 1: Green-Ampt infiltration (needs vinf buffer) */
+    double ks;           /* saturated conductivity K_s [m/s] */
+    double psi;          /* wetting-front suction head, magnitude >= 0 [m] */
+    double dtheta;       /* theta_s - theta_i, > 0 */
+} swe_params;
+
+typedef struct swe_buffers {
+    double* h;           /* water depth (in/out) */
+    double* qx;          /* discharge along x (in/out) */
+    double* qy;          /* discharge along y (in/out) */
+    const double* z;     /* topography (in) */
+    const double* fric;  /* per-cell friction coefficient, or NULL */
+    double* vinf;        /* infiltrated volume per unit area (in/out); NULL
+                            unless infil_on */
+} swe_buffers;
+
+typedef struct swe_ctx swe_ctx;
+
+typedef struct swe_diag {
+    double mass;         /* sum of h dx dy [m^3] */
+    double infiltrated;  /* sum of vinf dx dy [m^3] */
+    double h_min, h_max; /* extrema of h */
+    int64_t wet_cells;   /* cells with h > h_eps */
+} swe_diag;
+
+/* Size in bytes of the device workspace a context needs for these
+ * parameters: a second state (3 nx ny doubles), the stage rate Phi
+ * (3 nx ny doubles) and a 256-byte block of device scalars. */
+int swe_workspace_bytes(const swe_params* p, size_t* bytes);
+
+/* Create a context.  `workspace` is caller-owned device memory of at least
+ * swe_workspace_bytes() bytes, 256-byte aligned; `stream` is a hipStream_t
+ * (NULL = default stream).  The buffers must stay valid for the life of the
+ * context.  Sets t = 0 and clears the status flags (enqueued on the stream). */
+int swe_create(const swe_params* p, const swe_buffers* b, void* workspace,
+               size_t workspace_bytes, void* stream, swe_ctx** out);
+
+int swe_destroy(swe_ctx* ctx);
+
+/* Stream-ordered update of the simulated time t [s]. */
+int swe_set_time(swe_ctx* ctx, double t);
+
+/* Rain intensity [m/s] for steps enqueued after this call. */
+int swe_set_rain(swe_ctx* ctx, double rain);
+
+/* Optional device log of time steps: step k (counted from context creation)
+ * writes its dt to log[k] while k < capacity.  NULL disables. */
+int swe_set_dt_log(swe_ctx* ctx, double* dev_log, int64_t capacity);
+
+/* Enqueue `nsteps` time steps (Algorithm 1: two stages, then Heun, then rain
+ * and infiltration).  dt = min(dt_max, cfl / (Ax/dx + Ay/dy), t_end - t)
+ * where Ax, Ay bound |u| + sqrt(g h) over the reconstructed face states
+ * (eq. cfl).  Steps once t >= t_end are no-ops.  Asynchronous: the host
+ * never waits.  On return (stream order) the state is in the caller's
+ * h/qx/qy buffers. */
+int swe_step(swe_ctx* ctx, int32_t nsteps, double t_end);
+
+/* Synchronizes.  Current time, last dt and number of steps taken. */
+int swe_get_time(swe_ctx* ctx, double* t, double* last_dt, int64_t* steps);
+
+/* Synchronizes.  Sticky SWE_FLAG_* bits; returns the SWE_E* code of the
+ * most serious flag set (0 if none). */
+int swe_get_status(swe_ctx* ctx, uint32_t* flags);
+
+/* Synchronizes.  Deterministic (fixed-order) reductions of the state. */
+int swe_get_diagnostics(swe_ctx* ctx, swe_diag* d);
+
+/* One convective rate evaluation without stepping (Section 3.1, eq.
+ * SW1Dscheme in 2D): Phi(U) = -(X/dx + Y/dy) for the given state, written
+ * to ph/pqx/pqy (device, N doubles each), and the face wave-speed bounds
+ * (Ax, Ay) to amax (host, 2 doubles).  Synchronizes. */
+int swe_rate(swe_ctx* ctx, const double* h, const double* qx,
+             const double* qy, double* ph, double* pqx, double* pqy,
+             double* amax);
+
+/* Per-kernel timing of the next `max_steps` steps: HIP events are recorded
+ * on the context's stream before the stage-1 launch, between the stages and
+ * after the stage-2 launch of each step.  Host-side event objects only; no
+ * device memory.  SWE_EINVAL if a profile is already open. */
+int swe_profile_begin(swe_ctx* ctx, int32_t max_steps);
+
+/* Synchronizes.  Total milliseconds spent in the stage-1 (rate) and stage-2
+ * (update) kernels over the profiled steps, and their number; closes the
+ * profile. */
+int swe_profile_end(swe_ctx* ctx, double* ms_rate, double* ms_update,
+                    int32_t* nsteps);
+
+/* Human-readable text for an error code. */
+const char* swe_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SWE_H */

@@ -65,6 +65,7 @@ def lib(path: Optional[str] = None):
         l.orc_step_fixed.argtypes = [pp, C.c_double, dp, dp, dp, dp, dp, dp]
         l.orc_minmod.argtypes = [C.c_double, C.c_double]
         l.orc_minmod.restype = C.c_double
+        l.orc_num_threads.restype = C.c_int
         l.orc_muscl.argtypes = [dp, dp, dp, C.c_double, dp]
         l.orc_hll.argtypes = [C.c_double] + [C.c_double] * 6 + [dp]
         l.orc_face.argtypes = [C.c_double] + [C.c_double] * 8 + [dp]
@@ -184,6 +185,10 @@ class State:
         assert rc == 0
         self.t += dt
         self.steps += 1
+
+
+def num_threads() -> int:
+    return lib().orc_num_threads()
 
 
 def minmod(a, b):

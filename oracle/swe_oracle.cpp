@@ -42,6 +42,10 @@
 #include <cstring>
 #include <vector>
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
 namespace {
 
 // ---------------------------------------------------------------------------
@@ -617,6 +621,15 @@ int orc_step_fixed(const orc_params* p, double dt, double* h, double* qx,
 // --- single-formula entry points for the unit pins -------------------------
 
 double orc_minmod(double a, double b) { return minmod(a, b); }
+
+// threads the parallel loops use
+int orc_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 // prim rows: {h, un, ut, eta} for cells i-1, i, i+1.  out: {h_m, h_p, z_m,
 // z_p, un_m, un_p, ut_m, ut_p}.

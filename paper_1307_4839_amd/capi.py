@@ -1,0 +1,202 @@
+"""ctypes binding of the C ABI declared in ``include/swe.h``.
+
+Argument marshalling only: every step of the method runs in the HIP
+library.  If the library has not been built the import of this module
+raises, so there is no silent fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.environ.get("SWE_LIB") or os.path.join(_PKG, "libswe_mi355x.so")
+
+SWE_OK = 0
+SWE_EINVAL = -1
+SWE_EHIP = -2
+SWE_ENEGDEPTH = -3
+SWE_ENONFINITE = -4
+SWE_EDT = -5
+SWE_ENOMEM = -6
+
+SWE_FLAG_NEGDEPTH = 1
+SWE_FLAG_NONFINITE = 2
+SWE_FLAG_DT = 4
+
+SWE_BC_WALL = 0
+SWE_BC_OUTFLOW = 1
+SWE_FRIC_NONE = 0
+SWE_FRIC_MANNING = 1
+SWE_FRIC_DARCY = 2
+
+
+class swe_params(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32),
+                ("dx", C.c_double), ("dy", C.c_double),
+                ("g", C.c_double), ("cfl", C.c_double),
+                ("dt_max", C.c_double), ("h_eps", C.c_double),
+                ("bc", C.c_int32 * 4), ("fric_law", C.c_int32),
+                ("fric_coef", C.c_double), ("rain", C.c_double),
+                ("infil_on", C.c_int32), ("ks", C.c_double),
+                ("psi", C.c_double), ("dtheta", C.c_double)]
+
+
+class swe_buffers(C.Structure):
+    _fields_ = [("h", C.c_void_p), ("qx", C.c_void_p), ("qy", C.c_void_p),
+                ("z", C.c_void_p), ("fric", C.c_void_p), ("vinf", C.c_void_p)]
+
+
+class swe_diag(C.Structure):
+    _fields_ = [("mass", C.c_double), ("infiltrated", C.c_double),
+                ("h_min", C.c_double), ("h_max", C.c_double),
+                ("wet_cells", C.c_int64)]
+
+
+EXPORTS = {
+    # name: (restype, argtypes)
+    "swe_workspace_bytes": (C.c_int, [C.POINTER(swe_params), C.POINTER(C.c_size_t)]),
+    "swe_create": (C.c_int, [C.POINTER(swe_params), C.POINTER(swe_buffers),
+                             C.c_void_p, C.c_size_t, C.c_void_p, C.POINTER(C.c_void_p)]),
+    "swe_destroy": (C.c_int, [C.c_void_p]),
+    "swe_set_time": (C.c_int, [C.c_void_p, C.c_double]),
+    "swe_set_rain": (C.c_int, [C.c_void_p, C.c_double]),
+    "swe_set_dt_log": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64]),
+    "swe_step": (C.c_int, [C.c_void_p, C.c_int32, C.c_double]),
+    "swe_get_time": (C.c_int, [C.c_void_p, C.POINTER(C.c_double),
+                               C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+    "swe_get_status": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint32)]),
+    "swe_get_diagnostics": (C.c_int, [C.c_void_p, C.POINTER(swe_diag)]),
+    "swe_rate": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                           C.c_void_p, C.c_void_p, C.c_void_p,
+                           C.POINTER(C.c_double)]),
+    "swe_profile_begin": (C.c_int, [C.c_void_p, C.c_int32]),
+    "swe_profile_end": (C.c_int, [C.c_void_p, C.POINTER(C.c_double),
+                                  C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
+    "swe_strerror": (C.c_char_p, [C.c_int]),
+}
+
+
+def load(path: str = LIB_PATH) -> C.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(
+            f"HIP library {path} is not built; run "
+            "`python -m paper_1307_4839_amd.build` (or __graft_entry__.build())")
+    lib = C.CDLL(path)
+    for name, (res, args) in EXPORTS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    global _lib
+    if _lib is None:
+        _lib = load()
+    return _lib
+
+
+class SweError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        msg = lib().swe_strerror(code).decode()
+        super().__init__(f"{where}: {msg} ({code})")
+        self.code = code
+
+
+def check(code: int, where: str) -> int:
+    if code != SWE_OK:
+        raise SweError(code, where)
+    return code
+
+
+def make_params(nx, ny, dx, dy, g=9.81, cfl=0.5, dt_max=float("inf"),
+                h_eps=1e-12, bc=(0, 0, 0, 0), fric_law=0, fric_coef=0.0,
+                rain=0.0, infil_on=0, ks=0.0, psi=0.0, dtheta=0.0) -> swe_params:
+    p = swe_params()
+    p.nx, p.ny, p.dx, p.dy = nx, ny, dx, dy
+    p.g, p.cfl, p.dt_max, p.h_eps = g, cfl, dt_max, h_eps
+    for k in range(4):
+        p.bc[k] = int(bc[k])
+    p.fric_law, p.fric_coef, p.rain = int(fric_law), fric_coef, rain
+    p.infil_on, p.ks, p.psi, p.dtheta = int(infil_on), ks, psi, dtheta
+    return p
+
+
+# Thin wrappers with the C names (pointers are ints / ctypes values)
+
+def swe_workspace_bytes(p: swe_params) -> int:
+    n = C.c_size_t(0)
+    check(lib().swe_workspace_bytes(C.byref(p), C.byref(n)), "swe_workspace_bytes")
+    return n.value
+
+
+def swe_create(p: swe_params, b: swe_buffers, workspace: int, nbytes: int,
+               stream: int) -> int:
+    ctx = C.c_void_p(0)
+    check(lib().swe_create(C.byref(p), C.byref(b), C.c_void_p(workspace), nbytes,
+                           C.c_void_p(stream), C.byref(ctx)), "swe_create")
+    return ctx.value
+
+
+def swe_destroy(ctx: int) -> None:
+    check(lib().swe_destroy(C.c_void_p(ctx)), "swe_destroy")
+
+
+def swe_set_time(ctx: int, t: float) -> None:
+    check(lib().swe_set_time(C.c_void_p(ctx), t), "swe_set_time")
+
+
+def swe_set_rain(ctx: int, rain: float) -> None:
+    check(lib().swe_set_rain(C.c_void_p(ctx), rain), "swe_set_rain")
+
+
+def swe_set_dt_log(ctx: int, ptr: int, capacity: int) -> None:
+    check(lib().swe_set_dt_log(C.c_void_p(ctx), C.c_void_p(ptr), capacity),
+          "swe_set_dt_log")
+
+
+def swe_step(ctx: int, nsteps: int, t_end: float = float("inf")) -> None:
+    check(lib().swe_step(C.c_void_p(ctx), nsteps, t_end), "swe_step")
+
+
+def swe_get_time(ctx: int):
+    t, dt, n = C.c_double(), C.c_double(), C.c_int64()
+    check(lib().swe_get_time(C.c_void_p(ctx), C.byref(t), C.byref(dt), C.byref(n)),
+          "swe_get_time")
+    return t.value, dt.value, n.value
+
+
+def swe_get_status(ctx: int):
+    f = C.c_uint32(0)
+    rc = lib().swe_get_status(C.c_void_p(ctx), C.byref(f))
+    return rc, f.value
+
+
+def swe_get_diagnostics(ctx: int) -> swe_diag:
+    d = swe_diag()
+    check(lib().swe_get_diagnostics(C.c_void_p(ctx), C.byref(d)), "swe_get_diagnostics")
+    return d
+
+
+def swe_rate(ctx: int, h: int, qx: int, qy: int, ph: int, pqx: int, pqy: int):
+    amax = (C.c_double * 2)()
+    check(lib().swe_rate(C.c_void_p(ctx), C.c_void_p(h), C.c_void_p(qx),
+                         C.c_void_p(qy), C.c_void_p(ph), C.c_void_p(pqx),
+                         C.c_void_p(pqy), amax), "swe_rate")
+    return amax[0], amax[1]
+
+
+def swe_profile_begin(ctx: int, max_steps: int) -> None:
+    check(lib().swe_profile_begin(C.c_void_p(ctx), max_steps), "swe_profile_begin")
+
+
+def swe_profile_end(ctx: int):
+    a, b, n = C.c_double(), C.c_double(), C.c_int32()
+    check(lib().swe_profile_end(C.c_void_p(ctx), C.byref(a), C.byref(b), C.byref(n)),
+          "swe_profile_end")
+    return a.value, b.value, n.value

@@ -41,6 +41,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
+import os
 from typing import Dict, Optional
 
 import numpy as np
@@ -153,12 +154,17 @@ class _Perlin:
 def fbm(rng: np.random.Generator, nx: int, ny: int, dx: float, dy: float,
         wavelength: float, octaves: int = 4, lacunarity: float = 2.0,
         persistence: float = 0.5, chunk_rows: int = 256) -> np.ndarray:
-    """Fractal Brownian motion of Perlin noise normalised to max|.| = 1."""
+    """Fractal Brownian motion of Perlin noise normalised to max|.| = 1.
+
+    Row chunks are evaluated on a thread pool (numpy releases the GIL); the
+    values do not depend on the chunking or the thread count.
+    """
     noise = _Perlin(rng)
     offs = rng.uniform(0.0, 256.0, size=(octaves, 2))
     xs = (np.arange(nx) + 0.5) * dx
     out = np.empty((ny, nx), dtype=np.float64)
-    for r0 in range(0, ny, chunk_rows):
+
+    def work(r0):
         r1 = min(ny, r0 + chunk_rows)
         ys = (np.arange(r0, r1) + 0.5) * dy
         X, Y = np.meshgrid(xs, ys)
@@ -169,6 +175,15 @@ def fbm(rng: np.random.Generator, nx: int, ny: int, dx: float, dy: float,
             amp *= persistence
             freq *= lacunarity
         out[r0:r1] = acc
+
+    starts = list(range(0, ny, chunk_rows))
+    if len(starts) > 1:
+        from concurrent.futures import ThreadPoolExecutor
+        nthreads = min(len(starts), max(1, min(16, os.cpu_count() or 1)))
+        with ThreadPoolExecutor(nthreads) as ex:
+            list(ex.map(work, starts))
+    else:
+        work(0)
     m = np.abs(out).max()
     if m > 0:
         out /= m

@@ -1,0 +1,133 @@
+"""Torch-facing wrapper of the C ABI: tensors for device memory, the current
+stream for ordering.  No arithmetic of the method happens here."""
+
+from __future__ import annotations
+
+import math
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import capi
+
+
+def _dev(a, device) -> torch.Tensor:
+    t = torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64))
+    return t.to(device=device).contiguous()
+
+
+def params_from(wl) -> capi.swe_params:
+    return capi.make_params(**wl.params())
+
+
+class Solver:
+    """One simulation on one GPU.
+
+    The state tensors ``h``, ``qx``, ``qy`` (and ``vinf`` with infiltration)
+    are owned here and handed to the library by pointer; after ``step`` they
+    hold the new state (stream-ordered).
+    """
+
+    def __init__(self, wl, device: str = "cuda", dt_log: int = 0):
+        if not torch.cuda.is_available():
+            raise RuntimeError("the HIP library needs a GPU")
+        self.device = torch.device(device)
+        self.params = params_from(wl)
+        self.nx, self.ny = wl.nx, wl.ny
+        self.h = _dev(wl.h, self.device)
+        self.qx = _dev(wl.qx, self.device)
+        self.qy = _dev(wl.qy, self.device)
+        self.z = _dev(wl.z, self.device)
+        self.fric = None if wl.fric is None else _dev(wl.fric, self.device)
+        if wl.infil_on:
+            v = np.zeros((wl.ny, wl.nx)) if wl.vinf is None else wl.vinf
+            self.vinf = _dev(v, self.device)
+        else:
+            self.vinf = None
+        nbytes = capi.swe_workspace_bytes(self.params)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) & ~255
+        b = capi.swe_buffers()
+        b.h, b.qx, b.qy = self.h.data_ptr(), self.qx.data_ptr(), self.qy.data_ptr()
+        b.z = self.z.data_ptr()
+        b.fric = self.fric.data_ptr() if self.fric is not None else None
+        b.vinf = self.vinf.data_ptr() if self.vinf is not None else None
+        self._buffers = b
+        self.stream = torch.cuda.current_stream(self.device)
+        self.ctx = capi.swe_create(self.params, b, aligned, nbytes,
+                                   self.stream.cuda_stream)
+        self.dt_log = None
+        if dt_log:
+            self.dt_log = torch.zeros(dt_log, dtype=torch.float64, device=self.device)
+            capi.swe_set_dt_log(self.ctx, self.dt_log.data_ptr(), dt_log)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            capi.swe_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- stepping ---------------------------------------------------------
+    def step(self, nsteps: int, t_end: float = math.inf) -> None:
+        capi.swe_step(self.ctx, nsteps, t_end)
+
+    def profile_begin(self, max_steps: int) -> None:
+        capi.swe_profile_begin(self.ctx, max_steps)
+
+    def profile_end(self):
+        """(ms in the rate kernel, ms in the update kernel, steps)."""
+        return capi.swe_profile_end(self.ctx)
+
+    def time(self):
+        """(t, last_dt, steps); synchronizes."""
+        return capi.swe_get_time(self.ctx)
+
+    def status(self):
+        return capi.swe_get_status(self.ctx)
+
+    def set_time(self, t: float) -> None:
+        capi.swe_set_time(self.ctx, t)
+
+    def set_rain(self, r: float) -> None:
+        capi.swe_set_rain(self.ctx, r)
+
+    def diagnostics(self) -> capi.swe_diag:
+        return capi.swe_get_diagnostics(self.ctx)
+
+    def rate(self, h: torch.Tensor, qx: torch.Tensor, qy: torch.Tensor):
+        ph = torch.empty_like(h)
+        pqx = torch.empty_like(h)
+        pqy = torch.empty_like(h)
+        amax = capi.swe_rate(self.ctx, h.data_ptr(), qx.data_ptr(), qy.data_ptr(),
+                             ph.data_ptr(), pqx.data_ptr(), pqy.data_ptr())
+        return ph, pqx, pqy, amax
+
+    # -- state access -----------------------------------------------------
+    def state(self):
+        torch.cuda.synchronize(self.device)
+        out = dict(h=self.h.cpu().numpy(), qx=self.qx.cpu().numpy(),
+                   qy=self.qy.cpu().numpy())
+        if self.vinf is not None:
+            out["vinf"] = self.vinf.cpu().numpy()
+        return out
+
+    def set_state(self, h, qx, qy, vinf=None) -> None:
+        self.h.copy_(torch.as_tensor(np.asarray(h, dtype=np.float64)))
+        self.qx.copy_(torch.as_tensor(np.asarray(qx, dtype=np.float64)))
+        self.qy.copy_(torch.as_tensor(np.asarray(qy, dtype=np.float64)))
+        if vinf is not None and self.vinf is not None:
+            self.vinf.copy_(torch.as_tensor(np.asarray(vinf, dtype=np.float64)))
+
+    def dts(self, n: Optional[int] = None) -> np.ndarray:
+        if self.dt_log is None:
+            raise RuntimeError("no dt log")
+        _, _, steps = self.time()
+        k = steps if n is None else n
+        return self.dt_log[:k].cpu().numpy()

@@ -1,0 +1,76 @@
+"""Host-side checks of the C-ABI library (no GPU needed, no compute calls)."""
+
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared(header):
+    src = open(os.path.join(ROOT, "include", header)).read()
+    return re.findall(r"^\s*(?:const\s+)?\w+\**\s+\**(swe_\w+)\s*\(", src, re.M)
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1307_4839_amd import capi
+    lib = capi.lib()
+    names = declared("swe.h")
+    assert len(names) >= 12
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_every_declared_symbol():
+    from paper_1307_4839_amd import capi
+    names = set(declared("swe.h"))
+    assert names <= set(capi.EXPORTS), names - set(capi.EXPORTS)
+
+
+def test_parameter_validation_without_gpu():
+    # swe_workspace_bytes touches no device: it must validate on the host
+    from paper_1307_4839_amd import capi
+    ok = capi.make_params(10, 10, 1.0, 1.0)
+    n = capi.swe_workspace_bytes(ok)
+    assert n >= 6 * 100 * 8
+    for bad in (capi.make_params(1, 10, 1.0, 1.0),
+                capi.make_params(10, 10, 0.0, 1.0),
+                capi.make_params(10, 10, 1.0, 1.0, bc=(0, 0, 0, 7)),
+                capi.make_params(10, 10, 1.0, 1.0, fric_law=5),
+                capi.make_params(10, 10, 1.0, 1.0, infil_on=1, dtheta=0.0),
+                capi.make_params(10, 10, 1.0, 1.0, dt_max=0.0)):
+        with pytest.raises(capi.SweError) as e:
+            capi.swe_workspace_bytes(bad)
+        assert e.value.code == capi.SWE_EINVAL
+
+
+def test_strerror_texts():
+    from paper_1307_4839_amd import capi
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert capi.lib().swe_strerror(code)
+    assert capi.lib().swe_strerror(-99) == b"unknown error"
+
+
+def test_struct_layouts_match_header(tmp_path):
+    # the ctypes mirrors must have the C layout: compile the header with gcc
+    # and print every offset
+    import ctypes as C
+    import subprocess
+    from paper_1307_4839_amd import capi
+    checks = []
+    for sname, cls in (("swe_params", capi.swe_params), ("swe_buffers", capi.swe_buffers),
+                       ("swe_diag", capi.swe_diag)):
+        checks.append((sname, "sizeof", C.sizeof(cls)))
+        for f, _ in cls._fields_:
+            checks.append((sname, f, getattr(cls, f).offset))
+    body = "\n".join(
+        f'printf("%zu\\n", (size_t)sizeof({s}));' if f == "sizeof"
+        else f'printf("%zu\\n", (size_t)offsetof({s}, {f}));' for s, f, _ in checks)
+    src = tmp_path / "layout.c"
+    src.write_text("#include <stdio.h>\n#include <stddef.h>\n#include \"swe.h\"\n"
+                   "int main(void){" + body + "return 0;}\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
+    assert got == [v for _, _, v in checks]
