@@ -29,7 +29,7 @@ if ROOT not in sys.path:
 
 METRIC = "cell-updates/s (FP64) + % HBM roofline; ensemble & adjoint vs plain, same GPU"
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
-KERNEL_SRC = os.path.join(ROOT, "paper_1307_4839_amd", "csrc", "swe_step.hip")
+CSRC = os.path.join(ROOT, "paper_1307_4839_amd", "csrc")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_hillslope_8192.json")
 
 
@@ -50,8 +50,13 @@ def algorithmic_bytes(wl):
 
 
 def kernel_hash():
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Hash of the HIP sources the stage kernels are built from."""
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(name.encode())
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def load_traffic(kernel_name):
@@ -93,6 +98,56 @@ def cpu_baseline(wl, rows, steps):
                       f"in {el:.1f} s)"}
 
 
+def ensemble_leg(members, steps, trial_steps):
+    """The ensemble in one persistent launch per stage (autotuned tile shape,
+    graph-replayed steps) vs the same scenarios run one after another with
+    the single-simulation context on the same GPU."""
+    import torch
+
+    from paper_1307_4839_amd.solver import Ensemble, Solver
+    cells = sum(wl.nx * wl.ny for wl in members)
+    e = Ensemble(members, device="cuda:0")
+    tx, ty, ms_trial = e.autotune(trial_steps)
+    print(f"[bench] ensemble autotune: tiles {tx}x{ty} ({ms_trial:.3f} ms/step in trials)",
+          file=sys.stderr, flush=True)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(e.stream)
+    e.step(steps)
+    ev1.record(e.stream)
+    torch.cuda.synchronize()
+    ms_e = ev0.elapsed_time(ev1)
+    rc, flags = e.status()
+    e.close()
+    del e
+    torch.cuda.empty_cache()
+    print(f"[bench] ensemble: {len(members)} members, {cells} cells, {steps} steps in "
+          f"{ms_e:.1f} ms (status {rc})", file=sys.stderr, flush=True)
+    ms_seq = 0.0
+    for wl in members:
+        g = Solver(wl, device="cuda:0")
+        torch.cuda.synchronize()
+        ev0.record(g.stream)
+        g.step(steps)
+        ev1.record(g.stream)
+        torch.cuda.synchronize()
+        ms_seq += ev0.elapsed_time(ev1)
+        g.close()
+        del g
+    torch.cuda.empty_cache()
+    print(f"[bench] sequential single runs: {ms_seq:.1f} ms", file=sys.stderr, flush=True)
+    v_e = cells * steps / (ms_e / 1e3)
+    v_s = cells * steps / (ms_seq / 1e3)
+    return {"workload": f"ensemble of {len(members)} square grids, log-uniform 64..1024 cells "
+                        f"a side, {steps} steps each",
+            "members": len(members), "cells": cells, "steps": steps,
+            "value": v_e, "unit": "cell-updates/s", "ms": ms_e,
+            "sequential_value": v_s, "sequential_ms": ms_seq,
+            "speedup_vs_sequential": ms_seq / ms_e, "tiling": [tx, ty],
+            "status": rc}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -106,6 +161,9 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=2048)
     ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--ensemble-members", type=int, default=256)
+    ap.add_argument("--ensemble-steps", type=int, default=500)
     ap.add_argument("--probe-copy-mib", type=int, default=0,
                     help="after the run, copy a float64 tensor of this many MiB once "
                          "(a plain copy of known size that calibrates byte counters)")
@@ -193,6 +251,16 @@ def main(argv=None):
               flush=True)
         del src, dst
 
+    ens = None
+    if not args.no_ensemble:
+        del g
+        torch.cuda.empty_cache()
+        t0 = time.perf_counter()
+        members = I.ensemble(args.ensemble_members)
+        print(f"[bench] ensemble inputs generated in {time.perf_counter() - t0:.1f} s",
+              file=sys.stderr, flush=True)
+        ens = ensemble_leg(members, args.ensemble_steps, 4)
+
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
@@ -221,6 +289,8 @@ def main(argv=None):
         "kernels": kern,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "ensemble": ens,
+        "adjoint": None,
         "sim_time_s": t_sim,
         "status_flags": flags,
     }

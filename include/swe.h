@@ -112,6 +112,14 @@ int swe_create(const swe_params* p, const swe_buffers* b, void* workspace,
 
 int swe_destroy(swe_ctx* ctx);
 
+/* Tile shape of the stage kernels: `tx` threads per block (64, 128 or 256)
+ * own a strip of tx - 4 output columns; each block marches `ty` rows
+ * (0 = automatic).  Results do not depend on the tile shape (every cell and
+ * face is evaluated by the same formulas on the same inputs).  SWE_EINVAL
+ * for other widths or a ty that leaves more than 65535 row blocks. */
+int swe_set_tiling(swe_ctx* ctx, int32_t tx, int32_t ty);
+int swe_get_tiling(swe_ctx* ctx, int32_t* tx, int32_t* ty);
+
 /* Stream-ordered update of the simulated time t [s]. */
 int swe_set_time(swe_ctx* ctx, double t);
 
@@ -126,8 +134,9 @@ int swe_set_dt_log(swe_ctx* ctx, double* dev_log, int64_t capacity);
  * and infiltration).  dt = min(dt_max, cfl / (Ax/dx + Ay/dy), t_end - t)
  * where Ax, Ay bound |u| + sqrt(g h) over the reconstructed face states
  * (eq. cfl).  Steps once t >= t_end are no-ops.  Asynchronous: the host
- * never waits.  On return (stream order) the state is in the caller's
- * h/qx/qy buffers. */
+ * never waits.  Runs of 16 steps replay a captured HIP graph (re-captured
+ * when t_end, the rain, the tiling or the dt log change).  On return
+ * (stream order) the state is in the caller's h/qx/qy buffers. */
 int swe_step(swe_ctx* ctx, int32_t nsteps, double t_end);
 
 /* Synchronizes.  Current time, last dt and number of steps taken. */
@@ -159,6 +168,51 @@ int swe_profile_begin(swe_ctx* ctx, int32_t max_steps);
  * profile. */
 int swe_profile_end(swe_ctx* ctx, double* ms_rate, double* ms_update,
                     int32_t* nsteps);
+
+/* ---------------------------------------------------------------------------
+ * Ensembles: `count` independent simulations of arbitrary (uneven) sizes
+ * stepped together.  Member k has its own swe_params p[k] and caller-owned
+ * buffers b[k] (same conventions as swe_create), its own time, time step
+ * (its own CFL bound), status flags and rain.  One step of the ensemble is
+ * one persistent launch per stage over a work list of (member, strip, row
+ * range) tiles; runs of 16 steps replay a captured HIP graph.  Every member
+ * evolves exactly (bit for bit) as it would in its own context.
+ * ------------------------------------------------------------------------- */
+typedef struct swe_batch swe_batch;
+
+/* Device workspace for the ensemble: member table, work list, and per
+ * member a scalar block, a second state, the stage rate and a backup of the
+ * state used by the autotuner. */
+int swe_batch_workspace_bytes(const swe_params* p, int32_t count, size_t* bytes);
+
+int swe_batch_create(const swe_params* p, const swe_buffers* b, int32_t count,
+                     void* workspace, size_t workspace_bytes, void* stream,
+                     swe_batch** out);
+int swe_batch_destroy(swe_batch* b);
+
+/* Tile shape of the ensemble kernels: tx in {64, 128, 256}, ty >= 4. */
+int swe_batch_set_tiling(swe_batch* b, int32_t tx, int32_t ty);
+int swe_batch_get_tiling(swe_batch* b, int32_t* tx, int32_t* ty, int32_t* ntiles);
+
+/* Measure every tile shape (tx in {64, 128, 256} x ty in {8, 16, 32, 64})
+ * on `trial_steps` steps of the live ensemble, keep the fastest, and restore
+ * the state, times and flags exactly as they were.  Synchronizes.  Returns
+ * the chosen shape and its time per step [ms]. */
+int swe_batch_autotune(swe_batch* b, int32_t trial_steps, int32_t* tx, int32_t* ty,
+                       double* ms_per_step);
+
+int swe_batch_set_rain(swe_batch* b, int32_t member, double rain);
+int swe_batch_set_dt_log(swe_batch* b, int32_t member, double* dev_log, int64_t capacity);
+
+/* Enqueue `nsteps` steps of every member (members stop at t_end). */
+int swe_batch_step(swe_batch* b, int32_t nsteps, double t_end);
+
+/* Synchronize.  Time of one member; sticky flags of all members (flags has
+ * room for n >= count entries); the return code is that of the most serious
+ * flag set in any member. */
+int swe_batch_get_time(swe_batch* b, int32_t member, double* t, double* last_dt,
+                       int64_t* steps);
+int swe_batch_get_status(swe_batch* b, uint32_t* flags, int32_t n);
 
 /* Human-readable text for an error code. */
 const char* swe_strerror(int code);

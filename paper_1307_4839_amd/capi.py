@@ -60,6 +60,8 @@ EXPORTS = {
     "swe_create": (C.c_int, [C.POINTER(swe_params), C.POINTER(swe_buffers),
                              C.c_void_p, C.c_size_t, C.c_void_p, C.POINTER(C.c_void_p)]),
     "swe_destroy": (C.c_int, [C.c_void_p]),
+    "swe_set_tiling": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
+    "swe_get_tiling": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "swe_set_time": (C.c_int, [C.c_void_p, C.c_double]),
     "swe_set_rain": (C.c_int, [C.c_void_p, C.c_double]),
     "swe_set_dt_log": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64]),
@@ -74,6 +76,23 @@ EXPORTS = {
     "swe_profile_begin": (C.c_int, [C.c_void_p, C.c_int32]),
     "swe_profile_end": (C.c_int, [C.c_void_p, C.POINTER(C.c_double),
                                   C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
+    "swe_batch_workspace_bytes": (C.c_int, [C.POINTER(swe_params), C.c_int32,
+                                            C.POINTER(C.c_size_t)]),
+    "swe_batch_create": (C.c_int, [C.POINTER(swe_params), C.POINTER(swe_buffers), C.c_int32,
+                                   C.c_void_p, C.c_size_t, C.c_void_p,
+                                   C.POINTER(C.c_void_p)]),
+    "swe_batch_destroy": (C.c_int, [C.c_void_p]),
+    "swe_batch_set_tiling": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
+    "swe_batch_get_tiling": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32),
+                                       C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "swe_batch_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32),
+                                     C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
+    "swe_batch_set_rain": (C.c_int, [C.c_void_p, C.c_int32, C.c_double]),
+    "swe_batch_set_dt_log": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int64]),
+    "swe_batch_step": (C.c_int, [C.c_void_p, C.c_int32, C.c_double]),
+    "swe_batch_get_time": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_double),
+                                     C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+    "swe_batch_get_status": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint32), C.c_int32]),
     "swe_strerror": (C.c_char_p, [C.c_int]),
 }
 
@@ -147,6 +166,16 @@ def swe_destroy(ctx: int) -> None:
     check(lib().swe_destroy(C.c_void_p(ctx)), "swe_destroy")
 
 
+def swe_set_tiling(ctx: int, tx: int, ty: int = 0) -> None:
+    check(lib().swe_set_tiling(C.c_void_p(ctx), tx, ty), "swe_set_tiling")
+
+
+def swe_get_tiling(ctx: int):
+    tx, ty = C.c_int32(), C.c_int32()
+    check(lib().swe_get_tiling(C.c_void_p(ctx), C.byref(tx), C.byref(ty)), "swe_get_tiling")
+    return tx.value, ty.value
+
+
 def swe_set_time(ctx: int, t: float) -> None:
     check(lib().swe_set_time(C.c_void_p(ctx), t), "swe_set_time")
 
@@ -200,3 +229,69 @@ def swe_profile_end(ctx: int):
     check(lib().swe_profile_end(C.c_void_p(ctx), C.byref(a), C.byref(b), C.byref(n)),
           "swe_profile_end")
     return a.value, b.value, n.value
+
+
+# -- ensembles -----------------------------------------------------------------
+
+def swe_batch_workspace_bytes(ps) -> int:
+    arr = (swe_params * len(ps))(*ps)
+    n = C.c_size_t(0)
+    check(lib().swe_batch_workspace_bytes(arr, len(ps), C.byref(n)), "swe_batch_workspace_bytes")
+    return n.value
+
+
+def swe_batch_create(ps, bs, workspace: int, nbytes: int, stream: int) -> int:
+    pa = (swe_params * len(ps))(*ps)
+    ba = (swe_buffers * len(bs))(*bs)
+    out = C.c_void_p(0)
+    check(lib().swe_batch_create(pa, ba, len(ps), C.c_void_p(workspace), nbytes,
+                                 C.c_void_p(stream), C.byref(out)), "swe_batch_create")
+    return out.value
+
+
+def swe_batch_destroy(b: int) -> None:
+    check(lib().swe_batch_destroy(C.c_void_p(b)), "swe_batch_destroy")
+
+
+def swe_batch_set_tiling(b: int, tx: int, ty: int) -> None:
+    check(lib().swe_batch_set_tiling(C.c_void_p(b), tx, ty), "swe_batch_set_tiling")
+
+
+def swe_batch_get_tiling(b: int):
+    tx, ty, nt = C.c_int32(), C.c_int32(), C.c_int32()
+    check(lib().swe_batch_get_tiling(C.c_void_p(b), C.byref(tx), C.byref(ty), C.byref(nt)),
+          "swe_batch_get_tiling")
+    return tx.value, ty.value, nt.value
+
+
+def swe_batch_autotune(b: int, trial_steps: int):
+    tx, ty, ms = C.c_int32(), C.c_int32(), C.c_double()
+    check(lib().swe_batch_autotune(C.c_void_p(b), trial_steps, C.byref(tx), C.byref(ty),
+                                   C.byref(ms)), "swe_batch_autotune")
+    return tx.value, ty.value, ms.value
+
+
+def swe_batch_set_rain(b: int, member: int, rain: float) -> None:
+    check(lib().swe_batch_set_rain(C.c_void_p(b), member, rain), "swe_batch_set_rain")
+
+
+def swe_batch_set_dt_log(b: int, member: int, ptr: int, capacity: int) -> None:
+    check(lib().swe_batch_set_dt_log(C.c_void_p(b), member, C.c_void_p(ptr), capacity),
+          "swe_batch_set_dt_log")
+
+
+def swe_batch_step(b: int, nsteps: int, t_end: float = float("inf")) -> None:
+    check(lib().swe_batch_step(C.c_void_p(b), nsteps, t_end), "swe_batch_step")
+
+
+def swe_batch_get_time(b: int, member: int):
+    t, dt, n = C.c_double(), C.c_double(), C.c_int64()
+    check(lib().swe_batch_get_time(C.c_void_p(b), member, C.byref(t), C.byref(dt),
+                                   C.byref(n)), "swe_batch_get_time")
+    return t.value, dt.value, n.value
+
+
+def swe_batch_get_status(b: int, count: int):
+    flags = (C.c_uint32 * count)()
+    rc = lib().swe_batch_get_status(C.c_void_p(b), flags, count)
+    return rc, list(flags)

@@ -1,0 +1,523 @@
+// Ensemble of independent simulations of uneven sizes stepped together
+// (C ABI swe_batch_*, include/swe.h).
+//
+// Every member runs the same two stages as a single simulation (the tile
+// routine of swe_device.h), with its own grid, parameters, time, time step
+// (its own CFL bound, Section 3.3), status flags and buffers.  A step of the
+// whole ensemble is ONE persistent launch per stage: a grid sized to the
+// resident capacity of the GPU walks a work list of (member, strip, row
+// range) tiles, largest members first.  Runs of 16 steps replay a captured
+// HIP graph.  The tile shape (strip width x rows) is chosen by a measuring
+// autotuner that times the candidates on the live state and restores it
+// bit for bit afterwards; results never depend on the tile shape.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <vector>
+
+#include "swe.h"
+#include "swe_device.h"
+#include "swe_host.h"
+
+using namespace swe_dev;
+using namespace swe_host;
+
+namespace {
+
+constexpr int GRAPH_STEPS = 16;  // steps per captured graph (even)
+constexpr int MIN_TY = 4;        // smallest rows per tile the work list is sized for
+
+template <int STAGE, int TXT>
+__global__ __launch_bounds__(TXT) void batch_stage_kernel(const MemberArgs* __restrict__ ms,
+                                                          const int4* __restrict__ tiles,
+                                                          int ntiles, int phase, int slot,
+                                                          double t_end) {
+    for (int k = blockIdx.x; k < ntiles; k += gridDim.x) {
+        const int4 tl = tiles[k];  // member, strip, first row, end row
+        const MemberArgs m = ms[tl.x];
+        const TileIO io = step_io(m, phase, slot, t_end);
+        stage_tile<STAGE, TXT>(m, io, tl.y, tl.z, tl.w, tl.y == 0 && tl.z == 0);
+    }
+}
+
+// Copy the workspace state (buffer 1) back to the caller's buffers (0) for
+// every member: block row y handles member y.
+__global__ void batch_copyback_kernel(const MemberArgs* __restrict__ ms) {
+    const MemberArgs& m = ms[blockIdx.y];
+    size_t n = (size_t)m.p.nx * m.p.ny;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        m.h[0][i] = m.h[1][i];
+        m.qx[0][i] = m.qx[1][i];
+        m.qy[0][i] = m.qy[1][i];
+    }
+}
+
+// Save (dir = 0) or restore (dir = 1) each member's state, V_inf and
+// scalar block to/from the backup area.
+struct Backup {
+    double* h;
+    double* qx;
+    double* qy;
+    double* vinf;
+    DevScalars* sc;
+};
+
+__global__ void batch_backup_kernel(const MemberArgs* __restrict__ ms,
+                                    const Backup* __restrict__ bk, int dir) {
+    const MemberArgs& m = ms[blockIdx.y];
+    const Backup& b = bk[blockIdx.y];
+    size_t n = (size_t)m.p.nx * m.p.ny;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        if (dir == 0) {
+            b.h[i] = m.h[0][i];
+            b.qx[i] = m.qx[0][i];
+            b.qy[i] = m.qy[0][i];
+            if (m.vinf) b.vinf[i] = m.vinf[i];
+        } else {
+            m.h[0][i] = b.h[i];
+            m.qx[0][i] = b.qx[i];
+            m.qy[0][i] = b.qy[i];
+            if (m.vinf) m.vinf[i] = b.vinf[i];
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (dir == 0) *b.sc = *m.sc;
+        else *m.sc = *b.sc;
+    }
+}
+
+template <int STAGE>
+void launch_batch(int tx, int grid, hipStream_t s, const MemberArgs* ms, const int4* tiles,
+                  int ntiles, int phase, int slot, double t_end) {
+    switch (tx) {
+        case 64:
+            hipLaunchKernelGGL((batch_stage_kernel<STAGE, 64>), dim3(grid), dim3(64), 0, s, ms,
+                               tiles, ntiles, phase, slot, t_end);
+            break;
+        case 128:
+            hipLaunchKernelGGL((batch_stage_kernel<STAGE, 128>), dim3(grid), dim3(128), 0, s,
+                               ms, tiles, ntiles, phase, slot, t_end);
+            break;
+        default:
+            hipLaunchKernelGGL((batch_stage_kernel<STAGE, 256>), dim3(grid), dim3(256), 0, s,
+                               ms, tiles, ntiles, phase, slot, t_end);
+            break;
+    }
+}
+
+template <int STAGE, int TXT>
+int resident_blocks() {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_stage_kernel<STAGE, TXT>, TXT,
+                                                     0) != hipSuccess)
+        return 1;
+    return nb < 1 ? 1 : nb;
+}
+
+}  // namespace
+
+struct swe_batch {
+    int count;
+    std::vector<swe_params> prm;
+    std::vector<MemberArgs> mh;   // host copies of the member table
+    std::vector<Backup> bh;       // host copies of the backup table
+    MemberArgs* md;               // device member table
+    Backup* bd;                   // device backup table
+    int4* tiles;                  // device work list
+    size_t tiles_cap;
+    int ntiles;
+    int tx, ty;
+    int cus;
+    int grid1, grid2;             // persistent grid of each stage for this tiling
+    hipStream_t stream;
+    int slot;
+    size_t max_cells;
+    hipGraphExec_t graph;
+    hipStream_t cap_stream;  // private stream used only to capture graphs
+    int graph_slot;
+    double graph_t_end;
+    unsigned graph_epoch;
+    unsigned epoch;
+};
+
+namespace {
+
+size_t tiles_for(const swe_batch* b, int tx, int ty) {
+    size_t n = 0;
+    for (int k = 0; k < b->count; ++k)
+        n += (size_t)strips_of(b->prm[k].nx, tx) * ((b->prm[k].ny + ty - 1) / ty);
+    return n;
+}
+
+size_t max_tiles(const swe_params* p, int count) {
+    size_t n = 0;
+    for (int k = 0; k < count; ++k)
+        n += (size_t)strips_of(p[k].nx, 64) * ((p[k].ny + MIN_TY - 1) / MIN_TY);
+    return n;
+}
+
+int upload_members(swe_batch* b) {
+    if (hipMemcpyAsync(b->md, b->mh.data(), sizeof(MemberArgs) * b->count,
+                       hipMemcpyHostToDevice, b->stream) != hipSuccess)
+        return SWE_EHIP;
+    if (hipStreamSynchronize(b->stream) != hipSuccess) return SWE_EHIP;
+    b->epoch++;
+    return SWE_OK;
+}
+
+int persistent_grid(const swe_batch* b, int stage) {
+    int nb;
+    if (stage == 1)
+        nb = b->tx == 64 ? resident_blocks<1, 64>()
+             : b->tx == 128 ? resident_blocks<1, 128>() : resident_blocks<1, 256>();
+    else
+        nb = b->tx == 64 ? resident_blocks<2, 64>()
+             : b->tx == 128 ? resident_blocks<2, 128>() : resident_blocks<2, 256>();
+    long long g = (long long)nb * b->cus;
+    if (g > b->ntiles) g = b->ntiles;
+    return g < 1 ? 1 : (int)g;
+}
+
+// Work list for a tile shape: members from largest to smallest, each
+// member's tiles in strip-major order.
+int build_tiles(swe_batch* b, int tx, int ty) {
+    size_t n = tiles_for(b, tx, ty);
+    if (n > b->tiles_cap || n > (size_t)0x7fffffff) return SWE_EINVAL;
+    std::vector<int> order(b->count);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
+        return (size_t)b->prm[a].nx * b->prm[a].ny > (size_t)b->prm[c].nx * b->prm[c].ny;
+    });
+    std::vector<int4> t;
+    t.reserve(n);
+    for (int k : order) {
+        int strips = strips_of(b->prm[k].nx, tx);
+        for (int s = 0; s < strips; ++s)
+            for (int y = 0; y < b->prm[k].ny; y += ty)
+                t.push_back(make_int4(k, s, y, std::min(y + ty, b->prm[k].ny)));
+    }
+    if (hipMemcpyAsync(b->tiles, t.data(), sizeof(int4) * t.size(), hipMemcpyHostToDevice,
+                       b->stream) != hipSuccess)
+        return SWE_EHIP;
+    if (hipStreamSynchronize(b->stream) != hipSuccess) return SWE_EHIP;
+    b->ntiles = (int)t.size();
+    b->tx = tx;
+    b->ty = ty;
+    b->grid1 = persistent_grid(b, 1);
+    b->grid2 = persistent_grid(b, 2);
+    b->epoch++;
+    return SWE_OK;
+}
+
+void enqueue_step(swe_batch* b, int phase, double t_end) {
+    launch_batch<1>(b->tx, b->grid1, b->stream, b->md, b->tiles, b->ntiles, phase, b->slot,
+                    t_end);
+    launch_batch<2>(b->tx, b->grid2, b->stream, b->md, b->tiles, b->ntiles, phase, b->slot,
+                    t_end);
+    b->slot ^= 1;
+}
+
+void drop_graph(swe_batch* b) {
+    if (b->graph) {
+        (void)hipGraphExecDestroy(b->graph);
+        b->graph = nullptr;
+    }
+}
+
+int ensure_graph(swe_batch* b, double t_end) {
+    if (b->graph && b->graph_slot == b->slot && b->graph_t_end == t_end &&
+        b->graph_epoch == b->epoch)
+        return SWE_OK;
+    drop_graph(b);
+    int slot0 = b->slot;
+    // the caller's stream may be the legacy default stream, which cannot be
+    // captured: record on a private stream, launch on the caller's
+    if (!b->cap_stream &&
+        hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        b->cap_stream = nullptr;
+        return SWE_EHIP;
+    }
+    hipStream_t user = b->stream;
+    b->stream = b->cap_stream;
+    if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        b->stream = user;
+        return SWE_EHIP;
+    }
+    for (int k = 0; k < GRAPH_STEPS; ++k) enqueue_step(b, k & 1, t_end);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(b->stream, &g);
+    b->stream = user;
+    b->slot = slot0;
+    if (e != hipSuccess || !g) return SWE_EHIP;
+    e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        b->graph = nullptr;
+        return SWE_EHIP;
+    }
+    b->graph_slot = slot0;
+    b->graph_t_end = t_end;
+    b->graph_epoch = b->epoch;
+    return SWE_OK;
+}
+
+int run_steps(swe_batch* b, int32_t nsteps, double t_end, bool use_graph) {
+    int32_t k = 0;
+    if (use_graph && nsteps >= GRAPH_STEPS) {
+        int rc = ensure_graph(b, t_end);
+        if (rc) return rc;
+        for (; k + GRAPH_STEPS <= nsteps; k += GRAPH_STEPS)
+            if (hipGraphLaunch(b->graph, b->stream) != hipSuccess) return SWE_EHIP;
+    }
+    int phase = 0;
+    for (; k < nsteps; ++k) {
+        enqueue_step(b, phase, t_end);
+        phase ^= 1;
+    }
+    if (phase == 1)
+        hipLaunchKernelGGL(batch_copyback_kernel, dim3(256, b->count), dim3(256), 0, b->stream,
+                           (const MemberArgs*)b->md);
+    return hip_ok(hipGetLastError());
+}
+
+size_t member_bytes(const swe_params& p) {
+    size_t an = align256(ncells(&p) * sizeof(double));
+    // scalars, second state, rate, backup of the state (+ V_inf), backup scalars
+    return 256 + 3 * an + 3 * an + 3 * an + (p.infil_on ? an : 0) + 256;
+}
+
+}  // namespace
+
+extern "C" {
+
+int swe_batch_workspace_bytes(const swe_params* p, int32_t count, size_t* bytes) {
+    if (!p || count < 1 || !bytes) return SWE_EINVAL;
+    size_t total = align256(sizeof(MemberArgs) * count) + align256(sizeof(Backup) * count) +
+                   align256(sizeof(int4) * max_tiles(p, count));
+    for (int k = 0; k < count; ++k) {
+        int rc = check_params(&p[k]);
+        if (rc) return rc;
+        total += member_bytes(p[k]);
+    }
+    *bytes = total;
+    return SWE_OK;
+}
+
+int swe_batch_create(const swe_params* p, const swe_buffers* bufs, int32_t count,
+                     void* workspace, size_t workspace_bytes, void* stream, swe_batch** out) {
+    size_t need = 0;
+    int rc = swe_batch_workspace_bytes(p, count, &need);
+    if (rc) return rc;
+    if (!bufs || !out || !workspace || ((uintptr_t)workspace & 255) != 0) return SWE_EINVAL;
+    if (workspace_bytes < need) return SWE_ENOMEM;
+    for (int k = 0; k < count; ++k) {
+        const swe_buffers& b = bufs[k];
+        if (!b.h || !b.qx || !b.qy || !b.z) return SWE_EINVAL;
+        if (p[k].infil_on && !b.vinf) return SWE_EINVAL;
+    }
+    swe_batch* b = new (std::nothrow) swe_batch;
+    if (!b) return SWE_ENOMEM;
+    b->count = count;
+    b->prm.assign(p, p + count);
+    b->mh.resize(count);
+    b->bh.resize(count);
+    b->stream = (hipStream_t)stream;
+    b->slot = 0;
+    b->graph = nullptr;
+    b->cap_stream = nullptr;
+    b->epoch = 0;
+    b->graph_epoch = 0;
+    b->max_cells = 0;
+    char* w = (char*)workspace;
+    b->md = (MemberArgs*)w;
+    w += align256(sizeof(MemberArgs) * count);
+    b->bd = (Backup*)w;
+    w += align256(sizeof(Backup) * count);
+    b->tiles = (int4*)w;
+    b->tiles_cap = max_tiles(p, count);
+    w += align256(sizeof(int4) * b->tiles_cap);
+    for (int k = 0; k < count; ++k) {
+        MemberArgs& m = b->mh[k];
+        std::memset(&m, 0, sizeof m);
+        size_t n = ncells(&p[k]), an = align256(n * sizeof(double));
+        b->max_cells = std::max(b->max_cells, n);
+        m.p = to_kparams(p[k]);
+        m.z = bufs[k].z;
+        m.fric = bufs[k].fric;
+        m.vinf = p[k].infil_on ? bufs[k].vinf : nullptr;
+        m.sc = (DevScalars*)w; w += 256;
+        m.h[0] = bufs[k].h; m.qx[0] = bufs[k].qx; m.qy[0] = bufs[k].qy;
+        m.h[1] = (double*)w; w += an;
+        m.qx[1] = (double*)w; w += an;
+        m.qy[1] = (double*)w; w += an;
+        m.ph = (double*)w; w += an;
+        m.pqx = (double*)w; w += an;
+        m.pqy = (double*)w; w += an;
+        Backup& bk = b->bh[k];
+        bk.h = (double*)w; w += an;
+        bk.qx = (double*)w; w += an;
+        bk.qy = (double*)w; w += an;
+        bk.vinf = nullptr;
+        if (p[k].infil_on) { bk.vinf = (double*)w; w += an; }
+        bk.sc = (DevScalars*)w; w += 256;
+        hipLaunchKernelGGL(swe_init_scalars_kernel, dim3(1), dim3(64), 0, b->stream, m.sc, 0.0);
+    }
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    b->cus = 256;
+    (void)hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipMemcpyAsync(b->bd, b->bh.data(), sizeof(Backup) * count, hipMemcpyHostToDevice,
+                       b->stream) != hipSuccess) {
+        delete b;
+        return SWE_EHIP;
+    }
+    rc = upload_members(b);
+    // default tile shape: strips of 256 columns; rows for the largest member
+    int big = 0;
+    for (int k = 1; k < count; ++k)
+        if (ncells(&p[k]) > ncells(&p[big])) big = k;
+    if (!rc) rc = build_tiles(b, 256, std::max(MIN_TY, auto_rows(p[big].nx, p[big].ny, 256) / 2));
+    if (rc) {
+        delete b;
+        return rc;
+    }
+    *out = b;
+    return SWE_OK;
+}
+
+int swe_batch_destroy(swe_batch* b) {
+    if (!b) return SWE_OK;
+    drop_graph(b);
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    delete b;
+    return SWE_OK;
+}
+
+int swe_batch_set_tiling(swe_batch* b, int32_t tx, int32_t ty) {
+    if (!b || !valid_tx(tx) || ty < MIN_TY) return SWE_EINVAL;
+    return build_tiles(b, tx, ty);
+}
+
+int swe_batch_get_tiling(swe_batch* b, int32_t* tx, int32_t* ty, int32_t* ntiles) {
+    if (!b) return SWE_EINVAL;
+    if (tx) *tx = b->tx;
+    if (ty) *ty = b->ty;
+    if (ntiles) *ntiles = b->ntiles;
+    return SWE_OK;
+}
+
+int swe_batch_autotune(swe_batch* b, int32_t trial_steps, int32_t* tx_out, int32_t* ty_out,
+                       double* ms_out) {
+    if (!b || trial_steps < 2) return SWE_EINVAL;
+    trial_steps += trial_steps & 1;
+    const int cand_tx[3] = {64, 128, 256};
+    const int cand_ty[4] = {8, 16, 32, 64};
+    int slot0 = b->slot;
+    // save the state once; every candidate starts from it and it is put
+    // back at the end, so tuning leaves no trace in the results
+    hipLaunchKernelGGL(batch_backup_kernel, dim3(256, b->count), dim3(256), 0, b->stream,
+                       (const MemberArgs*)b->md, (const Backup*)b->bd, 0);
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return SWE_EHIP;
+    if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return SWE_EHIP; }
+    double best = INFINITY;
+    int btx = b->tx, bty = b->ty;
+    int rc = SWE_OK;
+    for (int i = 0; i < 3 && rc == SWE_OK; ++i) {
+        for (int j = 0; j < 4 && rc == SWE_OK; ++j) {
+            rc = build_tiles(b, cand_tx[i], cand_ty[j]);
+            if (rc) break;
+            rc = run_steps(b, 2, INFINITY, false);  // warm the caches and code
+            if (rc) break;
+            (void)hipEventRecord(e0, b->stream);
+            rc = run_steps(b, trial_steps, INFINITY, false);
+            (void)hipEventRecord(e1, b->stream);
+            if (rc) break;
+            if (hipEventSynchronize(e1) != hipSuccess) { rc = SWE_EHIP; break; }
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (ms < best) {
+                best = ms;
+                btx = cand_tx[i];
+                bty = cand_ty[j];
+            }
+            hipLaunchKernelGGL(batch_backup_kernel, dim3(256, b->count), dim3(256), 0,
+                               b->stream, (const MemberArgs*)b->md, (const Backup*)b->bd, 1);
+            b->slot = slot0;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc == SWE_OK) rc = build_tiles(b, btx, bty);
+    hipLaunchKernelGGL(batch_backup_kernel, dim3(256, b->count), dim3(256), 0, b->stream,
+                       (const MemberArgs*)b->md, (const Backup*)b->bd, 1);
+    b->slot = slot0;
+    if (hipStreamSynchronize(b->stream) != hipSuccess && rc == SWE_OK) rc = SWE_EHIP;
+    if (tx_out) *tx_out = b->tx;
+    if (ty_out) *ty_out = b->ty;
+    if (ms_out) *ms_out = best / trial_steps;
+    return rc;
+}
+
+int swe_batch_set_rain(swe_batch* b, int32_t member, double rain) {
+    if (!b || member < 0 || member >= b->count || !(rain >= 0.0) || !std::isfinite(rain))
+        return SWE_EINVAL;
+    b->prm[member].rain = rain;
+    b->mh[member].p.rain = rain;
+    return upload_members(b);
+}
+
+int swe_batch_set_dt_log(swe_batch* b, int32_t member, double* dev_log, int64_t capacity) {
+    if (!b || member < 0 || member >= b->count || capacity < 0) return SWE_EINVAL;
+    b->mh[member].dtlog = dev_log;
+    b->mh[member].dtlog_cap = dev_log ? capacity : 0;
+    return upload_members(b);
+}
+
+int swe_batch_step(swe_batch* b, int32_t nsteps, double t_end) {
+    if (!b || nsteps < 0 || std::isnan(t_end)) return SWE_EINVAL;
+    if (nsteps == 0) return SWE_OK;
+    return run_steps(b, nsteps, t_end, true);
+}
+
+int swe_batch_get_time(swe_batch* b, int32_t member, double* t, double* last_dt,
+                       int64_t* steps) {
+    if (!b || member < 0 || member >= b->count) return SWE_EINVAL;
+    DevScalars s;
+    if (hipMemcpyAsync(&s, b->mh[member].sc, sizeof s, hipMemcpyDeviceToHost, b->stream) !=
+        hipSuccess)
+        return SWE_EHIP;
+    if (hipStreamSynchronize(b->stream) != hipSuccess) return SWE_EHIP;
+    if (t) *t = s.t[b->slot];
+    if (last_dt) *last_dt = s.last_dt;
+    if (steps) *steps = s.steps[b->slot];
+    return SWE_OK;
+}
+
+int swe_batch_get_status(swe_batch* b, uint32_t* flags, int32_t n) {
+    if (!b || !flags || n < b->count) return SWE_EINVAL;
+    uint32_t any = 0;
+    for (int k = 0; k < b->count; ++k) {
+        DevScalars s;
+        if (hipMemcpyAsync(&s, b->mh[k].sc, sizeof s, hipMemcpyDeviceToHost, b->stream) !=
+            hipSuccess)
+            return SWE_EHIP;
+        if (hipStreamSynchronize(b->stream) != hipSuccess) return SWE_EHIP;
+        flags[k] = s.status;
+        any |= s.status;
+    }
+    if (any & SWE_FLAG_NONFINITE) return SWE_ENONFINITE;
+    if (any & SWE_FLAG_NEGDEPTH) return SWE_ENEGDEPTH;
+    if (any & SWE_FLAG_DT) return SWE_EDT;
+    return SWE_OK;
+}
+
+}  // extern "C"

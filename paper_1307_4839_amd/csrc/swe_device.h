@@ -1,0 +1,642 @@
+// Device code shared by the single-simulation and the ensemble kernels:
+// the formulas of the scheme (arXiv:1307.4839, Sections 2-3) and the
+// routine that advances one tile (a strip of columns over a range of rows)
+// through one stage.
+//
+// Tiling: a block of TXT threads owns a strip of TXT columns, of which the
+// TXT-4 interior ones are outputs (two halo columns per side feed the
+// second-order stencil), and marches down a range of rows.  Along y the
+// stencil lives in registers (each thread keeps a rolling window of its own
+// column, and the loads of the next row are issued one iteration ahead), so
+// every y-face is evaluated once.  Along x neighbours exchange values
+// through LDS, so every x-face is also evaluated once.  Boundary ghost cells
+// (Section 2.2, two layers at second order, Section 6.1) are index maps in
+// the loader; no ghost arrays exist in HBM.
+//
+// Arithmetic follows the formulas in the order they are written; with
+// -ffp-contract=off and IEEE division and square root the only operation
+// that is not correctly rounded is the cube root of the Manning law.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "swe.h"
+
+namespace swe_dev {
+
+constexpr int HALO = 2;  // ghost/halo width at second order
+
+// ---------------------------------------------------------------------------
+// Device-side scalars (in the workspace)
+// ---------------------------------------------------------------------------
+
+struct DevScalars {
+    unsigned long long amax[3][2];  // per slot: bit patterns of Ax, Ay >= 0
+    double t[2];                    // time, double-buffered by step parity
+    long long steps[2];             // steps taken, double-buffered
+    double last_dt;
+    unsigned int status;            // sticky SWE_FLAG_* bits
+    unsigned int pad;
+};
+static_assert(sizeof(DevScalars) <= 256, "scalar block must fit 256 bytes");
+
+struct KParams {
+    int nx, ny;
+    double dx, dy, g, cfl, dt_max, h_eps;
+    int bcw, bce, bcs, bcn;
+    int law;
+    double coef;
+    double rain;
+    int infil;
+    double ks, psi, dtheta;
+};
+
+// ---------------------------------------------------------------------------
+// Formulas (Sections 3.1, 3.3, 3.4)
+// ---------------------------------------------------------------------------
+
+// For ordered (non-NaN) operands these return the same value as the
+// comparisons they replace (up to the sign of a zero, which no later
+// operation can turn into a different non-zero value).
+__device__ __forceinline__ double vmax(double a, double b) { return fmax(a, b); }
+__device__ __forceinline__ double vmin(double a, double b) { return fmin(a, b); }
+
+// minmod limiter, Section 3.4: min(a, b) if both >= 0, max(a, b) if both
+// <= 0, else 0.  Branch-free form with the same value:
+// max(min(a, b), min(max(a, b), 0)).
+__device__ __forceinline__ double minmod(double a, double b) {
+    return fmax(fmin(a, b), fmin(fmax(a, b), 0.0));
+}
+
+// primitive variables of a cell: depth, velocity normal and tangential to
+// the sweep direction, free surface eta = h + z
+struct Prim {
+    double h, un, ut, eta;
+};
+
+// reconstructed face values: _m at the face i-1/2, _p at the face i+1/2
+struct Rec {
+    double h_m, h_p, z_m, z_p, un_m, un_p, ut_m, ut_p;
+};
+
+// MUSCL on h, h+z and the velocity with minmod on undivided differences;
+// z deduced; modified velocity reconstruction conserving discharge
+// (Section 3.4).  A cell at or below the dry threshold keeps its velocity.
+__device__ __forceinline__ Rec muscl(const Prim& a, const Prim& c, const Prim& b,
+                                     double h_eps) {
+    Rec r;
+    double dh = minmod(c.h - a.h, b.h - c.h);
+    r.h_m = c.h - 0.5 * dh;
+    r.h_p = c.h + 0.5 * dh;
+    double de = minmod(c.eta - a.eta, b.eta - c.eta);
+    double eta_m = c.eta - 0.5 * de;
+    double eta_p = c.eta + 0.5 * de;
+    r.z_m = eta_m - r.h_m;
+    r.z_p = eta_p - r.h_p;
+    double dun = minmod(c.un - a.un, b.un - c.un);
+    double dut = minmod(c.ut - a.ut, b.ut - c.ut);
+    if (c.h > h_eps) {
+        double wp = r.h_p / c.h;
+        double wm = r.h_m / c.h;
+        r.un_m = c.un - wp * (0.5 * dun);
+        r.un_p = c.un + wm * (0.5 * dun);
+        r.ut_m = c.ut - wp * (0.5 * dut);
+        r.ut_p = c.ut + wm * (0.5 * dut);
+    } else {
+        r.un_m = c.un;
+        r.un_p = c.un;
+        r.ut_m = c.ut;
+        r.ut_p = c.ut;
+    }
+    return r;
+}
+
+// Flux through one face: hydrostatic reconstruction (Section 3.1), HLL
+// (Section 3.3), and the normal-momentum corrections S_L (left cell) and
+// S_R (right cell).  fl = flux seen by the left cell, fr = by the right one.
+// speed = max(|u-| + sqrt(g h-), |u+| + sqrt(g h+)) on the MUSCL states.
+struct FaceOut {
+    double f0, fl1, fr1, f2;
+    double speed;
+};
+
+__device__ __forceinline__ FaceOut face(double g, double hm, double zm, double unm,
+                                        double utm, double hp, double zp, double unp,
+                                        double utp) {
+    double zs = vmax(zm, zp);
+    double hL = vmax(hm + zm - zs, 0.0);
+    double hR = vmax(hp + zp - zs, 0.0);
+    double cL = sqrt(g * hL);
+    double cR = sqrt(g * hR);
+    double c1 = vmin(unm - cL, unp - cR);
+    double c2 = vmax(unm + cL, unp + cR);
+    double qL = hL * unm;
+    double qR = hR * unp;
+    double hg = 0.5 * g;
+    double FL0 = qL, FL1 = qL * unm + hg * hL * hL, FL2 = qL * utm;
+    double FR0 = qR, FR1 = qR * unp + hg * hR * hR, FR2 = qR * utp;
+    double F0, F1, F2;
+    if (0.0 <= c1) {
+        F0 = FL0; F1 = FL1; F2 = FL2;
+    } else if (c2 <= 0.0) {
+        F0 = FR0; F1 = FR1; F2 = FR2;
+    } else {
+        double den = c2 - c1;
+        double w = c1 * c2 / den;
+        F0 = (c2 * FL0 - c1 * FR0) / den + w * (hR - hL);
+        F1 = (c2 * FL1 - c1 * FR1) / den + w * (qR - qL);
+        F2 = (c2 * FL2 - c1 * FR2) / den + w * (hR * utp - hL * utm);
+    }
+    double sL = hg * (hm * hm - hL * hL);
+    double sR = hg * (hp * hp - hR * hR);
+    FaceOut o;
+    o.f0 = F0;
+    o.fl1 = F1 + sL;
+    o.fr1 = F1 + sR;
+    o.f2 = F2;
+    double sm = fabs(unm) + sqrt(g * hm);
+    double sp = fabs(unp) + sqrt(g * hp);
+    o.speed = fmax(sm, sp);
+    return o;
+}
+
+// centred source Fc of Section 3.1 (normal momentum)
+__device__ __forceinline__ double centred(double g, const Rec& r) {
+    return (-g) * (0.5 * (r.h_m + r.h_p)) * (r.z_p - r.z_m);
+}
+
+// Semi-implicit friction of one stage (Section 3.2).  (h0, q0) stage input,
+// (h1, q1) convective output.
+__device__ __forceinline__ void friction(const KParams& p, double coef, double h0,
+                                         double qx0, double qy0, double h1,
+                                         double& qx1, double& qy1, double dt) {
+    if (h1 <= p.h_eps) {
+        qx1 = 0.0;
+        qy1 = 0.0;
+        return;
+    }
+    if (p.law == SWE_FRIC_NONE || !(h0 > p.h_eps)) return;
+    double qn = sqrt(qx0 * qx0 + qy0 * qy0);
+    double den;
+    if (p.law == SWE_FRIC_DARCY)
+        den = 1.0 + dt * (coef / 8.0) * qn / (h0 * h1);
+    else
+        den = 1.0 + dt * p.g * coef * coef * qn / (h0 * (h1 * cbrt(h1)));
+    qx1 = qx1 / den;
+    qy1 = qy1 / den;
+}
+
+// dt from the wave-speed bounds (eq. cfl in 2D), clipped to dt_max and to
+// the remaining time.
+__device__ __forceinline__ double time_step(const KParams& p, double ax, double ay,
+                                            double t, double t_end) {
+    double r = ax / p.dx + ay / p.dy;
+    double dt = p.dt_max;
+    if (r > 0.0) {
+        double c = p.cfl / r;
+        if (c < dt) dt = c;
+    }
+    double rest = t_end - t;
+    if (rest < dt) dt = rest;
+    return dt;
+}
+
+// Rain, then Green-Ampt (Section 3.5); the infiltrated water leaves with the
+// cell's velocity.
+__device__ __forceinline__ void rain_infiltration(const KParams& p, double dt,
+                                                  double& h, double& qx, double& qy,
+                                                  double& vinf) {
+    h = h + dt * p.rain;
+    if (!p.infil) return;
+    double d;
+    if (vinf > 0.0) {
+        double zf = vinf / p.dtheta;
+        double ic = p.ks * (1.0 + (p.psi + h) / zf);
+        d = vmin(h, dt * ic);
+    } else {
+        d = h;
+    }
+    double h_old = h;
+    h = h - d;
+    vinf = vinf + d;
+    if (h_old > 0.0) {
+        double r = h / h_old;
+        qx = qx * r;
+        qy = qy * r;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Ghost mapping (Section 2.2): wall = mirror with negated normal discharge;
+// outflow = copy of the boundary cell.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int map_index(int c, int n, int bc_lo, int bc_hi,
+                                         double& sign) {
+    sign = 1.0;
+    int s = c;
+    if (c < 0) {
+        if (bc_lo == SWE_BC_WALL) { s = -1 - c; sign = -1.0; }
+        else s = 0;
+    } else if (c >= n) {
+        if (bc_hi == SWE_BC_WALL) { s = 2 * n - 1 - c; sign = -1.0; }
+        else s = n - 1;
+    }
+    // indices beyond the two ghost layers are never used by an output;
+    // keep them in bounds
+    s = s < 0 ? 0 : (s >= n ? n - 1 : s);
+    return s;
+}
+
+// ---------------------------------------------------------------------------
+// Arguments
+// ---------------------------------------------------------------------------
+
+// One simulation (a member of an ensemble, or the single simulation of a
+// context).  Read-only during a step.
+struct MemberArgs {
+    KParams p;
+    const double* z;
+    const double* fric;    // per-cell coefficient or nullptr
+    double* vinf;          // Green-Ampt state or nullptr
+    double* h[2];          // state buffers: [0] caller's, [1] workspace
+    double* qx[2];
+    double* qy[2];
+    double* ph;            // stage rate Phi (3 arrays)
+    double* pqx;
+    double* pqy;
+    DevScalars* sc;
+    double* dtlog;
+    long long dtlog_cap;
+};
+
+// Buffers of one stage launch.
+struct TileIO {
+    const double* h;       // U^n
+    const double* qx;
+    const double* qy;
+    double* ph;            // stage 1 writes, stage 2 reads
+    double* pqx;
+    double* pqy;
+    double* ho;            // stage 2 output U^{n+1}
+    double* qxo;
+    double* qyo;
+    unsigned long long* acc;  // stage 1: (Ax, Ay) accumulators
+    unsigned long long* clr;  // stage 1: pair zeroed for the next step (or null)
+    int slot;                 // step parity (time buffer, accumulator slot)
+    double t_end;
+};
+
+__device__ __forceinline__ TileIO step_io(const MemberArgs& m, int phase, int slot,
+                                          double t_end) {
+    TileIO io;
+    io.h = m.h[phase];
+    io.qx = m.qx[phase];
+    io.qy = m.qy[phase];
+    io.ph = m.ph;
+    io.pqx = m.pqx;
+    io.pqy = m.pqy;
+    io.ho = m.h[phase ^ 1];
+    io.qxo = m.qx[phase ^ 1];
+    io.qyo = m.qy[phase ^ 1];
+    io.acc = m.sc->amax[slot];
+    io.clr = m.sc->amax[slot ^ 1];
+    io.slot = slot;
+    io.t_end = t_end;
+    return io;
+}
+
+struct RawCell {
+    double h, qx, qy, z;
+};
+
+// Raw values of one cell of the stage input as read from HBM.  Stage 1:
+// U^n and z.  Stage 2 also: Phi(U^n) and the friction coefficient.
+template <int STAGE> struct Fetch {
+    double h, qx, qy, z;
+    double ph, pqx, pqy, coef;
+    double sy;  // sign applied to qy (wall ghost rows)
+};
+
+__device__ __forceinline__ Prim prim_x(const RawCell& c, double h_eps) {
+    Prim p;
+    p.h = c.h;
+    if (c.h > h_eps) {
+        p.un = c.qx / c.h;
+        p.ut = c.qy / c.h;
+    } else {
+        p.un = 0.0;
+        p.ut = 0.0;
+    }
+    p.eta = c.h + c.z;
+    return p;
+}
+
+// y-view of a cell's primitives: normal velocity v, tangential u
+__device__ __forceinline__ Prim to_y(const Prim& px) {
+    Prim p;
+    p.h = px.h;
+    p.un = px.ut;
+    p.ut = px.un;
+    p.eta = px.eta;
+    return p;
+}
+
+// Issue the loads of cell (row r, mapped column cs).
+template <int STAGE>
+__device__ __forceinline__ Fetch<STAGE> fetch(const MemberArgs& m, const TileIO& io, int r,
+                                              int cs) {
+    Fetch<STAGE> f;
+    int rs = map_index(r, m.p.ny, m.p.bcs, m.p.bcn, f.sy);
+    size_t idx = (size_t)rs * m.p.nx + cs;
+    f.h = io.h[idx];
+    f.qx = io.qx[idx];
+    f.qy = io.qy[idx];
+    f.z = m.z[idx];
+    if (STAGE == 2) {
+        f.ph = io.ph[idx];
+        f.pqx = io.pqx[idx];
+        f.pqy = io.pqy[idx];
+        f.coef = m.fric ? m.fric[idx] : m.p.coef;
+    } else {
+        f.ph = f.pqx = f.pqy = f.coef = 0.0;
+    }
+    return f;
+}
+
+// Stage input of a fetched cell.  Stage 1: U^n.  Stage 2: U* =
+// friction(U^n + dt Phi(U^n)) (the first stage of Heun's method, Section
+// 3.2).  Ghost sign flips (walls) are applied last.
+template <int STAGE>
+__device__ __forceinline__ RawCell build(const KParams& p, const Fetch<STAGE>& f,
+                                         double sx, double dt) {
+    RawCell o;
+    o.z = f.z;
+    if (STAGE == 1) {
+        o.h = f.h;
+        o.qx = f.qx;
+        o.qy = f.qy;
+    } else {
+        double h1 = f.h + dt * f.ph;
+        double qx1 = f.qx + dt * f.pqx;
+        double qy1 = f.qy + dt * f.pqy;
+        friction(p, f.coef, f.h, f.qx, f.qy, h1, qx1, qy1, dt);
+        o.h = h1;
+        o.qx = qx1;
+        o.qy = qy1;
+    }
+    o.qx = sx * o.qx;
+    o.qy = f.sy * o.qy;
+    return o;
+}
+
+__device__ __forceinline__ unsigned long long as_bits(double x) {
+    return (unsigned long long)__double_as_longlong(x);
+}
+
+// block-wide maximum of two non-negative doubles, then one atomic each
+template <int TXT>
+__device__ void block_max2(double ax, double ay, unsigned long long* dst) {
+    __shared__ double red[2][TXT / 64];
+    for (int off = 32; off > 0; off >>= 1) {
+        double ox = __shfl_down(ax, off, 64);
+        double oy = __shfl_down(ay, off, 64);
+        ax = ax < ox ? ox : ax;
+        ay = ay < oy ? oy : ay;
+    }
+    int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+        red[0][wave] = ax;
+        red[1][wave] = ay;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double mx = red[0][0], my = red[1][0];
+        for (int w = 1; w < TXT / 64; ++w) {
+            mx = mx < red[0][w] ? red[0][w] : mx;
+            my = my < red[1][w] ? red[1][w] : my;
+        }
+        // non-negative doubles order like their bit patterns; NaN speeds
+        // never enter the maximum (every comparison with NaN is false), as
+        // in the oracle, and a non-finite state is flagged by the update
+        atomicMax(&dst[0], as_bits(mx));
+        atomicMax(&dst[1], as_bits(my));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// One tile through one stage
+// ---------------------------------------------------------------------------
+//
+// STAGE 1 (rate): Phi(U^n) to io.ph/pqx/pqy and the face wave-speed bounds
+// of eq. (cfl) into io.acc.  STAGE 2 (update): dt from the bounds, U* rebuilt
+// on the fly, Phi(U*), U** = friction(U* + dt Phi(U*)), Heun's average,
+// rain and Green-Ampt, U^{n+1} to io.ho/qxo/qyo.  `lead` marks the one tile
+// per simulation that does the scalar bookkeeping (time, step count, dt log,
+// clearing the next step's accumulators).
+template <int STAGE, int TXT>
+__device__ __forceinline__ void stage_tile(const MemberArgs& m, const TileIO& io, int strip,
+                                           int y0, int y1, bool lead) {
+    constexpr int OUTW = TXT - 2 * HALO;
+    const KParams& p = m.p;
+    const int t = threadIdx.x;
+    const int x0 = strip * OUTW;
+    const int c = x0 - HALO + t;
+    const bool out_col = (t >= HALO) && (t < TXT - HALO) && (c < p.nx);
+    const bool col_in = (c >= 0) && (c < p.nx);
+    // a face c+1/2 computed by thread t has valid neighbour data when
+    // 1 <= t <= TXT-3; it is a real face when -1 <= c <= nx-1
+    const bool xface_ok = (t >= 1) && (t <= TXT - 3) && (c >= -1) && (c <= p.nx - 1);
+
+    __shared__ double s_h[TXT], s_u[TXT], s_v[TXT], s_e[TXT];
+    __shared__ double s_hm[TXT], s_zm[TXT], s_unm[TXT], s_utm[TXT];
+    __shared__ double s_f0[TXT], s_f1[TXT], s_f2[TXT];
+
+    double dt = 0.0;
+    if (STAGE == 2) {
+        double ax = __longlong_as_double((long long)m.sc->amax[io.slot][0]);
+        double ay = __longlong_as_double((long long)m.sc->amax[io.slot][1]);
+        double tc = m.sc->t[io.slot];
+        dt = time_step(p, ax, ay, tc, io.t_end);
+        const bool finite = (dt - dt) == 0.0;  // false for inf and NaN
+        if (lead && t == 0) {
+            long long st = m.sc->steps[io.slot];
+            if (finite && dt > 0.0) {
+                m.sc->t[io.slot ^ 1] = tc + dt;
+                m.sc->steps[io.slot ^ 1] = st + 1;
+                m.sc->last_dt = dt;
+                if (m.dtlog && st < m.dtlog_cap) m.dtlog[st] = dt;
+            } else {
+                m.sc->t[io.slot ^ 1] = tc;
+                m.sc->steps[io.slot ^ 1] = st;
+                if (!finite) atomicOr(&m.sc->status, (unsigned)SWE_FLAG_DT);
+            }
+        }
+        if (!(finite && dt > 0.0)) {
+            // no step: U^{n+1} = U^n
+            if (out_col) {
+                for (int j = y0; j < y1; ++j) {
+                    size_t idx = (size_t)j * p.nx + c;
+                    io.ho[idx] = io.h[idx];
+                    io.qxo[idx] = io.qx[idx];
+                    io.qyo[idx] = io.qy[idx];
+                }
+            }
+            return;
+        }
+    } else {
+        if (io.clr && lead && t == 0) {
+            io.clr[0] = 0ull;
+            io.clr[1] = 0ull;
+        }
+    }
+
+    double sx;
+    const int cs = map_index(c, p.nx, p.bcw, p.bce, sx);
+
+    // --- prologue: rows y0-2 .. y0+1, face y0-1/2; prefetch row y0+2 -------
+    Fetch<STAGE> fA = fetch<STAGE>(m, io, y0 - 2, cs);
+    Fetch<STAGE> fB = fetch<STAGE>(m, io, y0 - 1, cs);
+    Fetch<STAGE> fC = fetch<STAGE>(m, io, y0, cs);
+    Fetch<STAGE> fD = fetch<STAGE>(m, io, y0 + 1, cs);
+    Fetch<STAGE> fnext = fetch<STAGE>(m, io, y0 + 2, cs);
+    RawCell rC = build<STAGE>(p, fC, sx, dt);
+    RawCell rD = build<STAGE>(p, fD, sx, dt);
+    Prim pA = prim_x(build<STAGE>(p, fA, sx, dt), p.h_eps);
+    Prim pB = prim_x(build<STAGE>(p, fB, sx, dt), p.h_eps);
+    Prim p0 = prim_x(rC, p.h_eps), p1 = prim_x(rD, p.h_eps);
+    // stage input discharges of rows j and j+1 (stage 2 needs them for U**)
+    double q0x = rC.qx, q0y = rC.qy, q1x = rD.qx, q1y = rD.qy;
+    // U^n of rows j and j+1 (stage 2: Heun's average)
+    double n0h = fC.h, n0x = fC.qx, n0y = fC.qy, n1h = fD.h, n1x = fD.qx, n1y = fD.qy;
+    double c0 = fC.coef, c1 = fD.coef;
+
+    Rec rprev = muscl(to_y(pA), to_y(pB), to_y(p0), p.h_eps);
+    Rec rcur = muscl(to_y(pB), to_y(p0), to_y(p1), p.h_eps);
+    double ax = 0.0, ay = 0.0;
+    double gm0, gm1, gm2;  // face below the current row, as seen from above
+    {
+        FaceOut gm = face(p.g, rprev.h_p, rprev.z_p, rprev.un_p, rprev.ut_p, rcur.h_m,
+                          rcur.z_m, rcur.un_m, rcur.ut_m);
+        if (y0 == 0 && col_in) ay = gm.speed;
+        gm0 = gm.f0;
+        gm1 = gm.fr1;
+        gm2 = gm.f2;
+    }
+
+    for (int j = y0; j < y1; ++j) {
+        // the loads of row j+2 were issued one iteration ahead; issue j+3
+        Fetch<STAGE> f2 = fnext;
+        if (j + 1 < y1) fnext = fetch<STAGE>(m, io, j + 3, cs);
+
+        // ---- y direction, all in registers ----
+        RawCell r2 = build<STAGE>(p, f2, sx, dt);
+        Prim p2 = prim_x(r2, p.h_eps);
+        Rec rnext = muscl(to_y(p0), to_y(p1), to_y(p2), p.h_eps);
+        FaceOut gp = face(p.g, rcur.h_p, rcur.z_p, rcur.un_p, rcur.ut_p, rnext.h_m,
+                          rnext.z_m, rnext.un_m, rnext.ut_m);
+        if (STAGE == 1 && col_in) ay = fmax(ay, gp.speed);
+        double fcy = centred(p.g, rcur);
+        double Y0 = gp.f0 - gm0;
+        double Y1 = gp.fl1 - gm1 - fcy;  // normal momentum (qy)
+        double Y2 = gp.f2 - gm2;         // tangential momentum (qx)
+
+        // ---- x direction, neighbours through LDS ----
+        s_h[t] = p0.h;
+        s_u[t] = p0.un;
+        s_v[t] = p0.ut;
+        s_e[t] = p0.eta;
+        __syncthreads();
+        Prim pl, pr;
+        {
+            int tl = t > 0 ? t - 1 : t;
+            int tr = t < TXT - 1 ? t + 1 : t;
+            pl.h = s_h[tl]; pl.un = s_u[tl]; pl.ut = s_v[tl]; pl.eta = s_e[tl];
+            pr.h = s_h[tr]; pr.un = s_u[tr]; pr.ut = s_v[tr]; pr.eta = s_e[tr];
+        }
+        Rec rx = muscl(pl, p0, pr, p.h_eps);
+        s_hm[t] = rx.h_m;
+        s_zm[t] = rx.z_m;
+        s_unm[t] = rx.un_m;
+        s_utm[t] = rx.ut_m;
+        __syncthreads();
+        FaceOut fp;
+        {
+            int tr = t < TXT - 1 ? t + 1 : t;
+            fp = face(p.g, rx.h_p, rx.z_p, rx.un_p, rx.ut_p, s_hm[tr], s_zm[tr],
+                      s_unm[tr], s_utm[tr]);
+        }
+        if (STAGE == 1 && xface_ok) ax = fmax(ax, fp.speed);
+        s_f0[t] = fp.f0;
+        s_f1[t] = fp.fr1;
+        s_f2[t] = fp.f2;
+        __syncthreads();
+        double fm0, fm1, fm2;
+        {
+            int tl = t > 0 ? t - 1 : t;
+            fm0 = s_f0[tl];
+            fm1 = s_f1[tl];
+            fm2 = s_f2[tl];
+        }
+        double fcx = centred(p.g, rx);
+        double X0 = fp.f0 - fm0;
+        double X1 = fp.fl1 - fm1 - fcx;  // normal momentum (qx)
+        double X2 = fp.f2 - fm2;         // tangential momentum (qy)
+
+        double rh = -(X0 / p.dx + Y0 / p.dy);
+        double rqx = -(X1 / p.dx + Y2 / p.dy);
+        double rqy = -(X2 / p.dx + Y1 / p.dy);
+
+        if (out_col) {
+            size_t idx = (size_t)j * p.nx + c;
+            if (STAGE == 1) {
+                io.ph[idx] = rh;
+                io.pqx[idx] = rqx;
+                io.pqy[idx] = rqy;
+            } else {
+                // U** = friction(U* + dt Phi(U*)), stage input U*
+                double h2 = p0.h + dt * rh;
+                double qx2 = q0x + dt * rqx;
+                double qy2 = q0y + dt * rqy;
+                friction(p, c0, p0.h, q0x, q0y, h2, qx2, qy2, dt);
+                // Heun: U^{n+1} = (U^n + U**)/2
+                double hn = 0.5 * (n0h + h2);
+                double qxn = 0.5 * (n0x + qx2);
+                double qyn = 0.5 * (n0y + qy2);
+                double vi = 0.0;
+                if (p.infil) vi = m.vinf[idx];
+                rain_infiltration(p, dt, hn, qxn, qyn, vi);
+                if (p.infil) m.vinf[idx] = vi;
+                io.ho[idx] = hn;
+                io.qxo[idx] = qxn;
+                io.qyo[idx] = qyn;
+                bool fin = (hn - hn) == 0.0 && (qxn - qxn) == 0.0 && (qyn - qyn) == 0.0;
+                if (!fin)
+                    atomicOr(&m.sc->status, (unsigned)SWE_FLAG_NONFINITE);
+                else if (hn < 0.0)
+                    atomicOr(&m.sc->status, (unsigned)SWE_FLAG_NEGDEPTH);
+            }
+        }
+
+        // ---- shift the rolling window ----
+        p0 = p1;
+        p1 = p2;
+        q0x = q1x; q0y = q1y;
+        q1x = r2.qx; q1y = r2.qy;
+        n0h = n1h; n0x = n1x; n0y = n1y;
+        n1h = f2.h; n1x = f2.qx; n1y = f2.qy;
+        c0 = c1;
+        c1 = f2.coef;
+        rcur = rnext;
+        gm0 = gp.f0;
+        gm1 = gp.fr1;
+        gm2 = gp.f2;
+    }
+
+    if (STAGE == 1) block_max2<TXT>(ax, ay, io.acc);
+}
+
+}  // namespace swe_dev

@@ -1,0 +1,126 @@
+// Host-side helpers shared by the single-simulation context and the
+// ensemble: parameter validation, kernel parameter packing, launch shapes,
+// the kernels that do not belong to a stage, and the launch of one stage
+// for a given strip width.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+
+#include "swe.h"
+#include "swe_device.h"
+
+namespace swe_host {
+
+using namespace swe_dev;
+
+inline size_t ncells(const swe_params* p) { return (size_t)p->nx * (size_t)p->ny; }
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+inline int check_params(const swe_params* p) {
+    if (!p) return SWE_EINVAL;
+    if (p->nx < 2 || p->ny < 2) return SWE_EINVAL;
+    if (!(p->dx > 0.0) || !(p->dy > 0.0) || !(p->g > 0.0) || !(p->cfl > 0.0))
+        return SWE_EINVAL;
+    if (!(p->h_eps >= 0.0) || !(p->dt_max > 0.0)) return SWE_EINVAL;
+    for (int k = 0; k < 4; ++k)
+        if (p->bc[k] != SWE_BC_WALL && p->bc[k] != SWE_BC_OUTFLOW) return SWE_EINVAL;
+    if (p->fric_law < SWE_FRIC_NONE || p->fric_law > SWE_FRIC_DARCY) return SWE_EINVAL;
+    if (p->infil_on && !(p->dtheta > 0.0)) return SWE_EINVAL;
+    if (!(p->rain >= 0.0) || !std::isfinite(p->rain)) return SWE_EINVAL;
+    if ((size_t)p->nx * (size_t)p->ny > ((size_t)1 << 36)) return SWE_EINVAL;
+    return SWE_OK;
+}
+
+inline KParams to_kparams(const swe_params& p) {
+    KParams k;
+    k.nx = p.nx; k.ny = p.ny;
+    k.dx = p.dx; k.dy = p.dy; k.g = p.g; k.cfl = p.cfl; k.dt_max = p.dt_max;
+    k.h_eps = p.h_eps;
+    k.bcw = p.bc[0]; k.bce = p.bc[1]; k.bcs = p.bc[2]; k.bcn = p.bc[3];
+    k.law = p.fric_law; k.coef = p.fric_coef; k.rain = p.rain;
+    k.infil = p.infil_on; k.ks = p.ks; k.psi = p.psi; k.dtheta = p.dtheta;
+    return k;
+}
+
+inline bool valid_tx(int tx) { return tx == 64 || tx == 128 || tx == 256; }
+
+inline int strips_of(int nx, int tx) {
+    int outw = tx - 2 * HALO;
+    return (nx + outw - 1) / outw;
+}
+
+// Rows per tile: enough tiles to fill 256 CUs several times over, at most
+// 64 rows (each tile re-reads two halo rows above and below).
+inline int auto_rows(int nx, int ny, int tx) {
+    long long strips = strips_of(nx, tx);
+    long long ty = (strips * (long long)ny) / 4096;
+    if (ty > 64) ty = 64;
+    if (ty < 8) ty = 8;
+    // keep the grid's y dimension within the launch limit
+    while ((ny + ty - 1) / ty > 65535) ty *= 2;
+    return (int)ty;
+}
+
+inline int hip_ok(hipError_t e) { return e == hipSuccess ? SWE_OK : SWE_EHIP; }
+
+// Host mirror of step_io(): the buffers of one step.
+inline TileIO host_step_io(const MemberArgs& m, int phase, int slot, double t_end) {
+    TileIO io;
+    std::memset(&io, 0, sizeof io);
+    io.h = m.h[phase];
+    io.qx = m.qx[phase];
+    io.qy = m.qy[phase];
+    io.ph = m.ph;
+    io.pqx = m.pqx;
+    io.pqy = m.pqy;
+    io.ho = m.h[phase ^ 1];
+    io.qxo = m.qx[phase ^ 1];
+    io.qyo = m.qy[phase ^ 1];
+    io.acc = m.sc->amax[slot];
+    io.clr = m.sc->amax[slot ^ 1];
+    io.slot = slot;
+    io.t_end = t_end;
+    return io;
+}
+
+}  // namespace swe_host
+
+// Kernels that are not stages.  Internal linkage: each translation unit
+// that includes this header gets its own copy.
+static __global__ void swe_init_scalars_kernel(swe_dev::DevScalars* sc, double t) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        for (int s = 0; s < 3; ++s) {
+            sc->amax[s][0] = 0ull;
+            sc->amax[s][1] = 0ull;
+        }
+        sc->t[0] = t;
+        sc->t[1] = t;
+        sc->steps[0] = 0;
+        sc->steps[1] = 0;
+        sc->last_dt = 0.0;
+        sc->status = 0u;
+    }
+}
+
+static __global__ void swe_set_time_kernel(swe_dev::DevScalars* sc, int slot, double t) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) sc->t[slot] = t;
+}
+
+static __global__ void swe_clear_amax_kernel(swe_dev::DevScalars* sc, int slot) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        sc->amax[slot][0] = 0ull;
+        sc->amax[slot][1] = 0ull;
+    }
+}
+
+static __global__ void swe_copy_kernel(const double* __restrict__ src, double* __restrict__ dst,
+                                       size_t n) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) dst[i] = src[i];
+}

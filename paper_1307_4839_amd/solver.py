@@ -78,6 +78,12 @@ class Solver:
     def step(self, nsteps: int, t_end: float = math.inf) -> None:
         capi.swe_step(self.ctx, nsteps, t_end)
 
+    def set_tiling(self, tx: int, ty: int = 0) -> None:
+        capi.swe_set_tiling(self.ctx, tx, ty)
+
+    def tiling(self):
+        return capi.swe_get_tiling(self.ctx)
+
     def profile_begin(self, max_steps: int) -> None:
         capi.swe_profile_begin(self.ctx, max_steps)
 
@@ -131,3 +137,81 @@ class Solver:
         _, _, steps = self.time()
         k = steps if n is None else n
         return self.dt_log[:k].cpu().numpy()
+
+
+class Ensemble:
+    """Independent simulations of uneven sizes stepped together on one GPU
+    (one persistent launch per stage for the whole ensemble)."""
+
+    def __init__(self, workloads, device: str = "cuda"):
+        if not torch.cuda.is_available():
+            raise RuntimeError("the HIP library needs a GPU")
+        self.device = torch.device(device)
+        self.count = len(workloads)
+        self.params = [params_from(wl) for wl in workloads]
+        self.members = []
+        bufs = []
+        for wl in workloads:
+            m = {"h": _dev(wl.h, self.device), "qx": _dev(wl.qx, self.device),
+                 "qy": _dev(wl.qy, self.device), "z": _dev(wl.z, self.device),
+                 "fric": None if wl.fric is None else _dev(wl.fric, self.device),
+                 "vinf": None}
+            if wl.infil_on:
+                v = np.zeros((wl.ny, wl.nx)) if wl.vinf is None else wl.vinf
+                m["vinf"] = _dev(v, self.device)
+            b = capi.swe_buffers()
+            b.h, b.qx, b.qy = m["h"].data_ptr(), m["qx"].data_ptr(), m["qy"].data_ptr()
+            b.z = m["z"].data_ptr()
+            b.fric = m["fric"].data_ptr() if m["fric"] is not None else None
+            b.vinf = m["vinf"].data_ptr() if m["vinf"] is not None else None
+            self.members.append(m)
+            bufs.append(b)
+        self._bufs = bufs
+        nbytes = capi.swe_batch_workspace_bytes(self.params)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        aligned = (self.workspace.data_ptr() + 255) & ~255
+        self.stream = torch.cuda.current_stream(self.device)
+        self.handle = capi.swe_batch_create(self.params, bufs, aligned, nbytes,
+                                            self.stream.cuda_stream)
+        self.cells = sum(int(p.nx) * int(p.ny) for p in self.params)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            capi.swe_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, nsteps: int, t_end: float = math.inf) -> None:
+        capi.swe_batch_step(self.handle, nsteps, t_end)
+
+    def set_tiling(self, tx: int, ty: int) -> None:
+        capi.swe_batch_set_tiling(self.handle, tx, ty)
+
+    def tiling(self):
+        return capi.swe_batch_get_tiling(self.handle)
+
+    def autotune(self, trial_steps: int = 8):
+        """(tx, ty, ms per step) of the fastest tile shape; state untouched."""
+        return capi.swe_batch_autotune(self.handle, trial_steps)
+
+    def set_rain(self, member: int, rain: float) -> None:
+        capi.swe_batch_set_rain(self.handle, member, rain)
+
+    def time(self, member: int):
+        return capi.swe_batch_get_time(self.handle, member)
+
+    def status(self):
+        return capi.swe_batch_get_status(self.handle, self.count)
+
+    def state(self, member: int):
+        torch.cuda.synchronize(self.device)
+        m = self.members[member]
+        out = {k: m[k].cpu().numpy() for k in ("h", "qx", "qy")}
+        if m["vinf"] is not None:
+            out["vinf"] = m["vinf"].cpu().numpy()
+        return out

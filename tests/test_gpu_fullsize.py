@@ -1,0 +1,115 @@
+"""Parity at full workload sizes, in the launch configuration bench.py times.
+
+The oracle cannot run thousands of steps on 67M cells, so after the GPU has
+advanced the full grid to a representative state, one more GPU step is
+checked on sampled cells:
+  * the oracle computes the global wave-speed bounds over the whole grid
+    and hence dt (which must equal the GPU's dt bit for bit);
+  * for each sampled cell, the oracle advances an 11 x 11 window of the
+    pre-step state by one step with that dt (a cell's update depends on
+    cells at most 4 away, and the window's artificial edges are 5 away) and
+    the centre must match the GPU's cell.
+Samples include domain corners and edges (where the window uses the true
+boundary conditions) and random interior cells.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1307_4839_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+R = 5
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def window_step(wl, st, j, i, dt):
+    ny, nx = wl.ny, wl.nx
+    j0, j1 = max(0, j - R), min(ny, j + R + 1)
+    i0, i1 = max(0, i - R), min(nx, i + R + 1)
+    bc = (wl.bc[0] if i0 == 0 else I.OUTFLOW, wl.bc[1] if i1 == nx else I.OUTFLOW,
+          wl.bc[2] if j0 == 0 else I.OUTFLOW, wl.bc[3] if j1 == ny else I.OUTFLOW)
+    w = I.Workload("win", i1 - i0, j1 - j0, wl.dx, wl.dy,
+                   z=np.ascontiguousarray(wl.z[j0:j1, i0:i1]),
+                   h=np.ascontiguousarray(st["h"][j0:j1, i0:i1]),
+                   qx=np.ascontiguousarray(st["qx"][j0:j1, i0:i1]),
+                   qy=np.ascontiguousarray(st["qy"][j0:j1, i0:i1]),
+                   bc=bc, g=wl.g, cfl=wl.cfl, dt_max=wl.dt_max, h_eps=wl.h_eps,
+                   fric_law=wl.fric_law, fric_coef=wl.fric_coef,
+                   fric=None if wl.fric is None else np.ascontiguousarray(wl.fric[j0:j1, i0:i1]),
+                   rain=wl.rain, infil_on=wl.infil_on, ks=wl.ks, psi=wl.psi,
+                   dtheta=wl.dtheta,
+                   vinf=None if "vinf" not in st else np.ascontiguousarray(st["vinf"][j0:j1, i0:i1]))
+    s = oracle.State(w)
+    s.step_fixed(dt)
+    out = {"h": s.h[j - j0, i - i0], "qx": s.qx[j - j0, i - i0], "qy": s.qy[j - j0, i - i0]}
+    if s.vinf is not None:
+        out["vinf"] = s.vinf[j - j0, i - i0]
+    return out
+
+
+def sample_cells(nx, ny, n, seed):
+    rng = np.random.default_rng(seed)
+    pts = [(0, 0), (0, nx - 1), (ny - 1, 0), (ny - 1, nx - 1), (1, nx // 2), (ny - 2, nx // 3),
+           (ny // 2, 0), (ny // 2, 1), (ny // 3, nx - 1), (ny // 3, nx - 2)]
+    # strip edges of the 252-column tiling and segment edges of 64 rows
+    pts += [(ny // 2, 251), (ny // 2, 252), (ny // 2, 253), (63, nx // 2), (64, nx // 2)]
+    pts += [(int(rng.integers(0, ny)), int(rng.integers(0, nx))) for _ in range(n)]
+    return pts
+
+
+def check_fullsize(wl, pre_steps, nsamples, seed):
+    import torch
+    from paper_1307_4839_amd.solver import Solver
+    say(f"[fullsize] {wl.name} {wl.nx}x{wl.ny}: {pre_steps} GPU steps")
+    g = Solver(wl, dt_log=pre_steps + 2)
+    g.step(pre_steps)
+    pre = g.state()
+    t_pre = g.time()[0]
+    g.step(1)
+    post = g.state()
+    t_post, dt_gpu, steps = g.time()
+    rc, flags = g.status()
+    assert rc == 0 and flags == 0
+    assert np.all(post["h"] >= 0)
+    say(f"[fullsize] oracle global bounds over {wl.nx * wl.ny} cells")
+    p = oracle.params_of(wl)
+    _, _, _, amax = oracle.rate(p, pre["h"], pre["qx"], pre["qy"], wl.z)
+    dt = oracle.time_step(p, amax, t_pre, np.inf)
+    assert dt == dt_gpu, (dt, dt_gpu)
+    assert t_post == t_pre + dt
+    say(f"[fullsize] dt = {dt}; checking {nsamples} sampled windows")
+    bad = 0
+    for (j, i) in sample_cells(wl.nx, wl.ny, nsamples, seed):
+        ref = window_step(wl, pre, j, i, dt)
+        for k, v in ref.items():
+            gv = post[k][j, i]
+            scale = max(np.abs(post[k]).max(), 1e-300)
+            if abs(gv - v) > 1e-14 * scale:
+                bad += 1
+                say(f"   mismatch {k} at ({j},{i}): gpu {gv!r} oracle {v!r}")
+    assert bad == 0
+    del g
+    torch.cuda.empty_cache()
+
+
+def test_fullsize_hillslope_8192():
+    wl = I.hillslope_8192()
+    check_fullsize(wl, 300, 200, seed=1)
+
+
+def test_fullsize_valley_2048():
+    wl = I.valley_2048()
+    check_fullsize(wl, 400, 200, seed=2)
+
+
+def test_fullsize_calibration_1024():
+    wl = I.calibration_1024()
+    check_fullsize(wl, 300, 150, seed=3)
