@@ -148,6 +148,61 @@ def ensemble_leg(members, steps, trial_steps):
             "status": rc}
 
 
+def adjoint_leg(steps, every):
+    """Adjoint (forward with checkpoints + reverse) vs the plain forward run on
+    the 1024 x 1024 calibration valley with a spatial Manning field."""
+    import numpy as np
+    import torch
+
+    from paper_1307_4839_amd import inputs as I
+    from paper_1307_4839_amd.solver import Calibration, Solver
+    wl = I.calibration_1024()
+    rows, ng = steps // every, len(wl.gauges)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    # plain forward (eq. cfl time steps, graph replay)
+    g = Solver(wl, device="cuda:0")
+    g.step(16)
+    torch.cuda.synchronize()
+    g.close()
+    g = Solver(wl, device="cuda:0")
+    torch.cuda.synchronize()
+    ev0.record(g.stream)
+    g.step(steps)
+    ev1.record(g.stream)
+    torch.cuda.synchronize()
+    ms_plain = ev0.elapsed_time(ev1)
+    g.close()
+    # observations from the perturbed friction field on the same time steps
+    cal = Calibration(wl, wl.gauges, every, np.zeros(rows * ng), steps)
+    cal.forward()
+    dts = cal.dts()
+    cal.fric.copy_(torch.as_tensor(wl.extra["fric_obs"], device="cuda:0"))
+    cal.forward()
+    obs = cal.series()
+    cal.close()
+    cal = Calibration(wl, wl.gauges, every, obs, steps)
+    cal.set_dts(dts)
+    cal.forward()  # warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loss = cal.forward()
+    t1 = time.perf_counter()
+    grad = cal.backward()
+    t2 = time.perf_counter()
+    gnorm = float(torch.linalg.vector_norm(grad).item())
+    cal.close()
+    ms_f, ms_b = (t1 - t0) * 1e3, (t2 - t1) * 1e3
+    print(f"[bench] adjoint: plain forward {ms_plain:.1f} ms, adjoint forward {ms_f:.1f} ms, "
+          f"reverse {ms_b:.1f} ms, loss {loss:.6e}", file=sys.stderr, flush=True)
+    return {"workload": f"calibration valley {wl.nx}x{wl.ny}, Manning field, {steps} steps, "
+                        f"{ng} gauges every {every} steps, checkpoints every "
+                        f"{int(round(math.sqrt(steps)))} steps",
+            "plain_forward_ms": ms_plain, "adjoint_forward_ms": ms_f,
+            "adjoint_reverse_ms": ms_b, "cost_ratio_vs_plain": (ms_f + ms_b) / ms_plain,
+            "loss": loss, "grad_norm": gnorm}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -162,6 +217,8 @@ def main(argv=None):
     ap.add_argument("--cpu-rows", type=int, default=2048)
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--adjoint-steps", type=int, default=2000)
     ap.add_argument("--ensemble-members", type=int, default=256)
     ap.add_argument("--ensemble-steps", type=int, default=500)
     ap.add_argument("--probe-copy-mib", type=int, default=0,
@@ -261,6 +318,11 @@ def main(argv=None):
               file=sys.stderr, flush=True)
         ens = ensemble_leg(members, args.ensemble_steps, 4)
 
+    adj = None
+    if not args.no_adjoint:
+        torch.cuda.empty_cache()
+        adj = adjoint_leg(args.adjoint_steps, 10)
+
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
@@ -290,7 +352,7 @@ def main(argv=None):
         "roofline": roofline,
         "cpu_baseline": cpu,
         "ensemble": ens,
-        "adjoint": None,
+        "adjoint": adj,
         "sim_time_s": t_sim,
         "status_flags": flags,
     }

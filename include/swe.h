@@ -214,6 +214,49 @@ int swe_batch_get_time(swe_batch* b, int32_t member, double* t, double* last_dt,
                        int64_t* steps);
 int swe_batch_get_status(swe_batch* b, uint32_t* flags, int32_t n);
 
+/* ---------------------------------------------------------------------------
+ * Adjoint (reverse-mode gradient) of a run with respect to the per-cell
+ * friction coefficient field (b->fric, required; Manning or Darcy-Weisbach;
+ * no infiltration).  The run is `nsteps` steps from the state in b->h/qx/qy
+ * (left untouched); the loss is
+ *     L = sum over k = every, 2 every, ... <= nsteps, over m < ngauges, of
+ *         (h after step k at cell gauges[m] - obs[(k/every - 1) ngauges + m])^2.
+ * The gradient is that of the discrete step (Sections 3.1-3.4) with the time
+ * step sequence frozen to the forward run's; kinks take the derivative of
+ * the selected branch (first argument on ties; 0 for minmod of opposite
+ * signs and for square/cube roots at 0).  States are recomputed from
+ * checkpoints every `ckpt_every` steps (sqrt(nsteps) is the usual choice).
+ * gauges (int32) and obs (FP64) are device arrays that must stay valid.
+ * ------------------------------------------------------------------------- */
+typedef struct swe_adj swe_adj;
+
+int swe_adj_workspace_bytes(const swe_params* p, int32_t nsteps, int32_t ckpt_every,
+                            int32_t ngauges, int32_t every, size_t* bytes);
+int swe_adj_create(const swe_params* p, const swe_buffers* b, int32_t nsteps,
+                   int32_t ckpt_every, const int32_t* gauges, int32_t ngauges,
+                   int32_t every, const double* obs, void* workspace,
+                   size_t workspace_bytes, void* stream, swe_adj** out);
+int swe_adj_destroy(swe_adj* a);
+
+/* Freeze the time step sequence to dts (device, nsteps values); NULL lets
+ * the next forward pass choose dt by eq. (cfl) and freezes what it chose. */
+int swe_adj_set_dts(swe_adj* a, const double* dts);
+/* Copy the frozen sequence to dts (device, nsteps values). */
+int swe_adj_get_dts(swe_adj* a, double* dts);
+
+/* Synchronizes.  Runs the forward pass, storing checkpoints and the gauge
+ * series, and returns the loss (host).  Status flags of the forward steps
+ * give the return code. */
+int swe_adj_forward(swe_adj* a, double* loss);
+
+/* Synchronizes.  dL/d(fric) into grad (device, nx ny values) for the last
+ * forward pass. */
+int swe_adj_backward(swe_adj* a, double* grad);
+
+/* Gauge depths of the last forward pass, (nsteps/every) x ngauges values
+ * (device, row-major), stream-ordered. */
+int swe_adj_get_series(swe_adj* a, double* out);
+
 /* Human-readable text for an error code. */
 const char* swe_strerror(int code);
 

@@ -93,6 +93,17 @@ EXPORTS = {
     "swe_batch_get_time": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_double),
                                      C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "swe_batch_get_status": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint32), C.c_int32]),
+    "swe_adj_workspace_bytes": (C.c_int, [C.POINTER(swe_params), C.c_int32, C.c_int32,
+                                          C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]),
+    "swe_adj_create": (C.c_int, [C.POINTER(swe_params), C.POINTER(swe_buffers), C.c_int32,
+                                 C.c_int32, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p,
+                                 C.c_void_p, C.c_size_t, C.c_void_p, C.POINTER(C.c_void_p)]),
+    "swe_adj_destroy": (C.c_int, [C.c_void_p]),
+    "swe_adj_set_dts": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "swe_adj_get_dts": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "swe_adj_forward": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
+    "swe_adj_backward": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "swe_adj_get_series": (C.c_int, [C.c_void_p, C.c_void_p]),
     "swe_strerror": (C.c_char_p, [C.c_int]),
 }
 
@@ -295,3 +306,48 @@ def swe_batch_get_status(b: int, count: int):
     flags = (C.c_uint32 * count)()
     rc = lib().swe_batch_get_status(C.c_void_p(b), flags, count)
     return rc, list(flags)
+
+
+# -- adjoint ---------------------------------------------------------------------
+
+def swe_adj_workspace_bytes(p, nsteps, ckpt_every, ngauges, every) -> int:
+    n = C.c_size_t(0)
+    check(lib().swe_adj_workspace_bytes(C.byref(p), nsteps, ckpt_every, ngauges, every,
+                                        C.byref(n)), "swe_adj_workspace_bytes")
+    return n.value
+
+
+def swe_adj_create(p, b, nsteps, ckpt_every, gauges_ptr, ngauges, every, obs_ptr,
+                   workspace, nbytes, stream) -> int:
+    out = C.c_void_p(0)
+    check(lib().swe_adj_create(C.byref(p), C.byref(b), nsteps, ckpt_every,
+                               C.c_void_p(gauges_ptr), ngauges, every, C.c_void_p(obs_ptr),
+                               C.c_void_p(workspace), nbytes, C.c_void_p(stream),
+                               C.byref(out)), "swe_adj_create")
+    return out.value
+
+
+def swe_adj_destroy(a: int) -> None:
+    check(lib().swe_adj_destroy(C.c_void_p(a)), "swe_adj_destroy")
+
+
+def swe_adj_set_dts(a: int, ptr) -> None:
+    check(lib().swe_adj_set_dts(C.c_void_p(a), C.c_void_p(ptr)), "swe_adj_set_dts")
+
+
+def swe_adj_get_dts(a: int, ptr: int) -> None:
+    check(lib().swe_adj_get_dts(C.c_void_p(a), C.c_void_p(ptr)), "swe_adj_get_dts")
+
+
+def swe_adj_forward(a: int) -> float:
+    loss = C.c_double(0.0)
+    check(lib().swe_adj_forward(C.c_void_p(a), C.byref(loss)), "swe_adj_forward")
+    return loss.value
+
+
+def swe_adj_backward(a: int, grad_ptr: int) -> None:
+    check(lib().swe_adj_backward(C.c_void_p(a), C.c_void_p(grad_ptr)), "swe_adj_backward")
+
+
+def swe_adj_get_series(a: int, ptr: int) -> None:
+    check(lib().swe_adj_get_series(C.c_void_p(a), C.c_void_p(ptr)), "swe_adj_get_series")

@@ -1,0 +1,1006 @@
+// Discrete adjoint of the time step with respect to a spatial friction
+// field (C ABI swe_adj_*, include/swe.h).
+//
+// The loss is the sum of squared gauge-depth misfits every `every` steps,
+// L = sum_k sum_m (h^{k}[g_m] - obs[k/every - 1][m])^2 for k a multiple of
+// every, and its gradient with respect to the per-cell friction coefficient
+// is computed by reverse-mode differentiation of the exact discrete step
+// (Sections 3.1-3.4 as implemented by the forward kernels) with the time
+// step sequence frozen to the forward run's.  States are recomputed from
+// sqrt(N)-spaced checkpoints segment by segment.
+//
+// Per step, reversed (U^n -> U* -> U** -> U^{n+1} = (U^n + U**)/2 + rain):
+//   lambda_{U^n} = lambda/2;  lambda_{U**} = lambda/2
+//   friction of stage 2 reversed cell by cell      -> lambda_{C2}, d/dU*, dL/dn
+//   C2 = U* + dt Phi(U*):  lambda_{U*} += lambda_{C2} + VJP_Phi(U*, dt lambda_{C2})
+//   friction of stage 1 reversed                   -> lambda_{C1}, d/dU^n, dL/dn
+//   C1 = U^n + dt Phi(U^n): lambda_{U^n} += lambda_{C1} + VJP_Phi(U^n, dt lambda_{C1})
+// The vector-Jacobian product of the rate Phi is computed per face: each
+// face recomputes its four-cell stencil (primitives, the two MUSCL
+// reconstructions, hydrostatic reconstruction, HLL, S and the centred term
+// of its left cell) and writes the adjoint contributions to those four
+// cells; a gather kernel sums the contributions of every cell in a fixed
+// order (no atomics), folding ghost cells back onto the cells they mirror.
+//
+// At points where the step is not differentiable the derivative follows
+// one fixed rule: max(a, b) and min(a, b) pass the derivative of the
+// selected argument (the first one on a tie), minmod passes that of the
+// selected difference (none when it returns 0 for opposite signs), and the
+// square root and cube root have derivative 0 at 0.
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "swe.h"
+#include "swe_device.h"
+#include "swe_host.h"
+
+using namespace swe_dev;
+using namespace swe_host;
+
+namespace {
+
+constexpr int T1 = 256;  // threads of the per-cell and per-face kernels
+
+// ---------------------------------------------------------------------------
+// Reverse of the building blocks
+// ---------------------------------------------------------------------------
+
+// minmod(a, b) as the three-case definition of Section 3.4: which argument
+// is returned (1 = a, 2 = b, 0 = the constant 0).
+__host__ __device__ __forceinline__ int minmod_sel(double a, double b) {
+    if (a >= 0.0 && b >= 0.0) return (b < a) ? 2 : 1;
+    if (a <= 0.0 && b <= 0.0) return (a < b) ? 2 : 1;
+    return 0;
+}
+
+__host__ __device__ __forceinline__ double sel_val(int s, double a, double b) {
+    return s == 1 ? a : (s == 2 ? b : 0.0);
+}
+
+struct PrimBar {
+    double h, un, ut, eta;
+};
+
+struct RecBar {
+    double h_m, h_p, z_m, z_p, un_m, un_p, ut_m, ut_p;
+};
+
+__host__ __device__ __forceinline__ void zero(PrimBar& p) { p.h = p.un = p.ut = p.eta = 0.0; }
+__host__ __device__ __forceinline__ void zero(RecBar& r) {
+    r.h_m = r.h_p = r.z_m = r.z_p = r.un_m = r.un_p = r.ut_m = r.ut_p = 0.0;
+}
+
+// d(minmod(x, y)) routed back to s_c - s_a = x and s_b - s_c = y
+__host__ __device__ __forceinline__ void route_minmod(int sel, double bar, double& abar, double& cbar,
+                                             double& bbar) {
+    if (sel == 1) {
+        cbar += bar;
+        abar -= bar;
+    } else if (sel == 2) {
+        bbar += bar;
+        cbar -= bar;
+    }
+}
+
+// Reverse of muscl(a, c, b): adds the adjoints of the three primitive
+// vectors given the adjoint R of the reconstruction.
+__host__ __device__ __forceinline__ void muscl_rev(const Prim& a, const Prim& c, const Prim& b,
+                                          double h_eps, const RecBar& R, PrimBar& ab,
+                                          PrimBar& cb, PrimBar& bb) {
+    // forward recomputation of the selections and the values used
+    double xh = c.h - a.h, yh = b.h - c.h;
+    int sh = minmod_sel(xh, yh);
+    double dh = sel_val(sh, xh, yh);
+    double h_m = c.h - 0.5 * dh, h_p = c.h + 0.5 * dh;
+    int se = minmod_sel(c.eta - a.eta, b.eta - c.eta);
+    double xu = c.un - a.un, yu = b.un - c.un;
+    int su = minmod_sel(xu, yu);
+    double dun = sel_val(su, xu, yu);
+    double xt = c.ut - a.ut, yt = b.ut - c.ut;
+    int st = minmod_sel(xt, yt);
+    double dut = sel_val(st, xt, yt);
+
+    double bh_m = R.h_m, bh_p = R.h_p;
+    // velocities
+    cb.un += R.un_m + R.un_p;
+    cb.ut += R.ut_m + R.ut_p;
+    if (c.h > h_eps) {
+        double wp = h_p / c.h, wm = h_m / c.h;
+        double bwp = -(R.un_m * (0.5 * dun) + R.ut_m * (0.5 * dut));
+        double bwm = R.un_p * (0.5 * dun) + R.ut_p * (0.5 * dut);
+        double bdun = 0.5 * (wm * R.un_p - wp * R.un_m);
+        double bdut = 0.5 * (wm * R.ut_p - wp * R.ut_m);
+        bh_p += bwp / c.h;
+        cb.h -= bwp * wp / c.h;
+        bh_m += bwm / c.h;
+        cb.h -= bwm * wm / c.h;
+        route_minmod(su, bdun, ab.un, cb.un, bb.un);
+        route_minmod(st, bdut, ab.ut, cb.ut, bb.ut);
+    }
+    // z = eta - h at each face
+    double beta_m = R.z_m, beta_p = R.z_p;
+    bh_m -= R.z_m;
+    bh_p -= R.z_p;
+    cb.eta += beta_m + beta_p;
+    route_minmod(se, 0.5 * (beta_p - beta_m), ab.eta, cb.eta, bb.eta);
+    cb.h += bh_m + bh_p;
+    route_minmod(sh, 0.5 * (bh_p - bh_m), ab.h, cb.h, bb.h);
+}
+
+// Reverse of prim_x: adjoints of (h, qx, qy) of the cell as loaded (x view:
+// un = u, ut = v).
+__host__ __device__ __forceinline__ void prim_rev(const RawCell& r, double h_eps, const PrimBar& pb,
+                                         double& bh, double& bqx, double& bqy) {
+    bh = pb.h + pb.eta;  // h enters as itself and through eta = h + z
+    bqx = 0.0;
+    bqy = 0.0;
+    if (r.h > h_eps) {
+        double u = r.qx / r.h, v = r.qy / r.h;
+        bqx = pb.un / r.h;
+        bqy = pb.ut / r.h;
+        bh -= (pb.un * u + pb.ut * v) / r.h;
+    }
+}
+
+// Reverse of face(): adjoints of the eight inputs given those of
+// (F0, F1, F2, s_L, s_R).
+struct FaceBar {
+    double hm, zm, unm, utm, hp, zp, unp, utp;
+};
+
+__host__ __device__ __forceinline__ FaceBar face_rev(double g, double hm, double zm, double unm,
+                                            double utm, double hp, double zp, double unp,
+                                            double utp, double bF0, double bF1, double bF2,
+                                            double bsL, double bsR) {
+    const double hg = 0.5 * g;
+    // forward
+    bool zs_b = zm < zp;
+    double zs = zs_b ? zp : zm;
+    double a1 = hm + zm - zs, a2 = hp + zp - zs;
+    bool l0 = a1 < 0.0, r0 = a2 < 0.0;
+    double hL = l0 ? 0.0 : a1, hR = r0 ? 0.0 : a2;
+    double cL = sqrt(g * hL), cR = sqrt(g * hR);
+    double l1 = unm - cL, l2 = unp - cR;
+    bool c1_b = l2 < l1;
+    double c1 = c1_b ? l2 : l1;
+    double u1 = unm + cL, u2 = unp + cR;
+    bool c2_b = u1 < u2;
+    double c2 = c2_b ? u2 : u1;
+    double qL = hL * unm, qR = hR * unp;
+    double FL[3] = {qL, qL * unm + hg * hL * hL, qL * utm};
+    double FR[3] = {qR, qR * unp + hg * hR * hR, qR * utp};
+    double UL[3] = {hL, qL, hL * utm};
+    double UR[3] = {hR, qR, hR * utp};
+    // reverse
+    FaceBar o;
+    o.hm = bsL * hg * 2.0 * hm;
+    o.hp = bsR * hg * 2.0 * hp;
+    o.zm = o.zp = 0.0;
+    o.unm = o.utm = o.unp = o.utp = 0.0;
+    double bhL = -bsL * hg * 2.0 * hL;
+    double bhR = -bsR * hg * 2.0 * hR;
+    double bF[3] = {bF0, bF1, bF2};
+    double bFL[3] = {0.0, 0.0, 0.0}, bFR[3] = {0.0, 0.0, 0.0};
+    double bUL[3] = {0.0, 0.0, 0.0}, bUR[3] = {0.0, 0.0, 0.0};
+    double bc1 = 0.0, bc2 = 0.0;
+    if (0.0 <= c1) {
+        for (int k = 0; k < 3; ++k) bFL[k] = bF[k];
+    } else if (c2 <= 0.0) {
+        for (int k = 0; k < 3; ++k) bFR[k] = bF[k];
+    } else {
+        double D = c2 - c1;
+        double D2 = D * D;
+        for (int k = 0; k < 3; ++k) {
+            double A = c2 * FL[k] - c1 * FR[k];
+            double dU = UR[k] - UL[k];
+            double W = c1 * c2 / D;
+            bFL[k] = bF[k] * c2 / D;
+            bFR[k] = -bF[k] * c1 / D;
+            bUR[k] = bF[k] * W;
+            bUL[k] = -bF[k] * W;
+            bc2 += bF[k] * (FL[k] / D - A / D2 + (c1 / D - c1 * c2 / D2) * dU);
+            bc1 += bF[k] * (-FR[k] / D + A / D2 + (c2 / D + c1 * c2 / D2) * dU);
+        }
+    }
+    double bqL = 0.0, bqR = 0.0;
+    // U_L = (hL, qL, hL utm), U_R likewise
+    bhL += bUL[0];
+    bqL += bUL[1];
+    bhL += bUL[2] * utm;
+    o.utm += bUL[2] * hL;
+    bhR += bUR[0];
+    bqR += bUR[1];
+    bhR += bUR[2] * utp;
+    o.utp += bUR[2] * hR;
+    // F(U_L) = (qL, qL unm + hg hL^2, qL utm)
+    bqL += bFL[0] + bFL[1] * unm + bFL[2] * utm;
+    o.unm += bFL[1] * qL;
+    bhL += bFL[1] * hg * 2.0 * hL;
+    o.utm += bFL[2] * qL;
+    bqR += bFR[0] + bFR[1] * unp + bFR[2] * utp;
+    o.unp += bFR[1] * qR;
+    bhR += bFR[1] * hg * 2.0 * hR;
+    o.utp += bFR[2] * qR;
+    // qL = hL unm, qR = hR unp
+    bhL += bqL * unm;
+    o.unm += bqL * hL;
+    bhR += bqR * unp;
+    o.unp += bqR * hR;
+    // c1 = min(unm - cL, unp - cR), c2 = max(unm + cL, unp + cR)
+    double bcL = 0.0, bcR = 0.0;
+    if (c1_b) { o.unp += bc1; bcR -= bc1; } else { o.unm += bc1; bcL -= bc1; }
+    if (c2_b) { o.unp += bc2; bcR += bc2; } else { o.unm += bc2; bcL += bc2; }
+    if (cL > 0.0) bhL += bcL * g / (2.0 * cL);
+    if (cR > 0.0) bhR += bcR * g / (2.0 * cR);
+    // hydrostatic reconstruction
+    double bzs = 0.0;
+    if (!l0) { o.hm += bhL; o.zm += bhL; bzs -= bhL; }
+    if (!r0) { o.hp += bhR; o.zp += bhR; bzs -= bhR; }
+    if (zs_b) o.zp += bzs; else o.zm += bzs;
+    return o;
+}
+
+// Reverse of the centred source of a cell (Section 3.1).
+__host__ __device__ __forceinline__ void centred_rev(double g, const Rec& r, double bfc, RecBar& R) {
+    double a = (-g) * 0.5 * (r.z_p - r.z_m);
+    R.h_m += bfc * a;
+    R.h_p += bfc * a;
+    double b = (-g) * (0.5 * (r.h_m + r.h_p));
+    R.z_p += bfc * b;
+    R.z_m -= bfc * b;
+}
+
+// Reverse of friction(): (h0, q0) stage input, (h1, q1) convective output.
+// Given the adjoints of the outputs (bh, bq), returns those of the
+// convective output (bh1, bq1), of the stage input through the friction
+// factor (bh0, bq0) and of the coefficient.
+__host__ __device__ __forceinline__ void friction_rev(const KParams& p, double coef, double h0,
+                                             double qx0, double qy0, double h1, double qx1,
+                                             double qy1, double dt, double bh, double bqx,
+                                             double bqy, double& bh1, double& bqx1,
+                                             double& bqy1, double& bh0, double& bqx0,
+                                             double& bqy0, double& bcoef) {
+    bh1 = bh;
+    bh0 = bqx0 = bqy0 = bcoef = 0.0;
+    if (h1 <= p.h_eps) {
+        bqx1 = bqy1 = 0.0;
+        return;
+    }
+    if (p.law == SWE_FRIC_NONE || !(h0 > p.h_eps)) {
+        bqx1 = bqx;
+        bqy1 = bqy;
+        return;
+    }
+    double qn = sqrt(qx0 * qx0 + qy0 * qy0);
+    double T, dT_dqn, dT_dcoef, dT_dh1;
+    if (p.law == SWE_FRIC_DARCY) {
+        double base = dt * qn / (h0 * h1);
+        T = base * (coef / 8.0);
+        dT_dcoef = base / 8.0;
+        dT_dqn = dt * (coef / 8.0) / (h0 * h1);
+        dT_dh1 = -T / h1;
+    } else {
+        double h43 = h1 * cbrt(h1);
+        double base = dt * p.g * qn / (h0 * h43);
+        T = base * coef * coef;
+        dT_dcoef = 2.0 * base * coef;
+        dT_dqn = dt * p.g * coef * coef / (h0 * h43);
+        dT_dh1 = -T * (4.0 / 3.0) / h1;
+    }
+    double den = 1.0 + T;
+    double oqx = qx1 / den, oqy = qy1 / den;
+    bqx1 = bqx / den;
+    bqy1 = bqy / den;
+    double bden = -(bqx * oqx + bqy * oqy) / den;
+    bcoef = bden * dT_dcoef;
+    bh0 = -bden * T / h0;
+    bh1 += bden * dT_dh1;
+    double bqn = bden * dT_dqn;
+    if (qn > 0.0) {
+        bqx0 = bqn * qx0 / qn;
+        bqy0 = bqn * qy0 / qn;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Kernels
+// ---------------------------------------------------------------------------
+
+struct AdjArgs {
+    KParams p;
+    const double* z;
+    const double* fric;
+    // contribution buffers: [slot 0..3][component 0..2] planes
+    double* xc;   // 12 planes of ny x (nx+1)
+    double* yc;   // 12 planes of (ny+1) x nx
+};
+
+__host__ __device__ __forceinline__ RawCell load_raw(const double* h, const double* qx,
+                                            const double* qy, const double* z, int nx,
+                                            int rs, int cs, double sx, double sy) {
+    size_t idx = (size_t)rs * nx + cs;
+    RawCell r;
+    r.h = h[idx];
+    r.qx = sx * qx[idx];
+    r.qy = sy * qy[idx];
+    r.z = z[idx];
+    return r;
+}
+
+// Adjoint contributions of one face.  DIR 0: x-face f of row `line`
+// (between columns f-1 and f, f = 0..nx); DIR 1: y-face f of column `line`
+// (between rows f-1 and f, f = 0..ny).  out[3k + c] is the contribution to
+// component c (h, qx, qy) of the cell at position f-2+k along the sweep
+// (ghost positions carry the contribution to the cell they mirror, sign
+// included): the face itself and the centred source of its lower/left cell.
+template <int DIR>
+__host__ __device__ __forceinline__ void face_contrib(const KParams& p, const double* z,
+                                                      const double* h, const double* qx,
+                                                      const double* qy, const double* mu_h,
+                                                      const double* mu_qx, const double* mu_qy,
+                                                      int f, int line, double out[12]) {
+    const int nx = p.nx, ny = p.ny;
+    const int n_along = DIR == 0 ? nx : ny;
+    const double d = DIR == 0 ? p.dx : p.dy;
+    RawCell r[4];
+    Prim pr[4];
+    double sgn[4];
+    for (int k = 0; k < 4; ++k) {
+        int pos = f - 2 + k;
+        if (DIR == 0) {
+            double sx;
+            int cs = map_index(pos, nx, p.bcw, p.bce, sx);
+            r[k] = load_raw(h, qx, qy, z, nx, line, cs, sx, 1.0);
+            sgn[k] = sx;
+            pr[k] = prim_x(r[k], p.h_eps);
+        } else {
+            double sy;
+            int rs = map_index(pos, ny, p.bcs, p.bcn, sy);
+            r[k] = load_raw(h, qx, qy, z, nx, rs, line, 1.0, sy);
+            sgn[k] = sy;
+            pr[k] = to_y(prim_x(r[k], p.h_eps));
+        }
+    }
+    Rec RL = muscl(pr[0], pr[1], pr[2], p.h_eps);  // cell f-1
+    Rec RR = muscl(pr[1], pr[2], pr[3], p.h_eps);  // cell f
+
+    // adjoint seeds: X_i enters Phi_i as -X_i/d
+    double bL[3] = {0.0, 0.0, 0.0}, bR[3] = {0.0, 0.0, 0.0};  // (mass, normal, tangential)
+    const bool L_real = f - 1 >= 0 && f - 1 < n_along;
+    const bool R_real = f < n_along;
+    if (L_real) {
+        size_t idx = DIR == 0 ? (size_t)line * nx + (f - 1) : (size_t)(f - 1) * nx + line;
+        bL[0] = -mu_h[idx] / d;
+        bL[1] = -(DIR == 0 ? mu_qx[idx] : mu_qy[idx]) / d;
+        bL[2] = -(DIR == 0 ? mu_qy[idx] : mu_qx[idx]) / d;
+    }
+    if (R_real) {
+        size_t idx = DIR == 0 ? (size_t)line * nx + f : (size_t)f * nx + line;
+        bR[0] = -mu_h[idx] / d;
+        bR[1] = -(DIR == 0 ? mu_qx[idx] : mu_qy[idx]) / d;
+        bR[2] = -(DIR == 0 ? mu_qy[idx] : mu_qx[idx]) / d;
+    }
+    FaceBar fb = face_rev(p.g, RL.h_p, RL.z_p, RL.un_p, RL.ut_p, RR.h_m, RR.z_m, RR.un_m,
+                          RR.ut_m, bL[0] - bR[0], bL[1] - bR[1], bL[2] - bR[2], bL[1], -bR[1]);
+    RecBar RLb, RRb;
+    zero(RLb);
+    zero(RRb);
+    RLb.h_p = fb.hm;
+    RLb.z_p = fb.zm;
+    RLb.un_p = fb.unm;
+    RLb.ut_p = fb.utm;
+    RRb.h_m = fb.hp;
+    RRb.z_m = fb.zp;
+    RRb.un_m = fb.unp;
+    RRb.ut_m = fb.utp;
+    // centred source of the left cell: X1 = ... - fc
+    if (L_real) centred_rev(p.g, RL, -bL[1], RLb);
+    PrimBar pb[4];
+    for (int k = 0; k < 4; ++k) zero(pb[k]);
+    muscl_rev(pr[0], pr[1], pr[2], p.h_eps, RLb, pb[0], pb[1], pb[2]);
+    muscl_rev(pr[1], pr[2], pr[3], p.h_eps, RRb, pb[1], pb[2], pb[3]);
+    for (int k = 0; k < 4; ++k) {
+        PrimBar xb = pb[k];
+        if (DIR == 1) {  // back to the x view of the primitives
+            double t = xb.un;
+            xb.un = xb.ut;
+            xb.ut = t;
+        }
+        double bh, bqx, bqy;
+        prim_rev(r[k], p.h_eps, xb, bh, bqx, bqy);
+        // the ghost's discharge is sign * source discharge
+        if (DIR == 0) bqx *= sgn[k]; else bqy *= sgn[k];
+        out[3 * k + 0] = bh;
+        out[3 * k + 1] = bqx;
+        out[3 * k + 2] = bqy;
+    }
+}
+
+template <int DIR>
+__global__ __launch_bounds__(T1) void adj_face_kernel(AdjArgs a, const double* __restrict__ h,
+                                                      const double* __restrict__ qx,
+                                                      const double* __restrict__ qy,
+                                                      const double* __restrict__ mu_h,
+                                                      const double* __restrict__ mu_qx,
+                                                      const double* __restrict__ mu_qy) {
+    const KParams& p = a.p;
+    const int nx = p.nx, ny = p.ny;
+    const int n_along = DIR == 0 ? nx : ny;
+    const int n_across = DIR == 0 ? ny : nx;
+    const int f = blockIdx.x * T1 + threadIdx.x;
+    const int line = blockIdx.y;
+    if (f > n_along || line >= n_across) return;
+    double out[12];
+    face_contrib<DIR>(p, a.z, h, qx, qy, mu_h, mu_qx, mu_qy, f, line, out);
+    const size_t plane = DIR == 0 ? (size_t)ny * (nx + 1) : (size_t)(ny + 1) * nx;
+    const size_t fidx = DIR == 0 ? (size_t)line * (nx + 1) + f : (size_t)f * nx + line;
+    double* buf = DIR == 0 ? a.xc : a.yc;
+    for (int k = 0; k < 12; ++k) buf[(size_t)k * plane + fidx] = out[k];
+}
+
+// lambda(cell) += sum of the face contributions addressed to it, in a fixed
+// order: interior positions, then the ghost positions that mirror it.
+__host__ __device__ __forceinline__ void add_contrib(const double* buf, size_t plane, size_t fidx,
+                                            int slot, double& h, double& qx, double& qy) {
+    h += buf[(size_t)(3 * slot + 0) * plane + fidx];
+    qx += buf[(size_t)(3 * slot + 1) * plane + fidx];
+    qy += buf[(size_t)(3 * slot + 2) * plane + fidx];
+}
+
+__host__ __device__ __forceinline__ void gather_cell(const KParams& p, const double* xc,
+                                                     const double* yc, int i, int j,
+                                                     double& sh, double& sqx, double& sqy) {
+    const int nx = p.nx, ny = p.ny;
+    sh = sqx = sqy = 0.0;
+    // x-faces of row j: faces f with i in [f-2, f+1], slot i-f+2
+    {
+        const size_t plane = (size_t)ny * (nx + 1);
+        const size_t row = (size_t)j * (nx + 1);
+        for (int f = (i - 1 > 0 ? i - 1 : 0); f <= (i + 2 < nx ? i + 2 : nx); ++f)
+            add_contrib(xc, plane, row + f, i - f + 2, sh, sqx, sqy);
+        // ghost columns -1, -2 (west) and nx, nx+1 (east)
+        if (i == 0) {
+            add_contrib(xc, plane, row + 0, 1, sh, sqx, sqy);  // column -1
+            add_contrib(xc, plane, row + 1, 0, sh, sqx, sqy);
+            if (p.bcw == SWE_BC_OUTFLOW) add_contrib(xc, plane, row + 0, 0, sh, sqx, sqy);
+        }
+        if (i == 1 && p.bcw == SWE_BC_WALL) add_contrib(xc, plane, row + 0, 0, sh, sqx, sqy);
+        if (i == nx - 1) {
+            add_contrib(xc, plane, row + nx - 1, 3, sh, sqx, sqy);  // column nx
+            add_contrib(xc, plane, row + nx, 2, sh, sqx, sqy);
+            if (p.bce == SWE_BC_OUTFLOW) add_contrib(xc, plane, row + nx, 3, sh, sqx, sqy);
+        }
+        if (i == nx - 2 && p.bce == SWE_BC_WALL)
+            add_contrib(xc, plane, row + nx, 3, sh, sqx, sqy);
+    }
+    // y-faces of column i: faces f with j in [f-2, f+1]
+    {
+        const size_t plane = (size_t)(ny + 1) * nx;
+        for (int f = (j - 1 > 0 ? j - 1 : 0); f <= (j + 2 < ny ? j + 2 : ny); ++f)
+            add_contrib(yc, plane, (size_t)f * nx + i, j - f + 2, sh, sqx, sqy);
+        if (j == 0) {
+            add_contrib(yc, plane, (size_t)0 * nx + i, 1, sh, sqx, sqy);  // row -1
+            add_contrib(yc, plane, (size_t)1 * nx + i, 0, sh, sqx, sqy);
+            if (p.bcs == SWE_BC_OUTFLOW) add_contrib(yc, plane, (size_t)0 * nx + i, 0, sh, sqx, sqy);
+        }
+        if (j == 1 && p.bcs == SWE_BC_WALL) add_contrib(yc, plane, (size_t)0 * nx + i, 0, sh, sqx, sqy);
+        if (j == ny - 1) {
+            add_contrib(yc, plane, (size_t)(ny - 1) * nx + i, 3, sh, sqx, sqy);  // row ny
+            add_contrib(yc, plane, (size_t)ny * nx + i, 2, sh, sqx, sqy);
+            if (p.bcn == SWE_BC_OUTFLOW) add_contrib(yc, plane, (size_t)ny * nx + i, 3, sh, sqx, sqy);
+        }
+        if (j == ny - 2 && p.bcn == SWE_BC_WALL)
+            add_contrib(yc, plane, (size_t)ny * nx + i, 3, sh, sqx, sqy);
+    }
+}
+
+// lambda(cell) += sum of the face contributions addressed to it
+__global__ __launch_bounds__(T1) void adj_gather_kernel(AdjArgs a, double* __restrict__ lh,
+                                                        double* __restrict__ lqx,
+                                                        double* __restrict__ lqy) {
+    const int i = blockIdx.x * T1 + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= a.p.nx || j >= a.p.ny) return;
+    double sh, sqx, sqy;
+    gather_cell(a.p, a.xc, a.yc, i, j, sh, sqx, sqy);
+    size_t idx = (size_t)j * a.p.nx + i;
+    lh[idx] += sh;
+    lqx[idx] += sqx;
+    lqy[idx] += sqy;
+}
+
+// U_out = friction(U_in + dt Phi(U_in)) cell by cell (a stage output).
+__global__ __launch_bounds__(T1) void stage_out_kernel(KParams p, const double* __restrict__ fric,
+                                                       const double* __restrict__ h,
+                                                       const double* __restrict__ qx,
+                                                       const double* __restrict__ qy,
+                                                       const double* __restrict__ ph,
+                                                       const double* __restrict__ pqx,
+                                                       const double* __restrict__ pqy, double dt,
+                                                       double* __restrict__ ho,
+                                                       double* __restrict__ qxo,
+                                                       double* __restrict__ qyo, size_t n) {
+    size_t i = (size_t)blockIdx.x * T1 + threadIdx.x;
+    if (i >= n) return;
+    double h1 = h[i] + dt * ph[i];
+    double qx1 = qx[i] + dt * pqx[i];
+    double qy1 = qy[i] + dt * pqy[i];
+    friction(p, fric ? fric[i] : p.coef, h[i], qx[i], qy[i], h1, qx1, qy1, dt);
+    ho[i] = h1;
+    qxo[i] = qx1;
+    qyo[i] = qy1;
+}
+
+// Reverse of a stage's friction and of C = U_in + dt Phi(U_in) up to the
+// rate: given the adjoint of the stage output (bo), writes
+//   lam_in  = (=|+=) bC + (friction-factor part)   [accumulate if acc]
+//   mu      = dt * bC                              (seed for VJP_Phi)
+//   grad   += d/dcoef
+// STAGE 2 also forms the Heun split: its output adjoint is half of `lam`,
+// and the other half seeds lam_n.
+__global__ __launch_bounds__(T1) void adj_stage_kernel(
+    KParams p, const double* __restrict__ fric, const double* __restrict__ h,
+    const double* __restrict__ qx, const double* __restrict__ qy,
+    const double* __restrict__ ph, const double* __restrict__ pqx,
+    const double* __restrict__ pqy, double dt, const double* __restrict__ bo_h,
+    const double* __restrict__ bo_qx, const double* __restrict__ bo_qy, double bo_scale,
+    double* __restrict__ lin_h, double* __restrict__ lin_qx, double* __restrict__ lin_qy,
+    int accumulate, double* __restrict__ mu_h, double* __restrict__ mu_qx,
+    double* __restrict__ mu_qy, double* __restrict__ grad, size_t n) {
+    size_t i = (size_t)blockIdx.x * T1 + threadIdx.x;
+    if (i >= n) return;
+    double h0 = h[i], qx0 = qx[i], qy0 = qy[i];
+    double h1 = h0 + dt * ph[i];
+    double qx1 = qx0 + dt * pqx[i];
+    double qy1 = qy0 + dt * pqy[i];
+    double coef = fric ? fric[i] : p.coef;
+    double bh1, bqx1, bqy1, bh0, bqx0, bqy0, bc;
+    friction_rev(p, coef, h0, qx0, qy0, h1, qx1, qy1, dt, bo_scale * bo_h[i],
+                 bo_scale * bo_qx[i], bo_scale * bo_qy[i], bh1, bqx1, bqy1, bh0, bqx0, bqy0,
+                 bc);
+    double lh = bh1 + bh0, lqx = bqx1 + bqx0, lqy = bqy1 + bqy0;
+    if (accumulate) {
+        lin_h[i] += lh;
+        lin_qx[i] += lqx;
+        lin_qy[i] += lqy;
+    } else {
+        lin_h[i] = lh;
+        lin_qx[i] = lqx;
+        lin_qy[i] = lqy;
+    }
+    mu_h[i] = dt * bh1;
+    mu_qx[i] = dt * bqx1;
+    mu_qy[i] = dt * bqy1;
+    if (grad) grad[i] += bc;
+}
+
+// Heun split of stage 2: lam_n = lam/2 (the other half enters the stage).
+__global__ __launch_bounds__(T1) void half_kernel(const double* __restrict__ a,
+                                                  const double* __restrict__ b,
+                                                  const double* __restrict__ c,
+                                                  double* __restrict__ A, double* __restrict__ B,
+                                                  double* __restrict__ Cc, size_t n) {
+    size_t i = (size_t)blockIdx.x * T1 + threadIdx.x;
+    if (i >= n) return;
+    A[i] = 0.5 * a[i];
+    B[i] = 0.5 * b[i];
+    Cc[i] = 0.5 * c[i];
+}
+
+// h at the gauges -> row of the gauge series
+__global__ void gauge_kernel(const double* __restrict__ h, const int* __restrict__ gauges,
+                             int ng, double* __restrict__ out) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < ng) out[k] = h[gauges[k]];
+}
+
+// lambda_h[g_m] += 2 (h[g_m] - obs_m), one thread in gauge order (gauges may
+// repeat)
+__global__ void inject_kernel(const double* __restrict__ series, const double* __restrict__ obs,
+                              const int* __restrict__ gauges, int ng, double* __restrict__ lh) {
+    if (threadIdx.x == 0 && blockIdx.x == 0)
+        for (int k = 0; k < ng; ++k) lh[gauges[k]] += 2.0 * (series[k] - obs[k]);
+}
+
+// loss = sum (series - obs)^2 in index order (single thread: a few
+// thousand terms)
+__global__ void loss_kernel(const double* __restrict__ series, const double* __restrict__ obs,
+                            size_t n, double* __restrict__ out) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double s = 0.0;
+        for (size_t k = 0; k < n; ++k) {
+            double e = series[k] - obs[k];
+            s += e * e;
+        }
+        *out = s;
+    }
+}
+
+// Forward stages of one tile grid (the same tile routine as the
+// single-simulation context).
+template <int STAGE>
+__global__ __launch_bounds__(256) void fwd_stage_kernel(MemberArgs m, TileIO io, int ty) {
+    const int y0 = blockIdx.y * ty;
+    const int y1 = min(y0 + ty, m.p.ny);
+    stage_tile<STAGE, 256>(m, io, blockIdx.x, y0, y1, blockIdx.x == 0 && blockIdx.y == 0);
+}
+
+// Per-step reset of the time bookkeeping (the status flags stay sticky).
+__global__ void reset_step_kernel(DevScalars* sc) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        sc->amax[0][0] = sc->amax[0][1] = 0ull;
+        sc->amax[1][0] = sc->amax[1][1] = 0ull;
+        sc->t[0] = sc->t[1] = 0.0;
+        sc->steps[0] = sc->steps[1] = 0;
+    }
+}
+
+__global__ void fill_kernel(double* __restrict__ a, double v, size_t n) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) a[i] = v;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Host driver
+// ---------------------------------------------------------------------------
+
+struct swe_adj {
+    swe_params prm;
+    MemberArgs m;          // forward view (state buffers re-pointed per launch)
+    AdjArgs aa;
+    hipStream_t stream;
+    int nsteps, every, ngauges, ckpt;
+    int nrows;             // loss evaluations = nsteps / every
+    const int* gauges;     // device
+    const double* obs;     // device, nrows x ngauges
+    const double* h0;      // initial state (caller's buffers)
+    const double* qx0;
+    const double* qy0;
+    double* dts;           // device, nsteps
+    bool dts_frozen;
+    double* series;        // device, nrows x ngauges
+    double* ckpts;         // device, nckpt x 3N
+    double* seg;           // device, (ckpt + 1) x 3N
+    double* ust;           // U* (3N)
+    double* phi;           // Phi (3N)
+    double* lamA;          // lambda of U^n (3N)
+    double* lamB;          // lambda of U* (3N)
+    double* lam;           // lambda of U^{n+1} (3N)
+    double* mu;            // VJP seed (3N)
+    double* loss_dev;
+    size_t n;
+};
+
+namespace {
+
+size_t adj_bytes(const swe_params* p, int nsteps, int ckpt, int ngauges, int every) {
+    size_t n = ncells(p), an = align256(n * sizeof(double));
+    size_t nck = (nsteps + ckpt - 1) / ckpt;
+    size_t rows = every > 0 ? nsteps / every : 0;
+    size_t faces = align256(12 * (size_t)p->ny * (p->nx + 1) * sizeof(double)) +
+                   align256(12 * (size_t)(p->ny + 1) * p->nx * sizeof(double));
+    return 256 + 256 + align256(nsteps * sizeof(double)) +
+           align256(rows * (size_t)ngauges * sizeof(double)) + 3 * an * nck +
+           3 * an * (ckpt + 1) + 3 * an * 6 + faces;
+}
+
+inline double* plane(double* base, size_t n, int k) { return base + (size_t)k * n; }
+
+int blocks(size_t n) { return (int)((n + T1 - 1) / T1); }
+
+// One forward step U_in -> U_out with a frozen dt (dt_fixed > 0) or the CFL
+// dt (dt_fixed = 0, logged to dts[k]).
+void fwd_step(swe_adj* A, const double* h, const double* qx, const double* qy, double* ho,
+              double* qxo, double* qyo, double dt_fixed, int k) {
+    MemberArgs m = A->m;
+    m.h[0] = (double*)h; m.qx[0] = (double*)qx; m.qy[0] = (double*)qy;
+    m.h[1] = ho; m.qx[1] = qxo; m.qy[1] = qyo;
+    m.dtlog = dt_fixed > 0.0 ? nullptr : A->dts + k;
+    m.dtlog_cap = dt_fixed > 0.0 ? 0 : 1;
+    // the logged entry is indexed by the step count of the scalar block,
+    // which is reset to 0 before each step so that dts[k] receives it
+    hipLaunchKernelGGL(reset_step_kernel, dim3(1), dim3(64), 0, A->stream, m.sc);
+    TileIO io = host_step_io(m, 0, 0, INFINITY);
+    io.dt_fixed = dt_fixed;
+    int ty = auto_rows(A->prm.nx, A->prm.ny, 256);
+    dim3 grid(strips_of(A->prm.nx, 256), (A->prm.ny + ty - 1) / ty);
+    hipLaunchKernelGGL(fwd_stage_kernel<1>, grid, dim3(256), 0, A->stream, m, io, ty);
+    hipLaunchKernelGGL(fwd_stage_kernel<2>, grid, dim3(256), 0, A->stream, m, io, ty);
+}
+
+// Phi(U) into A->phi (stage 1 kernel with a scratch accumulator).
+void rate_into(swe_adj* A, const double* h, const double* qx, const double* qy) {
+    MemberArgs m = A->m;
+    TileIO io;
+    std::memset(&io, 0, sizeof io);
+    io.h = h; io.qx = qx; io.qy = qy;
+    io.ph = plane(A->phi, A->n, 0);
+    io.pqx = plane(A->phi, A->n, 1);
+    io.pqy = plane(A->phi, A->n, 2);
+    io.acc = m.sc->amax[2];
+    io.clr = nullptr;
+    io.slot = 2;
+    int ty = auto_rows(A->prm.nx, A->prm.ny, 256);
+    dim3 grid(strips_of(A->prm.nx, 256), (A->prm.ny + ty - 1) / ty);
+    hipLaunchKernelGGL(swe_clear_amax_kernel, dim3(1), dim3(64), 0, A->stream, m.sc, 2);
+    hipLaunchKernelGGL(fwd_stage_kernel<1>, grid, dim3(256), 0, A->stream, m, io, ty);
+}
+
+// lam(h,qx,qy) += VJP_Phi(U, mu)
+void vjp_rate(swe_adj* A, const double* h, const double* qx, const double* qy, double* lam) {
+    const size_t n = A->n;
+    const int nx = A->prm.nx, ny = A->prm.ny;
+    double* mu = A->mu;
+    hipLaunchKernelGGL(adj_face_kernel<0>, dim3((nx + 1 + T1 - 1) / T1, ny), dim3(T1), 0,
+                       A->stream, A->aa, h, qx, qy, (const double*)plane(mu, n, 0),
+                       (const double*)plane(mu, n, 1), (const double*)plane(mu, n, 2));
+    hipLaunchKernelGGL(adj_face_kernel<1>, dim3((ny + 1 + T1 - 1) / T1, nx), dim3(T1), 0,
+                       A->stream, A->aa, h, qx, qy, (const double*)plane(mu, n, 0),
+                       (const double*)plane(mu, n, 1), (const double*)plane(mu, n, 2));
+    hipLaunchKernelGGL(adj_gather_kernel, dim3((nx + T1 - 1) / T1, ny), dim3(T1), 0, A->stream,
+                       A->aa, plane(lam, n, 0), plane(lam, n, 1), plane(lam, n, 2));
+}
+
+// lamA <- adjoint of U^k given lam = adjoint of U^{k+1}; grad += dL/dn.
+void adj_step(swe_adj* A, const double* Uk, double dt, double* grad) {
+    const size_t n = A->n;
+    const double* h = Uk;
+    const double* qx = Uk + n;
+    const double* qy = Uk + 2 * n;
+    double* us = A->ust;
+    // recompute Phi(U^k) and U*
+    rate_into(A, h, qx, qy);
+    hipLaunchKernelGGL(stage_out_kernel, dim3(blocks(n)), dim3(T1), 0, A->stream, A->m.p,
+                       A->m.fric, h, qx, qy, (const double*)plane(A->phi, n, 0),
+                       (const double*)plane(A->phi, n, 1), (const double*)plane(A->phi, n, 2),
+                       dt, plane(us, n, 0), plane(us, n, 1), plane(us, n, 2), n);
+    // Heun: lam_n = lam/2
+    hipLaunchKernelGGL(half_kernel, dim3(blocks(n)), dim3(T1), 0, A->stream,
+                       (const double*)plane(A->lam, n, 0), (const double*)plane(A->lam, n, 1),
+                       (const double*)plane(A->lam, n, 2), plane(A->lamA, n, 0),
+                       plane(A->lamA, n, 1), plane(A->lamA, n, 2), n);
+    // stage 2 on U*: Phi(U*), then its friction reversed with output
+    // adjoint lam/2
+    rate_into(A, plane(us, n, 0), plane(us, n, 1), plane(us, n, 2));
+    hipLaunchKernelGGL(adj_stage_kernel, dim3(blocks(n)), dim3(T1), 0, A->stream, A->m.p,
+                       A->m.fric, (const double*)plane(us, n, 0), (const double*)plane(us, n, 1),
+                       (const double*)plane(us, n, 2), (const double*)plane(A->phi, n, 0),
+                       (const double*)plane(A->phi, n, 1), (const double*)plane(A->phi, n, 2), dt,
+                       (const double*)plane(A->lam, n, 0), (const double*)plane(A->lam, n, 1),
+                       (const double*)plane(A->lam, n, 2), 0.5, plane(A->lamB, n, 0),
+                       plane(A->lamB, n, 1), plane(A->lamB, n, 2), 0, plane(A->mu, n, 0),
+                       plane(A->mu, n, 1), plane(A->mu, n, 2), grad, n);
+    vjp_rate(A, plane(us, n, 0), plane(us, n, 1), plane(us, n, 2), A->lamB);
+    // stage 1 on U^k: Phi(U^k) again, friction reversed with output adjoint
+    // lamB, accumulated into lamA
+    rate_into(A, h, qx, qy);
+    hipLaunchKernelGGL(adj_stage_kernel, dim3(blocks(n)), dim3(T1), 0, A->stream, A->m.p,
+                       A->m.fric, h, qx, qy, (const double*)plane(A->phi, n, 0),
+                       (const double*)plane(A->phi, n, 1), (const double*)plane(A->phi, n, 2), dt,
+                       (const double*)plane(A->lamB, n, 0), (const double*)plane(A->lamB, n, 1),
+                       (const double*)plane(A->lamB, n, 2), 1.0, plane(A->lamA, n, 0),
+                       plane(A->lamA, n, 1), plane(A->lamA, n, 2), 1, plane(A->mu, n, 0),
+                       plane(A->mu, n, 1), plane(A->mu, n, 2), grad, n);
+    vjp_rate(A, h, qx, qy, A->lamA);
+}
+
+}  // namespace
+
+extern "C" {
+
+int swe_adj_workspace_bytes(const swe_params* p, int32_t nsteps, int32_t ckpt_every,
+                            int32_t ngauges, int32_t every, size_t* bytes) {
+    int rc = check_params(p);
+    if (rc) return rc;
+    if (!bytes || nsteps < 1 || ckpt_every < 1 || ngauges < 0 || every < 1) return SWE_EINVAL;
+    *bytes = adj_bytes(p, nsteps, ckpt_every, ngauges, every);
+    return SWE_OK;
+}
+
+int swe_adj_create(const swe_params* p, const swe_buffers* b, int32_t nsteps,
+                   int32_t ckpt_every, const int32_t* gauges, int32_t ngauges, int32_t every,
+                   const double* obs, void* workspace, size_t workspace_bytes, void* stream,
+                   swe_adj** out) {
+    int rc = check_params(p);
+    if (rc) return rc;
+    if (!b || !out || !workspace || !b->h || !b->qx || !b->qy || !b->z || !b->fric)
+        return SWE_EINVAL;
+    if (p->infil_on || p->fric_law == SWE_FRIC_NONE) return SWE_EINVAL;
+    if (nsteps < 1 || ckpt_every < 1 || ngauges < 1 || every < 1 || !gauges || !obs)
+        return SWE_EINVAL;
+    if (((uintptr_t)workspace & 255) != 0) return SWE_EINVAL;
+    size_t need = adj_bytes(p, nsteps, ckpt_every, ngauges, every);
+    if (workspace_bytes < need) return SWE_ENOMEM;
+    {
+        // every gauge must be a cell of the grid
+        std::vector<int32_t> g(ngauges);
+        if (hipMemcpy(g.data(), gauges, ngauges * sizeof(int32_t), hipMemcpyDeviceToHost) !=
+            hipSuccess)
+            return SWE_EHIP;
+        for (int32_t v : g)
+            if (v < 0 || (size_t)v >= ncells(p)) return SWE_EINVAL;
+    }
+    swe_adj* A = new (std::nothrow) swe_adj;
+    if (!A) return SWE_ENOMEM;
+    std::memset(A, 0, sizeof *A);
+    A->prm = *p;
+    A->stream = (hipStream_t)stream;
+    A->nsteps = nsteps;
+    A->every = every;
+    A->ngauges = ngauges;
+    A->ckpt = ckpt_every;
+    A->nrows = nsteps / every;
+    A->gauges = gauges;
+    A->obs = obs;
+    A->h0 = b->h; A->qx0 = b->qx; A->qy0 = b->qy;
+    size_t n = ncells(p), an = align256(n * sizeof(double));
+    A->n = n;
+    char* w = (char*)workspace;
+    MemberArgs& m = A->m;
+    m.p = to_kparams(*p);
+    m.z = b->z;
+    m.fric = b->fric;
+    m.vinf = nullptr;
+    m.sc = (DevScalars*)w; w += 256;
+    A->loss_dev = (double*)w; w += 256;
+    A->dts = (double*)w; w += align256(nsteps * sizeof(double));
+    A->series = (double*)w; w += align256((size_t)A->nrows * ngauges * sizeof(double));
+    size_t nck = (nsteps + ckpt_every - 1) / ckpt_every;
+    A->ckpts = (double*)w; w += 3 * an * nck;
+    A->seg = (double*)w; w += 3 * an * (ckpt_every + 1);
+    A->ust = (double*)w; w += 3 * an;
+    A->phi = (double*)w; w += 3 * an;
+    A->lamA = (double*)w; w += 3 * an;
+    A->lamB = (double*)w; w += 3 * an;
+    A->lam = (double*)w; w += 3 * an;
+    A->mu = (double*)w; w += 3 * an;
+    A->aa.p = m.p;
+    A->aa.z = b->z;
+    A->aa.fric = b->fric;
+    A->aa.xc = (double*)w; w += align256(12 * (size_t)p->ny * (p->nx + 1) * sizeof(double));
+    A->aa.yc = (double*)w;
+    // the forward writes Phi into the same planes the rate kernel uses
+    m.ph = plane(A->phi, n, 0);
+    m.pqx = plane(A->phi, n, 1);
+    m.pqy = plane(A->phi, n, 2);
+    // the planes are laid out with stride n (not the aligned stride): keep
+    // that consistent by allocating 3 * an >= 3 * n * 8 per triple
+    hipLaunchKernelGGL(swe_init_scalars_kernel, dim3(1), dim3(64), 0, A->stream, m.sc, 0.0);
+    rc = hip_ok(hipGetLastError());
+    if (rc) { delete A; return rc; }
+    *out = A;
+    return SWE_OK;
+}
+
+int swe_adj_destroy(swe_adj* A) {
+    delete A;
+    return SWE_OK;
+}
+
+int swe_adj_set_dts(swe_adj* A, const double* dts) {
+    if (!A) return SWE_EINVAL;
+    if (!dts) {
+        A->dts_frozen = false;
+        return SWE_OK;
+    }
+    if (hipMemcpyAsync(A->dts, dts, A->nsteps * sizeof(double), hipMemcpyDeviceToDevice,
+                       A->stream) != hipSuccess)
+        return SWE_EHIP;
+    A->dts_frozen = true;
+    return SWE_OK;
+}
+
+int swe_adj_get_dts(swe_adj* A, double* dts) {
+    if (!A || !dts) return SWE_EINVAL;
+    if (hipMemcpyAsync(dts, A->dts, A->nsteps * sizeof(double), hipMemcpyDeviceToDevice,
+                       A->stream) != hipSuccess)
+        return SWE_EHIP;
+    return SWE_OK;
+}
+
+int swe_adj_get_series(swe_adj* A, double* out) {
+    if (!A || !out) return SWE_EINVAL;
+    if (hipMemcpyAsync(out, A->series, (size_t)A->nrows * A->ngauges * sizeof(double),
+                       hipMemcpyDeviceToDevice, A->stream) != hipSuccess)
+        return SWE_EHIP;
+    return SWE_OK;
+}
+
+int swe_adj_forward(swe_adj* A, double* loss) {
+    if (!A) return SWE_EINVAL;
+    const size_t n = A->n;
+    // state ping-pong in the segment buffer's first two slots
+    double* S0 = A->seg;
+    double* S1 = A->seg + 3 * n;
+    (void)hipMemcpyAsync(S0, A->h0, n * sizeof(double), hipMemcpyDeviceToDevice, A->stream);
+    (void)hipMemcpyAsync(S0 + n, A->qx0, n * sizeof(double), hipMemcpyDeviceToDevice, A->stream);
+    (void)hipMemcpyAsync(S0 + 2 * n, A->qy0, n * sizeof(double), hipMemcpyDeviceToDevice, A->stream);
+    std::vector<double> host_dts;
+    if (A->dts_frozen) {
+        host_dts.resize(A->nsteps);
+        if (hipMemcpyAsync(host_dts.data(), A->dts, A->nsteps * sizeof(double),
+                           hipMemcpyDeviceToHost, A->stream) != hipSuccess)
+            return SWE_EHIP;
+        if (hipStreamSynchronize(A->stream) != hipSuccess) return SWE_EHIP;
+    }
+    double* cur = S0;
+    double* nxt = S1;
+    for (int k = 0; k < A->nsteps; ++k) {
+        if (k % A->ckpt == 0)
+            (void)hipMemcpyAsync(A->ckpts + (size_t)(k / A->ckpt) * 3 * n, cur, 3 * n * sizeof(double),
+                           hipMemcpyDeviceToDevice, A->stream);
+        fwd_step(A, cur, cur + n, cur + 2 * n, nxt, nxt + n, nxt + 2 * n,
+                 A->dts_frozen ? host_dts[k] : 0.0, k);
+        if ((k + 1) % A->every == 0 && (k + 1) / A->every <= A->nrows)
+            hipLaunchKernelGGL(gauge_kernel, dim3((A->ngauges + 63) / 64), dim3(64), 0,
+                               A->stream, (const double*)nxt, A->gauges, A->ngauges,
+                               A->series + (size_t)((k + 1) / A->every - 1) * A->ngauges);
+        double* t = cur; cur = nxt; nxt = t;
+    }
+    hipLaunchKernelGGL(loss_kernel, dim3(1), dim3(64), 0, A->stream, (const double*)A->series,
+                       A->obs, (size_t)A->nrows * A->ngauges, A->loss_dev);
+    double l = 0.0;
+    if (hipMemcpyAsync(&l, A->loss_dev, sizeof l, hipMemcpyDeviceToHost, A->stream) != hipSuccess)
+        return SWE_EHIP;
+    if (hipStreamSynchronize(A->stream) != hipSuccess) return SWE_EHIP;
+    DevScalars s;
+    if (hipMemcpy(&s, A->m.sc, sizeof s, hipMemcpyDeviceToHost) != hipSuccess) return SWE_EHIP;
+    if (loss) *loss = l;
+    A->dts_frozen = true;  // the backward pass replays exactly these steps
+    if (s.status & SWE_FLAG_NONFINITE) return SWE_ENONFINITE;
+    if (s.status & SWE_FLAG_NEGDEPTH) return SWE_ENEGDEPTH;
+    if (s.status & SWE_FLAG_DT) return SWE_EDT;
+    return hip_ok(hipGetLastError());
+}
+
+int swe_adj_backward(swe_adj* A, double* grad) {
+    if (!A || !grad) return SWE_EINVAL;
+    const size_t n = A->n;
+    std::vector<double> dts(A->nsteps);
+    if (hipMemcpyAsync(dts.data(), A->dts, A->nsteps * sizeof(double), hipMemcpyDeviceToHost,
+                       A->stream) != hipSuccess)
+        return SWE_EHIP;
+    if (hipStreamSynchronize(A->stream) != hipSuccess) return SWE_EHIP;
+    hipLaunchKernelGGL(fill_kernel, dim3(1024), dim3(256), 0, A->stream, grad, 0.0, n);
+    hipLaunchKernelGGL(fill_kernel, dim3(1024), dim3(256), 0, A->stream, A->lam, 0.0, 3 * n);
+    const int nseg = (A->nsteps + A->ckpt - 1) / A->ckpt;
+    for (int sg = nseg - 1; sg >= 0; --sg) {
+        const int s = sg * A->ckpt;
+        const int e = s + A->ckpt < A->nsteps ? s + A->ckpt : A->nsteps;
+        // recompute U^s .. U^{e-1} into the segment buffer
+        (void)hipMemcpyAsync(A->seg, A->ckpts + (size_t)sg * 3 * n, 3 * n * sizeof(double),
+                       hipMemcpyDeviceToDevice, A->stream);
+        for (int k = s; k < e - 1; ++k) {
+            double* in = A->seg + (size_t)(k - s) * 3 * n;
+            double* o = in + 3 * n;
+            fwd_step(A, in, in + n, in + 2 * n, o, o + n, o + 2 * n, dts[k], k);
+        }
+        for (int k = e - 1; k >= s; --k) {
+            // loss term of U^{k+1}
+            if ((k + 1) % A->every == 0 && (k + 1) / A->every <= A->nrows) {
+                size_t row = (size_t)((k + 1) / A->every - 1) * A->ngauges;
+                hipLaunchKernelGGL(inject_kernel, dim3(1), dim3(64), 0, A->stream,
+                                   (const double*)(A->series + row), A->obs + row, A->gauges,
+                                   A->ngauges, A->lam);
+            }
+            const double* Uk = A->seg + (size_t)(k - s) * 3 * n;
+            adj_step(A, Uk, dts[k], grad);
+            // lam <- lamA
+            (void)hipMemcpyAsync(A->lam, A->lamA, 3 * n * sizeof(double), hipMemcpyDeviceToDevice,
+                           A->stream);
+        }
+    }
+    if (hipStreamSynchronize(A->stream) != hipSuccess) return SWE_EHIP;
+    return hip_ok(hipGetLastError());
+}
+
+}  // extern "C"

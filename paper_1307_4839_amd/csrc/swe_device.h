@@ -61,13 +61,13 @@ struct KParams {
 // For ordered (non-NaN) operands these return the same value as the
 // comparisons they replace (up to the sign of a zero, which no later
 // operation can turn into a different non-zero value).
-__device__ __forceinline__ double vmax(double a, double b) { return fmax(a, b); }
-__device__ __forceinline__ double vmin(double a, double b) { return fmin(a, b); }
+__host__ __device__ __forceinline__ double vmax(double a, double b) { return fmax(a, b); }
+__host__ __device__ __forceinline__ double vmin(double a, double b) { return fmin(a, b); }
 
 // minmod limiter, Section 3.4: min(a, b) if both >= 0, max(a, b) if both
 // <= 0, else 0.  Branch-free form with the same value:
 // max(min(a, b), min(max(a, b), 0)).
-__device__ __forceinline__ double minmod(double a, double b) {
+__host__ __device__ __forceinline__ double minmod(double a, double b) {
     return fmax(fmin(a, b), fmin(fmax(a, b), 0.0));
 }
 
@@ -85,7 +85,7 @@ struct Rec {
 // MUSCL on h, h+z and the velocity with minmod on undivided differences;
 // z deduced; modified velocity reconstruction conserving discharge
 // (Section 3.4).  A cell at or below the dry threshold keeps its velocity.
-__device__ __forceinline__ Rec muscl(const Prim& a, const Prim& c, const Prim& b,
+__host__ __device__ __forceinline__ Rec muscl(const Prim& a, const Prim& c, const Prim& b,
                                      double h_eps) {
     Rec r;
     double dh = minmod(c.h - a.h, b.h - c.h);
@@ -123,7 +123,7 @@ struct FaceOut {
     double speed;
 };
 
-__device__ __forceinline__ FaceOut face(double g, double hm, double zm, double unm,
+__host__ __device__ __forceinline__ FaceOut face(double g, double hm, double zm, double unm,
                                         double utm, double hp, double zp, double unp,
                                         double utp) {
     double zs = vmax(zm, zp);
@@ -164,13 +164,13 @@ __device__ __forceinline__ FaceOut face(double g, double hm, double zm, double u
 }
 
 // centred source Fc of Section 3.1 (normal momentum)
-__device__ __forceinline__ double centred(double g, const Rec& r) {
+__host__ __device__ __forceinline__ double centred(double g, const Rec& r) {
     return (-g) * (0.5 * (r.h_m + r.h_p)) * (r.z_p - r.z_m);
 }
 
 // Semi-implicit friction of one stage (Section 3.2).  (h0, q0) stage input,
 // (h1, q1) convective output.
-__device__ __forceinline__ void friction(const KParams& p, double coef, double h0,
+__host__ __device__ __forceinline__ void friction(const KParams& p, double coef, double h0,
                                          double qx0, double qy0, double h1,
                                          double& qx1, double& qy1, double dt) {
     if (h1 <= p.h_eps) {
@@ -191,7 +191,7 @@ __device__ __forceinline__ void friction(const KParams& p, double coef, double h
 
 // dt from the wave-speed bounds (eq. cfl in 2D), clipped to dt_max and to
 // the remaining time.
-__device__ __forceinline__ double time_step(const KParams& p, double ax, double ay,
+__host__ __device__ __forceinline__ double time_step(const KParams& p, double ax, double ay,
                                             double t, double t_end) {
     double r = ax / p.dx + ay / p.dy;
     double dt = p.dt_max;
@@ -206,7 +206,7 @@ __device__ __forceinline__ double time_step(const KParams& p, double ax, double 
 
 // Rain, then Green-Ampt (Section 3.5); the infiltrated water leaves with the
 // cell's velocity.
-__device__ __forceinline__ void rain_infiltration(const KParams& p, double dt,
+__host__ __device__ __forceinline__ void rain_infiltration(const KParams& p, double dt,
                                                   double& h, double& qx, double& qy,
                                                   double& vinf) {
     h = h + dt * p.rain;
@@ -234,7 +234,7 @@ __device__ __forceinline__ void rain_infiltration(const KParams& p, double dt,
 // outflow = copy of the boundary cell.
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ int map_index(int c, int n, int bc_lo, int bc_hi,
+__host__ __device__ __forceinline__ int map_index(int c, int n, int bc_lo, int bc_hi,
                                          double& sign) {
     sign = 1.0;
     int s = c;
@@ -288,6 +288,7 @@ struct TileIO {
     unsigned long long* clr;  // stage 1: pair zeroed for the next step (or null)
     int slot;                 // step parity (time buffer, accumulator slot)
     double t_end;
+    double dt_fixed;          // > 0: use this time step instead of the CFL bound
 };
 
 __device__ __forceinline__ TileIO step_io(const MemberArgs& m, int phase, int slot,
@@ -306,6 +307,7 @@ __device__ __forceinline__ TileIO step_io(const MemberArgs& m, int phase, int sl
     io.clr = m.sc->amax[slot ^ 1];
     io.slot = slot;
     io.t_end = t_end;
+    io.dt_fixed = 0.0;
     return io;
 }
 
@@ -321,7 +323,7 @@ template <int STAGE> struct Fetch {
     double sy;  // sign applied to qy (wall ghost rows)
 };
 
-__device__ __forceinline__ Prim prim_x(const RawCell& c, double h_eps) {
+__host__ __device__ __forceinline__ Prim prim_x(const RawCell& c, double h_eps) {
     Prim p;
     p.h = c.h;
     if (c.h > h_eps) {
@@ -336,7 +338,7 @@ __device__ __forceinline__ Prim prim_x(const RawCell& c, double h_eps) {
 }
 
 // y-view of a cell's primitives: normal velocity v, tangential u
-__device__ __forceinline__ Prim to_y(const Prim& px) {
+__host__ __device__ __forceinline__ Prim to_y(const Prim& px) {
     Prim p;
     p.h = px.h;
     p.un = px.ut;
@@ -460,7 +462,7 @@ __device__ __forceinline__ void stage_tile(const MemberArgs& m, const TileIO& io
         double ax = __longlong_as_double((long long)m.sc->amax[io.slot][0]);
         double ay = __longlong_as_double((long long)m.sc->amax[io.slot][1]);
         double tc = m.sc->t[io.slot];
-        dt = time_step(p, ax, ay, tc, io.t_end);
+        dt = io.dt_fixed > 0.0 ? io.dt_fixed : time_step(p, ax, ay, tc, io.t_end);
         const bool finite = (dt - dt) == 0.0;  // false for inf and NaN
         if (lead && t == 0) {
             long long st = m.sc->steps[io.slot];

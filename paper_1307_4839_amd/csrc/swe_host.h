@@ -85,6 +85,7 @@ inline TileIO host_step_io(const MemberArgs& m, int phase, int slot, double t_en
     io.clr = m.sc->amax[slot ^ 1];
     io.slot = slot;
     io.t_end = t_end;
+    io.dt_fixed = 0.0;
     return io;
 }
 

@@ -215,3 +215,107 @@ class Ensemble:
         if m["vinf"] is not None:
             out["vinf"] = m["vinf"].cpu().numpy()
         return out
+
+
+class Calibration:
+    """Gauge-misfit loss of a run and its adjoint gradient with respect to the
+    friction field (swe_adj_*).  The friction field lives in ``self.fric``
+    (device); ``forward`` runs the simulation, ``backward`` returns dL/dfric."""
+
+    def __init__(self, wl, gauges, every: int, obs, nsteps: int, ckpt_every: int = 0,
+                 device: str = "cuda"):
+        if not torch.cuda.is_available():
+            raise RuntimeError("the HIP library needs a GPU")
+        if wl.fric is None:
+            raise ValueError("the workload needs a friction field")
+        self.device = torch.device(device)
+        self.params = params_from(wl)
+        self.nx, self.ny = wl.nx, wl.ny
+        self.nsteps = nsteps
+        self.every = every
+        self.h = _dev(wl.h, self.device)
+        self.qx = _dev(wl.qx, self.device)
+        self.qy = _dev(wl.qy, self.device)
+        self.z = _dev(wl.z, self.device)
+        self.fric = _dev(wl.fric, self.device)
+        self.gauges = torch.as_tensor(np.ascontiguousarray(gauges, dtype=np.int32)).to(self.device)
+        self.obs = _dev(np.asarray(obs, dtype=np.float64).reshape(-1), self.device)
+        ng = int(self.gauges.numel())
+        assert self.obs.numel() == (nsteps // every) * ng
+        ck = ckpt_every or max(1, int(round(math.sqrt(nsteps))))
+        nbytes = capi.swe_adj_workspace_bytes(self.params, nsteps, ck, ng, every)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        aligned = (self.workspace.data_ptr() + 255) & ~255
+        b = capi.swe_buffers()
+        b.h, b.qx, b.qy = self.h.data_ptr(), self.qx.data_ptr(), self.qy.data_ptr()
+        b.z = self.z.data_ptr()
+        b.fric = self.fric.data_ptr()
+        b.vinf = None
+        self._b = b
+        self.stream = torch.cuda.current_stream(self.device)
+        self.handle = capi.swe_adj_create(self.params, b, nsteps, ck, self.gauges.data_ptr(), ng,
+                                          every, self.obs.data_ptr(), aligned, nbytes,
+                                          self.stream.cuda_stream)
+        self.ckpt_every = ck
+
+    def close(self):
+        if getattr(self, "handle", None):
+            capi.swe_adj_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_dts(self, dts) -> None:
+        if dts is None:
+            capi.swe_adj_set_dts(self.handle, None)
+            return
+        t = _dev(np.asarray(dts, dtype=np.float64), self.device)
+        capi.swe_adj_set_dts(self.handle, t.data_ptr())
+        torch.cuda.synchronize(self.device)
+
+    def dts(self) -> np.ndarray:
+        t = torch.empty(self.nsteps, dtype=torch.float64, device=self.device)
+        capi.swe_adj_get_dts(self.handle, t.data_ptr())
+        torch.cuda.synchronize(self.device)
+        return t.cpu().numpy()
+
+    def forward(self) -> float:
+        return capi.swe_adj_forward(self.handle)
+
+    def series(self) -> np.ndarray:
+        """Gauge depths of the last forward pass, one row per `every` steps."""
+        rows = self.nsteps // self.every
+        t = torch.empty(rows * int(self.gauges.numel()), dtype=torch.float64,
+                        device=self.device)
+        capi.swe_adj_get_series(self.handle, t.data_ptr())
+        torch.cuda.synchronize(self.device)
+        return t.cpu().numpy().reshape(rows, -1)
+
+    def backward(self) -> torch.Tensor:
+        g = torch.empty((self.ny, self.nx), dtype=torch.float64, device=self.device)
+        capi.swe_adj_backward(self.handle, g.data_ptr())
+        return g
+
+
+class GaugeMisfit(torch.autograd.Function):
+    """loss = GaugeMisfit.apply(fric, calibration): the gauge-misfit loss of
+    the calibration run as a differentiable function of the friction field
+    (a float64 tensor on the GPU); the backward pass is the hand-written
+    adjoint of the step."""
+
+    @staticmethod
+    def forward(ctx, fric: torch.Tensor, calib: "Calibration"):
+        with torch.no_grad():
+            calib.fric.copy_(fric.detach().to(calib.fric.dtype).reshape(calib.fric.shape))
+        loss = calib.forward()
+        ctx.calib = calib
+        return torch.tensor(loss, dtype=torch.float64, device=fric.device)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        g = ctx.calib.backward()
+        return grad_out * g, None

@@ -1,0 +1,156 @@
+"""GPU adjoint of the step with respect to the friction field.
+
+* Against the oracle's forward-mode tangent (itself pinned to finite
+  differences on the CPU): for random directions d, <grad, d> from the GPU
+  adjoint equals dL along d within 1e-10, with the oracle's time steps
+  frozen on both sides; the losses agree within 1e-12.
+* At the full 1024 x 1024 calibration size, 2000 steps with sqrt(N)
+  checkpoints: central finite differences of the GPU loss along 16 random
+  directions (time steps frozen) agree with <grad, d> within 5e-5.  The
+  discrete step is only piecewise smooth (wet/dry threshold, minmod and
+  hydrostatic-reconstruction switches), so for steps eps >= 1e-6 n the
+  differences cross switches and wander by up to 1e-2; below 1e-9 n round-off
+  of the loss dominates.  At eps = 1e-8 n both effects are a few 1e-6 (a
+  sweep over eps from 1e-3 to 1e-10 converges to the adjoint there).
+* The torch.autograd.Function path returns the same gradient.
+"""
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1307_4839_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def case_calibration():
+    wl = I.calibration_1024(96, 80, dam_row=20, ngauges=10, sigma_cells=4)
+    return wl, wl.extra["fric_obs"]
+
+
+def case_random_bcs():
+    rng = np.random.default_rng(9)
+    wl = I.random_state(70, 66, seed=9, bc=(1, 0, 0, 1), fric_law=I.FRIC_MANNING,
+                        fric_coef=0.04)
+    xi = I.smooth_field(rng, wl.nx, wl.ny, 4.0)
+    wl.fric = 0.04 * (1.0 + 0.2 * xi)
+    xo = I.smooth_field(rng, wl.nx, wl.ny, 4.0)
+    wl.gauges = np.sort(rng.choice(wl.nx * wl.ny, 12, replace=False)).astype(np.int32)
+    return wl, 0.04 * (1.0 + 0.2 * xo)
+
+
+def case_darcy():
+    wl = I.calibration_1024(64, 72, dam_row=15, ngauges=8, sigma_cells=3)
+    wl.fric_law = I.FRIC_DARCY
+    wl.fric = 0.3 + 0.1 * wl.fric / 0.03
+    wl.bc = (1, 1, 0, 1)
+    return wl, 0.3 + 0.1 * wl.extra["fric_obs"] / 0.03
+
+
+@pytest.mark.parametrize("make", [case_calibration, case_random_bcs, case_darcy])
+def test_adjoint_against_oracle_tangent(torch_cuda, make):
+    from paper_1307_4839_amd.solver import Calibration
+    wl, fric_obs = make()
+    nsteps, every = 60, 5
+    say(f"[adjoint] {make.__name__} {wl.nx}x{wl.ny} {nsteps} steps")
+    base = oracle.State(wl)
+    assert base.run(nsteps) == 0
+    dts = np.array(base.dts)
+    p = oracle.params_of(wl)
+    obs, _ = oracle.gauge_run(p, wl.h, wl.qx, wl.qy, wl.z, fric_obs, dts, wl.gauges, every)
+    cal = Calibration(wl, wl.gauges, every, obs, nsteps, ckpt_every=7)
+    cal.set_dts(dts)
+    L = cal.forward()
+    g = cal.backward().cpu().numpy()
+    assert np.isfinite(g).all()
+    rng = np.random.default_rng(3)
+    for k in range(4):
+        d = rng.standard_normal((wl.ny, wl.nx)) * 1e-3
+        L0, dL = oracle.tangent_run(p, wl.h, wl.qx, wl.qy, wl.z, wl.fric, d, dts, wl.gauges,
+                                    every, obs)
+        if k == 0:
+            say(f"    loss gpu {L!r} oracle {L0!r}")
+            assert abs(L - L0) <= 1e-12 * abs(L0)
+        gd = float((g * d).sum())
+        say(f"    <g,d> = {gd!r}  oracle tangent = {dL!r}")
+        assert abs(gd - dL) <= 1e-10 * max(abs(dL), 1e-300), (k, gd, dL)
+
+
+def test_autograd_function(torch_cuda):
+    torch = torch_cuda
+    from paper_1307_4839_amd.solver import Calibration, GaugeMisfit
+    wl, fric_obs = case_calibration()
+    nsteps, every = 40, 5
+    base = oracle.State(wl)
+    base.run(nsteps)
+    dts = np.array(base.dts)
+    p = oracle.params_of(wl)
+    obs, _ = oracle.gauge_run(p, wl.h, wl.qx, wl.qy, wl.z, fric_obs, dts, wl.gauges, every)
+    cal = Calibration(wl, wl.gauges, every, obs, nsteps)
+    cal.set_dts(dts)
+    n = torch.tensor(wl.fric, dtype=torch.float64, device="cuda", requires_grad=True)
+    loss = GaugeMisfit.apply(n, cal)
+    loss.backward()
+    cal2 = Calibration(wl, wl.gauges, every, obs, nsteps)
+    cal2.set_dts(dts)
+    L2 = cal2.forward()
+    g2 = cal2.backward()
+    assert loss.item() == L2
+    assert torch.equal(n.grad, g2)
+
+
+def test_adjoint_finite_differences_fullsize(torch_cuda):
+    torch = torch_cuda
+    from paper_1307_4839_amd.solver import Calibration
+    wl = I.calibration_1024()
+    nsteps, every = 2000, 10
+    rows, ng = nsteps // every, len(wl.gauges)
+    # synthetic observations: the same run with the perturbed friction
+    # field, on the time steps the base run chooses by eq. (cfl)
+    base_run = Calibration(wl, wl.gauges, every, np.zeros(rows * ng), nsteps)
+    say(f"[adjoint] full size {wl.nx}x{wl.ny}, {nsteps} steps, ckpt {base_run.ckpt_every}")
+    base_run.forward()
+    dts = base_run.dts()
+    base_run.fric.copy_(torch.as_tensor(wl.extra["fric_obs"], device="cuda"))
+    base_run.forward()
+    obs = base_run.series()
+    base_run.close()
+    cal = Calibration(wl, wl.gauges, every, obs, nsteps)
+    cal.set_dts(dts)
+    L = cal.forward()
+    g = cal.backward()
+    say(f"    loss {L!r}")
+    assert L > 0 and torch.isfinite(g).all()
+    rng = np.random.default_rng(11)
+    base = torch.as_tensor(wl.fric, device="cuda")
+    eps = 1e-8 * float(np.mean(wl.fric))
+    worst = 0.0
+    for k in range(16):
+        d = torch.as_tensor(I.smooth_field(rng, wl.nx, wl.ny, 20.0), device="cuda")
+        cal.fric.copy_(base + eps * d)
+        Lp = cal.forward()
+        cal.fric.copy_(base - eps * d)
+        Lm = cal.forward()
+        fd = (Lp - Lm) / (2 * eps)
+        gd = float((g * d).sum().item())
+        rel = abs(fd - gd) / max(abs(gd), 1e-300)
+        worst = max(worst, rel)
+        say(f"    dir {k}: FD {fd!r} adjoint {gd!r} rel {rel:.2e}")
+        assert rel <= 5e-5
+    say(f"    worst relative difference {worst:.2e}")
