@@ -50,9 +50,11 @@ _lib = None
 
 
 def lib(path: Optional[str] = None):
+    """The oracle library (SWE_ORACLE_LIB overrides the path; the mutation
+    tests use it to load deliberately broken builds)."""
     global _lib
     if _lib is None or path is not None:
-        l = C.CDLL(path or build())
+        l = C.CDLL(path or os.environ.get("SWE_ORACLE_LIB") or build())
         dp = C.POINTER(C.c_double)
         ip = C.POINTER(C.c_int32)
         pp = C.POINTER(OrcParams)

@@ -1,0 +1,81 @@
+"""Mutation check of the oracle pins: each plausible mistake below (a wrong
+sign, a swapped index, a dropped term, a transposed operand), planted in a
+copy of the oracle source on the CPU, must make at least one pin of
+tests/test_oracle_pins.py fail."""
+
+import os
+import subprocess
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+import pytest
+
+import oracle
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+
+MUTANTS = {
+    "hll_diffusion_sign": ("c1 * c2 / (c2 - c1) * (UR[k] - UL[k])",
+                           "c1 * c2 / (c2 - c1) * (UL[k] - UR[k])"),
+    "hll_wave_speed": ("T c2 = vmax(unL + cL, unR + cR);", "T c2 = vmax(unL + cL, unR - cR);"),
+    "hll_tangential_operand": ("qL * utL}", "qL * unL}"),
+    "hydrostatic_min": ("T zs = vmax(zm, zp);", "T zs = vmin(zm, zp);"),
+    "drop_source_sL": ("f.sL = T(0.5 * g) * (hm * hm - hL * hL);", "f.sL = T(0.0);"),
+    "centred_sign_x": ("T fcen = T(-g) *", "T fcen = T(g) *"),
+    "modified_velocity_index": ("r.un_m = c.un - (r.h_p / c.h)", "r.un_m = c.un - (r.h_m / c.h)"),
+    "z_deduction_index": ("r.z_m = eta_m - r.h_m;", "r.z_m = eta_m - r.h_p;"),
+    "minmod_min_max": ("if (a >= T(0.0) && b >= T(0.0)) return vmin(a, b);",
+                       "if (a >= T(0.0) && b >= T(0.0)) return vmax(a, b);"),
+    "primitive_v_operand": ("v[k] = qy[k] / h[k];", "v[k] = qx[k] / h[k];"),
+    "rate_y_tangential": ("pqx[s] = -(X1[s] / T(p.dx) + Y2[s] / T(p.dy));",
+                          "pqx[s] = -(X1[s] / T(p.dx) + Y1[s] / T(p.dy));"),
+    "wall_ghost_sign": ("qx[dst] = p.bc[0] == BC_WALL ? -qx[src] : qx[src];",
+                        "qx[dst] = qx[src];"),
+    "friction_h0_h1": ("qn / (h0 * h1);", "qn / (h0 * h0);"),
+    "manning_exponent": ("(h1 * dcbrt(h1))", "(h1 * h1)"),
+    "heun_average": ("T hn = T(0.5) * (h[s] + h2[s]);", "T hn = h2[s];"),
+    "cfl_drop_y": ("double r = amax[0] / p.dx + amax[1] / p.dy;", "double r = amax[0] / p.dx;"),
+    "green_ampt_sign": ("(T(p.psi) + h) / zf", "(T(p.psi) - h) / zf"),
+    "rain_missing_dt": ("h = h + T(dt) * T(p.rain);", "h = h + T(p.rain);"),
+}
+
+
+def build_mutant(name, tmp):
+    old, new = MUTANTS[name]
+    src = open(os.path.join(ROOT, "oracle", "swe_oracle.cpp")).read()
+    assert src.count(old) >= 1, name
+    path_src = os.path.join(tmp, f"{name}.cpp")
+    with open(path_src, "w") as f:
+        f.write(src.replace(old, new, 1))
+    lib = os.path.join(tmp, f"lib_{name}.so")
+    subprocess.check_call(["g++", *oracle.CFLAGS, path_src, "-o", lib])
+    return lib
+
+
+def run_pins(lib):
+    env = dict(os.environ, SWE_ORACLE_LIB=lib, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        os.path.join(HERE, "test_oracle_pins.py")],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=900)
+    return r.returncode
+
+
+def test_every_mutant_is_caught(tmp_path):
+    names = sorted(MUTANTS)
+
+    def one(name):
+        return name, run_pins(build_mutant(name, str(tmp_path)))
+
+    workers = max(1, min(8, os.cpu_count() or 1))
+    with ThreadPoolExecutor(workers) as ex:
+        results = dict(ex.map(one, names))
+    survivors = [n for n, rc in results.items() if rc == 0]
+    assert not survivors, f"mutants not caught by any pin: {survivors}"
+
+
+def test_unmutated_source_passes_the_same_run(tmp_path):
+    src = os.path.join(ROOT, "oracle", "swe_oracle.cpp")
+    lib = os.path.join(str(tmp_path), "lib_plain.so")
+    subprocess.check_call(["g++", *oracle.CFLAGS, src, "-o", lib])
+    assert run_pins(lib) == 0
