@@ -13,15 +13,17 @@
 // (Section 2.2, two layers at second order, Section 6.1) are index maps in
 // the loader; no ghost arrays exist in HBM.
 //
-// Arithmetic follows the formulas in the order they are written; with
-// -ffp-contract=off and IEEE division and square root the only operation
-// that is not correctly rounded is the cube root of the Manning law.
+// Arithmetic follows the formulas in the order they are written, without
+// contraction; divisions and square roots give the values of the IEEE
+// operators (see Division), so the only operation that is not correctly
+// rounded is the cube root of the Manning law.
 #pragma once
 
 #include <hip/hip_runtime.h>
 
 #include <cmath>
 #include <cstdint>
+#include <type_traits>
 
 #include "swe.h"
 
@@ -52,6 +54,112 @@ struct KParams {
     double rain;
     int infil;
     double ks, psi, dtheta;
+    // dx and dy both powers of two: X / dx == X * inv_dx exactly
+    int dxy_pow2;
+    double inv_dx, inv_dy;
+    // g in (0, 2^10] and dx, dy in [2^-300, 2^300]: the shared-reciprocal
+    // quotients may be used (their operand bounds are checked on the device)
+    int fast_div;
+};
+
+// ---------------------------------------------------------------------------
+// Division
+// ---------------------------------------------------------------------------
+//
+// On gfx9 a / b in double precision is: operand scaling, a reciprocal seed
+// of b, two Newton-Raphson steps y <- y + y (1 - b y), the quotient
+// q0 = a y, the exact residual r = a - b q0, the corrected quotient
+// q0 + r y, and a special-case fix-up.  The scaling and the fix-up only act
+// on zero, non-finite, tiny or huge operands: for b in [2^-300, 2^300] and
+// a in [2^-700, 2^460] neither does, the corrected quotient is the result of
+// the division operator, and the refined reciprocal depends on b alone.  It
+// can then be computed once per denominator and shared by every numerator
+// over it: three operations per quotient instead of eleven.  A zero
+// numerator gives a zero quotient (its sign may differ from the operator's;
+// nothing in the scheme tells the two zeros apart).
+//
+// The formulas take a division policy.  ExactDiv is the division operator.
+// FastDiv shares reciprocals and, without branches, keeps two running
+// bounds over the operands it is shown: the largest magnitude among the
+// capped values, and the smallest binary exponent among the values bounded
+// below (a zero counts as exponent 0, a depth with its sign bit set as a
+// huge negative exponent).  While every capped value stays at most 2^60 and
+// every value bounded below is zero or at least 2^-300, every operand of a
+// shared-reciprocal quotient lies in the window above, and so does every
+// operand of a square root without scaling (root); the comments at each
+// quotient give the reason.  The tile kernel checks the bounds once per row
+// and, when they fail, computes the row again with ExactDiv, as it does
+// every later row of the tile.
+
+struct Recip {
+    double b, y;  // denominator and its refined reciprocal (FastDiv only)
+};
+
+constexpr double NOTE_CAP = 0x1p60;
+constexpr int NOTE_EMIN = -299;  // frexp exponent of 2^-300
+
+struct ExactDiv {
+    __host__ __device__ Recip rcp(double b) const { return Recip{b, 0.0}; }
+    __host__ __device__ double div(double a, const Recip& r) const { return a / r.b; }
+    __host__ __device__ void cap(double) const {}
+    __host__ __device__ void low(double) const {}
+    __host__ __device__ void low2(double, double) const {}
+    __host__ __device__ void depth(double) const {}
+    __host__ __device__ double root(double x) const { return sqrt(x); }
+    __host__ __device__ bool ok() const { return true; }
+    __host__ __device__ void settle() const {}
+};
+
+struct FastDiv {
+    double hi = 0.0;  // largest magnitude among the capped values
+    int emin = 0;     // smallest exponent among the values bounded below
+
+    __device__ Recip rcp(double b) const {
+        double y = __builtin_amdgcn_rcp(b);
+        double e = fma(-b, y, 1.0);
+        y = fma(y, e, y);
+        e = fma(-b, y, 1.0);
+        return Recip{b, fma(y, e, y)};
+    }
+    __device__ double div(double a, const Recip& r) const {
+        double q0 = a * r.y;
+        double e = fma(-r.b, q0, a);
+        return fma(e, r.y, q0);
+    }
+    // Square root as gfx9 evaluates it for x = 0, x >= 2^-767, +inf, x < 0
+    // and NaN (reciprocal square root seed, Goldschmidt steps for g ~ sqrt(x)
+    // and h ~ 1 / (2 sqrt(x)), two corrections with the exact residual
+    // x - g^2, zero and infinity returned as they are), without the scaling
+    // by 2^256 that only positive x below 2^-767 take: the caller bounds x
+    // below.
+    __device__ double root(double x) const {
+        double r = __builtin_amdgcn_rsq(x);
+        double g = x * r;
+        double h = r * 0.5;
+        double e = fma(-h, g, 0.5);
+        g = fma(g, e, g);
+        h = fma(h, e, h);
+        double d = fma(-g, g, x);
+        g = fma(d, h, g);
+        d = fma(-g, g, x);
+        g = fma(d, h, g);
+        return (x == 0.0 || x == __builtin_inf()) ? x : g;
+    }
+    __device__ void cap(double v) { hi = fmax(hi, fabs(v)); }
+    __device__ void low(double v) { emin = min(emin, __builtin_amdgcn_frexp_exp(v)); }
+    __device__ void low2(double u, double v) {
+        emin = min(emin, min(__builtin_amdgcn_frexp_exp(u), __builtin_amdgcn_frexp_exp(v)));
+    }
+    // a depth: capped, bounded below, and not negative (the high word of a
+    // double with its sign bit set is a negative integer)
+    __device__ void depth(double h) {
+        cap(h);
+        emin = min(emin, min(__builtin_amdgcn_frexp_exp(h), __double2hiint(h)));
+    }
+    __device__ bool ok() const { return hi <= NOTE_CAP && emin >= NOTE_EMIN; }
+    // Pins the bounds at this point of the program, so that the values
+    // shown before it need not stay live until the row's check.
+    __device__ void settle() { asm volatile("" : "+v"(hi), "+v"(emin)); }
 };
 
 // ---------------------------------------------------------------------------
@@ -85,8 +193,12 @@ struct Rec {
 // MUSCL on h, h+z and the velocity with minmod on undivided differences;
 // z deduced; modified velocity reconstruction conserving discharge
 // (Section 3.4).  A cell at or below the dry threshold keeps its velocity.
+// rc = d.rcp(c.h).  With the three depths not negative, minmod keeps h_m and
+// h_p within [c.h / 2, 3 c.h / 2] (up to one rounding), so the two quotients
+// need no operand bounds beyond those of c.h.
+template <class D>
 __host__ __device__ __forceinline__ Rec muscl(const Prim& a, const Prim& c, const Prim& b,
-                                     double h_eps) {
+                                              double h_eps, const Recip& rc, D& d) {
     Rec r;
     double dh = minmod(c.h - a.h, b.h - c.h);
     r.h_m = c.h - 0.5 * dh;
@@ -99,8 +211,8 @@ __host__ __device__ __forceinline__ Rec muscl(const Prim& a, const Prim& c, cons
     double dun = minmod(c.un - a.un, b.un - c.un);
     double dut = minmod(c.ut - a.ut, b.ut - c.ut);
     if (c.h > h_eps) {
-        double wp = r.h_p / c.h;
-        double wm = r.h_m / c.h;
+        double wp = d.div(r.h_p, rc);
+        double wm = d.div(r.h_m, rc);
         r.un_m = c.un - wp * (0.5 * dun);
         r.un_p = c.un + wm * (0.5 * dun);
         r.ut_m = c.ut - wp * (0.5 * dut);
@@ -114,23 +226,35 @@ __host__ __device__ __forceinline__ Rec muscl(const Prim& a, const Prim& c, cons
     return r;
 }
 
+__host__ __device__ __forceinline__ Rec muscl(const Prim& a, const Prim& c, const Prim& b,
+                                              double h_eps) {
+    ExactDiv d;
+    return muscl(a, c, b, h_eps, d.rcp(c.h), d);
+}
+
 // Flux through one face: hydrostatic reconstruction (Section 3.1), HLL
 // (Section 3.3), and the normal-momentum corrections S_L (left cell) and
 // S_R (right cell).  fl = flux seen by the left cell, fr = by the right one.
-// speed = max(|u-| + sqrt(g h-), |u+| + sqrt(g h+)) on the MUSCL states.
+// face_speed = max(|u-| + sqrt(g h-), |u+| + sqrt(g h+)) on the MUSCL
+// states (stage 1 only).
 struct FaceOut {
     double f0, fl1, fr1, f2;
-    double speed;
 };
 
+// With depths, velocities and z capped at 2^60 and g at most 2^10, c1 and c2
+// stay below 2^62 and the HLL numerators below 2^251; den and the
+// numerators are bounded below here.
+template <class D>
 __host__ __device__ __forceinline__ FaceOut face(double g, double hm, double zm, double unm,
-                                        double utm, double hp, double zp, double unp,
-                                        double utp) {
+                                                 double utm, double hp, double zp, double unp,
+                                                 double utp, D& d) {
     double zs = vmax(zm, zp);
     double hL = vmax(hm + zm - zs, 0.0);
     double hR = vmax(hp + zp - zs, 0.0);
-    double cL = sqrt(g * hL);
-    double cR = sqrt(g * hR);
+    double gL = g * hL, gR = g * hR;
+    d.low2(gL, gR);
+    double cL = d.root(gL);
+    double cR = d.root(gR);
     double c1 = vmin(unm - cL, unp - cR);
     double c2 = vmax(unm + cL, unp + cR);
     double qL = hL * unm;
@@ -144,11 +268,19 @@ __host__ __device__ __forceinline__ FaceOut face(double g, double hm, double zm,
     } else if (c2 <= 0.0) {
         F0 = FR0; F1 = FR1; F2 = FR2;
     } else {
-        double den = c2 - c1;
-        double w = c1 * c2 / den;
-        F0 = (c2 * FL0 - c1 * FR0) / den + w * (hR - hL);
-        F1 = (c2 * FL1 - c1 * FR1) / den + w * (qR - qL);
-        F2 = (c2 * FL2 - c1 * FR2) / den + w * (hR * utp - hL * utm);
+        Recip den = d.rcp(c2 - c1);
+        double n0 = c1 * c2;
+        double n1 = c2 * FL0 - c1 * FR0;
+        double n2 = c2 * FL1 - c1 * FR1;
+        double n3 = c2 * FL2 - c1 * FR2;
+        d.low2(den.b, n0);
+        d.low2(n1, n2);
+        d.low(n3);
+        d.settle();
+        double w = d.div(n0, den);
+        F0 = d.div(n1, den) + w * (hR - hL);
+        F1 = d.div(n2, den) + w * (qR - qL);
+        F2 = d.div(n3, den) + w * (hR * utp - hL * utm);
     }
     double sL = hg * (hm * hm - hL * hL);
     double sR = hg * (hp * hp - hR * hR);
@@ -157,10 +289,24 @@ __host__ __device__ __forceinline__ FaceOut face(double g, double hm, double zm,
     o.fl1 = F1 + sL;
     o.fr1 = F1 + sR;
     o.f2 = F2;
-    double sm = fabs(unm) + sqrt(g * hm);
-    double sp = fabs(unp) + sqrt(g * hp);
-    o.speed = fmax(sm, sp);
     return o;
+}
+
+template <class D>
+__device__ __forceinline__ double face_speed(double g, double hm, double unm, double hp,
+                                             double unp, D& d) {
+    double gm = g * hm, gp = g * hp;
+    d.low2(gm, gp);
+    double sm = fabs(unm) + d.root(gm);
+    double sp = fabs(unp) + d.root(gp);
+    return fmax(sm, sp);
+}
+
+__host__ __device__ __forceinline__ FaceOut face(double g, double hm, double zm, double unm,
+                                                 double utm, double hp, double zp, double unp,
+                                                 double utp) {
+    ExactDiv d;
+    return face(g, hm, zm, unm, utm, hp, zp, unp, utp, d);
 }
 
 // centred source Fc of Section 3.1 (normal momentum)
@@ -169,24 +315,42 @@ __host__ __device__ __forceinline__ double centred(double g, const Rec& r) {
 }
 
 // Semi-implicit friction of one stage (Section 3.2).  (h0, q0) stage input,
-// (h1, q1) convective output.
+// (h1, q1) convective output.  The denominator and both numerators are
+// capped and bounded below here, the operand of the square root too.
+template <class D>
 __host__ __device__ __forceinline__ void friction(const KParams& p, double coef, double h0,
-                                         double qx0, double qy0, double h1,
-                                         double& qx1, double& qy1, double dt) {
+                                                  double qx0, double qy0, double h1,
+                                                  double& qx1, double& qy1, double dt, D& d) {
     if (h1 <= p.h_eps) {
         qx1 = 0.0;
         qy1 = 0.0;
         return;
     }
     if (p.law == SWE_FRIC_NONE || !(h0 > p.h_eps)) return;
-    double qn = sqrt(qx0 * qx0 + qy0 * qy0);
+    double q2 = qx0 * qx0 + qy0 * qy0;
+    d.low(q2);
+    double qn = d.root(q2);
     double den;
     if (p.law == SWE_FRIC_DARCY)
         den = 1.0 + dt * (coef / 8.0) * qn / (h0 * h1);
     else
         den = 1.0 + dt * p.g * coef * coef * qn / (h0 * (h1 * cbrt(h1)));
-    qx1 = qx1 / den;
-    qy1 = qy1 / den;
+    Recip rd = d.rcp(den);
+    d.cap(den);
+    d.cap(qx1);
+    d.cap(qy1);
+    d.low2(den, qx1);
+    d.low(qy1);
+    d.settle();
+    qx1 = d.div(qx1, rd);
+    qy1 = d.div(qy1, rd);
+}
+
+__host__ __device__ __forceinline__ void friction(const KParams& p, double coef, double h0,
+                                                  double qx0, double qy0, double h1,
+                                                  double& qx1, double& qy1, double dt) {
+    ExactDiv d;
+    friction(p, coef, h0, qx0, qy0, h1, qx1, qy1, dt, d);
 }
 
 // dt from the wave-speed bounds (eq. cfl in 2D), clipped to dt_max and to
@@ -323,18 +487,40 @@ template <int STAGE> struct Fetch {
     double sy;  // sign applied to qy (wall ghost rows)
 };
 
-__host__ __device__ __forceinline__ Prim prim_x(const RawCell& c, double h_eps) {
+// rh = d.rcp(c.h); the numerators are bounded by the caller (note_cell)
+template <class D>
+__host__ __device__ __forceinline__ Prim prim_x(const RawCell& c, double h_eps, const Recip& rh,
+                                                D& d) {
     Prim p;
     p.h = c.h;
     if (c.h > h_eps) {
-        p.un = c.qx / c.h;
-        p.ut = c.qy / c.h;
+        p.un = d.div(c.qx, rh);
+        p.ut = d.div(c.qy, rh);
     } else {
         p.un = 0.0;
         p.ut = 0.0;
     }
     p.eta = c.h + c.z;
     return p;
+}
+
+__host__ __device__ __forceinline__ Prim prim_x(const RawCell& c, double h_eps) {
+    ExactDiv d;
+    return prim_x(c, h_eps, d.rcp(c.h), d);
+}
+
+// The values of a cell that bound the operands of its quotients: depth,
+// discharges, bed and velocities.
+template <class D>
+__device__ __forceinline__ void note_cell(D& d, const RawCell& r, const Prim& pr) {
+    d.depth(r.h);
+    d.cap(r.qx);
+    d.cap(r.qy);
+    d.low2(r.qx, r.qy);
+    d.cap(r.z);
+    d.cap(pr.un);
+    d.cap(pr.ut);
+    d.settle();
 }
 
 // y-view of a cell's primitives: normal velocity v, tangential u
@@ -372,9 +558,9 @@ __device__ __forceinline__ Fetch<STAGE> fetch(const MemberArgs& m, const TileIO&
 // Stage input of a fetched cell.  Stage 1: U^n.  Stage 2: U* =
 // friction(U^n + dt Phi(U^n)) (the first stage of Heun's method, Section
 // 3.2).  Ghost sign flips (walls) are applied last.
-template <int STAGE>
-__device__ __forceinline__ RawCell build(const KParams& p, const Fetch<STAGE>& f,
-                                         double sx, double dt) {
+template <int STAGE, class D>
+__device__ __forceinline__ RawCell build(const KParams& p, const Fetch<STAGE>& f, double sx,
+                                         double dt, D& d) {
     RawCell o;
     o.z = f.z;
     if (STAGE == 1) {
@@ -385,7 +571,7 @@ __device__ __forceinline__ RawCell build(const KParams& p, const Fetch<STAGE>& f
         double h1 = f.h + dt * f.ph;
         double qx1 = f.qx + dt * f.pqx;
         double qy1 = f.qy + dt * f.pqy;
-        friction(p, f.coef, f.h, f.qx, f.qy, h1, qx1, qy1, dt);
+        friction(p, f.coef, f.h, f.qx, f.qy, h1, qx1, qy1, dt, d);
         o.h = h1;
         o.qx = qx1;
         o.qy = qy1;
@@ -432,7 +618,235 @@ __device__ void block_max2(double ax, double ay, unsigned long long* dst) {
 // ---------------------------------------------------------------------------
 // One tile through one stage
 // ---------------------------------------------------------------------------
-//
+
+template <int TXT> struct TileLds {
+    double h[TXT], u[TXT], v[TXT], e[TXT];       // primitives of row j
+    double hm[TXT], zm[TXT], unm[TXT], utm[TXT];  // x-reconstruction, face i-1/2 side
+    double f0[TXT], f1[TXT], f2[TXT];             // x-fluxes
+    int bad[2];                                   // operand bounds broken in row j (j & 1)
+};
+
+// March rows y0 .. y1-1 of a tile with division policy D (see Division).
+// With FastDiv a lane that finds its bounds broken in row j raises
+// L.bad[j & 1] before the row's last barrier; every lane reads the flag
+// after it and the march returns j before anything of row j is stored, for
+// the caller to march on from row j with ExactDiv.  Thread 0 lowers the flag
+// of row j+1 after the first barrier of row j, when every lane has read it
+// for row j-1.  Returns y1 when the tile is done.
+template <int STAGE, int TXT, class D>
+__device__ __forceinline__ int march(const MemberArgs& m, const TileIO& io, int strip, int y0,
+                                     int y1, double dt, double& ax, double& ay,
+                                     TileLds<TXT>& L) {
+    constexpr int OUTW = TXT - 2 * HALO;
+    constexpr bool FAST = !std::is_same<D, ExactDiv>::value;
+    const KParams& p = m.p;
+    const int t = threadIdx.x;
+    const int x0 = strip * OUTW;
+    const int c = x0 - HALO + t;
+    const bool out_col = (t >= HALO) && (t < TXT - HALO) && (c < p.nx);
+    const bool col_in = (c >= 0) && (c < p.nx);
+    // a face c+1/2 computed by thread t has valid neighbour data when
+    // 1 <= t <= TXT-3; it is a real face when -1 <= c <= nx-1
+    const bool xface_ok = (t >= 1) && (t <= TXT - 3) && (c >= -1) && (c <= p.nx - 1);
+    const int tl = t > 0 ? t - 1 : t;
+    const int tr = t < TXT - 1 ? t + 1 : t;
+
+    double sx;
+    const int cs = map_index(c, p.nx, p.bcw, p.bce, sx);
+    D d;
+    // X / dx and Y / dy: exact products when dx and dy are powers of two,
+    // else quotients sharing the reciprocals of dx and dy
+    const Recip Rdx = d.rcp(p.dx), Rdy = d.rcp(p.dy);
+
+    // --- prologue: rows y0-2 .. y0+1, face y0-1/2; prefetch row y0+2 -------
+    Fetch<STAGE> fA = fetch<STAGE>(m, io, y0 - 2, cs);
+    Fetch<STAGE> fB = fetch<STAGE>(m, io, y0 - 1, cs);
+    Fetch<STAGE> fC = fetch<STAGE>(m, io, y0, cs);
+    Fetch<STAGE> fD = fetch<STAGE>(m, io, y0 + 1, cs);
+    Fetch<STAGE> fnext = fetch<STAGE>(m, io, y0 + 2, cs);
+    RawCell rA = build<STAGE>(p, fA, sx, dt, d);
+    RawCell rB = build<STAGE>(p, fB, sx, dt, d);
+    RawCell rC = build<STAGE>(p, fC, sx, dt, d);
+    RawCell rD = build<STAGE>(p, fD, sx, dt, d);
+    // reciprocals of the depths of rows j and j+1, shared by the velocities
+    // and by both reconstructions of the cell
+    Recip R0 = d.rcp(rC.h), R1 = d.rcp(rD.h);
+    Prim pA = prim_x(rA, p.h_eps, d.rcp(rA.h), d);
+    Prim pB = prim_x(rB, p.h_eps, d.rcp(rB.h), d);
+    Prim p0 = prim_x(rC, p.h_eps, R0, d), p1 = prim_x(rD, p.h_eps, R1, d);
+    note_cell(d, rA, pA);
+    note_cell(d, rB, pB);
+    note_cell(d, rC, p0);
+    note_cell(d, rD, p1);
+    // stage input discharges of rows j and j+1 (stage 2 needs them for U**)
+    double q0x = rC.qx, q0y = rC.qy, q1x = rD.qx, q1y = rD.qy;
+    // U^n of rows j and j+1 (stage 2: Heun's average)
+    double n0h = fC.h, n0x = fC.qx, n0y = fC.qy, n1h = fD.h, n1x = fD.qx, n1y = fD.qy;
+    double c0 = fC.coef, c1 = fD.coef;
+
+    Rec rprev = muscl(to_y(pA), to_y(pB), to_y(p0), p.h_eps, d.rcp(pB.h), d);
+    Rec rcur = muscl(to_y(pB), to_y(p0), to_y(p1), p.h_eps, R0, d);
+    double gm0, gm1, gm2;  // face below the current row, as seen from above
+    double gm_speed = 0.0;
+    {
+        FaceOut gm = face(p.g, rprev.h_p, rprev.z_p, rprev.un_p, rprev.ut_p, rcur.h_m,
+                          rcur.z_m, rcur.un_m, rcur.ut_m, d);
+        if (STAGE == 1 && y0 == 0)
+            gm_speed = face_speed(p.g, rprev.h_p, rprev.un_p, rcur.h_m, rcur.un_m, d);
+        gm0 = gm.f0;
+        gm1 = gm.fr1;
+        gm2 = gm.f2;
+    }
+
+    for (int j = y0; j < y1; ++j) {
+        // the loads of row j+2 were issued one iteration ahead; issue j+3
+        Fetch<STAGE> f2 = fnext;
+        if (j + 1 < y1) fnext = fetch<STAGE>(m, io, j + 3, cs);
+        // stage 2: V_inf of the output row, loaded while the row is computed
+        double vi = 0.0;
+        if (STAGE == 2 && p.infil && out_col) vi = m.vinf[(size_t)j * p.nx + c];
+
+        // ---- y direction, all in registers ----
+        RawCell r2 = build<STAGE>(p, f2, sx, dt, d);
+        Recip R2 = d.rcp(r2.h);
+        Prim p2 = prim_x(r2, p.h_eps, R2, d);
+        note_cell(d, r2, p2);
+        d.settle();
+        Rec rnext = muscl(to_y(p0), to_y(p1), to_y(p2), p.h_eps, R1, d);
+        FaceOut gp = face(p.g, rcur.h_p, rcur.z_p, rcur.un_p, rcur.ut_p, rnext.h_m, rnext.z_m,
+                          rnext.un_m, rnext.ut_m, d);
+        double gp_speed = 0.0;
+        if (STAGE == 1)
+            gp_speed = face_speed(p.g, rcur.h_p, rcur.un_p, rnext.h_m, rnext.un_m, d);
+        d.settle();
+        double fcy = centred(p.g, rcur);
+        double Y0 = gp.f0 - gm0;
+        double Y1 = gp.fl1 - gm1 - fcy;  // normal momentum (qy)
+        double Y2 = gp.f2 - gm2;         // tangential momentum (qx)
+
+        // ---- x direction, neighbours through LDS ----
+        L.h[t] = p0.h;
+        L.u[t] = p0.un;
+        L.v[t] = p0.ut;
+        L.e[t] = p0.eta;
+        __syncthreads();
+        if (FAST && t == 0) {
+            L.bad[(j + 1) & 1] = 0;
+            if (j == y0) L.bad[j & 1] = 0;
+        }
+        Prim pl, pr;
+        pl.h = L.h[tl]; pl.un = L.u[tl]; pl.ut = L.v[tl]; pl.eta = L.e[tl];
+        pr.h = L.h[tr]; pr.un = L.u[tr]; pr.ut = L.v[tr]; pr.eta = L.e[tr];
+        Rec rx = muscl(pl, p0, pr, p.h_eps, R0, d);
+        L.hm[t] = rx.h_m;
+        L.zm[t] = rx.z_m;
+        L.unm[t] = rx.un_m;
+        L.utm[t] = rx.ut_m;
+        __syncthreads();
+        const double hm_r = L.hm[tr], zm_r = L.zm[tr], unm_r = L.unm[tr], utm_r = L.utm[tr];
+        FaceOut fp = face(p.g, rx.h_p, rx.z_p, rx.un_p, rx.ut_p, hm_r, zm_r, unm_r, utm_r, d);
+        double fp_speed = 0.0;
+        if (STAGE == 1) fp_speed = face_speed(p.g, rx.h_p, rx.un_p, hm_r, unm_r, d);
+        d.settle();
+        L.f0[t] = fp.f0;
+        L.f1[t] = fp.fr1;
+        L.f2[t] = fp.f2;
+        if (FAST && !d.ok()) L.bad[j & 1] = 1;
+        __syncthreads();
+        if (FAST && __builtin_amdgcn_readfirstlane(L.bad[j & 1]) != 0) return j;
+        double fm0 = L.f0[tl];
+        double fm1 = L.f1[tl];
+        double fm2 = L.f2[tl];
+
+        if (STAGE == 1) {
+            if (j == 0 && col_in) ay = fmax(ay, gm_speed);
+            if (col_in) ay = fmax(ay, gp_speed);
+            if (xface_ok) ax = fmax(ax, fp_speed);
+        }
+        double fcx = centred(p.g, rx);
+        double X0 = fp.f0 - fm0;
+        double X1 = fp.fl1 - fm1 - fcx;  // normal momentum (qx)
+        double X2 = fp.f2 - fm2;         // tangential momentum (qy)
+
+        if (out_col) {
+            // the rest of the row is lane-local: with FastDiv a lane whose
+            // bounds fail computes it again with IEEE division
+            double rh, rqx, rqy;
+            double h2 = 0.0, qx2 = 0.0, qy2 = 0.0;
+            auto tail = [&](auto& dv) {
+                if (p.dxy_pow2) {
+                    rh = -(X0 * p.inv_dx + Y0 * p.inv_dy);
+                    rqx = -(X1 * p.inv_dx + Y2 * p.inv_dy);
+                    rqy = -(X2 * p.inv_dx + Y1 * p.inv_dy);
+                } else {
+                    // |X|, |Y| < 2^253 follow from the face bounds
+                    dv.low2(X0, Y0);
+                    dv.low2(X1, Y2);
+                    dv.low2(X2, Y1);
+                    rh = -(dv.div(X0, Rdx) + dv.div(Y0, Rdy));
+                    rqx = -(dv.div(X1, Rdx) + dv.div(Y2, Rdy));
+                    rqy = -(dv.div(X2, Rdx) + dv.div(Y1, Rdy));
+                }
+                if (STAGE == 2) {
+                    // U** = friction(U* + dt Phi(U*)), stage input U*
+                    h2 = p0.h + dt * rh;
+                    qx2 = q0x + dt * rqx;
+                    qy2 = q0y + dt * rqy;
+                    friction(p, c0, p0.h, q0x, q0y, h2, qx2, qy2, dt, dv);
+                }
+            };
+            if (FAST) {
+                D lt;
+                tail(lt);
+                if (!lt.ok()) {
+                    ExactDiv ed;
+                    tail(ed);
+                }
+            } else {
+                tail(d);
+            }
+            size_t idx = (size_t)j * p.nx + c;
+            if (STAGE == 1) {
+                io.ph[idx] = rh;
+                io.pqx[idx] = rqx;
+                io.pqy[idx] = rqy;
+            } else {
+                // Heun: U^{n+1} = (U^n + U**)/2
+                double hn = 0.5 * (n0h + h2);
+                double qxn = 0.5 * (n0x + qx2);
+                double qyn = 0.5 * (n0y + qy2);
+                rain_infiltration(p, dt, hn, qxn, qyn, vi);
+                if (p.infil) m.vinf[idx] = vi;
+                io.ho[idx] = hn;
+                io.qxo[idx] = qxn;
+                io.qyo[idx] = qyn;
+                bool fin = (hn - hn) == 0.0 && (qxn - qxn) == 0.0 && (qyn - qyn) == 0.0;
+                if (!fin)
+                    atomicOr(&m.sc->status, (unsigned)SWE_FLAG_NONFINITE);
+                else if (hn < 0.0)
+                    atomicOr(&m.sc->status, (unsigned)SWE_FLAG_NEGDEPTH);
+            }
+        }
+
+        // ---- shift the rolling window ----
+        p0 = p1;
+        p1 = p2;
+        R0 = R1;
+        R1 = R2;
+        q0x = q1x; q0y = q1y;
+        q1x = r2.qx; q1y = r2.qy;
+        n0h = n1h; n0x = n1x; n0y = n1y;
+        n1h = f2.h; n1x = f2.qx; n1y = f2.qy;
+        c0 = c1;
+        c1 = f2.coef;
+        rcur = rnext;
+        gm0 = gp.f0;
+        gm1 = gp.fr1;
+        gm2 = gp.f2;
+    }
+    return y1;
+}
+
 // STAGE 1 (rate): Phi(U^n) to io.ph/pqx/pqy and the face wave-speed bounds
 // of eq. (cfl) into io.acc.  STAGE 2 (update): dt from the bounds, U* rebuilt
 // on the fly, Phi(U*), U** = friction(U* + dt Phi(U*)), Heun's average,
@@ -445,17 +859,10 @@ __device__ __forceinline__ void stage_tile(const MemberArgs& m, const TileIO& io
     constexpr int OUTW = TXT - 2 * HALO;
     const KParams& p = m.p;
     const int t = threadIdx.x;
-    const int x0 = strip * OUTW;
-    const int c = x0 - HALO + t;
+    const int c = strip * OUTW - HALO + t;
     const bool out_col = (t >= HALO) && (t < TXT - HALO) && (c < p.nx);
-    const bool col_in = (c >= 0) && (c < p.nx);
-    // a face c+1/2 computed by thread t has valid neighbour data when
-    // 1 <= t <= TXT-3; it is a real face when -1 <= c <= nx-1
-    const bool xface_ok = (t >= 1) && (t <= TXT - 3) && (c >= -1) && (c <= p.nx - 1);
 
-    __shared__ double s_h[TXT], s_u[TXT], s_v[TXT], s_e[TXT];
-    __shared__ double s_hm[TXT], s_zm[TXT], s_unm[TXT], s_utm[TXT];
-    __shared__ double s_f0[TXT], s_f1[TXT], s_f2[TXT];
+    __shared__ TileLds<TXT> L;
 
     double dt = 0.0;
     if (STAGE == 2) {
@@ -496,148 +903,10 @@ __device__ __forceinline__ void stage_tile(const MemberArgs& m, const TileIO& io
         }
     }
 
-    double sx;
-    const int cs = map_index(c, p.nx, p.bcw, p.bce, sx);
-
-    // --- prologue: rows y0-2 .. y0+1, face y0-1/2; prefetch row y0+2 -------
-    Fetch<STAGE> fA = fetch<STAGE>(m, io, y0 - 2, cs);
-    Fetch<STAGE> fB = fetch<STAGE>(m, io, y0 - 1, cs);
-    Fetch<STAGE> fC = fetch<STAGE>(m, io, y0, cs);
-    Fetch<STAGE> fD = fetch<STAGE>(m, io, y0 + 1, cs);
-    Fetch<STAGE> fnext = fetch<STAGE>(m, io, y0 + 2, cs);
-    RawCell rC = build<STAGE>(p, fC, sx, dt);
-    RawCell rD = build<STAGE>(p, fD, sx, dt);
-    Prim pA = prim_x(build<STAGE>(p, fA, sx, dt), p.h_eps);
-    Prim pB = prim_x(build<STAGE>(p, fB, sx, dt), p.h_eps);
-    Prim p0 = prim_x(rC, p.h_eps), p1 = prim_x(rD, p.h_eps);
-    // stage input discharges of rows j and j+1 (stage 2 needs them for U**)
-    double q0x = rC.qx, q0y = rC.qy, q1x = rD.qx, q1y = rD.qy;
-    // U^n of rows j and j+1 (stage 2: Heun's average)
-    double n0h = fC.h, n0x = fC.qx, n0y = fC.qy, n1h = fD.h, n1x = fD.qx, n1y = fD.qy;
-    double c0 = fC.coef, c1 = fD.coef;
-
-    Rec rprev = muscl(to_y(pA), to_y(pB), to_y(p0), p.h_eps);
-    Rec rcur = muscl(to_y(pB), to_y(p0), to_y(p1), p.h_eps);
     double ax = 0.0, ay = 0.0;
-    double gm0, gm1, gm2;  // face below the current row, as seen from above
-    {
-        FaceOut gm = face(p.g, rprev.h_p, rprev.z_p, rprev.un_p, rprev.ut_p, rcur.h_m,
-                          rcur.z_m, rcur.un_m, rcur.ut_m);
-        if (y0 == 0 && col_in) ay = gm.speed;
-        gm0 = gm.f0;
-        gm1 = gm.fr1;
-        gm2 = gm.f2;
-    }
-
-    for (int j = y0; j < y1; ++j) {
-        // the loads of row j+2 were issued one iteration ahead; issue j+3
-        Fetch<STAGE> f2 = fnext;
-        if (j + 1 < y1) fnext = fetch<STAGE>(m, io, j + 3, cs);
-
-        // ---- y direction, all in registers ----
-        RawCell r2 = build<STAGE>(p, f2, sx, dt);
-        Prim p2 = prim_x(r2, p.h_eps);
-        Rec rnext = muscl(to_y(p0), to_y(p1), to_y(p2), p.h_eps);
-        FaceOut gp = face(p.g, rcur.h_p, rcur.z_p, rcur.un_p, rcur.ut_p, rnext.h_m,
-                          rnext.z_m, rnext.un_m, rnext.ut_m);
-        if (STAGE == 1 && col_in) ay = fmax(ay, gp.speed);
-        double fcy = centred(p.g, rcur);
-        double Y0 = gp.f0 - gm0;
-        double Y1 = gp.fl1 - gm1 - fcy;  // normal momentum (qy)
-        double Y2 = gp.f2 - gm2;         // tangential momentum (qx)
-
-        // ---- x direction, neighbours through LDS ----
-        s_h[t] = p0.h;
-        s_u[t] = p0.un;
-        s_v[t] = p0.ut;
-        s_e[t] = p0.eta;
-        __syncthreads();
-        Prim pl, pr;
-        {
-            int tl = t > 0 ? t - 1 : t;
-            int tr = t < TXT - 1 ? t + 1 : t;
-            pl.h = s_h[tl]; pl.un = s_u[tl]; pl.ut = s_v[tl]; pl.eta = s_e[tl];
-            pr.h = s_h[tr]; pr.un = s_u[tr]; pr.ut = s_v[tr]; pr.eta = s_e[tr];
-        }
-        Rec rx = muscl(pl, p0, pr, p.h_eps);
-        s_hm[t] = rx.h_m;
-        s_zm[t] = rx.z_m;
-        s_unm[t] = rx.un_m;
-        s_utm[t] = rx.ut_m;
-        __syncthreads();
-        FaceOut fp;
-        {
-            int tr = t < TXT - 1 ? t + 1 : t;
-            fp = face(p.g, rx.h_p, rx.z_p, rx.un_p, rx.ut_p, s_hm[tr], s_zm[tr],
-                      s_unm[tr], s_utm[tr]);
-        }
-        if (STAGE == 1 && xface_ok) ax = fmax(ax, fp.speed);
-        s_f0[t] = fp.f0;
-        s_f1[t] = fp.fr1;
-        s_f2[t] = fp.f2;
-        __syncthreads();
-        double fm0, fm1, fm2;
-        {
-            int tl = t > 0 ? t - 1 : t;
-            fm0 = s_f0[tl];
-            fm1 = s_f1[tl];
-            fm2 = s_f2[tl];
-        }
-        double fcx = centred(p.g, rx);
-        double X0 = fp.f0 - fm0;
-        double X1 = fp.fl1 - fm1 - fcx;  // normal momentum (qx)
-        double X2 = fp.f2 - fm2;         // tangential momentum (qy)
-
-        double rh = -(X0 / p.dx + Y0 / p.dy);
-        double rqx = -(X1 / p.dx + Y2 / p.dy);
-        double rqy = -(X2 / p.dx + Y1 / p.dy);
-
-        if (out_col) {
-            size_t idx = (size_t)j * p.nx + c;
-            if (STAGE == 1) {
-                io.ph[idx] = rh;
-                io.pqx[idx] = rqx;
-                io.pqy[idx] = rqy;
-            } else {
-                // U** = friction(U* + dt Phi(U*)), stage input U*
-                double h2 = p0.h + dt * rh;
-                double qx2 = q0x + dt * rqx;
-                double qy2 = q0y + dt * rqy;
-                friction(p, c0, p0.h, q0x, q0y, h2, qx2, qy2, dt);
-                // Heun: U^{n+1} = (U^n + U**)/2
-                double hn = 0.5 * (n0h + h2);
-                double qxn = 0.5 * (n0x + qx2);
-                double qyn = 0.5 * (n0y + qy2);
-                double vi = 0.0;
-                if (p.infil) vi = m.vinf[idx];
-                rain_infiltration(p, dt, hn, qxn, qyn, vi);
-                if (p.infil) m.vinf[idx] = vi;
-                io.ho[idx] = hn;
-                io.qxo[idx] = qxn;
-                io.qyo[idx] = qyn;
-                bool fin = (hn - hn) == 0.0 && (qxn - qxn) == 0.0 && (qyn - qyn) == 0.0;
-                if (!fin)
-                    atomicOr(&m.sc->status, (unsigned)SWE_FLAG_NONFINITE);
-                else if (hn < 0.0)
-                    atomicOr(&m.sc->status, (unsigned)SWE_FLAG_NEGDEPTH);
-            }
-        }
-
-        // ---- shift the rolling window ----
-        p0 = p1;
-        p1 = p2;
-        q0x = q1x; q0y = q1y;
-        q1x = r2.qx; q1y = r2.qy;
-        n0h = n1h; n0x = n1x; n0y = n1y;
-        n1h = f2.h; n1x = f2.qx; n1y = f2.qy;
-        c0 = c1;
-        c1 = f2.coef;
-        rcur = rnext;
-        gm0 = gp.f0;
-        gm1 = gp.fr1;
-        gm2 = gp.f2;
-    }
-
+    int stop = y0;
+    if (p.fast_div) stop = march<STAGE, TXT, FastDiv>(m, io, strip, y0, y1, dt, ax, ay, L);
+    if (stop < y1) march<STAGE, TXT, ExactDiv>(m, io, strip, stop, y1, dt, ax, ay, L);
     if (STAGE == 1) block_max2<TXT>(ax, ay, io.acc);
 }
 

@@ -36,6 +36,15 @@ inline int check_params(const swe_params* p) {
     return SWE_OK;
 }
 
+// v = 2^k with a normal inverse: inv = 2^-k, and x / v == x * inv for every x
+inline bool exact_pow2(double v, double& inv) {
+    int e = 0;
+    double m = std::frexp(v, &e);
+    if (!(v > 0.0) || m != 0.5) return false;
+    inv = std::ldexp(1.0, 1 - e);
+    return std::isnormal(inv);
+}
+
 inline KParams to_kparams(const swe_params& p) {
     KParams k;
     k.nx = p.nx; k.ny = p.ny;
@@ -44,6 +53,13 @@ inline KParams to_kparams(const swe_params& p) {
     k.bcw = p.bc[0]; k.bce = p.bc[1]; k.bcs = p.bc[2]; k.bcn = p.bc[3];
     k.law = p.fric_law; k.coef = p.fric_coef; k.rain = p.rain;
     k.infil = p.infil_on; k.ks = p.ks; k.psi = p.psi; k.dtheta = p.dtheta;
+    double ix = 0.0, iy = 0.0;
+    k.dxy_pow2 = exact_pow2(p.dx, ix) && exact_pow2(p.dy, iy);
+    k.inv_dx = k.dxy_pow2 ? ix : 0.0;
+    k.inv_dy = k.dxy_pow2 ? iy : 0.0;
+    auto in = [](double v, double lo, double hi) { return v >= lo && v <= hi; };
+    k.fast_div = in(p.g, 0x1p-1074, 0x1p10) && in(p.dx, 0x1p-300, 0x1p300) &&
+                 in(p.dy, 0x1p-300, 0x1p300);
     return k;
 }
 
@@ -54,11 +70,12 @@ inline int strips_of(int nx, int tx) {
     return (nx + outw - 1) / outw;
 }
 
-// Rows per tile: enough tiles to fill 256 CUs several times over, at most
-// 64 rows (each tile re-reads two halo rows above and below).
+// Rows per tile: enough tiles to fill 256 CUs many times over (a short last
+// wave of tiles), at most 64 rows (each tile re-reads two halo rows above
+// and below).
 inline int auto_rows(int nx, int ny, int tx) {
     long long strips = strips_of(nx, tx);
-    long long ty = (strips * (long long)ny) / 4096;
+    long long ty = (strips * (long long)ny) / 8192;
     if (ty > 64) ty = 64;
     if (ty < 8) ty = 8;
     // keep the grid's y dimension within the launch limit

@@ -243,3 +243,53 @@ def test_invalid_arguments(torch_cuda):
         capi.swe_step(g.ctx, -1, 1.0)
     with pytest.raises(capi.SweError):
         capi.swe_set_rain(g.ctx, -1.0)
+
+
+# ---------------------------------------------------------------------------
+# Division paths.  The kernels share the reciprocal of a denominator among
+# its quotients while the operands stay inside a window where this gives the
+# division operator's value, and fall back to IEEE division for the rest of
+# a tile (or for one lane's tail) otherwise.  Each case forces one path and
+# must still match the oracle bit for bit (Darcy-Weisbach friction: every
+# operation correctly rounded on both sides).
+# ---------------------------------------------------------------------------
+
+def _fallback_case(case):
+    if case == "g_outside_window":
+        # g > 2^10: every tile uses IEEE division from its first row
+        return I.random_state(261, 77, seed=31, fric_law=2, fric_coef=0.3, g=2048.0)
+    if case == "tiny_depth_mid_tile":
+        # a wet cell of depth 1e-200 (h_eps = 0): the fast march of its tile
+        # stops two rows before it and the tile ends in IEEE division
+        wl = I.random_state(261, 150, seed=32, fric_law=2, fric_coef=0.3, h_eps=0.0)
+        wl.h[100, 50], wl.qx[100, 50], wl.qy[100, 50] = 1e-200, 3e-201, -2e-201
+        return wl
+    if case == "huge_bed":
+        wl = I.random_state(261, 150, seed=33, fric_law=2, fric_coef=0.3)
+        wl.z[70, 120] += 1e70
+        return wl
+    if case == "negative_depth":
+        wl = I.random_state(261, 150, seed=34, fric_law=2, fric_coef=0.3)
+        wl.h[60, 40] = -1e-3
+        return wl
+    if case == "non_pow2_cells":
+        return I.random_state(261, 150, seed=35, fric_law=2, fric_coef=0.3, dx=1.5, dy=0.7,
+                              rain=1e-3, infil_on=1, ks=1e-5, psi=0.1, dtheta=0.4)
+    raise ValueError(case)
+
+
+@pytest.mark.parametrize("case", ["g_outside_window", "tiny_depth_mid_tile", "huge_bed",
+                                  "negative_depth", "non_pow2_cells"])
+def test_division_paths(torch_cuda, case):
+    wl = _fallback_case(case)
+    wl.dt_max = 0.01
+    say(f"[division] {case}")
+    s = oracle.State(wl)
+    s.run(1)
+    g = gpu_solver(wl, dt_log=1)
+    g.step(1)
+    st = g.state()
+    for k in ("h", "qx", "qy"):
+        assert np.array_equal(st[k], getattr(s, k)), k
+    assert np.array_equal(g.dts(), np.array(s.dts))
+    g.close()
