@@ -620,13 +620,16 @@ __device__ void block_max2(double ax, double ay, unsigned long long* dst) {
 // ---------------------------------------------------------------------------
 
 template <int TXT> struct TileLds {
-    double h[TXT], u[TXT], v[TXT], e[TXT];       // primitives of row j
+    double h[2][TXT], u[2][TXT], v[2][TXT], e[2][TXT];  // primitives of row j (j & 1)
     double hm[TXT], zm[TXT], unm[TXT], utm[TXT];  // x-reconstruction, face i-1/2 side
     double f0[TXT], f1[TXT], f2[TXT];             // x-fluxes
     int bad[2];                                   // operand bounds broken in row j (j & 1)
 };
 
 // March rows y0 .. y1-1 of a tile with division policy D (see Division).
+// Two barriers per row: the primitives of row j+1 go to LDS (buffer
+// (j+1) & 1) together with the x-fluxes of row j, before the second
+// barrier of row j, so the reconstruction of row j+1 finds them there.
 // With FastDiv a lane that finds its bounds broken in row j raises
 // L.bad[j & 1] before the row's last barrier; every lane reads the flag
 // after it and the march returns j before anything of row j is stored, for
@@ -698,6 +701,17 @@ __device__ __forceinline__ int march(const MemberArgs& m, const TileIO& io, int 
         gm2 = gm.f2;
     }
 
+    // primitives of row y0 for the x-reconstruction of the first row
+    L.h[y0 & 1][t] = p0.h;
+    L.u[y0 & 1][t] = p0.un;
+    L.v[y0 & 1][t] = p0.ut;
+    L.e[y0 & 1][t] = p0.eta;
+    if (FAST && t == 0) {
+        L.bad[0] = 0;
+        L.bad[1] = 0;
+    }
+    __syncthreads();
+
     for (int j = y0; j < y1; ++j) {
         // the loads of row j+2 were issued one iteration ahead; issue j+3
         Fetch<STAGE> f2 = fnext;
@@ -725,24 +739,17 @@ __device__ __forceinline__ int march(const MemberArgs& m, const TileIO& io, int 
         double Y2 = gp.f2 - gm2;         // tangential momentum (qx)
 
         // ---- x direction, neighbours through LDS ----
-        L.h[t] = p0.h;
-        L.u[t] = p0.un;
-        L.v[t] = p0.ut;
-        L.e[t] = p0.eta;
-        __syncthreads();
-        if (FAST && t == 0) {
-            L.bad[(j + 1) & 1] = 0;
-            if (j == y0) L.bad[j & 1] = 0;
-        }
+        const int b = j & 1;
         Prim pl, pr;
-        pl.h = L.h[tl]; pl.un = L.u[tl]; pl.ut = L.v[tl]; pl.eta = L.e[tl];
-        pr.h = L.h[tr]; pr.un = L.u[tr]; pr.ut = L.v[tr]; pr.eta = L.e[tr];
+        pl.h = L.h[b][tl]; pl.un = L.u[b][tl]; pl.ut = L.v[b][tl]; pl.eta = L.e[b][tl];
+        pr.h = L.h[b][tr]; pr.un = L.u[b][tr]; pr.ut = L.v[b][tr]; pr.eta = L.e[b][tr];
         Rec rx = muscl(pl, p0, pr, p.h_eps, R0, d);
         L.hm[t] = rx.h_m;
         L.zm[t] = rx.z_m;
         L.unm[t] = rx.un_m;
         L.utm[t] = rx.ut_m;
         __syncthreads();
+        if (FAST && t == 0) L.bad[(j + 1) & 1] = 0;
         const double hm_r = L.hm[tr], zm_r = L.zm[tr], unm_r = L.unm[tr], utm_r = L.utm[tr];
         FaceOut fp = face(p.g, rx.h_p, rx.z_p, rx.un_p, rx.ut_p, hm_r, zm_r, unm_r, utm_r, d);
         double fp_speed = 0.0;
@@ -751,6 +758,10 @@ __device__ __forceinline__ int march(const MemberArgs& m, const TileIO& io, int 
         L.f0[t] = fp.f0;
         L.f1[t] = fp.fr1;
         L.f2[t] = fp.f2;
+        L.h[b ^ 1][t] = p1.h;
+        L.u[b ^ 1][t] = p1.un;
+        L.v[b ^ 1][t] = p1.ut;
+        L.e[b ^ 1][t] = p1.eta;
         if (FAST && !d.ok()) L.bad[j & 1] = 1;
         __syncthreads();
         if (FAST && __builtin_amdgcn_readfirstlane(L.bad[j & 1]) != 0) return j;
