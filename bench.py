@@ -16,7 +16,6 @@ bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import math
 import os
@@ -29,8 +28,10 @@ if ROOT not in sys.path:
 
 METRIC = "cell-updates/s (FP64) + % HBM roofline; ensemble & adjoint vs plain, same GPU"
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
-CSRC = os.path.join(ROOT, "paper_1307_4839_amd", "csrc")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_hillslope_8192.json")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "counters_hillslope_8192.json")
+# FP64 VALU issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one lane-op per
+# lane per cycle; the vendor 78.6 TFLOP/s counts an FMA as two)
+VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 
 
 def algorithmic_bytes(wl):
@@ -49,30 +50,18 @@ def algorithmic_bytes(wl):
     return rate, upd
 
 
-def kernel_hash():
-    """Hash of the HIP sources the stage kernels are built from."""
-    h = hashlib.sha256()
-    for name in sorted(os.listdir(CSRC)):
-        with open(os.path.join(CSRC, name), "rb") as f:
-            h.update(name.encode())
-            h.update(f.read())
-    return h.hexdigest()[:16]
-
-
-def load_traffic(kernel_name):
-    """Measured HBM bytes per launch from the committed PMC summary, if it was
-    taken on the current kernel source."""
+def load_counters():
+    """Counters measured on the current kernel sources (committed summary of
+    rocprofv3 runs of this benchmark), or None."""
+    from paper_1307_4839_amd.build import source_hash
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(COUNTERS_FILE) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_sha256_16") != kernel_hash():
+    if rec.get("kernel_sha256_16") != source_hash():
         return None
-    k = rec.get("kernels", {}).get(kernel_name)
-    if not k:
-        return None
-    return k.get("bytes_per_launch")
+    return rec
 
 
 def cpu_baseline(wl, rows, steps):
@@ -221,9 +210,6 @@ def main(argv=None):
     ap.add_argument("--adjoint-steps", type=int, default=2000)
     ap.add_argument("--ensemble-members", type=int, default=256)
     ap.add_argument("--ensemble-steps", type=int, default=500)
-    ap.add_argument("--probe-copy-mib", type=int, default=0,
-                    help="after the run, copy a float64 tensor of this many MiB once "
-                         "(a plain copy of known size that calibrates byte counters)")
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
@@ -288,25 +274,51 @@ def main(argv=None):
     }
     dom = "update" if avg_upd >= avg_rate else "rate"
     kname = "stage_kernel<2>" if dom == "update" else "stage_kernel<1>"
+    tx, ty = g.tiling()
     ach = kern[dom]["GBps"]
-    traffic = load_traffic(kname)
+    # measured HBM bytes and VALU instructions per launch (rocprofv3 counters
+    # committed under profiles/, used only when taken on these kernel sources)
+    traffic, alu = None, None
+    cnt = load_counters()
+    if cnt and kname in cnt["kernels"]:
+        kc = cnt["kernels"][kname]
+        traffic = round(kc["bytes_per_launch"])
+        sq = kc.get("sq", {})
+        if "SQ_INSTS_VALU" in sq:
+            for key, avg in (("rate", avg_rate), ("update", avg_upd)):
+                kk = "stage_kernel<1>" if key == "rate" else "stage_kernel<2>"
+                sqk = cnt["kernels"].get(kk, {}).get("sq", {})
+                if "SQ_INSTS_VALU" in sqk:
+                    lane_ops = sqk["SQ_INSTS_VALU"] * 64
+                    kern[key]["valu_lane_ops_per_cell"] = lane_ops / cells
+                    kern[key]["valu_frac"] = lane_ops / (avg / 1e3) / VALU_PEAK_LANE_OPS
+            lane_ops = sq["SQ_INSTS_VALU"] * 64
+            a_ops = lane_ops / (kern[dom]["avg_ms"] / 1e3)
+            alu = {"bound": "alu", "achieved": a_ops, "peak": VALU_PEAK_LANE_OPS,
+                   "unit": "FP64 VALU lane-op/s", "frac": round(a_ops / VALU_PEAK_LANE_OPS, 4),
+                   "kernel": kname, "lane_ops_per_launch": lane_ops}
     roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "kernel": kname,
+                "traffic": traffic, "kernel": kname, "tile": [tx, ty],
                 "algorithmic_bytes_per_launch": kern[dom]["bytes_per_cell"] * cells}
     step_bytes = (b_rate + b_upd) * cells
     print(f"[bench] kernels: {json.dumps(kern)}", file=sys.stderr, flush=True)
 
-    if args.probe_copy_mib:
-        n = args.probe_copy_mib * (1 << 20) // 8
-        src = torch.ones(n, dtype=torch.float64, device="cuda:0")
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
+    # achievable HBM bandwidth: a plain 1 GiB device copy, best of 5
+    n = (1 << 30) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    best = math.inf
+    for _ in range(5):
+        e0.record()
         dst.copy_(src)
+        e1.record()
         torch.cuda.synchronize()
-        print(f"[bench] probe copy of {args.probe_copy_mib} MiB done", file=sys.stderr,
-              flush=True)
-        del src, dst
+        best = min(best, e0.elapsed_time(e1))
+    copy_gbps = 2 * (1 << 30) / (best / 1e3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    print(f"[bench] 1 GiB device copy: {copy_gbps:.0f} GB/s", file=sys.stderr, flush=True)
 
     ens = None
     if not args.no_ensemble:
@@ -350,6 +362,8 @@ def main(argv=None):
         "step_algorithmic_bytes": step_bytes,
         "kernels": kern,
         "roofline": roofline,
+        "alu_roofline": alu,
+        "hbm_copy_GBps": round(copy_gbps, 1),
         "cpu_baseline": cpu,
         "ensemble": ens,
         "adjoint": adj,

@@ -33,6 +33,18 @@ HIPCC_FLAGS = [
 ]
 
 
+def source_hash() -> str:
+    """Short hash of the HIP sources and headers the kernels are built from
+    (names and contents), used to tie measured counters to a kernel version."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(name.encode())
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
 def hipcc() -> str:
     for cand in (shutil.which("hipcc"), "/opt/rocm/bin/hipcc"):
         if cand and os.path.exists(cand):

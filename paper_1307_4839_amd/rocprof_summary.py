@@ -1,21 +1,43 @@
-"""Summarise a rocprofv3 kernel trace (rocpd SQLite output) per kernel.
+"""Summaries of rocprofv3 output (rocpd SQLite databases) for the stage kernels.
 
-    python -m paper_1307_4839_amd.rocprof_summary RESULTS.db [--skip NAME=K ...]
+    python -m paper_1307_4839_amd.rocprof_summary trace RESULTS.db [--skip NAME=K ...]
 
-Prints, per kernel name: dispatch count, total and average duration over all
-dispatches, and the average over the dispatches left after skipping the
-first K dispatches of that kernel (``--skip``), e.g. the warmup steps of a
-benchmark whose timed region starts after them.
+per kernel name: dispatch count, total and average duration over all
+dispatches, and the average over the dispatches left after skipping the first
+K dispatches of that kernel (``--skip``), e.g. the warmup steps of a benchmark
+whose timed region starts after them.
+
+    python -m paper_1307_4839_amd.rocprof_summary counters --fetch DB --write DB \\
+        [--sq DB] --skip K --cells N --bytes1 B1 --bytes2 B2 --json OUT.json
+
+per stage kernel: FETCH_SIZE and WRITE_SIZE (KiB per dispatch) averaged over
+the dispatches after the first K, scaled by what the same counters read for
+the plain device copy in the same runs (the largest __amd_rocclr_copyBuffer
+dispatch, of known size 2^30 bytes each way), next to the algorithmic bytes
+per launch (B1, B2 bytes per cell times N cells); with --sq, the SQ counters
+of a third run (VALU and SALU instructions, waves).  The JSON carries the
+hash of the kernel sources so that a benchmark reads it only for the kernels
+it was taken on.
 """
 
 from __future__ import annotations
 
 import argparse
+import json
 import sqlite3
 import sys
 
+COPY_BYTES = 1 << 30
 
-def summarize(db: str, skip: dict) -> str:
+
+def _stage(name: str) -> str | None:
+    for s in ("1", "2"):
+        if f"stage_kernel<{s}" in name:
+            return f"stage_kernel<{s}>"
+    return None
+
+
+def trace(db: str, skip: dict) -> str:
     con = sqlite3.connect(db)
     rows = con.execute("select name, start, duration from kernels order by start").fetchall()
     per = {}
@@ -37,17 +59,127 @@ def summarize(db: str, skip: dict) -> str:
     return "\n".join(out)
 
 
+def _counters(db: str):
+    """{kernel name: [(dispatch id, {counter: value}), ...]} in dispatch order."""
+    con = sqlite3.connect(db)
+    rows = con.execute("select name, dispatch_id, counter_name, sum(counter_value) "
+                       "from pmc_events group by dispatch_id, counter_name").fetchall()
+    per = {}
+    for name, did, cn, v in rows:
+        per.setdefault(name, {}).setdefault(did, {})[cn] = v
+    return {n: sorted(d.items()) for n, d in per.items()}
+
+
+def _stage_avgs(db: str, skip: int):
+    out = {}
+    for name, disp in _counters(db).items():
+        st = _stage(name)
+        if st is None:
+            continue
+        rest = [c for _, c in disp[skip:]]
+        if not rest:
+            continue
+        keys = set().union(*[c.keys() for c in rest])
+        out[st] = {k: sum(c.get(k, 0.0) for c in rest) / len(rest) for k in keys}
+        out[st]["_name"] = name
+        out[st]["_dispatches"] = len(rest)
+    return out
+
+
+def _copy_counter(db: str, counter: str) -> float:
+    best = 0.0
+    for name, disp in _counters(db).items():
+        if "copyBuffer" in name:
+            for _, c in disp:
+                best = max(best, c.get(counter, 0.0))
+    if best <= 0.0:
+        raise SystemExit(f"{db}: no copy dispatch with {counter} to calibrate against")
+    return best
+
+
+def counters(a) -> dict:
+    from .build import source_hash
+    fetch = _stage_avgs(a.fetch, a.skip)
+    write = _stage_avgs(a.write, a.skip)
+    cf = _copy_counter(a.fetch, "FETCH_SIZE")
+    cw = _copy_counter(a.write, "WRITE_SIZE")
+    ff = COPY_BYTES / 1024.0 / cf
+    fw = COPY_BYTES / 1024.0 / cw
+    sq = _stage_avgs(a.sq, a.skip) if a.sq else {}
+    rec = {"kernel_sha256_16": source_hash(), "workload": a.workload, "cells": a.cells,
+           "calibration": {"probe": "1 GiB device-to-device copy (__amd_rocclr_copyBuffer)",
+                           "fetch_KiB": cf, "write_KiB": cw,
+                           "fetch_factor": ff, "write_factor": fw},
+           "kernels": {}}
+    for st, bpc in (("stage_kernel<1>", a.bytes1), ("stage_kernel<2>", a.bytes2)):
+        if st not in fetch or st not in write:
+            continue
+        fk, wk = fetch[st]["FETCH_SIZE"], write[st]["WRITE_SIZE"]
+        fb, wb = fk * 1024.0 * ff, wk * 1024.0 * fw
+        alg = bpc * a.cells
+        k = {"name": fetch[st]["_name"], "dispatches": fetch[st]["_dispatches"],
+             "fetch_KiB_raw": fk, "write_KiB_raw": wk,
+             "fetch_bytes": fb, "write_bytes": wb, "bytes_per_launch": fb + wb,
+             "algorithmic_bytes_per_launch": alg,
+             "traffic_over_algorithmic": (fb + wb) / alg}
+        if st in sq:
+            k["sq"] = {kk: v for kk, v in sq[st].items() if not kk.startswith("_")}
+        rec["kernels"][st] = k
+    return rec
+
+
+def counters_text(rec: dict) -> str:
+    c = rec["calibration"]
+    out = [f"calibration: the 1 GiB copy reads FETCH_SIZE = {c['fetch_KiB']:.0f} KiB and "
+           f"WRITE_SIZE = {c['write_KiB']:.0f} KiB for 1048576 KiB moved each way: "
+           f"fetch x{c['fetch_factor']:.4f}, write x{c['write_factor']:.4f}"]
+    for st, k in rec["kernels"].items():
+        out.append(f"{st:<16} FETCH {k['fetch_KiB_raw']:>12.0f} KiB ({k['fetch_bytes'] / 1e9:.3f} GB)"
+                   f"  WRITE {k['write_KiB_raw']:>12.0f} KiB ({k['write_bytes'] / 1e9:.3f} GB)"
+                   f"  total {k['bytes_per_launch'] / 1e9:.3f} GB  algorithmic "
+                   f"{k['algorithmic_bytes_per_launch'] / 1e9:.3f} GB  ratio "
+                   f"{k['traffic_over_algorithmic']:.3f}")
+        if "sq" in k:
+            sq = k["sq"]
+            waves = sq.get("SQ_WAVES", 0.0)
+            line = "   SQ: " + "  ".join(f"{kk}={v:.4g}" for kk, v in sorted(sq.items()))
+            out.append(line)
+            if "SQ_INSTS_VALU" in sq and rec["cells"]:
+                out.append(f"   VALU wave-instructions x 64 lanes per cell: "
+                           f"{sq['SQ_INSTS_VALU'] * 64 / rec['cells']:.1f}")
+    return "\n".join(out)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("db")
-    ap.add_argument("--skip", action="append", default=[],
-                    help="NAME=K: ignore the first K dispatches of kernels matching NAME")
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    t = sub.add_parser("trace")
+    t.add_argument("db")
+    t.add_argument("--skip", action="append", default=[],
+                   help="NAME=K: ignore the first K dispatches of kernels matching NAME")
+    c = sub.add_parser("counters")
+    c.add_argument("--fetch", required=True)
+    c.add_argument("--write", required=True)
+    c.add_argument("--sq")
+    c.add_argument("--skip", type=int, default=0)
+    c.add_argument("--cells", type=int, required=True)
+    c.add_argument("--bytes1", type=int, required=True)
+    c.add_argument("--bytes2", type=int, required=True)
+    c.add_argument("--workload", default="")
+    c.add_argument("--json")
     a = ap.parse_args(argv)
-    skip = {}
-    for s in a.skip:
-        k, v = s.split("=")
-        skip[k] = int(v)
-    print(summarize(a.db, skip))
+    if a.cmd == "trace":
+        skip = {}
+        for s in a.skip:
+            k, v = s.rsplit("=", 1)
+            skip[k] = int(v)
+        print(trace(a.db, skip))
+        return 0
+    rec = counters(a)
+    if a.json:
+        with open(a.json, "w") as f:
+            json.dump(rec, f, indent=1)
+    print(counters_text(rec))
     return 0
 
 
