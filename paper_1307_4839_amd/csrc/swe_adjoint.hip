@@ -433,8 +433,10 @@ __global__ __launch_bounds__(T1) void adj_face_kernel(AdjArgs a, const double* _
     const int nx = p.nx, ny = p.ny;
     const int n_along = DIR == 0 ? nx : ny;
     const int n_across = DIR == 0 ? ny : nx;
-    const int f = blockIdx.x * T1 + threadIdx.x;
-    const int line = blockIdx.y;
+    // consecutive threads take consecutive columns in both directions, so
+    // every load and store of a wave is one contiguous run of a row
+    const int f = DIR == 0 ? (int)(blockIdx.x * T1 + threadIdx.x) : (int)blockIdx.y;
+    const int line = DIR == 0 ? (int)blockIdx.y : (int)(blockIdx.x * T1 + threadIdx.x);
     if (f > n_along || line >= n_across) return;
     double out[12];
     face_contrib<DIR>(p, a.z, h, qx, qy, mu_h, mu_qx, mu_qy, f, line, out);
@@ -672,6 +674,7 @@ struct swe_adj {
     double* seg;           // device, (ckpt + 1) x 3N
     double* ust;           // U* (3N)
     double* phi;           // Phi (3N)
+    double* phi0;          // Phi(U^k) kept for the reverse of stage 1 (3N)
     double* lamA;          // lambda of U^n (3N)
     double* lamB;          // lambda of U* (3N)
     double* lam;           // lambda of U^{n+1} (3N)
@@ -690,7 +693,7 @@ size_t adj_bytes(const swe_params* p, int nsteps, int ckpt, int ngauges, int eve
                    align256(12 * (size_t)(p->ny + 1) * p->nx * sizeof(double));
     return 256 + 256 + align256(nsteps * sizeof(double)) +
            align256(rows * (size_t)ngauges * sizeof(double)) + 3 * an * nck +
-           3 * an * (ckpt + 1) + 3 * an * 6 + faces;
+           3 * an * (ckpt + 1) + 3 * an * 7 + faces;
 }
 
 inline double* plane(double* base, size_t n, int k) { return base + (size_t)k * n; }
@@ -717,15 +720,15 @@ void fwd_step(swe_adj* A, const double* h, const double* qx, const double* qy, d
     hipLaunchKernelGGL(fwd_stage_kernel<2>, grid, dim3(256), 0, A->stream, m, io, ty);
 }
 
-// Phi(U) into A->phi (stage 1 kernel with a scratch accumulator).
-void rate_into(swe_adj* A, const double* h, const double* qx, const double* qy) {
+// Phi(U) into dst (stage 1 kernel with a scratch accumulator).
+void rate_into(swe_adj* A, const double* h, const double* qx, const double* qy, double* dst) {
     MemberArgs m = A->m;
     TileIO io;
     std::memset(&io, 0, sizeof io);
     io.h = h; io.qx = qx; io.qy = qy;
-    io.ph = plane(A->phi, A->n, 0);
-    io.pqx = plane(A->phi, A->n, 1);
-    io.pqy = plane(A->phi, A->n, 2);
+    io.ph = plane(dst, A->n, 0);
+    io.pqx = plane(dst, A->n, 1);
+    io.pqy = plane(dst, A->n, 2);
     io.acc = m.sc->amax[2];
     io.clr = nullptr;
     io.slot = 2;
@@ -743,7 +746,7 @@ void vjp_rate(swe_adj* A, const double* h, const double* qx, const double* qy, d
     hipLaunchKernelGGL(adj_face_kernel<0>, dim3((nx + 1 + T1 - 1) / T1, ny), dim3(T1), 0,
                        A->stream, A->aa, h, qx, qy, (const double*)plane(mu, n, 0),
                        (const double*)plane(mu, n, 1), (const double*)plane(mu, n, 2));
-    hipLaunchKernelGGL(adj_face_kernel<1>, dim3((ny + 1 + T1 - 1) / T1, nx), dim3(T1), 0,
+    hipLaunchKernelGGL(adj_face_kernel<1>, dim3((nx + T1 - 1) / T1, ny + 1), dim3(T1), 0,
                        A->stream, A->aa, h, qx, qy, (const double*)plane(mu, n, 0),
                        (const double*)plane(mu, n, 1), (const double*)plane(mu, n, 2));
     hipLaunchKernelGGL(adj_gather_kernel, dim3((nx + T1 - 1) / T1, ny), dim3(T1), 0, A->stream,
@@ -757,11 +760,11 @@ void adj_step(swe_adj* A, const double* Uk, double dt, double* grad) {
     const double* qx = Uk + n;
     const double* qy = Uk + 2 * n;
     double* us = A->ust;
-    // recompute Phi(U^k) and U*
-    rate_into(A, h, qx, qy);
+    // recompute Phi(U^k) (kept for stage 1) and U*
+    rate_into(A, h, qx, qy, A->phi0);
     hipLaunchKernelGGL(stage_out_kernel, dim3(blocks(n)), dim3(T1), 0, A->stream, A->m.p,
-                       A->m.fric, h, qx, qy, (const double*)plane(A->phi, n, 0),
-                       (const double*)plane(A->phi, n, 1), (const double*)plane(A->phi, n, 2),
+                       A->m.fric, h, qx, qy, (const double*)plane(A->phi0, n, 0),
+                       (const double*)plane(A->phi0, n, 1), (const double*)plane(A->phi0, n, 2),
                        dt, plane(us, n, 0), plane(us, n, 1), plane(us, n, 2), n);
     // Heun: lam_n = lam/2
     hipLaunchKernelGGL(half_kernel, dim3(blocks(n)), dim3(T1), 0, A->stream,
@@ -770,7 +773,7 @@ void adj_step(swe_adj* A, const double* Uk, double dt, double* grad) {
                        plane(A->lamA, n, 1), plane(A->lamA, n, 2), n);
     // stage 2 on U*: Phi(U*), then its friction reversed with output
     // adjoint lam/2
-    rate_into(A, plane(us, n, 0), plane(us, n, 1), plane(us, n, 2));
+    rate_into(A, plane(us, n, 0), plane(us, n, 1), plane(us, n, 2), A->phi);
     hipLaunchKernelGGL(adj_stage_kernel, dim3(blocks(n)), dim3(T1), 0, A->stream, A->m.p,
                        A->m.fric, (const double*)plane(us, n, 0), (const double*)plane(us, n, 1),
                        (const double*)plane(us, n, 2), (const double*)plane(A->phi, n, 0),
@@ -780,12 +783,11 @@ void adj_step(swe_adj* A, const double* Uk, double dt, double* grad) {
                        plane(A->lamB, n, 1), plane(A->lamB, n, 2), 0, plane(A->mu, n, 0),
                        plane(A->mu, n, 1), plane(A->mu, n, 2), grad, n);
     vjp_rate(A, plane(us, n, 0), plane(us, n, 1), plane(us, n, 2), A->lamB);
-    // stage 1 on U^k: Phi(U^k) again, friction reversed with output adjoint
-    // lamB, accumulated into lamA
-    rate_into(A, h, qx, qy);
+    // stage 1 on U^k (Phi(U^k) kept above): friction reversed with output
+    // adjoint lamB, accumulated into lamA
     hipLaunchKernelGGL(adj_stage_kernel, dim3(blocks(n)), dim3(T1), 0, A->stream, A->m.p,
-                       A->m.fric, h, qx, qy, (const double*)plane(A->phi, n, 0),
-                       (const double*)plane(A->phi, n, 1), (const double*)plane(A->phi, n, 2), dt,
+                       A->m.fric, h, qx, qy, (const double*)plane(A->phi0, n, 0),
+                       (const double*)plane(A->phi0, n, 1), (const double*)plane(A->phi0, n, 2), dt,
                        (const double*)plane(A->lamB, n, 0), (const double*)plane(A->lamB, n, 1),
                        (const double*)plane(A->lamB, n, 2), 1.0, plane(A->lamA, n, 0),
                        plane(A->lamA, n, 1), plane(A->lamA, n, 2), 1, plane(A->mu, n, 0),
@@ -859,6 +861,7 @@ int swe_adj_create(const swe_params* p, const swe_buffers* b, int32_t nsteps,
     A->seg = (double*)w; w += 3 * an * (ckpt_every + 1);
     A->ust = (double*)w; w += 3 * an;
     A->phi = (double*)w; w += 3 * an;
+    A->phi0 = (double*)w; w += 3 * an;
     A->lamA = (double*)w; w += 3 * an;
     A->lamB = (double*)w; w += 3 * an;
     A->lam = (double*)w; w += 3 * an;
