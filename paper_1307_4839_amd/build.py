@@ -33,14 +33,19 @@ HIPCC_FLAGS = [
 ]
 
 
+# the files the stage kernels of the single-simulation library are built from
+STAGE_SOURCES = [os.path.join(CSRC, f) for f in ("swe_device.h", "swe_host.h", "swe_step.hip")] + [
+    os.path.join(INCLUDE, "swe.h")]
+
+
 def source_hash() -> str:
-    """Short hash of the HIP sources and headers the kernels are built from
-    (names and contents), used to tie measured counters to a kernel version."""
+    """Short hash of the sources of the stage kernels (names and contents),
+    which ties measured counters to a kernel version."""
     import hashlib
     h = hashlib.sha256()
-    for name in sorted(os.listdir(CSRC)):
-        with open(os.path.join(CSRC, name), "rb") as f:
-            h.update(name.encode())
+    for path in STAGE_SOURCES:
+        with open(path, "rb") as f:
+            h.update(os.path.basename(path).encode())
             h.update(f.read())
     return h.hexdigest()[:16]
 
