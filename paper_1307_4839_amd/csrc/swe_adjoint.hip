@@ -76,16 +76,18 @@ __host__ __device__ __forceinline__ void zero(RecBar& r) {
     r.h_m = r.h_p = r.z_m = r.z_p = r.un_m = r.un_p = r.ut_m = r.ut_p = 0.0;
 }
 
-// d(minmod(x, y)) routed back to s_c - s_a = x and s_b - s_c = y
+// d(minmod(x, y)) routed back to s_c - s_a = x and s_b - s_c = y.  Written
+// without branches: a conditional update of one of three references becomes
+// a select between their addresses, which keeps the adjoints in scratch
+// memory.  Adding an exact zero to the slots not selected changes no value
+// (at most the sign of a zero).
 __host__ __device__ __forceinline__ void route_minmod(int sel, double bar, double& abar, double& cbar,
                                              double& bbar) {
-    if (sel == 1) {
-        cbar += bar;
-        abar -= bar;
-    } else if (sel == 2) {
-        bbar += bar;
-        cbar -= bar;
-    }
+    const double x = sel == 1 ? bar : 0.0;  // through s_c - s_a
+    const double y = sel == 2 ? bar : 0.0;  // through s_b - s_c
+    cbar += x - y;
+    abar -= x;
+    bbar += y;
 }
 
 // Reverse of muscl(a, c, b): adds the adjoints of the three primitive
@@ -351,6 +353,7 @@ __host__ __device__ __forceinline__ void face_contrib(const KParams& p, const do
     RawCell r[4];
     Prim pr[4];
     double sgn[4];
+    #pragma unroll
     for (int k = 0; k < 4; ++k) {
         int pos = f - 2 + k;
         if (DIR == 0) {
@@ -402,9 +405,11 @@ __host__ __device__ __forceinline__ void face_contrib(const KParams& p, const do
     // centred source of the left cell: X1 = ... - fc
     if (L_real) centred_rev(p.g, RL, -bL[1], RLb);
     PrimBar pb[4];
+    #pragma unroll
     for (int k = 0; k < 4; ++k) zero(pb[k]);
     muscl_rev(pr[0], pr[1], pr[2], p.h_eps, RLb, pb[0], pb[1], pb[2]);
     muscl_rev(pr[1], pr[2], pr[3], p.h_eps, RRb, pb[1], pb[2], pb[3]);
+    #pragma unroll
     for (int k = 0; k < 4; ++k) {
         PrimBar xb = pb[k];
         if (DIR == 1) {  // back to the x view of the primitives
@@ -443,6 +448,7 @@ __global__ __launch_bounds__(T1) void adj_face_kernel(AdjArgs a, const double* _
     const size_t plane = DIR == 0 ? (size_t)ny * (nx + 1) : (size_t)(ny + 1) * nx;
     const size_t fidx = DIR == 0 ? (size_t)line * (nx + 1) + f : (size_t)f * nx + line;
     double* buf = DIR == 0 ? a.xc : a.yc;
+    #pragma unroll
     for (int k = 0; k < 12; ++k) buf[(size_t)k * plane + fidx] = out[k];
 }
 

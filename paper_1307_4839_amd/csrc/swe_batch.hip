@@ -40,7 +40,9 @@ __global__ __launch_bounds__(TXT) void batch_stage_kernel(const MemberArgs* __re
                                                           double t_end) {
     for (int k = blockIdx.x; k < ntiles; k += gridDim.x) {
         const int4 tl = tiles[k];  // member, strip, first row, end row
-        const MemberArgs m = ms[tl.x];
+        // read in place (uniform loads): a private copy of the record would
+        // live in scratch memory, since its buffer pairs are indexed by phase
+        const MemberArgs& m = ms[tl.x];
         const TileIO io = step_io(m, phase, slot, t_end);
         stage_tile<STAGE, TXT>(m, io, tl.y, tl.z, tl.w, tl.y == 0 && tl.z == 0);
     }
