@@ -619,6 +619,22 @@ __device__ void block_max2(double ax, double ay, unsigned long long* dst) {
 // One tile through one stage
 // ---------------------------------------------------------------------------
 
+// Neighbour exchange inside one wave64 (tiles one wave wide): the value of
+// lane t-1 (lane 0 keeps its own) and of lane t+1 (lane 63 keeps its own),
+// moved by the full-wave DPP shifts.
+__device__ __forceinline__ double from_left(double v) {
+    int lo = __double2loint(v), hi = __double2hiint(v);
+    lo = __builtin_amdgcn_update_dpp(lo, lo, 0x138, 0xf, 0xf, false);  // wave_shr:1
+    hi = __builtin_amdgcn_update_dpp(hi, hi, 0x138, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double from_right(double v) {
+    int lo = __double2loint(v), hi = __double2hiint(v);
+    lo = __builtin_amdgcn_update_dpp(lo, lo, 0x130, 0xf, 0xf, false);  // wave_shl:1
+    hi = __builtin_amdgcn_update_dpp(hi, hi, 0x130, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
 template <int TXT> struct TileLds {
     double h[2][TXT], u[2][TXT], v[2][TXT], e[2][TXT];  // primitives of row j (j & 1)
     double hm[TXT], zm[TXT], unm[TXT], utm[TXT];  // x-reconstruction, face i-1/2 side
@@ -627,9 +643,11 @@ template <int TXT> struct TileLds {
 };
 
 // March rows y0 .. y1-1 of a tile with division policy D (see Division).
-// Two barriers per row: the primitives of row j+1 go to LDS (buffer
-// (j+1) & 1) together with the x-fluxes of row j, before the second
-// barrier of row j, so the reconstruction of row j+1 finds them there.
+// A tile one wave wide (TXT = 64) exchanges x-neighbours with DPP lane
+// shifts and takes its decisions by a wave vote: no LDS, no barrier.  Wider
+// tiles use LDS with two barriers per row: the primitives of row j+1 go to
+// LDS (buffer (j+1) & 1) together with the x-fluxes of row j, before the
+// second barrier of row j, so the reconstruction of row j+1 finds them there.
 // With FastDiv a lane that finds its bounds broken in row j raises
 // L.bad[j & 1] before the row's last barrier; every lane reads the flag
 // after it and the march returns j before anything of row j is stored, for
@@ -701,16 +719,19 @@ __device__ __forceinline__ int march(const MemberArgs& m, const TileIO& io, int 
         gm2 = gm.f2;
     }
 
-    // primitives of row y0 for the x-reconstruction of the first row
-    L.h[y0 & 1][t] = p0.h;
-    L.u[y0 & 1][t] = p0.un;
-    L.v[y0 & 1][t] = p0.ut;
-    L.e[y0 & 1][t] = p0.eta;
-    if (FAST && t == 0) {
-        L.bad[0] = 0;
-        L.bad[1] = 0;
+    constexpr bool WAVE = TXT == 64;
+    if (!WAVE) {
+        // primitives of row y0 for the x-reconstruction of the first row
+        L.h[y0 & 1][t] = p0.h;
+        L.u[y0 & 1][t] = p0.un;
+        L.v[y0 & 1][t] = p0.ut;
+        L.e[y0 & 1][t] = p0.eta;
+        if (FAST && t == 0) {
+            L.bad[0] = 0;
+            L.bad[1] = 0;
+        }
+        __syncthreads();
     }
-    __syncthreads();
 
     for (int j = y0; j < y1; ++j) {
         // the loads of row j+2 were issued one iteration ahead; issue j+3
@@ -738,36 +759,62 @@ __device__ __forceinline__ int march(const MemberArgs& m, const TileIO& io, int 
         double Y1 = gp.fl1 - gm1 - fcy;  // normal momentum (qy)
         double Y2 = gp.f2 - gm2;         // tangential momentum (qx)
 
-        // ---- x direction, neighbours through LDS ----
+        // ---- x direction, neighbours through DPP or LDS ----
         const int b = j & 1;
         Prim pl, pr;
-        pl.h = L.h[b][tl]; pl.un = L.u[b][tl]; pl.ut = L.v[b][tl]; pl.eta = L.e[b][tl];
-        pr.h = L.h[b][tr]; pr.un = L.u[b][tr]; pr.ut = L.v[b][tr]; pr.eta = L.e[b][tr];
+        if (WAVE) {
+            pl.h = from_left(p0.h); pl.un = from_left(p0.un);
+            pl.ut = from_left(p0.ut); pl.eta = from_left(p0.eta);
+            pr.h = from_right(p0.h); pr.un = from_right(p0.un);
+            pr.ut = from_right(p0.ut); pr.eta = from_right(p0.eta);
+        } else {
+            pl.h = L.h[b][tl]; pl.un = L.u[b][tl]; pl.ut = L.v[b][tl]; pl.eta = L.e[b][tl];
+            pr.h = L.h[b][tr]; pr.un = L.u[b][tr]; pr.ut = L.v[b][tr]; pr.eta = L.e[b][tr];
+        }
         Rec rx = muscl(pl, p0, pr, p.h_eps, R0, d);
-        L.hm[t] = rx.h_m;
-        L.zm[t] = rx.z_m;
-        L.unm[t] = rx.un_m;
-        L.utm[t] = rx.ut_m;
-        __syncthreads();
-        if (FAST && t == 0) L.bad[(j + 1) & 1] = 0;
-        const double hm_r = L.hm[tr], zm_r = L.zm[tr], unm_r = L.unm[tr], utm_r = L.utm[tr];
+        double hm_r, zm_r, unm_r, utm_r;
+        if (WAVE) {
+            hm_r = from_right(rx.h_m);
+            zm_r = from_right(rx.z_m);
+            unm_r = from_right(rx.un_m);
+            utm_r = from_right(rx.ut_m);
+        } else {
+            L.hm[t] = rx.h_m;
+            L.zm[t] = rx.z_m;
+            L.unm[t] = rx.un_m;
+            L.utm[t] = rx.ut_m;
+            __syncthreads();
+            if (FAST && t == 0) L.bad[(j + 1) & 1] = 0;
+            hm_r = L.hm[tr];
+            zm_r = L.zm[tr];
+            unm_r = L.unm[tr];
+            utm_r = L.utm[tr];
+        }
         FaceOut fp = face(p.g, rx.h_p, rx.z_p, rx.un_p, rx.ut_p, hm_r, zm_r, unm_r, utm_r, d);
         double fp_speed = 0.0;
         if (STAGE == 1) fp_speed = face_speed(p.g, rx.h_p, rx.un_p, hm_r, unm_r, d);
         d.settle();
-        L.f0[t] = fp.f0;
-        L.f1[t] = fp.fr1;
-        L.f2[t] = fp.f2;
-        L.h[b ^ 1][t] = p1.h;
-        L.u[b ^ 1][t] = p1.un;
-        L.v[b ^ 1][t] = p1.ut;
-        L.e[b ^ 1][t] = p1.eta;
-        if (FAST && !d.ok()) L.bad[j & 1] = 1;
-        __syncthreads();
-        if (FAST && __builtin_amdgcn_readfirstlane(L.bad[j & 1]) != 0) return j;
-        double fm0 = L.f0[tl];
-        double fm1 = L.f1[tl];
-        double fm2 = L.f2[tl];
+        double fm0, fm1, fm2;
+        if (WAVE) {
+            if (FAST && __builtin_amdgcn_ballot_w64(!d.ok()) != 0) return j;
+            fm0 = from_left(fp.f0);
+            fm1 = from_left(fp.fr1);
+            fm2 = from_left(fp.f2);
+        } else {
+            L.f0[t] = fp.f0;
+            L.f1[t] = fp.fr1;
+            L.f2[t] = fp.f2;
+            L.h[b ^ 1][t] = p1.h;
+            L.u[b ^ 1][t] = p1.un;
+            L.v[b ^ 1][t] = p1.ut;
+            L.e[b ^ 1][t] = p1.eta;
+            if (FAST && !d.ok()) L.bad[j & 1] = 1;
+            __syncthreads();
+            if (FAST && __builtin_amdgcn_readfirstlane(L.bad[j & 1]) != 0) return j;
+            fm0 = L.f0[tl];
+            fm1 = L.f1[tl];
+            fm2 = L.f2[tl];
+        }
 
         if (STAGE == 1) {
             if (j == 0 && col_in) ay = fmax(ay, gm_speed);
