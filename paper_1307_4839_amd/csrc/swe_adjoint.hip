@@ -18,9 +18,13 @@
 // The vector-Jacobian product of the rate Phi is computed per face: each
 // face recomputes its four-cell stencil (primitives, the two MUSCL
 // reconstructions, hydrostatic reconstruction, HLL, S and the centred term
-// of its left cell) and writes the adjoint contributions to those four
-// cells; a gather kernel sums the contributions of every cell in a fixed
-// order (no atomics), folding ghost cells back onto the cells they mirror.
+// of its left cell) and yields the adjoint contributions to those four
+// cells (face_contrib).  One tile kernel (adj_vjp_kernel) evaluates the
+// faces of a tile and sums the contributions of every cell in the fixed
+// order of gather_cell (no atomics), folding ghost cells back onto the cells
+// they mirror.  face_contrib and gather_cell, run face by face over whole
+// contribution planes, are the plain form of the same sums; the host tests
+// check them against finite differences of the oracle.
 //
 // At points where the step is not differentiable the derivative follows
 // one fixed rule: max(a, b) and min(a, b) pass the derivative of the
@@ -318,10 +322,19 @@ struct AdjArgs {
     KParams p;
     const double* z;
     const double* fric;
-    // contribution buffers: [slot 0..3][component 0..2] planes
-    double* xc;   // 12 planes of ny x (nx+1)
-    double* yc;   // 12 planes of (ny+1) x nx
 };
+
+// one-wave tiles for the VJP kernel, about 2048 of them (the 1024^2 grids of
+// a calibration are small): 4 to 32 rows each
+constexpr int VJP_TX = 64;
+inline int vjp_rows(int nx, int ny) {
+    long long strips = (nx + VJP_TX - 7) / (VJP_TX - 6);
+    long long ty = strips * (long long)ny / 2048;
+    if (ty > 32) ty = 32;
+    if (ty < 4) ty = 4;
+    while ((ny + ty - 1) / ty > 65535) ty *= 2;
+    return (int)ty;
+}
 
 __host__ __device__ __forceinline__ RawCell load_raw(const double* h, const double* qx,
                                             const double* qy, const double* z, int nx,
@@ -335,59 +348,39 @@ __host__ __device__ __forceinline__ RawCell load_raw(const double* h, const doub
     return r;
 }
 
-// Adjoint contributions of one face.  DIR 0: x-face f of row `line`
-// (between columns f-1 and f, f = 0..nx); DIR 1: y-face f of column `line`
-// (between rows f-1 and f, f = 0..ny).  out[3k + c] is the contribution to
-// component c (h, qx, qy) of the cell at position f-2+k along the sweep
-// (ghost positions carry the contribution to the cell they mirror, sign
-// included): the face itself and the centred source of its lower/left cell.
+// Adjoint contributions of one face from the four cells of its stencil.
+// r[k], sgn[k]: the cell at position f-2+k along the sweep (a ghost position
+// holds the cell it mirrors, its discharge normal to the boundary multiplied
+// by sgn[k]); muL / muR: the adjoint seeds (h, qx, qy) of the cells left of
+// and right of the face, used when L_real / R_real.  out[3k + c] is the
+// contribution to component c (h, qx, qy) of the cell at position f-2+k
+// (ghost positions carry it to the cell they mirror, sign included): the
+// face itself and the centred source of its lower/left cell.
 template <int DIR>
-__host__ __device__ __forceinline__ void face_contrib(const KParams& p, const double* z,
-                                                      const double* h, const double* qx,
-                                                      const double* qy, const double* mu_h,
-                                                      const double* mu_qx, const double* mu_qy,
-                                                      int f, int line, double out[12]) {
-    const int nx = p.nx, ny = p.ny;
-    const int n_along = DIR == 0 ? nx : ny;
+__host__ __device__ __forceinline__ void face_contrib_cells(const KParams& p, const RawCell r[4],
+                                                            const double sgn[4], bool L_real,
+                                                            bool R_real, const double muL[3],
+                                                            const double muR[3],
+                                                            double out[12]) {
     const double d = DIR == 0 ? p.dx : p.dy;
-    RawCell r[4];
     Prim pr[4];
-    double sgn[4];
-    #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        int pos = f - 2 + k;
-        if (DIR == 0) {
-            double sx;
-            int cs = map_index(pos, nx, p.bcw, p.bce, sx);
-            r[k] = load_raw(h, qx, qy, z, nx, line, cs, sx, 1.0);
-            sgn[k] = sx;
-            pr[k] = prim_x(r[k], p.h_eps);
-        } else {
-            double sy;
-            int rs = map_index(pos, ny, p.bcs, p.bcn, sy);
-            r[k] = load_raw(h, qx, qy, z, nx, rs, line, 1.0, sy);
-            sgn[k] = sy;
-            pr[k] = to_y(prim_x(r[k], p.h_eps));
-        }
-    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        pr[k] = DIR == 0 ? prim_x(r[k], p.h_eps) : to_y(prim_x(r[k], p.h_eps));
     Rec RL = muscl(pr[0], pr[1], pr[2], p.h_eps);  // cell f-1
     Rec RR = muscl(pr[1], pr[2], pr[3], p.h_eps);  // cell f
 
     // adjoint seeds: X_i enters Phi_i as -X_i/d
     double bL[3] = {0.0, 0.0, 0.0}, bR[3] = {0.0, 0.0, 0.0};  // (mass, normal, tangential)
-    const bool L_real = f - 1 >= 0 && f - 1 < n_along;
-    const bool R_real = f < n_along;
     if (L_real) {
-        size_t idx = DIR == 0 ? (size_t)line * nx + (f - 1) : (size_t)(f - 1) * nx + line;
-        bL[0] = -mu_h[idx] / d;
-        bL[1] = -(DIR == 0 ? mu_qx[idx] : mu_qy[idx]) / d;
-        bL[2] = -(DIR == 0 ? mu_qy[idx] : mu_qx[idx]) / d;
+        bL[0] = -muL[0] / d;
+        bL[1] = -(DIR == 0 ? muL[1] : muL[2]) / d;
+        bL[2] = -(DIR == 0 ? muL[2] : muL[1]) / d;
     }
     if (R_real) {
-        size_t idx = DIR == 0 ? (size_t)line * nx + f : (size_t)f * nx + line;
-        bR[0] = -mu_h[idx] / d;
-        bR[1] = -(DIR == 0 ? mu_qx[idx] : mu_qy[idx]) / d;
-        bR[2] = -(DIR == 0 ? mu_qy[idx] : mu_qx[idx]) / d;
+        bR[0] = -muR[0] / d;
+        bR[1] = -(DIR == 0 ? muR[1] : muR[2]) / d;
+        bR[2] = -(DIR == 0 ? muR[2] : muR[1]) / d;
     }
     FaceBar fb = face_rev(p.g, RL.h_p, RL.z_p, RL.un_p, RL.ut_p, RR.h_m, RR.z_m, RR.un_m,
                           RR.ut_m, bL[0] - bR[0], bL[1] - bR[1], bL[2] - bR[2], bL[1], -bR[1]);
@@ -405,11 +398,11 @@ __host__ __device__ __forceinline__ void face_contrib(const KParams& p, const do
     // centred source of the left cell: X1 = ... - fc
     if (L_real) centred_rev(p.g, RL, -bL[1], RLb);
     PrimBar pb[4];
-    #pragma unroll
+#pragma unroll
     for (int k = 0; k < 4; ++k) zero(pb[k]);
     muscl_rev(pr[0], pr[1], pr[2], p.h_eps, RLb, pb[0], pb[1], pb[2]);
     muscl_rev(pr[1], pr[2], pr[3], p.h_eps, RRb, pb[1], pb[2], pb[3]);
-    #pragma unroll
+#pragma unroll
     for (int k = 0; k < 4; ++k) {
         PrimBar xb = pb[k];
         if (DIR == 1) {  // back to the x view of the primitives
@@ -427,33 +420,54 @@ __host__ __device__ __forceinline__ void face_contrib(const KParams& p, const do
     }
 }
 
+// The same, loading the stencil: DIR 0: x-face f of row `line` (between
+// columns f-1 and f, f = 0..nx); DIR 1: y-face f of column `line` (between
+// rows f-1 and f, f = 0..ny).
 template <int DIR>
-__global__ __launch_bounds__(T1) void adj_face_kernel(AdjArgs a, const double* __restrict__ h,
-                                                      const double* __restrict__ qx,
-                                                      const double* __restrict__ qy,
-                                                      const double* __restrict__ mu_h,
-                                                      const double* __restrict__ mu_qx,
-                                                      const double* __restrict__ mu_qy) {
-    const KParams& p = a.p;
+__host__ __device__ __forceinline__ void face_contrib(const KParams& p, const double* z,
+                                                      const double* h, const double* qx,
+                                                      const double* qy, const double* mu_h,
+                                                      const double* mu_qx, const double* mu_qy,
+                                                      int f, int line, double out[12]) {
     const int nx = p.nx, ny = p.ny;
     const int n_along = DIR == 0 ? nx : ny;
-    const int n_across = DIR == 0 ? ny : nx;
-    // consecutive threads take consecutive columns in both directions, so
-    // every load and store of a wave is one contiguous run of a row
-    const int f = DIR == 0 ? (int)(blockIdx.x * T1 + threadIdx.x) : (int)blockIdx.y;
-    const int line = DIR == 0 ? (int)blockIdx.y : (int)(blockIdx.x * T1 + threadIdx.x);
-    if (f > n_along || line >= n_across) return;
-    double out[12];
-    face_contrib<DIR>(p, a.z, h, qx, qy, mu_h, mu_qx, mu_qy, f, line, out);
-    const size_t plane = DIR == 0 ? (size_t)ny * (nx + 1) : (size_t)(ny + 1) * nx;
-    const size_t fidx = DIR == 0 ? (size_t)line * (nx + 1) + f : (size_t)f * nx + line;
-    double* buf = DIR == 0 ? a.xc : a.yc;
-    #pragma unroll
-    for (int k = 0; k < 12; ++k) buf[(size_t)k * plane + fidx] = out[k];
+    RawCell r[4];
+    double sgn[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        int pos = f - 2 + k;
+        double sg;
+        if (DIR == 0) {
+            int cs = map_index(pos, nx, p.bcw, p.bce, sg);
+            r[k] = load_raw(h, qx, qy, z, nx, line, cs, sg, 1.0);
+        } else {
+            int rs = map_index(pos, ny, p.bcs, p.bcn, sg);
+            r[k] = load_raw(h, qx, qy, z, nx, rs, line, 1.0, sg);
+        }
+        sgn[k] = sg;
+    }
+    const bool L_real = f - 1 >= 0 && f - 1 < n_along;
+    const bool R_real = f < n_along;
+    double muL[3] = {0.0, 0.0, 0.0}, muR[3] = {0.0, 0.0, 0.0};
+    if (L_real) {
+        size_t idx = DIR == 0 ? (size_t)line * nx + (f - 1) : (size_t)(f - 1) * nx + line;
+        muL[0] = mu_h[idx];
+        muL[1] = mu_qx[idx];
+        muL[2] = mu_qy[idx];
+    }
+    if (R_real) {
+        size_t idx = DIR == 0 ? (size_t)line * nx + f : (size_t)f * nx + line;
+        muR[0] = mu_h[idx];
+        muR[1] = mu_qx[idx];
+        muR[2] = mu_qy[idx];
+    }
+    face_contrib_cells<DIR>(p, r, sgn, L_real, R_real, muL, muR, out);
 }
 
-// lambda(cell) += sum of the face contributions addressed to it, in a fixed
-// order: interior positions, then the ghost positions that mirror it.
+// The face contributions addressed to cell (i, j), summed in a fixed order:
+// interior positions, then the ghost positions that mirror it; xc and yc
+// hold 12 planes (slot 0..3 x component) of the x-faces (ny x (nx+1)) and
+// the y-faces ((ny+1) x nx).
 __host__ __device__ __forceinline__ void add_contrib(const double* buf, size_t plane, size_t fidx,
                                             int slot, double& h, double& qx, double& qy) {
     h += buf[(size_t)(3 * slot + 0) * plane + fidx];
@@ -508,19 +522,214 @@ __host__ __device__ __forceinline__ void gather_cell(const KParams& p, const dou
     }
 }
 
-// lambda(cell) += sum of the face contributions addressed to it
-__global__ __launch_bounds__(T1) void adj_gather_kernel(AdjArgs a, double* __restrict__ lh,
-                                                        double* __restrict__ lqx,
-                                                        double* __restrict__ lqy) {
-    const int i = blockIdx.x * T1 + threadIdx.x;
-    const int j = blockIdx.y;
-    if (i >= a.p.nx || j >= a.p.ny) return;
-    double sh, sqx, sqy;
-    gather_cell(a.p, a.xc, a.yc, i, j, sh, sqx, sqy);
-    size_t idx = (size_t)j * a.p.nx + i;
-    lh[idx] += sh;
-    lqx[idx] += sqx;
-    lqy[idx] += sqy;
+// VJP of Phi over one tile (TXT lanes, rows y0 .. y1-1), summed per cell in
+// the order of gather_cell: x-faces left to right, the x ghost folds, then
+// y-faces bottom to top, the y ghost folds; lambda += the sum.  Each face of
+// the tile's stencil is evaluated once per tile (faces on a tile's border by
+// both tiles), and no per-face contribution goes to HBM.
+//
+// Lane t owns column c = strip * (TXT - 6) - 3 + t; lanes 3 .. TXT-4 are
+// outputs.  The x-face c (between columns c-1 and c) is evaluated by lane t
+// from the cells of lanes t-2 .. t+1 (LDS); its 12 contributions go through
+// LDS to the lanes of the four cells.  Down the column, the march at step k
+// loads row k+1, forms the x-part of row k+1, evaluates the y-face k (rows
+// k-2 .. k+1, a register window) and completes row k-2, which no later face
+// touches.
+template <int TXT>
+__global__ __launch_bounds__(TXT) void adj_vjp_kernel(AdjArgs a, const double* __restrict__ h,
+                                                      const double* __restrict__ qx,
+                                                      const double* __restrict__ qy,
+                                                      const double* __restrict__ mu_h,
+                                                      const double* __restrict__ mu_qx,
+                                                      const double* __restrict__ mu_qy,
+                                                      double* __restrict__ lh,
+                                                      double* __restrict__ lqx,
+                                                      double* __restrict__ lqy, int ty) {
+    constexpr int H = 3, OUTW = TXT - 2 * H;
+    const KParams& p = a.p;
+    const int nx = p.nx, ny = p.ny;
+    const int t = threadIdx.x;
+    const int c = (int)blockIdx.x * OUTW - H + t;
+    const int y0 = (int)blockIdx.y * ty;
+    const int y1 = y0 + ty < ny ? y0 + ty : ny;
+    double sx;
+    const int cs = map_index(c, nx, p.bcw, p.bce, sx);
+    const bool col_real = c >= 0 && c < nx;
+    const bool out = t >= H && t < TXT - H && col_real;
+    const bool xface = t >= 2 && t <= TXT - 2 && c >= 0 && c <= nx;
+
+    __shared__ double Lc[4][TXT];   // cell of the row (h, qx, qy, z)
+    __shared__ double Lm[3][TXT];   // its adjoint seed
+    __shared__ double Ls[TXT];      // ghost sign of the column
+    __shared__ double Lx[12][TXT];  // x-face contributions
+    // y contributions to ghost rows (each lane its own column), folded into
+    // the rows they mirror: 0, 1 = face 0 to rows -2, -1; 2 = face 1 to row
+    // -1; 3 = face ny-1 to row ny; 4, 5 = face ny to rows ny, ny+1
+    __shared__ double Lg[6][3][TXT];
+
+    // load row r of this column (ghost rows mapped, discharge signs applied)
+    auto load = [&](int r, RawCell& cell, double& sy, double m[3]) {
+        const int rs = map_index(r, ny, p.bcs, p.bcn, sy);
+        cell = load_raw(h, qx, qy, a.z, nx, rs, cs, sx, sy);
+        const bool real = r >= 0 && r < ny && col_real;
+        const size_t idx = (size_t)(real ? r : 0) * nx + (real ? c : 0);
+        m[0] = real ? mu_h[idx] : 0.0;
+        m[1] = real ? mu_qx[idx] : 0.0;
+        m[2] = real ? mu_qy[idx] : 0.0;
+    };
+
+    // window: rows k-2, k-1, k (+ k+1 loaded at step k)
+    RawCell w0, w1, w2;
+    double s0, s1, s2;
+    double m0[3], m1[3], m2[3];  // seeds of rows k-2 (unused), k-1, k
+    load(y0 - 3, w0, s0, m0);
+    load(y0 - 2, w1, s1, m1);
+    load(y0 - 1, w2, s2, m2);
+    // sums of rows k-2 .. k+1 (a0 .. a3)
+    double a0[3] = {0.0, 0.0, 0.0}, a1[3] = {0.0, 0.0, 0.0}, a2[3] = {0.0, 0.0, 0.0};
+    double a3[3];
+
+    for (int k = y0 - 1; k <= y1 + 1; ++k) {
+        const int r = k + 1;
+        RawCell w3;
+        double s3, m3[3];
+        load(r, w3, s3, m3);
+
+        // ---- x-part of row r ----
+        a3[0] = a3[1] = a3[2] = 0.0;
+        if (r >= y0 && r < y1) {
+            Lc[0][t] = w3.h;
+            Lc[1][t] = w3.qx;
+            Lc[2][t] = w3.qy;
+            Lc[3][t] = w3.z;
+            Lm[0][t] = m3[0];
+            Lm[1][t] = m3[1];
+            Lm[2][t] = m3[2];
+            Ls[t] = sx;
+            __syncthreads();
+            if (xface) {
+                RawCell rc[4];
+                double sg[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int l = t - 2 + q;
+                    rc[q].h = Lc[0][l];
+                    rc[q].qx = Lc[1][l];
+                    rc[q].qy = Lc[2][l];
+                    rc[q].z = Lc[3][l];
+                    sg[q] = Ls[l];
+                }
+                const double muL[3] = {Lm[0][t - 1], Lm[1][t - 1], Lm[2][t - 1]};
+                const double muR[3] = {m3[0], m3[1], m3[2]};
+                double o[12];
+                face_contrib_cells<0>(p, rc, sg, c - 1 >= 0 && c - 1 < nx, c < nx, muL, muR, o);
+#pragma unroll
+                for (int q = 0; q < 12; ++q) Lx[q][t] = o[q];
+            }
+            __syncthreads();
+            if (out) {
+                // faces f = max(c-1, 0) .. min(c+2, nx), slot c - f + 2
+                const int f0 = c - 1 > 0 ? c - 1 : 0;
+                const int f1 = c + 2 < nx ? c + 2 : nx;
+                for (int f = f0; f <= f1; ++f) {
+                    const int l = t + (f - c), sl = c - f + 2;
+                    a3[0] += Lx[3 * sl + 0][l];
+                    a3[1] += Lx[3 * sl + 1][l];
+                    a3[2] += Lx[3 * sl + 2][l];
+                }
+                auto add = [&](int l, int sl) {
+                    a3[0] += Lx[3 * sl + 0][l];
+                    a3[1] += Lx[3 * sl + 1][l];
+                    a3[2] += Lx[3 * sl + 2][l];
+                };
+                if (c == 0) {
+                    add(t, 1);      // column -1 (face 0)
+                    add(t + 1, 0);  // column -1 (face 1)
+                    if (p.bcw == SWE_BC_OUTFLOW) add(t, 0);
+                }
+                if (c == 1 && p.bcw == SWE_BC_WALL) add(t - 1, 0);
+                if (c == nx - 1) {
+                    add(t, 3);      // column nx (face nx-1)
+                    add(t + 1, 2);  // column nx (face nx)
+                    if (p.bce == SWE_BC_OUTFLOW) add(t + 1, 3);
+                }
+                if (c == nx - 2 && p.bce == SWE_BC_WALL) add(t + 2, 3);
+            }
+        }
+
+        // ---- y-face k of this column (rows k-2 .. k+1) ----
+        if (k >= 0 && k <= ny && col_real) {
+            const RawCell rc[4] = {w0, w1, w2, w3};
+            const double sg[4] = {s0, s1, s2, s3};
+            double o[12];
+            face_contrib_cells<1>(p, rc, sg, k - 1 >= 0 && k - 1 < ny, k < ny, m1, m2, o);
+            // contributions to rows k-2+q, q = 0..3, in the order of the faces
+            auto addq = [&](double s[3], int q) {
+                if (k - 2 + q >= y0 && k - 2 + q < y1) {
+                    s[0] += o[3 * q + 0];
+                    s[1] += o[3 * q + 1];
+                    s[2] += o[3 * q + 2];
+                }
+            };
+            addq(a0, 0);
+            addq(a1, 1);
+            addq(a2, 2);
+            addq(a3, 3);
+            auto keep = [&](int g, int q) {
+                Lg[g][0][t] = o[3 * q + 0];
+                Lg[g][1][t] = o[3 * q + 1];
+                Lg[g][2][t] = o[3 * q + 2];
+            };
+            if (k == 0) {
+                keep(0, 0);
+                keep(1, 1);
+            }
+            if (k == 1) keep(2, 0);
+            if (k == ny - 1) keep(3, 3);
+            if (k == ny) {
+                keep(4, 2);
+                keep(5, 3);
+            }
+        }
+
+        // ---- row k-2 is complete: ghost folds, then lambda += sum ----
+        const int jd = k - 2;
+        if (jd >= y0 && jd < y1 && out) {
+            auto add = [&](int g) {
+                a0[0] += Lg[g][0][t];
+                a0[1] += Lg[g][1][t];
+                a0[2] += Lg[g][2][t];
+            };
+            if (jd == 0) {
+                add(1);  // row -1 (face 0)
+                add(2);  // row -1 (face 1)
+                if (p.bcs == SWE_BC_OUTFLOW) add(0);
+            }
+            if (jd == 1 && p.bcs == SWE_BC_WALL) add(0);
+            if (jd == ny - 1) {
+                add(3);  // row ny (face ny-1)
+                add(4);  // row ny (face ny)
+                if (p.bcn == SWE_BC_OUTFLOW) add(5);
+            }
+            if (jd == ny - 2 && p.bcn == SWE_BC_WALL) add(5);
+            const size_t idx = (size_t)jd * nx + c;
+            lh[idx] += a0[0];
+            lqx[idx] += a0[1];
+            lqy[idx] += a0[2];
+        }
+
+        // ---- shift the window ----
+        w0 = w1; w1 = w2; w2 = w3;
+        s0 = s1; s1 = s2; s2 = s3;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            m1[q] = m2[q];
+            m2[q] = m3[q];
+            a0[q] = a1[q];
+            a1[q] = a2[q];
+            a2[q] = a3[q];
+        }
+    }
 }
 
 // U_out = friction(U_in + dt Phi(U_in)) cell by cell (a stage output).
@@ -695,11 +904,9 @@ size_t adj_bytes(const swe_params* p, int nsteps, int ckpt, int ngauges, int eve
     size_t n = ncells(p), an = align256(n * sizeof(double));
     size_t nck = (nsteps + ckpt - 1) / ckpt;
     size_t rows = every > 0 ? nsteps / every : 0;
-    size_t faces = align256(12 * (size_t)p->ny * (p->nx + 1) * sizeof(double)) +
-                   align256(12 * (size_t)(p->ny + 1) * p->nx * sizeof(double));
     return 256 + 256 + align256(nsteps * sizeof(double)) +
            align256(rows * (size_t)ngauges * sizeof(double)) + 3 * an * nck +
-           3 * an * (ckpt + 1) + 3 * an * 7 + faces;
+           3 * an * (ckpt + 1) + 3 * an * 7;
 }
 
 inline double* plane(double* base, size_t n, int k) { return base + (size_t)k * n; }
@@ -748,15 +955,13 @@ void rate_into(swe_adj* A, const double* h, const double* qx, const double* qy, 
 void vjp_rate(swe_adj* A, const double* h, const double* qx, const double* qy, double* lam) {
     const size_t n = A->n;
     const int nx = A->prm.nx, ny = A->prm.ny;
+    const int ty = vjp_rows(nx, ny);
+    dim3 grid((nx + VJP_TX - 7) / (VJP_TX - 6), (ny + ty - 1) / ty);
     double* mu = A->mu;
-    hipLaunchKernelGGL(adj_face_kernel<0>, dim3((nx + 1 + T1 - 1) / T1, ny), dim3(T1), 0,
-                       A->stream, A->aa, h, qx, qy, (const double*)plane(mu, n, 0),
-                       (const double*)plane(mu, n, 1), (const double*)plane(mu, n, 2));
-    hipLaunchKernelGGL(adj_face_kernel<1>, dim3((nx + T1 - 1) / T1, ny + 1), dim3(T1), 0,
-                       A->stream, A->aa, h, qx, qy, (const double*)plane(mu, n, 0),
-                       (const double*)plane(mu, n, 1), (const double*)plane(mu, n, 2));
-    hipLaunchKernelGGL(adj_gather_kernel, dim3((nx + T1 - 1) / T1, ny), dim3(T1), 0, A->stream,
-                       A->aa, plane(lam, n, 0), plane(lam, n, 1), plane(lam, n, 2));
+    hipLaunchKernelGGL(adj_vjp_kernel<VJP_TX>, grid, dim3(VJP_TX), 0, A->stream, A->aa, h, qx,
+                       qy, (const double*)plane(mu, n, 0), (const double*)plane(mu, n, 1),
+                       (const double*)plane(mu, n, 2), plane(lam, n, 0), plane(lam, n, 1),
+                       plane(lam, n, 2), ty);
 }
 
 // lamA <- adjoint of U^k given lam = adjoint of U^{k+1}; grad += dL/dn.
@@ -875,8 +1080,6 @@ int swe_adj_create(const swe_params* p, const swe_buffers* b, int32_t nsteps,
     A->aa.p = m.p;
     A->aa.z = b->z;
     A->aa.fric = b->fric;
-    A->aa.xc = (double*)w; w += align256(12 * (size_t)p->ny * (p->nx + 1) * sizeof(double));
-    A->aa.yc = (double*)w;
     // the forward writes Phi into the same planes the rate kernel uses
     m.ph = plane(A->phi, n, 0);
     m.pqx = plane(A->phi, n, 1);
