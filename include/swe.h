@@ -116,7 +116,8 @@ int swe_destroy(swe_ctx* ctx);
  * own a strip of tx - 4 output columns; each block marches `ty` rows
  * (0 = automatic).  Results do not depend on the tile shape (every cell and
  * face is evaluated by the same formulas on the same inputs).  SWE_EINVAL
- * for other widths or a ty that leaves more than 65535 row blocks. */
+ * for other widths, ty > ny, or a ty that leaves more than 65535 row
+ * blocks. */
 int swe_set_tiling(swe_ctx* ctx, int32_t tx, int32_t ty);
 int swe_get_tiling(swe_ctx* ctx, int32_t* tx, int32_t* ty);
 

@@ -278,15 +278,18 @@ def _fallback_case(case):
     raise ValueError(case)
 
 
+@pytest.mark.parametrize("tx", [256, 64])
 @pytest.mark.parametrize("case", ["g_outside_window", "tiny_depth_mid_tile", "huge_bed",
                                   "negative_depth", "non_pow2_cells"])
-def test_division_paths(torch_cuda, case):
+def test_division_paths(torch_cuda, case, tx):
+    # tx 256: LDS exchange, block-wide flag; tx 64: DPP exchange, wave vote
     wl = _fallback_case(case)
     wl.dt_max = 0.01
-    say(f"[division] {case}")
+    say(f"[division] {case} tiles {tx}")
     s = oracle.State(wl)
     s.run(1)
     g = gpu_solver(wl, dt_log=1)
+    g.set_tiling(tx, 8)
     g.step(1)
     st = g.state()
     for k in ("h", "qx", "qy"):
