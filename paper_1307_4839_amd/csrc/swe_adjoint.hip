@@ -841,18 +841,33 @@ __global__ void loss_kernel(const double* __restrict__ series, const double* __r
 
 // Forward stages of one tile grid (the same tile routine as the
 // single-simulation context).
-template <int STAGE>
-__global__ __launch_bounds__(256) void fwd_stage_kernel(MemberArgs m, TileIO io, int ty) {
+template <int STAGE, int TXT>
+__global__ __launch_bounds__(TXT) void fwd_stage_kernel(MemberArgs m, TileIO io, int ty) {
     const int y0 = blockIdx.y * ty;
     const int y1 = min(y0 + ty, m.p.ny);
-    stage_tile<STAGE, 256>(m, io, blockIdx.x, y0, y1, blockIdx.x == 0 && blockIdx.y == 0);
+    stage_tile<STAGE, TXT>(m, io, blockIdx.x, y0, y1, blockIdx.x == 0 && blockIdx.y == 0,
+                           blockIdx.x + blockIdx.y * gridDim.x);
+}
+
+// One stage over the whole grid with the default tiling of its size.
+template <int STAGE>
+void launch_fwd(const swe_params& prm, hipStream_t s, const MemberArgs& m, const TileIO& io) {
+    const int tx = default_tx(prm.nx, prm.ny);
+    const int ty = auto_rows(prm.nx, prm.ny, tx);
+    const dim3 grid(strips_of(prm.nx, tx), (prm.ny + ty - 1) / ty);
+    if (tx == 64)
+        hipLaunchKernelGGL((fwd_stage_kernel<STAGE, 64>), grid, dim3(64), 0, s, m, io, ty);
+    else
+        hipLaunchKernelGGL((fwd_stage_kernel<STAGE, 256>), grid, dim3(256), 0, s, m, io, ty);
 }
 
 // Per-step reset of the time bookkeeping (the status flags stay sticky).
 __global__ void reset_step_kernel(DevScalars* sc) {
+    if (blockIdx.x == 0 && threadIdx.x < AMAX_SPREAD) {
+        sc->amax[0][threadIdx.x][0] = sc->amax[0][threadIdx.x][1] = 0ull;
+        sc->amax[1][threadIdx.x][0] = sc->amax[1][threadIdx.x][1] = 0ull;
+    }
     if (threadIdx.x == 0 && blockIdx.x == 0) {
-        sc->amax[0][0] = sc->amax[0][1] = 0ull;
-        sc->amax[1][0] = sc->amax[1][1] = 0ull;
         sc->t[0] = sc->t[1] = 0.0;
         sc->steps[0] = sc->steps[1] = 0;
     }
@@ -904,7 +919,7 @@ size_t adj_bytes(const swe_params* p, int nsteps, int ckpt, int ngauges, int eve
     size_t n = ncells(p), an = align256(n * sizeof(double));
     size_t nck = (nsteps + ckpt - 1) / ckpt;
     size_t rows = every > 0 ? nsteps / every : 0;
-    return 256 + 256 + align256(nsteps * sizeof(double)) +
+    return SCALAR_BYTES + 256 + align256(nsteps * sizeof(double)) +
            align256(rows * (size_t)ngauges * sizeof(double)) + 3 * an * nck +
            3 * an * (ckpt + 1) + 3 * an * 7;
 }
@@ -927,10 +942,8 @@ void fwd_step(swe_adj* A, const double* h, const double* qx, const double* qy, d
     hipLaunchKernelGGL(reset_step_kernel, dim3(1), dim3(64), 0, A->stream, m.sc);
     TileIO io = host_step_io(m, 0, 0, INFINITY);
     io.dt_fixed = dt_fixed;
-    int ty = auto_rows(A->prm.nx, A->prm.ny, 256);
-    dim3 grid(strips_of(A->prm.nx, 256), (A->prm.ny + ty - 1) / ty);
-    hipLaunchKernelGGL(fwd_stage_kernel<1>, grid, dim3(256), 0, A->stream, m, io, ty);
-    hipLaunchKernelGGL(fwd_stage_kernel<2>, grid, dim3(256), 0, A->stream, m, io, ty);
+    launch_fwd<1>(A->prm, A->stream, m, io);
+    launch_fwd<2>(A->prm, A->stream, m, io);
 }
 
 // Phi(U) into dst (stage 1 kernel with a scratch accumulator).
@@ -942,13 +955,11 @@ void rate_into(swe_adj* A, const double* h, const double* qx, const double* qy, 
     io.ph = plane(dst, A->n, 0);
     io.pqx = plane(dst, A->n, 1);
     io.pqy = plane(dst, A->n, 2);
-    io.acc = m.sc->amax[2];
+    io.acc = &m.sc->amax[2][0][0];
     io.clr = nullptr;
     io.slot = 2;
-    int ty = auto_rows(A->prm.nx, A->prm.ny, 256);
-    dim3 grid(strips_of(A->prm.nx, 256), (A->prm.ny + ty - 1) / ty);
     hipLaunchKernelGGL(swe_clear_amax_kernel, dim3(1), dim3(64), 0, A->stream, m.sc, 2);
-    hipLaunchKernelGGL(fwd_stage_kernel<1>, grid, dim3(256), 0, A->stream, m, io, ty);
+    launch_fwd<1>(A->prm, A->stream, m, io);
 }
 
 // lam(h,qx,qy) += VJP_Phi(U, mu)
@@ -1063,7 +1074,7 @@ int swe_adj_create(const swe_params* p, const swe_buffers* b, int32_t nsteps,
     m.z = b->z;
     m.fric = b->fric;
     m.vinf = nullptr;
-    m.sc = (DevScalars*)w; w += 256;
+    m.sc = (DevScalars*)w; w += SCALAR_BYTES;
     A->loss_dev = (double*)w; w += 256;
     A->dts = (double*)w; w += align256(nsteps * sizeof(double));
     A->series = (double*)w; w += align256((size_t)A->nrows * ngauges * sizeof(double));

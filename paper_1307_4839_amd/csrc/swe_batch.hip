@@ -44,7 +44,7 @@ __global__ __launch_bounds__(TXT) void batch_stage_kernel(const MemberArgs* __re
         // live in scratch memory, since its buffer pairs are indexed by phase
         const MemberArgs& m = ms[tl.x];
         const TileIO io = step_io(m, phase, slot, t_end);
-        stage_tile<STAGE, TXT>(m, io, tl.y, tl.z, tl.w, tl.y == 0 && tl.z == 0);
+        stage_tile<STAGE, TXT>(m, io, tl.y, tl.z, tl.w, tl.y == 0 && tl.z == 0, k);
     }
 }
 
@@ -90,9 +90,12 @@ __global__ void batch_backup_kernel(const MemberArgs* __restrict__ ms,
             if (m.vinf) m.vinf[i] = b.vinf[i];
         }
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        if (dir == 0) *b.sc = *m.sc;
-        else *m.sc = *b.sc;
+    if (blockIdx.x == 0) {
+        // the scalar block, word by word across the block's threads
+        const unsigned long long* src =
+            (const unsigned long long*)(dir == 0 ? (const void*)m.sc : (const void*)b.sc);
+        unsigned long long* dst = (unsigned long long*)(dir == 0 ? (void*)b.sc : (void*)m.sc);
+        for (size_t i = threadIdx.x; i < sizeof(DevScalars) / 8; i += blockDim.x) dst[i] = src[i];
     }
 }
 
@@ -293,7 +296,7 @@ int run_steps(swe_batch* b, int32_t nsteps, double t_end, bool use_graph) {
 size_t member_bytes(const swe_params& p) {
     size_t an = align256(ncells(&p) * sizeof(double));
     // scalars, second state, rate, backup of the state (+ V_inf), backup scalars
-    return 256 + 3 * an + 3 * an + 3 * an + (p.infil_on ? an : 0) + 256;
+    return SCALAR_BYTES + 3 * an + 3 * an + 3 * an + (p.infil_on ? an : 0) + SCALAR_BYTES;
 }
 
 }  // namespace
@@ -355,7 +358,7 @@ int swe_batch_create(const swe_params* p, const swe_buffers* bufs, int32_t count
         m.z = bufs[k].z;
         m.fric = bufs[k].fric;
         m.vinf = p[k].infil_on ? bufs[k].vinf : nullptr;
-        m.sc = (DevScalars*)w; w += 256;
+        m.sc = (DevScalars*)w; w += SCALAR_BYTES;
         m.h[0] = bufs[k].h; m.qx[0] = bufs[k].qx; m.qy[0] = bufs[k].qy;
         m.h[1] = (double*)w; w += an;
         m.qx[1] = (double*)w; w += an;
@@ -369,7 +372,7 @@ int swe_batch_create(const swe_params* p, const swe_buffers* bufs, int32_t count
         bk.qy = (double*)w; w += an;
         bk.vinf = nullptr;
         if (p[k].infil_on) { bk.vinf = (double*)w; w += an; }
-        bk.sc = (DevScalars*)w; w += 256;
+        bk.sc = (DevScalars*)w; w += SCALAR_BYTES;
         hipLaunchKernelGGL(swe_init_scalars_kernel, dim3(1), dim3(64), 0, b->stream, m.sc, 0.0);
     }
     int dev = 0;

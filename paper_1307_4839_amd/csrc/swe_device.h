@@ -35,15 +35,25 @@ constexpr int HALO = 2;  // ghost/halo width at second order
 // Device-side scalars (in the workspace)
 // ---------------------------------------------------------------------------
 
+// The wave-speed maxima of a step are accumulated in AMAX_SPREAD pairs
+// (Ax, Ay), each on its own 128-byte line: the stage-1 block with spread
+// index b folds its maxima into pair b mod AMAX_SPREAD, so that thousands of
+// blocks finishing together do not queue on one address; readers take the
+// maximum over the pairs (the same value: max is associative).
+constexpr int AMAX_SPREAD = 16;
+constexpr int AMAX_LINE = 16;  // unsigned long long per 128-byte line
+
 struct DevScalars {
-    unsigned long long amax[3][2];  // per slot: bit patterns of Ax, Ay >= 0
+    // per slot: bit patterns of Ax, Ay >= 0 at [pair][0], [pair][1]
+    unsigned long long amax[3][AMAX_SPREAD][AMAX_LINE];
     double t[2];                    // time, double-buffered by step parity
     long long steps[2];             // steps taken, double-buffered
     double last_dt;
     unsigned int status;            // sticky SWE_FLAG_* bits
     unsigned int pad;
 };
-static_assert(sizeof(DevScalars) <= 256, "scalar block must fit 256 bytes");
+// bytes a scalar block takes in a workspace (a multiple of 256)
+constexpr size_t SCALAR_BYTES = (sizeof(DevScalars) + 255) / 256 * 256;
 
 struct KParams {
     int nx, ny;
@@ -448,8 +458,8 @@ struct TileIO {
     double* ho;            // stage 2 output U^{n+1}
     double* qxo;
     double* qyo;
-    unsigned long long* acc;  // stage 1: (Ax, Ay) accumulators
-    unsigned long long* clr;  // stage 1: pair zeroed for the next step (or null)
+    unsigned long long* acc;  // stage 1: the (Ax, Ay) accumulators of the step (pairs)
+    unsigned long long* clr;  // stage 1: accumulators zeroed for the next step (or null)
     int slot;                 // step parity (time buffer, accumulator slot)
     double t_end;
     double dt_fixed;          // > 0: use this time step instead of the CFL bound
@@ -467,8 +477,8 @@ __device__ __forceinline__ TileIO step_io(const MemberArgs& m, int phase, int sl
     io.ho = m.h[phase ^ 1];
     io.qxo = m.qx[phase ^ 1];
     io.qyo = m.qy[phase ^ 1];
-    io.acc = m.sc->amax[slot];
-    io.clr = m.sc->amax[slot ^ 1];
+    io.acc = &m.sc->amax[slot][0][0];
+    io.clr = &m.sc->amax[slot ^ 1][0][0];
     io.slot = slot;
     io.t_end = t_end;
     io.dt_fixed = 0.0;
@@ -585,9 +595,31 @@ __device__ __forceinline__ unsigned long long as_bits(double x) {
     return (unsigned long long)__double_as_longlong(x);
 }
 
-// block-wide maximum of two non-negative doubles, then one atomic each
+// (Ax, Ay) of a step: the maximum over the accumulator pairs, reduced by
+// the first AMAX_SPREAD lanes of each wave and broadcast to all lanes
+__device__ __forceinline__ void read_amax(const unsigned long long* acc, double& ax, double& ay) {
+    const int l = threadIdx.x & 63;
+    unsigned long long x = 0ull, y = 0ull;
+    if (l < AMAX_SPREAD) {
+        x = acc[l * AMAX_LINE + 0];
+        y = acc[l * AMAX_LINE + 1];
+    }
+    for (int off = AMAX_SPREAD / 2; off > 0; off >>= 1) {
+        unsigned long long ox = __shfl_xor(x, off, 64);
+        unsigned long long oy = __shfl_xor(y, off, 64);
+        x = x < ox ? ox : x;
+        y = y < oy ? oy : y;
+    }
+    x = __shfl(x, 0, 64);
+    y = __shfl(y, 0, 64);
+    ax = __longlong_as_double((long long)x);
+    ay = __longlong_as_double((long long)y);
+}
+
+// block-wide maximum of two non-negative doubles, then one atomic each into
+// accumulator pair `spread` mod AMAX_SPREAD of dst
 template <int TXT>
-__device__ void block_max2(double ax, double ay, unsigned long long* dst) {
+__device__ void block_max2(double ax, double ay, unsigned long long* dst, int spread) {
     __shared__ double red[2][TXT / 64];
     for (int off = 32; off > 0; off >>= 1) {
         double ox = __shfl_down(ax, off, 64);
@@ -610,8 +642,9 @@ __device__ void block_max2(double ax, double ay, unsigned long long* dst) {
         // non-negative doubles order like their bit patterns; NaN speeds
         // never enter the maximum (every comparison with NaN is false), as
         // in the oracle, and a non-finite state is flagged by the update
-        atomicMax(&dst[0], as_bits(mx));
-        atomicMax(&dst[1], as_bits(my));
+        unsigned long long* pair = dst + (spread & (AMAX_SPREAD - 1)) * AMAX_LINE;
+        atomicMax(&pair[0], as_bits(mx));
+        atomicMax(&pair[1], as_bits(my));
     }
 }
 
@@ -911,9 +944,10 @@ __device__ __forceinline__ int march(const MemberArgs& m, const TileIO& io, int 
 // rain and Green-Ampt, U^{n+1} to io.ho/qxo/qyo.  `lead` marks the one tile
 // per simulation that does the scalar bookkeeping (time, step count, dt log,
 // clearing the next step's accumulators).
+// `spread` picks the accumulator pair of stage 1 (any block-dependent index).
 template <int STAGE, int TXT>
 __device__ __forceinline__ void stage_tile(const MemberArgs& m, const TileIO& io, int strip,
-                                           int y0, int y1, bool lead) {
+                                           int y0, int y1, bool lead, int spread) {
     constexpr int OUTW = TXT - 2 * HALO;
     const KParams& p = m.p;
     const int t = threadIdx.x;
@@ -924,8 +958,8 @@ __device__ __forceinline__ void stage_tile(const MemberArgs& m, const TileIO& io
 
     double dt = 0.0;
     if (STAGE == 2) {
-        double ax = __longlong_as_double((long long)m.sc->amax[io.slot][0]);
-        double ay = __longlong_as_double((long long)m.sc->amax[io.slot][1]);
+        double ax, ay;
+        read_amax(&m.sc->amax[io.slot][0][0], ax, ay);
         double tc = m.sc->t[io.slot];
         dt = io.dt_fixed > 0.0 ? io.dt_fixed : time_step(p, ax, ay, tc, io.t_end);
         const bool finite = (dt - dt) == 0.0;  // false for inf and NaN
@@ -955,9 +989,9 @@ __device__ __forceinline__ void stage_tile(const MemberArgs& m, const TileIO& io
             return;
         }
     } else {
-        if (io.clr && lead && t == 0) {
-            io.clr[0] = 0ull;
-            io.clr[1] = 0ull;
+        if (io.clr && lead && t < AMAX_SPREAD) {
+            io.clr[t * AMAX_LINE + 0] = 0ull;
+            io.clr[t * AMAX_LINE + 1] = 0ull;
         }
     }
 
@@ -965,7 +999,7 @@ __device__ __forceinline__ void stage_tile(const MemberArgs& m, const TileIO& io
     int stop = y0;
     if (p.fast_div) stop = march<STAGE, TXT, FastDiv>(m, io, strip, y0, y1, dt, ax, ay, L);
     if (stop < y1) march<STAGE, TXT, ExactDiv>(m, io, strip, stop, y1, dt, ax, ay, L);
-    if (STAGE == 1) block_max2<TXT>(ax, ay, io.acc);
+    if (STAGE == 1) block_max2<TXT>(ax, ay, io.acc, spread);
 }
 
 }  // namespace swe_dev

@@ -65,6 +65,11 @@ inline KParams to_kparams(const swe_params& p) {
 
 inline bool valid_tx(int tx) { return tx == 64 || tx == 128 || tx == 256; }
 
+// Default strip width: one-wave strips (no LDS, no barrier) below 8M cells,
+// where they give enough blocks to fill the GPU; 256-column strips above
+// (less halo work per output column).
+inline int default_tx(int nx, int ny) { return (long long)nx * ny < (8LL << 20) ? 64 : 256; }
+
 inline int strips_of(int nx, int tx) {
     int outw = tx - 2 * HALO;
     return (nx + outw - 1) / outw;
@@ -98,8 +103,8 @@ inline TileIO host_step_io(const MemberArgs& m, int phase, int slot, double t_en
     io.ho = m.h[phase ^ 1];
     io.qxo = m.qx[phase ^ 1];
     io.qyo = m.qy[phase ^ 1];
-    io.acc = m.sc->amax[slot];
-    io.clr = m.sc->amax[slot ^ 1];
+    io.acc = &m.sc->amax[slot][0][0];
+    io.clr = &m.sc->amax[slot ^ 1][0][0];
     io.slot = slot;
     io.t_end = t_end;
     io.dt_fixed = 0.0;
@@ -111,11 +116,12 @@ inline TileIO host_step_io(const MemberArgs& m, int phase, int slot, double t_en
 // Kernels that are not stages.  Internal linkage: each translation unit
 // that includes this header gets its own copy.
 static __global__ void swe_init_scalars_kernel(swe_dev::DevScalars* sc, double t) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
+    if (blockIdx.x == 0 && threadIdx.x < swe_dev::AMAX_SPREAD)
         for (int s = 0; s < 3; ++s) {
-            sc->amax[s][0] = 0ull;
-            sc->amax[s][1] = 0ull;
+            sc->amax[s][threadIdx.x][0] = 0ull;
+            sc->amax[s][threadIdx.x][1] = 0ull;
         }
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
         sc->t[0] = t;
         sc->t[1] = t;
         sc->steps[0] = 0;
@@ -130,9 +136,9 @@ static __global__ void swe_set_time_kernel(swe_dev::DevScalars* sc, int slot, do
 }
 
 static __global__ void swe_clear_amax_kernel(swe_dev::DevScalars* sc, int slot) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        sc->amax[slot][0] = 0ull;
-        sc->amax[slot][1] = 0ull;
+    if (blockIdx.x == 0 && threadIdx.x < swe_dev::AMAX_SPREAD) {
+        sc->amax[slot][threadIdx.x][0] = 0ull;
+        sc->amax[slot][threadIdx.x][1] = 0ull;
     }
 }
 

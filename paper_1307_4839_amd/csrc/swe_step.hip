@@ -23,6 +23,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstdlib>
@@ -46,7 +47,8 @@ template <int STAGE, int TXT>
 __global__ __launch_bounds__(TXT) void stage_kernel(MemberArgs m, TileIO io, int ty) {
     const int y0 = blockIdx.y * ty;
     const int y1 = min(y0 + ty, m.p.ny);
-    stage_tile<STAGE, TXT>(m, io, blockIdx.x, y0, y1, blockIdx.x == 0 && blockIdx.y == 0);
+    stage_tile<STAGE, TXT>(m, io, blockIdx.x, y0, y1, blockIdx.x == 0 && blockIdx.y == 0,
+                           blockIdx.x + blockIdx.y * gridDim.x);
 }
 
 // Deterministic diagnostics: block b reduces the cells b, b + B, b + 2B, ...
@@ -206,7 +208,7 @@ int swe_workspace_bytes(const swe_params* p, size_t* bytes) {
     if (rc) return rc;
     if (!bytes) return SWE_EINVAL;
     size_t n = ncells(p);
-    *bytes = 256 + 6 * align256(n * sizeof(double)) +
+    *bytes = SCALAR_BYTES + 6 * align256(n * sizeof(double)) +
              align256((size_t)DIAG_BLOCKS * 5 * sizeof(double));
     return SWE_OK;
 }
@@ -234,7 +236,7 @@ int swe_create(const swe_params* p, const swe_buffers* b, void* workspace,
     m.fric = b->fric;
     m.vinf = p->infil_on ? b->vinf : nullptr;
     m.sc = (DevScalars*)w;
-    w += 256;
+    w += SCALAR_BYTES;
     m.h[0] = b->h; m.qx[0] = b->qx; m.qy[0] = b->qy;
     m.h[1] = (double*)w; w += an;
     m.qx[1] = (double*)w; w += an;
@@ -244,7 +246,7 @@ int swe_create(const swe_params* p, const swe_buffers* b, void* workspace,
     m.pqy = (double*)w; w += an;
     c->diag = (double*)w;
     c->slot = 0;
-    c->tx = 256;
+    c->tx = default_tx(p->nx, p->ny);
     c->ty = auto_rows(p->nx, p->ny, c->tx);
     hipLaunchKernelGGL(swe_init_scalars_kernel, dim3(1), dim3(64), 0, c->stream, m.sc, 0.0);
     rc = hip_ok(hipGetLastError());
@@ -429,18 +431,23 @@ int swe_rate(swe_ctx* c, const double* h, const double* qx, const double* qy,
     io.h = h; io.qx = qx; io.qy = qy;
     io.ph = ph; io.pqx = pqx; io.pqy = pqy;
     // slot 2 of the maxima is reserved for this call and is not a step slot
-    io.acc = c->m.sc->amax[2];
+    io.acc = &c->m.sc->amax[2][0][0];
     io.clr = nullptr;
     io.slot = 2;
     launch_stage<1>(c->tx, stage_grid(c), c->stream, c->m, io, c->ty);
-    unsigned long long got[2];
-    if (hipMemcpyAsync(got, &c->m.sc->amax[2][0], sizeof got, hipMemcpyDeviceToHost,
+    unsigned long long got[AMAX_SPREAD][AMAX_LINE];
+    if (hipMemcpyAsync(got, &c->m.sc->amax[2][0][0], sizeof got, hipMemcpyDeviceToHost,
                        c->stream) != hipSuccess)
         return SWE_EHIP;
     if (hipStreamSynchronize(c->stream) != hipSuccess) return SWE_EHIP;
     if (amax) {
-        std::memcpy(&amax[0], &got[0], 8);
-        std::memcpy(&amax[1], &got[1], 8);
+        unsigned long long x = 0ull, y = 0ull;
+        for (int k = 0; k < AMAX_SPREAD; ++k) {
+            x = std::max(x, got[k][0]);
+            y = std::max(y, got[k][1]);
+        }
+        std::memcpy(&amax[0], &x, 8);
+        std::memcpy(&amax[1], &y, 8);
     }
     return hip_ok(hipGetLastError());
 }
