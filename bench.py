@@ -192,14 +192,52 @@ def adjoint_leg(steps, every):
             "loss": loss, "grad_norm": gnorm}
 
 
+def paper_runs_leg(iterations):
+    """Wall time of whole runs of the 5120 x 5120 valley from its initial
+    state, at the iteration counts of the scaling runs of Section 6.3 (one
+    run, timed with HIP events at each count)."""
+    import torch
+
+    from paper_1307_4839_amd import inputs as I
+    from paper_1307_4839_amd.solver import Solver
+    wl = I.valley_5120()
+    g = Solver(wl, device="cuda:0")
+    iterations = sorted(iterations)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(len(iterations) + 1)]
+    torch.cuda.synchronize()
+    evs[0].record(g.stream)
+    done = 0
+    for k, n in enumerate(iterations):
+        g.step(n - done)
+        done = n
+        evs[k + 1].record(g.stream)
+    torch.cuda.synchronize()
+    rc, flags = g.status()
+    t_sim, _, steps = g.time()
+    g.close()
+    del g
+    torch.cuda.empty_cache()
+    cells = wl.nx * wl.ny
+    runs = []
+    for k, n in enumerate(iterations):
+        ms = evs[0].elapsed_time(evs[k + 1])
+        runs.append({"iterations": n, "s": ms / 1e3, "ms_per_step": ms / n,
+                     "value": cells * n / (ms / 1e3)})
+        print(f"[bench] valley_5120: {n} iterations in {ms / 1e3:.2f} s",
+              file=sys.stderr, flush=True)
+    return {"workload": f"valley {wl.nx}x{wl.ny}, {wl.dx:g} m cells, dam break, Manning "
+                        f"{wl.fric_coef}, from t = 0", "unit": "cell-updates/s",
+            "runs": runs, "sim_time_s": t_sim, "status": rc}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=300)
     ap.add_argument("--warmup", type=int, default=300)
     ap.add_argument("--workload", default="hillslope_8192",
-                    choices=["hillslope_8192", "valley_2048", "dam_break_200",
-                             "calibration_1024"])
+                    choices=["hillslope_8192", "valley_2048", "valley_5120",
+                             "dam_break_200", "calibration_1024"])
     ap.add_argument("--size", type=int, default=0, help="override nx = ny (testing)")
     ap.add_argument("--profile-steps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -210,6 +248,8 @@ def main(argv=None):
     ap.add_argument("--adjoint-steps", type=int, default=2000)
     ap.add_argument("--ensemble-members", type=int, default=256)
     ap.add_argument("--ensemble-steps", type=int, default=500)
+    ap.add_argument("--no-paper-runs", action="store_true")
+    ap.add_argument("--paper-iterations", default="5000,20000")
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
@@ -335,6 +375,10 @@ def main(argv=None):
         torch.cuda.empty_cache()
         adj = adjoint_leg(args.adjoint_steps, 10)
 
+    paper = None
+    if not args.no_paper_runs:
+        paper = paper_runs_leg([int(v) for v in args.paper_iterations.split(",")])
+
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
@@ -367,6 +411,7 @@ def main(argv=None):
         "cpu_baseline": cpu,
         "ensemble": ens,
         "adjoint": adj,
+        "paper_runs": paper,
         "sim_time_s": t_sim,
         "status_flags": flags,
     }

@@ -241,6 +241,25 @@ def valley_2048(nx: int = 2048, ny: int = 2048, seed: int = 2,
                     fric_coef=0.033, nsteps=2000)
 
 
+def valley_5120(nx: int = 5120, ny: int = 5120, seed: int = 6,
+                dam_row: int = 750) -> Workload:
+    """The valley of valley_2048 (same 10.24 km extent, side slopes, down-valley
+    slope, 1280 m terrain wavelength, 50 m reservoir) on a 2 m mesh: the
+    5120 x 5120 domain size of the scaling runs of Section 6.3, whose terrain
+    and physics the paper does not give."""
+    rng = np.random.default_rng(seed)
+    d = 10240.0 / nx if nx == ny else 2.0
+    z, x, y, xc = _valley(rng, nx, ny, d, 0.2, 0.003, 3.0, 1280.0)
+    rows = np.arange(ny)[:, None]
+    dam = int(round(dam_row * ny / 5120))
+    h = np.where(rows < dam, np.maximum(50.0 - z, 0.0), 0.0)
+    zero = np.zeros((ny, nx))
+    return Workload("valley_5120", nx, ny, d, d, z=z, h=np.ascontiguousarray(h),
+                    qx=zero.copy(), qy=zero.copy(),
+                    bc=(WALL, WALL, WALL, OUTFLOW), fric_law=FRIC_MANNING,
+                    fric_coef=0.033, nsteps=20000)
+
+
 def hillslope_8192(nx: int = 8192, ny: int = 8192, seed: int = 3) -> Workload:
     rng = np.random.default_rng(seed)
     d = 1.0
@@ -344,6 +363,7 @@ def random_state(nx: int, ny: int, seed: int, dry_frac: float = 0.3,
 WORKLOADS = {
     "dam_break_200": dam_break_200,
     "valley_2048": valley_2048,
+    "valley_5120": valley_5120,
     "hillslope_8192": hillslope_8192,
     "calibration_1024": calibration_1024,
 }

@@ -113,3 +113,8 @@ def test_fullsize_valley_2048():
 def test_fullsize_calibration_1024():
     wl = I.calibration_1024()
     check_fullsize(wl, 300, 150, seed=3)
+
+
+def test_fullsize_valley_5120():
+    wl = I.valley_5120()
+    check_fullsize(wl, 2000, 200, seed=4)
