@@ -192,6 +192,40 @@ def adjoint_leg(steps, every):
             "loss": loss, "grad_norm": gnorm}
 
 
+def flow_dir_leg(wl, reps):
+    """The flow-direction kernel (Section 5.2) on the workload's terrain, as
+    float32 (the paper's element type) and float64: average of ``reps``
+    launches between HIP events on the current stream."""
+    import torch
+
+    from paper_1307_4839_amd.solver import flow_directions
+    out = {}
+    cells = wl.nx * wl.ny
+    for name, dt, nbytes in (("f32", torch.float32, 4), ("f64", torch.float64, 8)):
+        z = torch.as_tensor(wl.z).to(device="cuda:0", dtype=dt).contiguous()
+        code = torch.empty((wl.ny, wl.nx), dtype=torch.uint8, device="cuda:0")
+        for _ in range(3):
+            flow_directions(z, out=code)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            flow_directions(z, out=code)
+        e1.record()
+        torch.cuda.synchronize()
+        avg = e0.elapsed_time(e1) / reps
+        gbps = (nbytes + 1) * cells / (avg / 1e3) / 1e9
+        out[name] = {"avg_ms": avg, "bytes_per_cell": nbytes + 1, "GBps": round(gbps, 1),
+                     "frac": round(gbps / HBM_PEAK_GBS, 4),
+                     "cells_per_s": cells / (avg / 1e3)}
+        print(f"[bench] flow directions {name}: {avg * 1e3:.1f} us/launch, {gbps:.0f} GB/s",
+              file=sys.stderr, flush=True)
+        del z, code
+    torch.cuda.empty_cache()
+    return {"workload": f"{wl.name} terrain {wl.nx}x{wl.ny}", "launches": reps, **out}
+
+
 def paper_runs_leg(iterations):
     """Wall time of whole runs of the 5120 x 5120 valley from its initial
     state, at the iteration counts of the scaling runs of Section 6.3 (one
@@ -249,6 +283,8 @@ def main(argv=None):
     ap.add_argument("--ensemble-members", type=int, default=256)
     ap.add_argument("--ensemble-steps", type=int, default=500)
     ap.add_argument("--no-paper-runs", action="store_true")
+    ap.add_argument("--no-flow-dir", action="store_true")
+    ap.add_argument("--flow-dir-reps", type=int, default=50)
     ap.add_argument("--paper-iterations", default="5000,20000")
     args = ap.parse_args(argv)
 
@@ -360,6 +396,10 @@ def main(argv=None):
     torch.cuda.empty_cache()
     print(f"[bench] 1 GiB device copy: {copy_gbps:.0f} GB/s", file=sys.stderr, flush=True)
 
+    fdir = None
+    if not args.no_flow_dir:
+        fdir = flow_dir_leg(wl, args.flow_dir_reps)
+
     ens = None
     if not args.no_ensemble:
         del g
@@ -412,6 +452,7 @@ def main(argv=None):
         "ensemble": ens,
         "adjoint": adj,
         "paper_runs": paper,
+        "flow_directions": fdir,
         "sim_time_s": t_sim,
         "status_flags": flags,
     }

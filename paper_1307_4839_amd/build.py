@@ -16,7 +16,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libswe_mi355x.so")
-SOURCES = ["swe_step.hip", "swe_batch.hip", "swe_adjoint.hip"]
+SOURCES = ["swe_step.hip", "swe_batch.hip", "swe_adjoint.hip", "swe_flowdir.hip"]
 HEADERS = ["swe_device.h", "swe_host.h"]
 
 HIPCC_FLAGS = [

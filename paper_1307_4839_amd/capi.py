@@ -1,4 +1,5 @@
-"""ctypes binding of the C ABI declared in ``include/swe.h``.
+"""ctypes binding of the C ABI declared in ``include/swe.h`` and
+``include/swe_flowdir.h``.
 
 Argument marshalling only: every step of the method runs in the HIP
 library.  If the library has not been built the import of this module
@@ -104,6 +105,11 @@ EXPORTS = {
     "swe_adj_forward": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     "swe_adj_backward": (C.c_int, [C.c_void_p, C.c_void_p]),
     "swe_adj_get_series": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "swe_flow_dir_f32": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int32,
+                                   C.c_void_p]),
+    "swe_flow_dir_f64": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int32,
+                                   C.c_void_p]),
+    "swe_flow_dir_rows": (C.c_int, [C.c_int32, C.c_int32, C.POINTER(C.c_int32)]),
     "swe_strerror": (C.c_char_p, [C.c_int]),
 }
 
@@ -351,3 +357,19 @@ def swe_adj_backward(a: int, grad_ptr: int) -> None:
 
 def swe_adj_get_series(a: int, ptr: int) -> None:
     check(lib().swe_adj_get_series(C.c_void_p(a), C.c_void_p(ptr)), "swe_adj_get_series")
+
+
+def swe_flow_dir_f32(z: int, nx: int, ny: int, code: int, rows: int, stream: int) -> None:
+    check(lib().swe_flow_dir_f32(C.c_void_p(z), nx, ny, C.c_void_p(code), rows,
+                                 C.c_void_p(stream)), "swe_flow_dir_f32")
+
+
+def swe_flow_dir_f64(z: int, nx: int, ny: int, code: int, rows: int, stream: int) -> None:
+    check(lib().swe_flow_dir_f64(C.c_void_p(z), nx, ny, C.c_void_p(code), rows,
+                                 C.c_void_p(stream)), "swe_flow_dir_f64")
+
+
+def swe_flow_dir_rows(nx: int, ny: int) -> int:
+    r = C.c_int32(0)
+    check(lib().swe_flow_dir_rows(nx, ny, C.byref(r)), "swe_flow_dir_rows")
+    return r.value

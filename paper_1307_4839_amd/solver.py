@@ -319,3 +319,24 @@ class GaugeMisfit(torch.autograd.Function):
     def backward(ctx, grad_out):
         g = ctx.calib.backward()
         return grad_out * g, None
+
+
+def flow_directions(z: torch.Tensor, out: Optional[torch.Tensor] = None,
+                    rows: int = 0) -> torch.Tensor:
+    """Eight-neighbour flow-direction codes (0..8, uint8) of a [ny][nx]
+    float32 or float64 DEM on the GPU (Section 5.2), enqueued on the current
+    stream.  ``out`` may be given (uint8, same shape, contiguous)."""
+    if z.dim() != 2 or not z.is_cuda or z.dtype not in (torch.float32, torch.float64):
+        raise ValueError("z must be a 2-D float32 or float64 CUDA tensor")
+    z = z.contiguous()
+    ny, nx = z.shape
+    if out is None:
+        out = torch.empty((ny, nx), dtype=torch.uint8, device=z.device)
+    elif out.shape != z.shape or out.dtype != torch.uint8 or not out.is_contiguous() \
+            or out.device != z.device:
+        raise ValueError("out must be a contiguous uint8 tensor shaped like z on its device")
+    stream = torch.cuda.current_stream(z.device).cuda_stream
+    fn = capi.swe_flow_dir_f32 if z.dtype == torch.float32 else capi.swe_flow_dir_f64
+    with torch.cuda.device(z.device):
+        fn(z.data_ptr(), nx, ny, out.data_ptr(), rows, stream)
+    return out

@@ -13,19 +13,44 @@ def declared(header):
     return re.findall(r"^\s*(?:const\s+)?\w+\**\s+\**(swe_\w+)\s*\(", src, re.M)
 
 
+HEADERS = sorted(f for f in os.listdir(os.path.join(ROOT, "include")) if f.endswith(".h"))
+
+
 def test_library_exports_every_declared_symbol():
     from paper_1307_4839_amd import capi
     lib = capi.lib()
-    names = declared("swe.h")
-    assert len(names) >= 12
+    assert "swe.h" in HEADERS and "swe_flowdir.h" in HEADERS
+    names = [n for h in HEADERS for n in declared(h)]
+    assert len(names) >= 15
     missing = [n for n in names if not hasattr(lib, n)]
     assert not missing, missing
 
 
 def test_binding_covers_every_declared_symbol():
     from paper_1307_4839_amd import capi
-    names = set(declared("swe.h"))
+    names = {n for h in HEADERS for n in declared(h)}
     assert names <= set(capi.EXPORTS), names - set(capi.EXPORTS)
+
+
+def test_flow_dir_validation_without_gpu():
+    # argument checks happen on the host before any HIP call; an empty grid
+    # is a no-op that launches nothing
+    from paper_1307_4839_amd import capi
+    for fn in (capi.swe_flow_dir_f32, capi.swe_flow_dir_f64):
+        fn(0, 0, 5, 0, 0, 0)
+        fn(0, 7, 0, 0, 0, 0)
+        for args in ((0, 4, 4, 0, 0, 0),            # null buffers with cells
+                     (16, -1, 4, 16, 0, 0),         # negative size
+                     (16, 4, 4, 16, -1, 0),         # negative rows
+                     (16, 4, 4, 16, 70000, 0),      # rows too large
+                     (16, (1 << 30) + 4, 1, 16, 0, 0),
+                     (16, 1 << 20, 1 << 17, 16, 0, 0)):  # more than 2^36 cells
+            with pytest.raises(capi.SweError) as e:
+                fn(*args)
+            assert e.value.code == capi.SWE_EINVAL
+    assert capi.swe_flow_dir_rows(8192, 8192) == 16
+    assert capi.swe_flow_dir_rows(3, 3) == 4
+    assert capi.swe_flow_dir_rows(1 << 16, 1 << 16) == 64
 
 
 def test_parameter_validation_without_gpu():

@@ -1,0 +1,123 @@
+"""GPU parity of the flow-direction kernel (Section 5.2) with the oracle.
+
+Codes come from comparisons only, so the bar is bit-exact equality of every
+code, on ragged and aligned shapes (both kernel paths: four cells per lane
+and one), several rows-per-workgroup values, ties, nodata and NaN cells,
+unaligned buffers, and the full 8192 x 8192 terrain of the benchmark.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import flowdir as F
+from paper_1307_4839_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def dem(shape, seed, dtype):
+    """Terrain with plateaus (values on a coarse lattice, so ties are
+    common), nodata cells (0 and negative) and a few NaNs."""
+    rng = np.random.default_rng(seed)
+    ny, nx = shape
+    z = np.round(rng.uniform(0.0, 6.0, (ny, nx)) * 2.0) / 2.0
+    z[rng.random((ny, nx)) < 0.05] = 0.0
+    z[rng.random((ny, nx)) < 0.02] = -1.0
+    if ny * nx > 4:
+        z[rng.random((ny, nx)) < 0.01] = np.nan
+    return np.ascontiguousarray(z.astype(dtype))
+
+
+def run(torch, z, rows=0, offset=0):
+    from paper_1307_4839_amd.solver import flow_directions
+    ny, nx = z.shape
+    if offset:
+        zb = torch.empty(ny * nx + offset, dtype=torch.float32 if z.dtype == np.float32
+                         else torch.float64, device="cuda")
+        zb[offset:].copy_(torch.as_tensor(z.ravel()))
+        zt = zb[offset:].view(ny, nx)
+        ob = torch.full((ny * nx + offset,), 255, dtype=torch.uint8, device="cuda")
+        out = ob[offset:].view(ny, nx)
+    else:
+        zt = torch.as_tensor(z).cuda()
+        out = torch.full((ny, nx), 255, dtype=torch.uint8, device="cuda")
+    flow_directions(zt, out=out, rows=rows)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+SHAPES = [(1, 1), (1, 7), (7, 1), (2, 2), (3, 5), (37, 29), (64, 1024), (70, 1028),
+          (33, 1030), (129, 2052), (5, 4096)]
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_random_dem(torch_cuda, shape, dtype):
+    say(f"[flowdir] shape {shape} dtype {np.dtype(dtype).name}")
+    z = dem(shape, seed=shape[0] * 1000 + shape[1], dtype=dtype)
+    ref = F.flow_directions(z)
+    for rows in (0, 1, 3, 4, 5, 64):
+        got = run(torch_cuda, z, rows=rows)
+        assert np.array_equal(got, ref), (rows, np.argwhere(got != ref)[:5])
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_unaligned_buffers(torch_cuda, dtype):
+    # nx a multiple of 4 but buffers off their vector alignment: the
+    # one-cell-per-lane path
+    z = dem((45, 1032), seed=5, dtype=dtype)
+    ref = F.flow_directions(z)
+    for offset in (1, 2, 3):
+        say(f"[flowdir] unaligned offset {offset} dtype {np.dtype(dtype).name}")
+        assert np.array_equal(run(torch_cuda, z, rows=0, offset=offset), ref)
+
+
+def test_closed_forms_on_gpu(torch_cuda):
+    # the pit of the oracle pins, on the kernel: every code of its offset
+    n, c = 41, 20
+    r = np.arange(n)[:, None] - c
+    s = np.arange(n)[None, :] - c
+    z = (1.0 + np.sqrt(r * r + s * s)).astype(np.float32)
+    got = run(torch_cuda, z)
+    assert got[c, c] == 0
+    for d in (1, 7, 20):
+        assert [got[c + d, c], got[c - d, c], got[c, c + d], got[c, c - d],
+                got[c + d, c + d], got[c + d, c - d], got[c - d, c + d],
+                got[c - d, c - d]] == [6, 2, 4, 8, 5, 7, 3, 1]
+    assert np.array_equal(got, F.flow_directions(z))
+
+
+def test_empty_grid_is_a_noop(torch_cuda):
+    from paper_1307_4839_amd import capi
+    torch = torch_cuda
+    stream = torch.cuda.current_stream().cuda_stream
+    capi.swe_flow_dir_f32(0, 0, 9, 0, 0, stream)
+    capi.swe_flow_dir_f64(0, 9, 0, 0, 0, stream)
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_fullsize_hillslope_terrain(torch_cuda, dtype):
+    # the benchmark's input: the 8192 x 8192 hillslope bed, every cell
+    wl = I.hillslope_8192()
+    z = np.ascontiguousarray(wl.z.astype(dtype))
+    say(f"[flowdir] 8192 x 8192 {np.dtype(dtype).name}: oracle")
+    ref = F.flow_directions(z)
+    say("[flowdir] kernel")
+    got = run(torch_cuda, z)
+    assert np.array_equal(got, ref)
+    assert got.max() <= 8
