@@ -29,6 +29,7 @@ if ROOT not in sys.path:
 METRIC = "cell-updates/s (FP64) + % HBM roofline; ensemble & adjoint vs plain, same GPU"
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "counters_hillslope_8192.json")
+FLOWDIR_COUNTERS_FILE = os.path.join(ROOT, "profiles", "counters_flow_dir_8192.json")
 # FP64 VALU issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one lane-op per
 # lane per cycle; the vendor 78.6 TFLOP/s counts an FMA as two)
 VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
@@ -50,16 +51,16 @@ def algorithmic_bytes(wl):
     return rate, upd
 
 
-def load_counters():
+def load_counters(path=COUNTERS_FILE, sources=None):
     """Counters measured on the current kernel sources (committed summary of
     rocprofv3 runs of this benchmark), or None."""
     from paper_1307_4839_amd.build import source_hash
     try:
-        with open(COUNTERS_FILE) as f:
+        with open(path) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_sha256_16") != source_hash():
+    if rec.get("kernel_sha256_16") != source_hash(sources):
         return None
     return rec
 
@@ -198,9 +199,12 @@ def flow_dir_leg(wl, reps):
     launches between HIP events on the current stream."""
     import torch
 
+    from paper_1307_4839_amd.build import FLOWDIR_SOURCES
     from paper_1307_4839_amd.solver import flow_directions
     out = {}
     cells = wl.nx * wl.ny
+    cnt = load_counters(FLOWDIR_COUNTERS_FILE, FLOWDIR_SOURCES) \
+        if (wl.nx, wl.ny) == (8192, 8192) else None
     for name, dt, nbytes in (("f32", torch.float32, 4), ("f64", torch.float64, 8)):
         z = torch.as_tensor(wl.z).to(device="cuda:0", dtype=dt).contiguous()
         code = torch.empty((wl.ny, wl.nx), dtype=torch.uint8, device="cuda:0")
@@ -216,8 +220,14 @@ def flow_dir_leg(wl, reps):
         torch.cuda.synchronize()
         avg = e0.elapsed_time(e1) / reps
         gbps = (nbytes + 1) * cells / (avg / 1e3) / 1e9
-        out[name] = {"avg_ms": avg, "bytes_per_cell": nbytes + 1, "GBps": round(gbps, 1),
-                     "frac": round(gbps / HBM_PEAK_GBS, 4),
+        traffic = None
+        kname = f"flow_dir_kernel<{'float' if name == 'f32' else 'double'}, 4>"
+        if cnt and kname in cnt["kernels"]:
+            traffic = round(cnt["kernels"][kname]["bytes_per_launch"])
+        out[name] = {"bound": "hbm", "avg_ms": avg, "bytes_per_cell": nbytes + 1,
+                     "achieved": round(gbps, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(gbps / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "algorithmic_bytes_per_launch": (nbytes + 1) * cells,
                      "cells_per_s": cells / (avg / 1e3)}
         print(f"[bench] flow directions {name}: {avg * 1e3:.1f} us/launch, {gbps:.0f} GB/s",
               file=sys.stderr, flush=True)

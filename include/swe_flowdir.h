@@ -51,8 +51,11 @@ int swe_flow_dir_f32(const float* z, int32_t nx, int32_t ny, uint8_t* code,
 int swe_flow_dir_f64(const double* z, int32_t nx, int32_t ny, uint8_t* code,
                      int32_t rows, void* hip_stream);
 
-/* Rows per workgroup that swe_flow_dir_* uses for rows == 0 (host only). */
-int swe_flow_dir_rows(int32_t nx, int32_t ny, int32_t* rows);
+/* Rows per workgroup that swe_flow_dir_f32 (elem_bytes 4) or
+ * swe_flow_dir_f64 (elem_bytes 8) uses for rows == 0, before any raise for
+ * the grid limit.  Host only; SWE_EINVAL for other elem_bytes, negative
+ * sizes or a null rows. */
+int swe_flow_dir_rows(int32_t nx, int32_t ny, int32_t elem_bytes, int32_t* rows);
 
 #ifdef __cplusplus
 }

@@ -38,12 +38,17 @@ STAGE_SOURCES = [os.path.join(CSRC, f) for f in ("swe_device.h", "swe_host.h", "
     os.path.join(INCLUDE, "swe.h")]
 
 
-def source_hash() -> str:
-    """Short hash of the sources of the stage kernels (names and contents),
-    which ties measured counters to a kernel version."""
+# the files the flow-direction kernel is built from
+FLOWDIR_SOURCES = [os.path.join(CSRC, "swe_flowdir.hip"), os.path.join(INCLUDE, "swe_flowdir.h"),
+                   os.path.join(INCLUDE, "swe.h")]
+
+
+def source_hash(paths=None) -> str:
+    """Short hash of kernel sources (names and contents; the stage kernels'
+    by default), which ties measured counters to a kernel version."""
     import hashlib
     h = hashlib.sha256()
-    for path in STAGE_SOURCES:
+    for path in (STAGE_SOURCES if paths is None else paths):
         with open(path, "rb") as f:
             h.update(os.path.basename(path).encode())
             h.update(f.read())

@@ -109,7 +109,7 @@ EXPORTS = {
                                    C.c_void_p]),
     "swe_flow_dir_f64": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int32,
                                    C.c_void_p]),
-    "swe_flow_dir_rows": (C.c_int, [C.c_int32, C.c_int32, C.POINTER(C.c_int32)]),
+    "swe_flow_dir_rows": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_int32)]),
     "swe_strerror": (C.c_char_p, [C.c_int]),
 }
 
@@ -369,7 +369,7 @@ def swe_flow_dir_f64(z: int, nx: int, ny: int, code: int, rows: int, stream: int
                                  C.c_void_p(stream)), "swe_flow_dir_f64")
 
 
-def swe_flow_dir_rows(nx: int, ny: int) -> int:
+def swe_flow_dir_rows(nx: int, ny: int, elem_bytes: int) -> int:
     r = C.c_int32(0)
-    check(lib().swe_flow_dir_rows(nx, ny, C.byref(r)), "swe_flow_dir_rows")
+    check(lib().swe_flow_dir_rows(nx, ny, elem_bytes, C.byref(r)), "swe_flow_dir_rows")
     return r.value

@@ -5,9 +5,10 @@
 // lanes owns a strip of 256*V columns (V = 4 cells per lane on aligned
 // rows, else 1) and marches down `rows` grid rows, keeping its columns
 // (plus one column on each side) of the rows around the current one in
-// registers: every row is loaded once per strip, in batches of four rows
-// whose loads are all in flight together, and the two halo rows of a
-// segment are the only re-reads.
+// registers: every row is loaded once per strip, in batches of two rows
+// whose loads are in flight together, and the two halo rows of a segment
+// are the only re-reads.  Codes are written with non-temporal stores (they
+// are not read again by the kernel).
 //
 // Cells outside the grid read as elevation 0, which the strictly-positive
 // test never selects, so the boundary needs no special case.
@@ -21,7 +22,10 @@
 namespace {
 
 constexpr int FD_THREADS = 256;
-constexpr int FD_BATCH = 4;  // rows loaded together per lane
+// rows loaded together per lane: two keeps the kernel within 64 VGPRs (8
+// waves per SIMD), which measured faster than four or eight rows in flight
+// per lane at 7 or 5 waves, and than one row with no overlap at all
+constexpr int FD_BATCH = 2;
 
 template <typename T, int V>
 struct Row {
@@ -133,9 +137,12 @@ __global__ __launch_bounds__(FD_THREADS) void flow_dir_kernel(const T* __restric
     }
 }
 
-int default_rows(long long nx, long long ny) {
+// About 4096 workgroups of 1024 columns for float32 and 16384 for float64
+// (measured optimum on 8192 x 8192: 16 and 4 rows).
+int default_rows(long long nx, long long ny, int elem_bytes) {
+    const int shift = elem_bytes == 8 ? 24 : 22;
     long long cells = nx * ny;
-    long long r = (cells + (1LL << 22) - 1) >> 22;  // about 4096 workgroups of 1024 columns
+    long long r = (cells + (1LL << shift) - 1) >> shift;
     if (r < 4) r = 4;
     if (r > 64) r = 64;
     return (int)r;
@@ -157,7 +164,7 @@ int flow_dir_launch(const T* z, int32_t nx, int32_t ny, uint8_t* code, int32_t r
                      reinterpret_cast<uintptr_t>(code) % 4 == 0;
     const int width = FD_THREADS * (vec ? 4 : 1);
     const long long strips = (nx + width - 1) / width;
-    long long r = rows > 0 ? rows : default_rows(nx, ny);
+    long long r = rows > 0 ? rows : default_rows(nx, ny, (int)sizeof(T));
     // one-dimensional grid of strips x segments
     while (strips * ((ny + r - 1) / r) > 0x7fffffffLL) r *= 2;
     const long long blocks = strips * ((ny + r - 1) / r);
@@ -183,8 +190,8 @@ extern "C" int swe_flow_dir_f64(const double* z, int32_t nx, int32_t ny, uint8_t
     return flow_dir_launch<double>(z, nx, ny, code, rows, hip_stream);
 }
 
-extern "C" int swe_flow_dir_rows(int32_t nx, int32_t ny, int32_t* rows) {
-    if (!rows || nx < 0 || ny < 0) return SWE_EINVAL;
-    *rows = default_rows(nx, ny);
+extern "C" int swe_flow_dir_rows(int32_t nx, int32_t ny, int32_t elem_bytes, int32_t* rows) {
+    if (!rows || nx < 0 || ny < 0 || (elem_bytes != 4 && elem_bytes != 8)) return SWE_EINVAL;
+    *rows = default_rows(nx, ny, elem_bytes);
     return SWE_OK;
 }

@@ -1,4 +1,4 @@
-"""Summaries of rocprofv3 output (rocpd SQLite databases) for the stage kernels.
+"""Summaries of rocprofv3 output (rocpd SQLite databases) for the library's kernels.
 
     python -m paper_1307_4839_amd.rocprof_summary trace RESULTS.db [--skip NAME=K ...]
 
@@ -10,7 +10,14 @@ whose timed region starts after them.
     python -m paper_1307_4839_amd.rocprof_summary counters --fetch DB --write DB \\
         [--sq DB] --skip K --cells N --bytes1 B1 --bytes2 B2 --json OUT.json
 
-per stage kernel: FETCH_SIZE and WRITE_SIZE (KiB per dispatch) averaged over
+    python -m paper_1307_4839_amd.rocprof_summary kernel --fetch DB --write DB \\
+        --expect NAME=BYTES [...] --skip K --sources flowdir --json OUT.json
+
+the same copy-calibrated FETCH_SIZE / WRITE_SIZE figures for every kernel
+whose name contains NAME (one entry per full kernel name), against BYTES
+algorithmic bytes per launch.
+
+For ``counters``, per stage kernel: FETCH_SIZE and WRITE_SIZE (KiB per dispatch) averaged over
 the dispatches after the first K, scaled by what the same counters read for
 the plain device copy in the same runs (the largest __amd_rocclr_copyBuffer
 dispatch, of known size 2^30 bytes each way), next to the algorithmic bytes
@@ -128,6 +135,42 @@ def counters(a) -> dict:
     return rec
 
 
+def kernel_counters(a) -> dict:
+    from . import build
+    paths = build.FLOWDIR_SOURCES if a.sources == "flowdir" else build.STAGE_SOURCES
+    cf = _copy_counter(a.fetch, "FETCH_SIZE")
+    cw = _copy_counter(a.write, "WRITE_SIZE")
+    ff = COPY_BYTES / 1024.0 / cf
+    fw = COPY_BYTES / 1024.0 / cw
+    expect = {}
+    for e in a.expect:
+        k, v = e.rsplit("=", 1)
+        expect[k] = int(v)
+    fetch, write = _counters(a.fetch), _counters(a.write)
+    rec = {"kernel_sha256_16": build.source_hash(paths), "workload": a.workload,
+           "calibration": {"probe": "1 GiB device-to-device copy (__amd_rocclr_copyBuffer)",
+                           "fetch_KiB": cf, "write_KiB": cw,
+                           "fetch_factor": ff, "write_factor": fw},
+           "kernels": {}}
+    for name in sorted(fetch):
+        key = next((k for k in expect if k in name), None)
+        if key is None or name not in write:
+            continue
+        fr = [c["FETCH_SIZE"] for _, c in fetch[name][a.skip:] if "FETCH_SIZE" in c]
+        wr = [c["WRITE_SIZE"] for _, c in write[name][a.skip:] if "WRITE_SIZE" in c]
+        if not fr or not wr:
+            continue
+        fk, wk = sum(fr) / len(fr), sum(wr) / len(wr)
+        fb, wb = fk * 1024.0 * ff, wk * 1024.0 * fw
+        short = name.replace("void ", "").replace("(anonymous namespace)::", "").split("(")[0]
+        rec["kernels"][short] = {
+            "name": name, "dispatches": len(fr), "fetch_KiB_raw": fk, "write_KiB_raw": wk,
+            "fetch_bytes": fb, "write_bytes": wb, "bytes_per_launch": fb + wb,
+            "algorithmic_bytes_per_launch": expect[key],
+            "traffic_over_algorithmic": (fb + wb) / expect[key]}
+    return rec
+
+
 def counters_text(rec: dict) -> str:
     c = rec["calibration"]
     out = [f"calibration: the 1 GiB copy reads FETCH_SIZE = {c['fetch_KiB']:.0f} KiB and "
@@ -167,6 +210,15 @@ def main(argv=None):
     c.add_argument("--bytes2", type=int, required=True)
     c.add_argument("--workload", default="")
     c.add_argument("--json")
+    k = sub.add_parser("kernel")
+    k.add_argument("--fetch", required=True)
+    k.add_argument("--write", required=True)
+    k.add_argument("--expect", action="append", default=[],
+                   help="NAME=BYTES: algorithmic bytes per launch of kernels matching NAME")
+    k.add_argument("--skip", type=int, default=0)
+    k.add_argument("--sources", choices=["stage", "flowdir"], default="stage")
+    k.add_argument("--workload", default="")
+    k.add_argument("--json")
     a = ap.parse_args(argv)
     if a.cmd == "trace":
         skip = {}
@@ -175,7 +227,7 @@ def main(argv=None):
             skip[k] = int(v)
         print(trace(a.db, skip))
         return 0
-    rec = counters(a)
+    rec = kernel_counters(a) if a.cmd == "kernel" else counters(a)
     if a.json:
         with open(a.json, "w") as f:
             json.dump(rec, f, indent=1)

@@ -48,9 +48,12 @@ def test_flow_dir_validation_without_gpu():
             with pytest.raises(capi.SweError) as e:
                 fn(*args)
             assert e.value.code == capi.SWE_EINVAL
-    assert capi.swe_flow_dir_rows(8192, 8192) == 16
-    assert capi.swe_flow_dir_rows(3, 3) == 4
-    assert capi.swe_flow_dir_rows(1 << 16, 1 << 16) == 64
+    assert capi.swe_flow_dir_rows(8192, 8192, 4) == 16
+    assert capi.swe_flow_dir_rows(8192, 8192, 8) == 4
+    assert capi.swe_flow_dir_rows(3, 3, 4) == 4
+    assert capi.swe_flow_dir_rows(1 << 16, 1 << 16, 4) == 64
+    with pytest.raises(capi.SweError):
+        capi.swe_flow_dir_rows(8, 8, 2)
 
 
 def test_parameter_validation_without_gpu():
