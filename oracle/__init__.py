@@ -43,7 +43,11 @@ class OrcParams(C.Structure):
                 ("bc", C.c_int32 * 4), ("fric_law", C.c_int32),
                 ("fric_coef", C.c_double), ("rain", C.c_double),
                 ("infil_on", C.c_int32), ("ks", C.c_double),
-                ("psi", C.c_double), ("dtheta", C.c_double)]
+                ("psi", C.c_double), ("dtheta", C.c_double),
+                ("rain_n", C.c_int32), ("rain_t", C.POINTER(C.c_double)),
+                ("rain_r", C.POINTER(C.c_double)), ("rain_w", C.POINTER(C.c_double)),
+                ("ks_f", C.POINTER(C.c_double)), ("psi_f", C.POINTER(C.c_double)),
+                ("dtheta_f", C.POINTER(C.c_double))]
 
 
 _lib = None
@@ -64,7 +68,7 @@ def lib(path: Optional[str] = None):
         l.orc_time_step.restype = C.c_double
         l.orc_run.argtypes = [pp, dp, dp, dp, dp, dp, dp, dp, C.c_double,
                               C.c_int32, dp, ip]
-        l.orc_step_fixed.argtypes = [pp, C.c_double, dp, dp, dp, dp, dp, dp]
+        l.orc_step_fixed.argtypes = [pp, C.c_double, C.c_double, dp, dp, dp, dp, dp, dp]
         l.orc_minmod.argtypes = [C.c_double, C.c_double]
         l.orc_minmod.restype = C.c_double
         l.orc_num_threads.restype = C.c_int
@@ -108,8 +112,33 @@ def params(nx, ny, dx, dy, g=9.81, cfl=0.5, dt_max=math.inf, h_eps=1e-12,
     return p
 
 
+_KEEP = "_arrays"
+
+
 def params_of(wl) -> OrcParams:
-    return params(**wl.params())
+    """Parameters of a workload, with its hyetograph and per-cell rain and
+    Green-Ampt fields attached (the arrays are kept alive on the struct)."""
+    p = params(**wl.params())
+    keep = []
+
+    def attach(name, a):
+        if a is None:
+            return
+        a = _f64(a)
+        keep.append(a)
+        setattr(p, name, _dp(a))
+
+    if wl.rain_t is not None:
+        assert wl.rain_r is not None and len(wl.rain_t) == len(wl.rain_r)
+        p.rain_n = len(wl.rain_t)
+        attach("rain_t", wl.rain_t)
+        attach("rain_r", wl.rain_r)
+    attach("rain_w", wl.rain_w)
+    attach("ks_f", wl.ks_f)
+    attach("psi_f", wl.psi_f)
+    attach("dtheta_f", wl.dtheta_f)
+    setattr(p, _KEEP, keep)
+    return p
 
 
 def _f64(a):
@@ -181,7 +210,7 @@ class State:
         return rc
 
     def step_fixed(self, dt: float):
-        rc = lib().orc_step_fixed(C.byref(self.p), dt, _dp(self.h),
+        rc = lib().orc_step_fixed(C.byref(self.p), self.t, dt, _dp(self.h),
                                   _dp(self.qx), _dp(self.qy), _dp(self.z),
                                   _dp(self.fric), _dp(self.vinf))
         assert rc == 0

@@ -116,6 +116,17 @@ struct orc_params {
     double rain;
     int32_t infil_on;
     double ks, psi, dtheta;
+    // R(t, x, y) = r(t) w(x, y) (Section 2.1 lets rain vary in time and
+    // space).  r(t) is the piecewise-constant hyetograph: r_k from t_k up to
+    // t_{k+1}, 0 before t_0; with rain_n = 0 it is the constant `rain`.
+    int32_t rain_n;
+    const double* rain_t;
+    const double* rain_r;
+    const double* rain_w;    // per-cell weight w, or NULL for 1
+    // per-cell Green-Ampt parameters (Section 3.5), or NULL for the scalars
+    const double* ks_f;
+    const double* psi_f;
+    const double* dtheta_f;
 };
 }
 
@@ -489,19 +500,34 @@ double time_step(const orc_params& p, const double amax[2], double t, double t_e
     return dt;
 }
 
+// Rain intensity r(t) of the hyetograph at the start time t of a step
+// (rain is explicit, Section 3.1): the last breakpoint at or before t.
+inline double rain_rate(const orc_params& p, double t) {
+    if (p.rain_n <= 0) return p.rain;
+    double r = 0.0;
+    for (int32_t k = 0; k < p.rain_n; ++k)
+        if (p.rain_t[k] <= t) r = p.rain_r[k];
+    return r;
+}
+
 // Once per step after Heun's combination (reading): explicit rain, then the
 // modified Green-Ampt model of Section 3.5 with A = 1 and the capillary term
 // read as (psi + h_over)/Z_f with psi >= 0 the suction head.  The water that
 // infiltrates leaves with the cell's velocity (reading: q scales with h).
+// `r` is the step's rain intensity r(t); cell s takes r w_s.
 template <class T>
-inline void rain_infiltration(const orc_params& p, double dt, T& h, T& qx,
-                              T& qy, T* vinf) {
-    h = h + T(dt) * T(p.rain);
+inline void rain_infiltration(const orc_params& p, double dt, double r, size_t s, T& h,
+                              T& qx, T& qy, T* vinf) {
+    const double rate = p.rain_w ? r * p.rain_w[s] : r;
+    h = h + T(dt) * T(rate);
     if (!p.infil_on) return;
+    const double ks = p.ks_f ? p.ks_f[s] : p.ks;
+    const double psi = p.psi_f ? p.psi_f[s] : p.psi;
+    const double dtheta = p.dtheta_f ? p.dtheta_f[s] : p.dtheta;
     T d;
     if (*vinf > T(0.0)) {
-        T zf = *vinf / T(p.dtheta);                           // Z_f = V_inf / (theta_s - theta_i)
-        T ic = T(p.ks) * (T(1.0) + (T(p.psi) + h) / zf);      // I_C
+        T zf = *vinf / T(dtheta);                             // Z_f = V_inf / (theta_s - theta_i)
+        T ic = T(ks) * (T(1.0) + (T(psi) + h) / zf);          // I_C
         d = vmin(h, T(dt) * ic);                              // dt I = min(h_over, dt I_C)
     } else {
         d = h;  // Z_f = 0: unbounded capacity, all available water infiltrates
@@ -516,11 +542,13 @@ inline void rain_infiltration(const orc_params& p, double dt, T& h, T& qx,
     }
 }
 
-// One full time step with a given dt (Algorithm 1: two stages, then Heun).
+// One full time step from time t with a given dt (Algorithm 1: two stages,
+// then Heun).
 template <class T>
-void step_fixed(const orc_params& p, const T* fric, double dt, T* h, T* qx,
+void step_fixed(const orc_params& p, const T* fric, double t, double dt, T* h, T* qx,
                 T* qy, const double* z, T* vinf) {
     size_t n = (size_t)p.nx * p.ny;
+    const double r = rain_rate(p, t);
     std::vector<T> h1(n), qx1(n), qy1(n), h2(n), qx2(n), qy2(n);
     stage(p, fric, dt, h, qx, qy, z, h1.data(), qx1.data(), qy1.data(), nullptr);
     stage(p, fric, dt, h1.data(), qx1.data(), qy1.data(), z, h2.data(), qx2.data(),
@@ -531,7 +559,7 @@ void step_fixed(const orc_params& p, const T* fric, double dt, T* h, T* qx,
         T qxn = T(0.5) * (qx[s] + qx2[s]);
         T qyn = T(0.5) * (qy[s] + qy2[s]);
         T vdummy = T(0.0);
-        rain_infiltration(p, dt, hn, qxn, qyn, vinf ? &vinf[s] : &vdummy);
+        rain_infiltration(p, dt, r, s, hn, qxn, qyn, vinf ? &vinf[s] : &vdummy);
         h[s] = hn;
         qx[s] = qxn;
         qy[s] = qyn;
@@ -598,7 +626,7 @@ int orc_run(const orc_params* p, double* h, double* qx, double* qy,
         double dt = time_step(*p, amax, *t, t_end);
         if (!std::isfinite(dt)) { rc = -7; break; }
         if (!(dt > 0.0)) { rc = 1; break; }
-        step_fixed<double>(*p, fric, dt, h, qx, qy, z, vinf);
+        step_fixed<double>(*p, fric, *t, dt, h, qx, qy, z, vinf);
         *t = *t + dt;
         if (dt_log) dt_log[k] = dt;
         int f = check_state(n, h, qx, qy);
@@ -609,12 +637,13 @@ int orc_run(const orc_params* p, double* h, double* qx, double* qy,
     return rc;
 }
 
-// One step with an imposed dt (used for windowed checks of large grids).
-int orc_step_fixed(const orc_params* p, double dt, double* h, double* qx,
+// One step from time t with an imposed dt (used for windowed checks of
+// large grids).
+int orc_step_fixed(const orc_params* p, double t, double dt, double* h, double* qx,
                    double* qy, const double* z, const double* fric,
                    double* vinf) {
     if (!p || p->nx < 1 || p->ny < 1) return -1;
-    step_fixed<double>(*p, fric, dt, h, qx, qy, z, vinf);
+    step_fixed<double>(*p, fric, t, dt, h, qx, qy, z, vinf);
     return 0;
 }
 
@@ -679,9 +708,11 @@ int orc_tangent_run(const orc_params* p, const double* h0, const double* qx0,
     }
     Dual L(0.0);
     int obs_row = 0;
+    double t = 0.0;
     for (int32_t k = 0; k < nsteps; ++k) {
-        step_fixed<Dual>(*p, fr.data(), dts[k], h.data(), qx.data(), qy.data(), z,
+        step_fixed<Dual>(*p, fr.data(), t, dts[k], h.data(), qx.data(), qy.data(), z,
                          nullptr);
+        t = t + dts[k];
         if (every > 0 && (k + 1) % every == 0) {
             for (int32_t m = 0; m < ngauges; ++m) {
                 Dual e = h[gauges[m]] - Dual(obs[(size_t)obs_row * ngauges + m]);
@@ -703,8 +734,10 @@ int orc_gauge_run(const orc_params* p, double* h, double* qx, double* qy,
                   int32_t every, double* out) {
     if (!p || p->nx < 1 || p->ny < 1) return -1;
     int row = 0;
+    double t = 0.0;
     for (int32_t k = 0; k < nsteps; ++k) {
-        step_fixed<double>(*p, fric, dts[k], h, qx, qy, z, nullptr);
+        step_fixed<double>(*p, fric, t, dts[k], h, qx, qy, z, nullptr);
+        t = t + dts[k];
         if (every > 0 && (k + 1) % every == 0) {
             for (int32_t m = 0; m < ngauges; ++m)
                 out[(size_t)row * ngauges + m] = h[gauges[m]];

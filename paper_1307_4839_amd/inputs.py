@@ -83,6 +83,16 @@ class Workload:
     psi: float = 0.0
     dtheta: float = 0.0
     vinf: Optional[np.ndarray] = None
+    # rain R(t, x, y) = r(t) w(x, y): piecewise-constant hyetograph r (values
+    # rain_r [m/s] from breakpoints rain_t [s]; `rain` when absent) and a
+    # per-cell weight w (1 when absent)
+    rain_t: Optional[np.ndarray] = None
+    rain_r: Optional[np.ndarray] = None
+    rain_w: Optional[np.ndarray] = None
+    # per-cell Green-Ampt parameters (the scalars when absent)
+    ks_f: Optional[np.ndarray] = None
+    psi_f: Optional[np.ndarray] = None
+    dtheta_f: Optional[np.ndarray] = None
     t_end: float = math.inf
     nsteps: int = 0
     gauges: Optional[np.ndarray] = None  # flat cell indices
@@ -98,7 +108,8 @@ class Workload:
 
     def copy(self) -> "Workload":
         out = dataclasses.replace(self)
-        for f in ("z", "h", "qx", "qy", "fric", "vinf", "gauges"):
+        for f in ("z", "h", "qx", "qy", "fric", "vinf", "gauges", "rain_t", "rain_r",
+                  "rain_w", "ks_f", "psi_f", "dtheta_f"):
             a = getattr(self, f)
             if a is not None:
                 setattr(out, f, a.copy())

@@ -36,8 +36,20 @@ MUTANTS = {
     "manning_exponent": ("(h1 * dcbrt(h1))", "(h1 * h1)"),
     "heun_average": ("T hn = T(0.5) * (h[s] + h2[s]);", "T hn = h2[s];"),
     "cfl_drop_y": ("double r = amax[0] / p.dx + amax[1] / p.dy;", "double r = amax[0] / p.dx;"),
-    "green_ampt_sign": ("(T(p.psi) + h) / zf", "(T(p.psi) - h) / zf"),
-    "rain_missing_dt": ("h = h + T(dt) * T(p.rain);", "h = h + T(p.rain);"),
+    "green_ampt_sign": ("(T(psi) + h) / zf", "(T(psi) - h) / zf"),
+    "rain_missing_dt": ("h = h + T(dt) * T(rate);", "h = h + T(rate);"),
+    "hyetograph_open_interval": ("if (p.rain_t[k] <= t) r = p.rain_r[k];",
+                                 "if (p.rain_t[k] < t) r = p.rain_r[k];"),
+    "hyetograph_next_value": ("if (p.rain_t[k] <= t) r = p.rain_r[k];",
+                              "if (p.rain_t[k] <= t) r = p.rain_r[k + 1 < p.rain_n ? k + 1 : k];"),
+    "rain_weight_ignored": ("const double rate = p.rain_w ? r * p.rain_w[s] : r;",
+                            "const double rate = r;"),
+    "ga_ks_field_ignored": ("const double ks = p.ks_f ? p.ks_f[s] : p.ks;",
+                            "const double ks = p.ks;"),
+    "ga_psi_field_ignored": ("const double psi = p.psi_f ? p.psi_f[s] : p.psi;",
+                             "const double psi = p.psi;"),
+    "ga_dtheta_field_ignored": ("const double dtheta = p.dtheta_f ? p.dtheta_f[s] : p.dtheta;",
+                                "const double dtheta = p.dtheta;"),
 }
 
 

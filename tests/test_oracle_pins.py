@@ -409,6 +409,81 @@ def test_rain_only():
     assert np.all(s.qx == 0) and np.all(s.qy == 0)
 
 
+# R(t, x, y) = r(t) w(x, y) (Section 2.1: rain may vary in time and space;
+# rain is explicit, Section 3.1, so a step takes the rate at its start).
+# With dt fixed at 0.5 s every step starts on a multiple of 0.5, so the
+# hyetograph below gives, by hand: no rain before its first breakpoint at
+# 1.0 s (2 steps), 10 mm/h for the steps at 1.0 and 1.5 (2), 40 mm/h at
+# 2.0, 2.5, 3.0 (3: the breakpoint at 2.0 applies to the step starting
+# there), 0 from 3.25 (the step at 3.5), 20 mm/h at 4.0 ... 5.5 (4):
+# depth = 0.5 s x (2 x 10 + 3 x 40 + 4 x 20) mm/h.
+HYETO_T = np.array([1.0, 2.0, 3.25, 4.0])
+HYETO_R = np.array([10.0, 40.0, 0.0, 20.0]) * I.MM_PER_HOUR
+
+
+def test_hyetograph_rain_only():
+    wl = flat_workload(6, 5, bc=(0, 0, 0, 0), dt_max=0.5, rain=99.0,
+                       rain_t=HYETO_T, rain_r=HYETO_R)
+    s = oracle.State(wl)
+    assert s.run(12) == 0
+    assert s.dts == [0.5] * 12
+    expect = 0.5 * (2 * 10.0 + 3 * 40.0 + 4 * 20.0) * I.MM_PER_HOUR
+    assert np.all(np.abs(s.h - expect) <= 1e-15 * expect)
+    assert np.all(s.qx == 0) and np.all(s.qy == 0)
+
+
+def test_rain_weight_mass_balance():
+    # a spatial weight makes the depth uneven, so water moves; the total
+    # stays sum_k dt_k r(t_k) sum(w) dx dy under walls (Section 4.1)
+    rng = np.random.default_rng(4)
+    w = rng.uniform(0.0, 2.0, (9, 11))
+    wl = flat_workload(11, 9, dx=2.0, dy=1.5, bc=(0, 0, 0, 0), dt_max=0.5,
+                       rain_t=HYETO_T, rain_r=HYETO_R, rain_w=w,
+                       fric_law=I.FRIC_MANNING, fric_coef=0.03)
+    s = oracle.State(wl)
+    assert s.run(12) == 0
+    assert s.dts == [0.5] * 12
+    per_w = 0.5 * (2 * 10.0 + 3 * 40.0 + 4 * 20.0) * I.MM_PER_HOUR
+    expect = per_w * math.fsum(w.ravel()) * 2.0 * 1.5
+    got = math.fsum(s.h.ravel()) * 2.0 * 1.5
+    assert abs(got - expect) <= 1e-13 * expect
+    assert np.abs(s.qx).max() > 0  # the uneven rain did set water moving
+
+
+def test_green_ampt_fields_two_zones():
+    # Per-cell K_s, psi, dtheta (Section 3.5 with spatially varying soil):
+    # two soils on either side of a 1 m ridge under uniform rain.  Before a
+    # zone ponds its depth stays 0, so each zone's far cell ponds at its own
+    # Mein-Larson time t_p = F_p / R, F_p = psi dtheta K_s / (R - K_s),
+    # whatever the scalar parameters say.
+    R = 50 * I.MM_PER_HOUR
+    nx, dt = 21, 0.5
+    zA = (1e-6, 0.1, 0.4)
+    zB = (2e-6, 0.2, 0.3)
+    fields = [np.zeros((1, nx)) for _ in range(3)]
+    for k in range(3):
+        fields[k][0, :11] = zA[k]
+        fields[k][0, 11:] = zB[k]
+    z = np.zeros((1, nx))
+    z[0, 10] = 1.0
+    wl = flat_workload(nx, 1, bc=(0, 0, 0, 0), rain=R, infil_on=1, ks=4e-6, psi=0.05,
+                       dtheta=0.25, dt_max=dt, ks_f=fields[0], psi_f=fields[1],
+                       dtheta_f=fields[2])
+    wl.z = z
+    wl.vinf = np.zeros((1, nx))
+    s = oracle.State(wl)
+    pond = {}
+    for k in range(1700):
+        s.run(1)
+        for name, col in (("A", 0), ("B", nx - 1)):
+            if name not in pond and s.h[0, col] > 0:
+                pond[name] = s.t
+    for name, (ks, psi, dth) in (("A", zA), ("B", zB)):
+        tp = psi * dth * ks / (R - ks) / R
+        assert name in pond and abs(pond[name] - tp) <= 2 * dt, (name, pond.get(name), tp)
+    assert pond["B"] > pond["A"] + 400.0
+
+
 # ---------------------------------------------------------------------------
 # P13: Green-Ampt ponding (Section 3.5, reading A = 1, capacity
 # Ks (1 + (psi + h) dtheta / V)): under constant rain R > Ks all water
