@@ -79,6 +79,12 @@ typedef struct swe_params {
     double dtheta;       /* theta_s - theta_i, > 0 */
 } swe_params;
 
+/* Optional per-cell fields below are read only, [ny][nx] FP64 device
+ * arrays like the state; NULL selects the scalar of swe_params.  Rain is
+ * R(t, x, y) = r(t) rain_w(x, y) (Section 2.1 lets R vary in time and
+ * space), with r(t) the hyetograph of swe_set_hyetograph or the constant
+ * swe_params.rain.  Values are used as given (a negative weight or
+ * conductivity is not rejected; the status flags report what follows). */
 typedef struct swe_buffers {
     double* h;           /* water depth (in/out) */
     double* qx;          /* discharge along x (in/out) */
@@ -87,7 +93,14 @@ typedef struct swe_buffers {
     const double* fric;  /* per-cell friction coefficient, or NULL */
     double* vinf;        /* infiltrated volume per unit area (in/out); NULL
                             unless infil_on */
+    const double* rain_w;  /* rain weight w >= 0 (dimensionless), or NULL */
+    const double* ks;      /* Green-Ampt K_s [m/s] per cell, or NULL */
+    const double* psi;     /* Green-Ampt suction head >= 0 [m], or NULL */
+    const double* dtheta;  /* theta_s - theta_i > 0 per cell, or NULL */
 } swe_buffers;
+
+/* largest number of hyetograph breakpoints */
+#define SWE_HYETO_MAX 128
 
 typedef struct swe_ctx swe_ctx;
 
@@ -100,7 +113,8 @@ typedef struct swe_diag {
 
 /* Size in bytes of the device workspace a context needs for these
  * parameters: a second state (3 nx ny doubles), the stage rate Phi
- * (3 nx ny doubles) and a 256-byte block of device scalars. */
+ * (3 nx ny doubles) and a block of device scalars (time, step count,
+ * wave-speed accumulators, hyetograph; about 8 KB). */
 int swe_workspace_bytes(const swe_params* p, size_t* bytes);
 
 /* Create a context.  `workspace` is caller-owned device memory of at least
@@ -124,8 +138,19 @@ int swe_get_tiling(swe_ctx* ctx, int32_t* tx, int32_t* ty);
 /* Stream-ordered update of the simulated time t [s]. */
 int swe_set_time(swe_ctx* ctx, double t);
 
-/* Rain intensity [m/s] for steps enqueued after this call. */
+/* Rain intensity [m/s] for steps enqueued after this call (used while no
+ * hyetograph is set). */
 int swe_set_rain(swe_ctx* ctx, double rain);
+
+/* Hyetograph r(t) (Section 2.1: R depends on t): a step from time t rains
+ * r[k] for the last k with t_pts[k] <= t (rain is explicit, so the rate at
+ * the start of the step holds for the whole step), and 0 when t < t_pts[0].
+ * Host arrays of n values, copied: 1 <= n <= SWE_HYETO_MAX, t_pts finite
+ * and strictly increasing, r finite and >= 0 [m/s]; n == 0 (pointers may be
+ * NULL) removes the hyetograph.  The copy is stream-ordered after the steps
+ * enqueued before it, and the call synchronizes the stream before it
+ * returns.  SWE_EINVAL for invalid tables, SWE_EHIP if the copy fails. */
+int swe_set_hyetograph(swe_ctx* ctx, const double* t_pts, const double* r, int32_t n);
 
 /* Optional device log of time steps: step k (counted from context creation)
  * writes its dt to log[k] while k < capacity.  NULL disables. */
@@ -203,6 +228,9 @@ int swe_batch_autotune(swe_batch* b, int32_t trial_steps, int32_t* tx, int32_t* 
                        double* ms_per_step);
 
 int swe_batch_set_rain(swe_batch* b, int32_t member, double rain);
+/* swe_set_hyetograph for one member (same rules; synchronizes). */
+int swe_batch_set_hyetograph(swe_batch* b, int32_t member, const double* t_pts,
+                             const double* r, int32_t n);
 int swe_batch_set_dt_log(swe_batch* b, int32_t member, double* dev_log, int64_t capacity);
 
 /* Enqueue `nsteps` steps of every member (members stop at t_end). */

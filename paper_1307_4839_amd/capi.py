@@ -46,7 +46,12 @@ class swe_params(C.Structure):
 
 class swe_buffers(C.Structure):
     _fields_ = [("h", C.c_void_p), ("qx", C.c_void_p), ("qy", C.c_void_p),
-                ("z", C.c_void_p), ("fric", C.c_void_p), ("vinf", C.c_void_p)]
+                ("z", C.c_void_p), ("fric", C.c_void_p), ("vinf", C.c_void_p),
+                ("rain_w", C.c_void_p), ("ks", C.c_void_p), ("psi", C.c_void_p),
+                ("dtheta", C.c_void_p)]
+
+
+SWE_HYETO_MAX = 128
 
 
 class swe_diag(C.Structure):
@@ -65,6 +70,8 @@ EXPORTS = {
     "swe_get_tiling": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "swe_set_time": (C.c_int, [C.c_void_p, C.c_double]),
     "swe_set_rain": (C.c_int, [C.c_void_p, C.c_double]),
+    "swe_set_hyetograph": (C.c_int, [C.c_void_p, C.POINTER(C.c_double),
+                                     C.POINTER(C.c_double), C.c_int32]),
     "swe_set_dt_log": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64]),
     "swe_step": (C.c_int, [C.c_void_p, C.c_int32, C.c_double]),
     "swe_get_time": (C.c_int, [C.c_void_p, C.POINTER(C.c_double),
@@ -89,6 +96,8 @@ EXPORTS = {
     "swe_batch_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32),
                                      C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
     "swe_batch_set_rain": (C.c_int, [C.c_void_p, C.c_int32, C.c_double]),
+    "swe_batch_set_hyetograph": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_double),
+                                           C.POINTER(C.c_double), C.c_int32]),
     "swe_batch_set_dt_log": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int64]),
     "swe_batch_step": (C.c_int, [C.c_void_p, C.c_int32, C.c_double]),
     "swe_batch_get_time": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_double),
@@ -199,6 +208,39 @@ def swe_set_time(ctx: int, t: float) -> None:
 
 def swe_set_rain(ctx: int, rain: float) -> None:
     check(lib().swe_set_rain(C.c_void_p(ctx), rain), "swe_set_rain")
+
+
+def _table(a):
+    if a is None:
+        return None, 0
+    import numpy as np
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, len(a)
+
+
+def swe_set_hyetograph(ctx: int, t_pts, r) -> None:
+    """Host sequences (or None to remove the hyetograph)."""
+    t_a, n = _table(t_pts)
+    r_a, m = _table(r)
+    if n != m:
+        raise ValueError("t_pts and r differ in length")
+    dp = C.POINTER(C.c_double)
+    check(lib().swe_set_hyetograph(C.c_void_p(ctx),
+                                   None if t_a is None else t_a.ctypes.data_as(dp),
+                                   None if r_a is None else r_a.ctypes.data_as(dp), n),
+          "swe_set_hyetograph")
+
+
+def swe_batch_set_hyetograph(b: int, member: int, t_pts, r) -> None:
+    t_a, n = _table(t_pts)
+    r_a, m = _table(r)
+    if n != m:
+        raise ValueError("t_pts and r differ in length")
+    dp = C.POINTER(C.c_double)
+    check(lib().swe_batch_set_hyetograph(C.c_void_p(b), member,
+                                         None if t_a is None else t_a.ctypes.data_as(dp),
+                                         None if r_a is None else r_a.ctypes.data_as(dp), n),
+          "swe_batch_set_hyetograph")
 
 
 def swe_set_dt_log(ctx: int, ptr: int, capacity: int) -> None:

@@ -358,6 +358,7 @@ int swe_batch_create(const swe_params* p, const swe_buffers* bufs, int32_t count
         m.z = bufs[k].z;
         m.fric = bufs[k].fric;
         m.vinf = p[k].infil_on ? bufs[k].vinf : nullptr;
+        attach_fields(m, bufs[k]);
         m.sc = (DevScalars*)w; w += SCALAR_BYTES;
         m.h[0] = bufs[k].h; m.qx[0] = bufs[k].qx; m.qy[0] = bufs[k].qy;
         m.h[1] = (double*)w; w += an;
@@ -478,6 +479,15 @@ int swe_batch_set_rain(swe_batch* b, int32_t member, double rain) {
     b->prm[member].rain = rain;
     b->mh[member].p.rain = rain;
     return upload_members(b);
+}
+
+int swe_batch_set_hyetograph(swe_batch* b, int32_t member, const double* t_pts,
+                             const double* r, int32_t n) {
+    if (!b || member < 0 || member >= b->count) return SWE_EINVAL;
+    HyetoStage st;
+    int rc = stage_hyetograph(t_pts, r, n, st);
+    if (rc) return rc;
+    return upload_hyetograph(b->mh[member].sc, st, b->stream);
 }
 
 int swe_batch_set_dt_log(swe_batch* b, int32_t member, double* dev_log, int64_t capacity) {

@@ -43,6 +43,8 @@ constexpr int HALO = 2;  // ghost/halo width at second order
 constexpr int AMAX_SPREAD = 16;
 constexpr int AMAX_LINE = 16;  // unsigned long long per 128-byte line
 
+static_assert(SWE_HYETO_MAX <= 128, "the hyetograph lookup counts with two wave64 ballots");
+
 struct DevScalars {
     // per slot: bit patterns of Ax, Ay >= 0 at [pair][0], [pair][1]
     unsigned long long amax[3][AMAX_SPREAD][AMAX_LINE];
@@ -51,6 +53,13 @@ struct DevScalars {
     double last_dt;
     unsigned int status;            // sticky SWE_FLAG_* bits
     unsigned int pad;
+    // hyetograph r(t): hy_r[k] from hy_t[k] (strictly increasing) up to the
+    // next breakpoint, 0 before hy_t[0]; hy_n = 0: the constant rain of the
+    // parameters
+    int hy_n;
+    int hy_pad;
+    double hy_t[SWE_HYETO_MAX];
+    double hy_r[SWE_HYETO_MAX];
 };
 // bytes a scalar block takes in a workspace (a multiple of 256)
 constexpr size_t SCALAR_BYTES = (sizeof(DevScalars) + 255) / 256 * 256;
@@ -378,17 +387,19 @@ __host__ __device__ __forceinline__ double time_step(const KParams& p, double ax
     return dt;
 }
 
-// Rain, then Green-Ampt (Section 3.5); the infiltrated water leaves with the
-// cell's velocity.
+// Rain at `rate` (the cell's R), then Green-Ampt (Section 3.5) with the
+// cell's soil parameters; the infiltrated water leaves with the cell's
+// velocity.
 __host__ __device__ __forceinline__ void rain_infiltration(const KParams& p, double dt,
-                                                  double& h, double& qx, double& qy,
-                                                  double& vinf) {
-    h = h + dt * p.rain;
+                                                  double rate, double ks, double psi,
+                                                  double dtheta, double& h, double& qx,
+                                                  double& qy, double& vinf) {
+    h = h + dt * rate;
     if (!p.infil) return;
     double d;
     if (vinf > 0.0) {
-        double zf = vinf / p.dtheta;
-        double ic = p.ks * (1.0 + (p.psi + h) / zf);
+        double zf = vinf / dtheta;
+        double ic = ks * (1.0 + (psi + h) / zf);
         d = vmin(h, dt * ic);
     } else {
         d = h;
@@ -445,6 +456,12 @@ struct MemberArgs {
     DevScalars* sc;
     double* dtlog;
     long long dtlog_cap;
+    // optional per-cell fields (nullptr: the scalar of the parameters):
+    // rain weight w (R = r(t) w), Green-Ampt K_s, psi, theta_s - theta_i
+    const double* rain_w;
+    const double* ks_f;
+    const double* psi_f;
+    const double* dth_f;
 };
 
 // Buffers of one stage launch.
@@ -689,7 +706,7 @@ template <int TXT> struct TileLds {
 // for row j-1.  Returns y1 when the tile is done.
 template <int STAGE, int TXT, class D>
 __device__ __forceinline__ int march(const MemberArgs& m, const TileIO& io, int strip, int y0,
-                                     int y1, double dt, double& ax, double& ay,
+                                     int y1, double dt, double rain, double& ax, double& ay,
                                      TileLds<TXT>& L) {
     constexpr int OUTW = TXT - 2 * HALO;
     constexpr bool FAST = !std::is_same<D, ExactDiv>::value;
@@ -906,7 +923,16 @@ __device__ __forceinline__ int march(const MemberArgs& m, const TileIO& io, int 
                 double hn = 0.5 * (n0h + h2);
                 double qxn = 0.5 * (n0x + qx2);
                 double qyn = 0.5 * (n0y + qy2);
-                rain_infiltration(p, dt, hn, qxn, qyn, vi);
+                // R = r(t) w and the soil of the cell (optional fields,
+                // loaded here only when present)
+                double rate = rain, gks = p.ks, gpsi = p.psi, gdth = p.dtheta;
+                if (m.rain_w) rate = rain * m.rain_w[idx];
+                if (p.infil) {
+                    if (m.ks_f) gks = m.ks_f[idx];
+                    if (m.psi_f) gpsi = m.psi_f[idx];
+                    if (m.dth_f) gdth = m.dth_f[idx];
+                }
+                rain_infiltration(p, dt, rate, gks, gpsi, gdth, hn, qxn, qyn, vi);
                 if (p.infil) m.vinf[idx] = vi;
                 io.ho[idx] = hn;
                 io.qxo[idx] = qxn;
@@ -938,6 +964,21 @@ __device__ __forceinline__ int march(const MemberArgs& m, const TileIO& io, int 
     return y1;
 }
 
+// Rain intensity r(t) at the start time t of a step (rain is explicit,
+// Section 3.1): the value of the last hyetograph breakpoint at or before t,
+// 0 before the first, the parameters' constant without a hyetograph.  The
+// breakpoints increase strictly, so those at or before t are a prefix of
+// the table; each wave counts it with two ballots.
+__device__ __forceinline__ double rain_rate(const MemberArgs& m, double t) {
+    const int n = m.sc->hy_n;
+    if (n <= 0) return m.p.rain;
+    const int l = threadIdx.x & 63;
+    const bool a = l < n && m.sc->hy_t[l] <= t;
+    const bool b = l + 64 < n && m.sc->hy_t[l + 64] <= t;
+    const int k = __popcll(__ballot(a)) + __popcll(__ballot(b));
+    return k == 0 ? 0.0 : m.sc->hy_r[k - 1];
+}
+
 // STAGE 1 (rate): Phi(U^n) to io.ph/pqx/pqy and the face wave-speed bounds
 // of eq. (cfl) into io.acc.  STAGE 2 (update): dt from the bounds, U* rebuilt
 // on the fly, Phi(U*), U** = friction(U* + dt Phi(U*)), Heun's average,
@@ -956,11 +997,12 @@ __device__ __forceinline__ void stage_tile(const MemberArgs& m, const TileIO& io
 
     __shared__ TileLds<TXT> L;
 
-    double dt = 0.0;
+    double dt = 0.0, rain = 0.0;
     if (STAGE == 2) {
         double ax, ay;
         read_amax(&m.sc->amax[io.slot][0][0], ax, ay);
         double tc = m.sc->t[io.slot];
+        rain = rain_rate(m, tc);
         dt = io.dt_fixed > 0.0 ? io.dt_fixed : time_step(p, ax, ay, tc, io.t_end);
         const bool finite = (dt - dt) == 0.0;  // false for inf and NaN
         if (lead && t == 0) {
@@ -997,8 +1039,8 @@ __device__ __forceinline__ void stage_tile(const MemberArgs& m, const TileIO& io
 
     double ax = 0.0, ay = 0.0;
     int stop = y0;
-    if (p.fast_div) stop = march<STAGE, TXT, FastDiv>(m, io, strip, y0, y1, dt, ax, ay, L);
-    if (stop < y1) march<STAGE, TXT, ExactDiv>(m, io, strip, stop, y1, dt, ax, ay, L);
+    if (p.fast_div) stop = march<STAGE, TXT, FastDiv>(m, io, strip, y0, y1, dt, rain, ax, ay, L);
+    if (stop < y1) march<STAGE, TXT, ExactDiv>(m, io, strip, stop, y1, dt, rain, ax, ay, L);
     if (STAGE == 1) block_max2<TXT>(ax, ay, io.acc, spread);
 }
 

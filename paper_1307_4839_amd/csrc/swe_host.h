@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstddef>
 #include <cstdint>
 #include <cstring>
 
@@ -111,6 +112,48 @@ inline TileIO host_step_io(const MemberArgs& m, int phase, int slot, double t_en
     return io;
 }
 
+// A validated hyetograph laid out like the tail of the scalar block
+// (hy_n, hy_pad, hy_t, hy_r), for one host-to-device copy.
+struct HyetoStage {
+    int n;
+    int pad;
+    double t[SWE_HYETO_MAX];
+    double r[SWE_HYETO_MAX];
+};
+static_assert(offsetof(DevScalars, hy_t) - offsetof(DevScalars, hy_n) == offsetof(HyetoStage, t) &&
+                  offsetof(DevScalars, hy_r) - offsetof(DevScalars, hy_n) == offsetof(HyetoStage, r),
+              "hyetograph staging layout");
+
+inline int stage_hyetograph(const double* t, const double* r, int32_t n, HyetoStage& st) {
+    if (n < 0 || n > SWE_HYETO_MAX) return SWE_EINVAL;
+    if (n > 0 && (!t || !r)) return SWE_EINVAL;
+    std::memset(&st, 0, sizeof st);
+    st.n = n;
+    for (int k = 0; k < n; ++k) {
+        if (!std::isfinite(t[k]) || !std::isfinite(r[k]) || !(r[k] >= 0.0)) return SWE_EINVAL;
+        if (k > 0 && !(t[k] > t[k - 1])) return SWE_EINVAL;
+        st.t[k] = t[k];
+        st.r[k] = r[k];
+    }
+    return SWE_OK;
+}
+
+// Stream-ordered copy into a scalar block; waits for it, so the host table
+// may be reused on return.
+inline int upload_hyetograph(DevScalars* sc, const HyetoStage& st, hipStream_t s) {
+    if (hipMemcpyAsync(&sc->hy_n, &st, sizeof st, hipMemcpyHostToDevice, s) != hipSuccess)
+        return SWE_EHIP;
+    return hipStreamSynchronize(s) == hipSuccess ? SWE_OK : SWE_EHIP;
+}
+
+// The optional per-cell fields of a buffer set.
+inline void attach_fields(MemberArgs& m, const swe_buffers& b) {
+    m.rain_w = b.rain_w;
+    m.ks_f = b.ks;
+    m.psi_f = b.psi;
+    m.dth_f = b.dtheta;
+}
+
 }  // namespace swe_host
 
 // Kernels that are not stages.  Internal linkage: each translation unit
@@ -128,6 +171,7 @@ static __global__ void swe_init_scalars_kernel(swe_dev::DevScalars* sc, double t
         sc->steps[1] = 0;
         sc->last_dt = 0.0;
         sc->status = 0u;
+        sc->hy_n = 0;
     }
 }
 

@@ -235,6 +235,7 @@ int swe_create(const swe_params* p, const swe_buffers* b, void* workspace,
     m.z = b->z;
     m.fric = b->fric;
     m.vinf = p->infil_on ? b->vinf : nullptr;
+    attach_fields(m, *b);
     m.sc = (DevScalars*)w;
     w += SCALAR_BYTES;
     m.h[0] = b->h; m.qx[0] = b->qx; m.qy[0] = b->qy;
@@ -335,6 +336,14 @@ int swe_set_rain(swe_ctx* c, double rain) {
     c->m.p.rain = rain;
     c->epoch++;
     return SWE_OK;
+}
+
+int swe_set_hyetograph(swe_ctx* c, const double* t_pts, const double* r, int32_t n) {
+    if (!c) return SWE_EINVAL;
+    HyetoStage st;
+    int rc = stage_hyetograph(t_pts, r, n, st);
+    if (rc) return rc;
+    return upload_hyetograph(c->m.sc, st, c->stream);
 }
 
 int swe_set_dt_log(swe_ctx* c, double* dev_log, int64_t capacity) {

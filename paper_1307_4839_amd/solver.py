@@ -21,6 +21,19 @@ def params_from(wl) -> capi.swe_params:
     return capi.make_params(**wl.params())
 
 
+def _attach_fields(b: capi.swe_buffers, wl, device) -> dict:
+    """Device copies of the workload's optional rain and soil fields, their
+    pointers set in ``b``; the returned tensors must outlive the context."""
+    out = {}
+    for attr, field in (("rain_w", "rain_w"), ("ks_f", "ks"), ("psi_f", "psi"),
+                        ("dtheta_f", "dtheta")):
+        a = getattr(wl, attr)
+        if a is not None:
+            out[field] = _dev(a, device)
+            setattr(b, field, out[field].data_ptr())
+    return out
+
+
 class Solver:
     """One simulation on one GPU.
 
@@ -54,10 +67,13 @@ class Solver:
         b.z = self.z.data_ptr()
         b.fric = self.fric.data_ptr() if self.fric is not None else None
         b.vinf = self.vinf.data_ptr() if self.vinf is not None else None
+        self.fields = _attach_fields(b, wl, self.device)
         self._buffers = b
         self.stream = torch.cuda.current_stream(self.device)
         self.ctx = capi.swe_create(self.params, b, aligned, nbytes,
                                    self.stream.cuda_stream)
+        if wl.rain_t is not None:
+            capi.swe_set_hyetograph(self.ctx, wl.rain_t, wl.rain_r)
         self.dt_log = None
         if dt_log:
             self.dt_log = torch.zeros(dt_log, dtype=torch.float64, device=self.device)
@@ -103,6 +119,10 @@ class Solver:
 
     def set_rain(self, r: float) -> None:
         capi.swe_set_rain(self.ctx, r)
+
+    def set_hyetograph(self, t_pts, r) -> None:
+        """Piecewise-constant rain r(t) (None removes it); synchronizes."""
+        capi.swe_set_hyetograph(self.ctx, t_pts, r)
 
     def diagnostics(self) -> capi.swe_diag:
         return capi.swe_get_diagnostics(self.ctx)
@@ -164,6 +184,7 @@ class Ensemble:
             b.z = m["z"].data_ptr()
             b.fric = m["fric"].data_ptr() if m["fric"] is not None else None
             b.vinf = m["vinf"].data_ptr() if m["vinf"] is not None else None
+            m["fields"] = _attach_fields(b, wl, self.device)
             self.members.append(m)
             bufs.append(b)
         self._bufs = bufs
@@ -173,6 +194,9 @@ class Ensemble:
         self.stream = torch.cuda.current_stream(self.device)
         self.handle = capi.swe_batch_create(self.params, bufs, aligned, nbytes,
                                             self.stream.cuda_stream)
+        for k, wl in enumerate(workloads):
+            if wl.rain_t is not None:
+                capi.swe_batch_set_hyetograph(self.handle, k, wl.rain_t, wl.rain_r)
         self.cells = sum(int(p.nx) * int(p.ny) for p in self.params)
 
     def close(self):
@@ -202,6 +226,9 @@ class Ensemble:
     def set_rain(self, member: int, rain: float) -> None:
         capi.swe_batch_set_rain(self.handle, member, rain)
 
+    def set_hyetograph(self, member: int, t_pts, r) -> None:
+        capi.swe_batch_set_hyetograph(self.handle, member, t_pts, r)
+
     def time(self, member: int):
         return capi.swe_batch_get_time(self.handle, member)
 
@@ -228,6 +255,9 @@ class Calibration:
             raise RuntimeError("the HIP library needs a GPU")
         if wl.fric is None:
             raise ValueError("the workload needs a friction field")
+        if any(getattr(wl, a) is not None for a in ("rain_t", "rain_w", "ks_f", "psi_f",
+                                                    "dtheta_f")):
+            raise ValueError("the adjoint takes uniform, constant rain and no soil fields")
         self.device = torch.device(device)
         self.params = params_from(wl)
         self.nx, self.ny = wl.nx, wl.ny

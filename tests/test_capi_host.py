@@ -102,3 +102,18 @@ def test_struct_layouts_match_header(tmp_path):
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
     got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
     assert got == [v for _, _, v in checks]
+
+
+def test_adjoint_rejects_rain_and_soil_fields_without_gpu():
+    # the reverse pass has uniform rain and no infiltration: a buffer set
+    # with any optional rain or soil field is refused before any device work
+    # (the pointers below are never dereferenced)
+    from paper_1307_4839_amd import capi
+    p = capi.make_params(16, 16, 1.0, 1.0, fric_law=capi.SWE_FRIC_MANNING, fric_coef=0.03)
+    for field in ("rain_w", "ks", "psi", "dtheta"):
+        b = capi.swe_buffers()
+        b.h = b.qx = b.qy = b.z = b.fric = 4096
+        setattr(b, field, 4096)
+        with pytest.raises(capi.SweError) as e:
+            capi.swe_adj_create(p, b, 10, 3, 4096, 1, 5, 4096, 4096, 1 << 30, 0)
+        assert e.value.code == capi.SWE_EINVAL
