@@ -33,7 +33,7 @@ namespace {
 constexpr int GRAPH_STEPS = 16;  // steps per captured graph (even)
 constexpr int MIN_TY = 4;        // smallest rows per tile the work list is sized for
 
-template <int STAGE, int TXT>
+template <int STAGE, int TXT, bool FIELDS>
 __global__ __launch_bounds__(TXT) void batch_stage_kernel(const MemberArgs* __restrict__ ms,
                                                           const int4* __restrict__ tiles,
                                                           int ntiles, int phase, int slot,
@@ -44,7 +44,7 @@ __global__ __launch_bounds__(TXT) void batch_stage_kernel(const MemberArgs* __re
         // live in scratch memory, since its buffer pairs are indexed by phase
         const MemberArgs& m = ms[tl.x];
         const TileIO io = step_io(m, phase, slot, t_end);
-        stage_tile<STAGE, TXT>(m, io, tl.y, tl.z, tl.w, tl.y == 0 && tl.z == 0, k);
+        stage_tile<STAGE, TXT, FIELDS>(m, io, tl.y, tl.z, tl.w, tl.y == 0 && tl.z == 0, k);
     }
 }
 
@@ -99,31 +99,45 @@ __global__ void batch_backup_kernel(const MemberArgs* __restrict__ ms,
     }
 }
 
-template <int STAGE>
-void launch_batch(int tx, int grid, hipStream_t s, const MemberArgs* ms, const int4* tiles,
-                  int ntiles, int phase, int slot, double t_end) {
+template <int STAGE, bool FIELDS>
+void launch_batch_t(int tx, int grid, hipStream_t s, const MemberArgs* ms, const int4* tiles,
+                    int ntiles, int phase, int slot, double t_end) {
     switch (tx) {
         case 64:
-            hipLaunchKernelGGL((batch_stage_kernel<STAGE, 64>), dim3(grid), dim3(64), 0, s, ms,
-                               tiles, ntiles, phase, slot, t_end);
+            hipLaunchKernelGGL((batch_stage_kernel<STAGE, 64, FIELDS>), dim3(grid), dim3(64), 0,
+                               s, ms, tiles, ntiles, phase, slot, t_end);
             break;
         case 128:
-            hipLaunchKernelGGL((batch_stage_kernel<STAGE, 128>), dim3(grid), dim3(128), 0, s,
-                               ms, tiles, ntiles, phase, slot, t_end);
+            hipLaunchKernelGGL((batch_stage_kernel<STAGE, 128, FIELDS>), dim3(grid), dim3(128),
+                               0, s, ms, tiles, ntiles, phase, slot, t_end);
             break;
         default:
-            hipLaunchKernelGGL((batch_stage_kernel<STAGE, 256>), dim3(grid), dim3(256), 0, s,
-                               ms, tiles, ntiles, phase, slot, t_end);
+            hipLaunchKernelGGL((batch_stage_kernel<STAGE, 256, FIELDS>), dim3(grid), dim3(256),
+                               0, s, ms, tiles, ntiles, phase, slot, t_end);
             break;
     }
 }
 
+// stage 2 of an ensemble with any rain or soil field takes the FIELDS
+// variant (stage 1 never reads them)
+template <int STAGE>
+void launch_batch(bool fields, int tx, int grid, hipStream_t s, const MemberArgs* ms,
+                  const int4* tiles, int ntiles, int phase, int slot, double t_end) {
+    if (STAGE == 2 && fields)
+        launch_batch_t<STAGE, true>(tx, grid, s, ms, tiles, ntiles, phase, slot, t_end);
+    else
+        launch_batch_t<STAGE, false>(tx, grid, s, ms, tiles, ntiles, phase, slot, t_end);
+}
+
 template <int STAGE, int TXT>
-int resident_blocks() {
+int resident_blocks(bool fields) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_stage_kernel<STAGE, TXT>, TXT,
-                                                     0) != hipSuccess)
-        return 1;
+    hipError_t e = STAGE == 2 && fields
+                       ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                             &nb, batch_stage_kernel<STAGE, TXT, true>, TXT, 0)
+                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                             &nb, batch_stage_kernel<STAGE, TXT, false>, TXT, 0);
+    if (e != hipSuccess) return 1;
     return nb < 1 ? 1 : nb;
 }
 
@@ -145,6 +159,7 @@ struct swe_batch {
     hipStream_t stream;
     int slot;
     size_t max_cells;
+    bool any_fields;              // some member has a rain or soil field
     hipGraphExec_t graph;
     hipStream_t cap_stream;  // private stream used only to capture graphs
     int graph_slot;
@@ -181,11 +196,12 @@ int upload_members(swe_batch* b) {
 int persistent_grid(const swe_batch* b, int stage) {
     int nb;
     if (stage == 1)
-        nb = b->tx == 64 ? resident_blocks<1, 64>()
-             : b->tx == 128 ? resident_blocks<1, 128>() : resident_blocks<1, 256>();
+        nb = b->tx == 64 ? resident_blocks<1, 64>(false)
+             : b->tx == 128 ? resident_blocks<1, 128>(false) : resident_blocks<1, 256>(false);
     else
-        nb = b->tx == 64 ? resident_blocks<2, 64>()
-             : b->tx == 128 ? resident_blocks<2, 128>() : resident_blocks<2, 256>();
+        nb = b->tx == 64 ? resident_blocks<2, 64>(b->any_fields)
+             : b->tx == 128 ? resident_blocks<2, 128>(b->any_fields)
+                            : resident_blocks<2, 256>(b->any_fields);
     long long g = (long long)nb * b->cus;
     if (g > b->ntiles) g = b->ntiles;
     return g < 1 ? 1 : (int)g;
@@ -223,9 +239,9 @@ int build_tiles(swe_batch* b, int tx, int ty) {
 }
 
 void enqueue_step(swe_batch* b, int phase, double t_end) {
-    launch_batch<1>(b->tx, b->grid1, b->stream, b->md, b->tiles, b->ntiles, phase, b->slot,
+    launch_batch<1>(false, b->tx, b->grid1, b->stream, b->md, b->tiles, b->ntiles, phase, b->slot,
                     t_end);
-    launch_batch<2>(b->tx, b->grid2, b->stream, b->md, b->tiles, b->ntiles, phase, b->slot,
+    launch_batch<2>(b->any_fields, b->tx, b->grid2, b->stream, b->md, b->tiles, b->ntiles, phase, b->slot,
                     t_end);
     b->slot ^= 1;
 }
@@ -341,6 +357,7 @@ int swe_batch_create(const swe_params* p, const swe_buffers* bufs, int32_t count
     b->epoch = 0;
     b->graph_epoch = 0;
     b->max_cells = 0;
+    b->any_fields = false;
     char* w = (char*)workspace;
     b->md = (MemberArgs*)w;
     w += align256(sizeof(MemberArgs) * count);
@@ -359,6 +376,7 @@ int swe_batch_create(const swe_params* p, const swe_buffers* bufs, int32_t count
         m.fric = bufs[k].fric;
         m.vinf = p[k].infil_on ? bufs[k].vinf : nullptr;
         attach_fields(m, bufs[k]);
+        if (has_fields(m)) b->any_fields = true;
         m.sc = (DevScalars*)w; w += SCALAR_BYTES;
         m.h[0] = bufs[k].h; m.qx[0] = bufs[k].qx; m.qy[0] = bufs[k].qy;
         m.h[1] = (double*)w; w += an;

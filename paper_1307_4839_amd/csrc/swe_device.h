@@ -704,7 +704,7 @@ template <int TXT> struct TileLds {
 // the caller to march on from row j with ExactDiv.  Thread 0 lowers the flag
 // of row j+1 after the first barrier of row j, when every lane has read it
 // for row j-1.  Returns y1 when the tile is done.
-template <int STAGE, int TXT, class D>
+template <int STAGE, int TXT, class D, bool FIELDS>
 __device__ __forceinline__ int march(const MemberArgs& m, const TileIO& io, int strip, int y0,
                                      int y1, double dt, double rain, double& ax, double& ay,
                                      TileLds<TXT>& L) {
@@ -923,14 +923,16 @@ __device__ __forceinline__ int march(const MemberArgs& m, const TileIO& io, int 
                 double hn = 0.5 * (n0h + h2);
                 double qxn = 0.5 * (n0x + qx2);
                 double qyn = 0.5 * (n0y + qy2);
-                // R = r(t) w and the soil of the cell (optional fields,
-                // loaded here only when present)
+                // R = r(t) w and the soil of the cell (the optional fields
+                // are compiled in only for launches that have some)
                 double rate = rain, gks = p.ks, gpsi = p.psi, gdth = p.dtheta;
-                if (m.rain_w) rate = rain * m.rain_w[idx];
-                if (p.infil) {
-                    if (m.ks_f) gks = m.ks_f[idx];
-                    if (m.psi_f) gpsi = m.psi_f[idx];
-                    if (m.dth_f) gdth = m.dth_f[idx];
+                if constexpr (FIELDS) {
+                    if (m.rain_w) rate = rain * m.rain_w[idx];
+                    if (p.infil) {
+                        if (m.ks_f) gks = m.ks_f[idx];
+                        if (m.psi_f) gpsi = m.psi_f[idx];
+                        if (m.dth_f) gdth = m.dth_f[idx];
+                    }
                 }
                 rain_infiltration(p, dt, rate, gks, gpsi, gdth, hn, qxn, qyn, vi);
                 if (p.infil) m.vinf[idx] = vi;
@@ -979,6 +981,12 @@ __device__ __forceinline__ double rain_rate(const MemberArgs& m, double t) {
     return k == 0 ? 0.0 : m.sc->hy_r[k - 1];
 }
 
+// Whether a simulation has any optional per-cell rain or soil field (its
+// stage-2 launches then take the FIELDS variant of the tile routine).
+__host__ __device__ __forceinline__ bool has_fields(const MemberArgs& m) {
+    return m.rain_w || m.ks_f || m.psi_f || m.dth_f;
+}
+
 // STAGE 1 (rate): Phi(U^n) to io.ph/pqx/pqy and the face wave-speed bounds
 // of eq. (cfl) into io.acc.  STAGE 2 (update): dt from the bounds, U* rebuilt
 // on the fly, Phi(U*), U** = friction(U* + dt Phi(U*)), Heun's average,
@@ -986,7 +994,8 @@ __device__ __forceinline__ double rain_rate(const MemberArgs& m, double t) {
 // per simulation that does the scalar bookkeeping (time, step count, dt log,
 // clearing the next step's accumulators).
 // `spread` picks the accumulator pair of stage 1 (any block-dependent index).
-template <int STAGE, int TXT>
+// FIELDS compiles in the reads of the optional rain and soil fields.
+template <int STAGE, int TXT, bool FIELDS = false>
 __device__ __forceinline__ void stage_tile(const MemberArgs& m, const TileIO& io, int strip,
                                            int y0, int y1, bool lead, int spread) {
     constexpr int OUTW = TXT - 2 * HALO;
@@ -1039,8 +1048,10 @@ __device__ __forceinline__ void stage_tile(const MemberArgs& m, const TileIO& io
 
     double ax = 0.0, ay = 0.0;
     int stop = y0;
-    if (p.fast_div) stop = march<STAGE, TXT, FastDiv>(m, io, strip, y0, y1, dt, rain, ax, ay, L);
-    if (stop < y1) march<STAGE, TXT, ExactDiv>(m, io, strip, stop, y1, dt, rain, ax, ay, L);
+    if (p.fast_div)
+        stop = march<STAGE, TXT, FastDiv, FIELDS>(m, io, strip, y0, y1, dt, rain, ax, ay, L);
+    if (stop < y1)
+        march<STAGE, TXT, ExactDiv, FIELDS>(m, io, strip, stop, y1, dt, rain, ax, ay, L);
     if (STAGE == 1) block_max2<TXT>(ax, ay, io.acc, spread);
 }
 

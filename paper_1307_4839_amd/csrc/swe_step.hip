@@ -43,12 +43,13 @@ constexpr int DIAG_BLOCKS = 512;  // blocks of the diagnostics reduction
 constexpr int DIAG_T = 256;
 constexpr int GRAPH_STEPS = 16;   // steps per captured graph (even)
 
-template <int STAGE, int TXT>
+template <int STAGE, int TXT, bool FIELDS>
 __global__ __launch_bounds__(TXT) void stage_kernel(MemberArgs m, TileIO io, int ty) {
     const int y0 = blockIdx.y * ty;
     const int y1 = min(y0 + ty, m.p.ny);
-    stage_tile<STAGE, TXT>(m, io, blockIdx.x, y0, y1, blockIdx.x == 0 && blockIdx.y == 0,
-                           blockIdx.x + blockIdx.y * gridDim.x);
+    stage_tile<STAGE, TXT, FIELDS>(m, io, blockIdx.x, y0, y1,
+                                   blockIdx.x == 0 && blockIdx.y == 0,
+                                   blockIdx.x + blockIdx.y * gridDim.x);
 }
 
 // Deterministic diagnostics: block b reduces the cells b, b + B, b + 2B, ...
@@ -97,14 +98,24 @@ __global__ void diag_final_kernel(double* part, int nb) {
     }
 }
 
+template <int STAGE, bool FIELDS>
+void launch_stage_t(int tx, dim3 grid, hipStream_t s, const MemberArgs& m, const TileIO& io,
+                    int ty) {
+    switch (tx) {
+        case 64: hipLaunchKernelGGL((stage_kernel<STAGE, 64, FIELDS>), grid, dim3(64), 0, s, m, io, ty); break;
+        case 128: hipLaunchKernelGGL((stage_kernel<STAGE, 128, FIELDS>), grid, dim3(128), 0, s, m, io, ty); break;
+        default: hipLaunchKernelGGL((stage_kernel<STAGE, 256, FIELDS>), grid, dim3(256), 0, s, m, io, ty); break;
+    }
+}
+
+// stage 1 never reads the rain and soil fields
 template <int STAGE>
 void launch_stage(int tx, dim3 grid, hipStream_t s, const MemberArgs& m, const TileIO& io,
                   int ty) {
-    switch (tx) {
-        case 64: hipLaunchKernelGGL((stage_kernel<STAGE, 64>), grid, dim3(64), 0, s, m, io, ty); break;
-        case 128: hipLaunchKernelGGL((stage_kernel<STAGE, 128>), grid, dim3(128), 0, s, m, io, ty); break;
-        default: hipLaunchKernelGGL((stage_kernel<STAGE, 256>), grid, dim3(256), 0, s, m, io, ty); break;
-    }
+    if (STAGE == 2 && has_fields(m))
+        launch_stage_t<STAGE, true>(tx, grid, s, m, io, ty);
+    else
+        launch_stage_t<STAGE, false>(tx, grid, s, m, io, ty);
 }
 
 }  // namespace
