@@ -47,7 +47,7 @@ class OrcParams(C.Structure):
                 ("rain_n", C.c_int32), ("rain_t", C.POINTER(C.c_double)),
                 ("rain_r", C.POINTER(C.c_double)), ("rain_w", C.POINTER(C.c_double)),
                 ("ks_f", C.POINTER(C.c_double)), ("psi_f", C.POINTER(C.c_double)),
-                ("dtheta_f", C.POINTER(C.c_double))]
+                ("dtheta_f", C.POINTER(C.c_double)), ("order", C.c_int32)]
 
 
 _lib = None
@@ -101,8 +101,9 @@ def _ip(a: Optional[np.ndarray]):
 
 def params(nx, ny, dx, dy, g=9.81, cfl=0.5, dt_max=math.inf, h_eps=1e-12,
            bc=(0, 0, 0, 0), fric_law=0, fric_coef=0.0, rain=0.0, infil_on=0,
-           ks=0.0, psi=0.0, dtheta=0.0) -> OrcParams:
+           ks=0.0, psi=0.0, dtheta=0.0, order=2) -> OrcParams:
     p = OrcParams()
+    p.order = int(order)
     p.nx, p.ny, p.dx, p.dy = nx, ny, dx, dy
     p.g, p.cfl, p.dt_max, p.h_eps = g, cfl, dt_max, h_eps
     for k in range(4):

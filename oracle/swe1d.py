@@ -11,7 +11,9 @@ formulas as printed, vectorised over cells and faces:
   u + sqrt(gh), Section 3.3;
 * MUSCL with minmod on h, h+z and u and the modified velocity, Section 3.4,
   written with divided differences exactly as printed;
-* semi-implicit friction and Heun's method, Section 3.2.
+* semi-implicit friction and Heun's method, Section 3.2;
+* first order (Section 3.3): no reconstruction (zero slopes) and one
+  explicit Euler stage per step.
 
 Two ghost cells per side (wall: mirror with negated discharge; outflow:
 copy of the boundary cell).  The dry threshold h_eps and the Manning split
@@ -46,7 +48,7 @@ def _minmod(x, y):
     return out
 
 
-def convective_rate(h, q, z, dx, g, h_eps, bc):
+def convective_rate(h, q, z, dx, g, h_eps, bc, order=2):
     """Returns the bracket [F_{i+1/2L} - F_{i-1/2R} - Fc_i] and max speed."""
     hp = _ghost(h, bc[0], bc[1], False)
     qp = _ghost(q, bc[0], bc[1], True)
@@ -61,6 +63,8 @@ def convective_rate(h, q, z, dx, g, h_eps, bc):
     Dh = _minmod((hp[c] - hp[lo]) / dx, (hp[hi] - hp[c]) / dx)
     De = _minmod((eta[c] - eta[lo]) / dx, (eta[hi] - eta[c]) / dx)
     Du = _minmod((u[c] - u[lo]) / dx, (u[hi] - u[c]) / dx)
+    if order == 1:
+        Dh, De, Du = np.zeros_like(Dh), np.zeros_like(De), np.zeros_like(Du)
     h_m = hp[c] - dx / 2 * Dh           # h_{i-1/2+}
     h_p = hp[c] + dx / 2 * Dh           # h_{i+1/2-}
     z_m = (eta[c] - dx / 2 * De) - h_m
@@ -126,6 +130,14 @@ def heun_step(h, q, z, dt, dx, g=9.81, h_eps=1e-12, bc=(WALL, WALL), law=0,
     h1, q1 = phi_stage(h, q)
     h2, q2 = phi_stage(h1, q1)
     return (h + h2) / 2, (q + q2) / 2
+
+
+def euler_step(h, q, z, dt, dx, g=9.81, h_eps=1e-12, bc=(WALL, WALL), law=0, coef=0.0):
+    """First order: U^{n+1} = friction(U^n + dt Phi_1(U^n))."""
+    B0, B1, _ = convective_rate(h, q, z, dx, g, h_eps, bc, order=1)
+    h1 = h - dt / dx * B0
+    q1 = q - dt / dx * B1
+    return h1, friction(h, q, h1, q1, dt, law, coef, g, h_eps)
 
 
 def cfl_dt(h, q, z, dx, cfl=0.5, g=9.81, h_eps=1e-12, bc=(WALL, WALL)):

@@ -127,6 +127,9 @@ struct orc_params {
     const double* ks_f;
     const double* psi_f;
     const double* dtheta_f;
+    // 1: first order (Section 3.3: piecewise-constant reconstruction, one
+    // explicit Euler stage per step); 0 or 2: the second-order scheme
+    int32_t order;
 };
 }
 
@@ -187,6 +190,19 @@ inline Recon<T> muscl(const Prim<T>& a, const Prim<T>& c, const Prim<T>& b,
         r.un_m = r.un_p = c.un;
         r.ut_m = r.ut_p = c.ut;
     }
+    return r;
+}
+
+// First order (Section 3.3 gives n_CFL = 1 for it): no reconstruction, the
+// face values are the cell's.  Written as the reconstruction above with
+// zero slopes, so z at the faces is still deduced from h and h+z.
+template <class T>
+inline Recon<T> piecewise_constant(const Prim<T>& c) {
+    Recon<T> r;
+    r.h_m = r.h_p = c.h;
+    r.z_m = r.z_p = c.eta - c.h;
+    r.un_m = r.un_p = c.un;
+    r.ut_m = r.ut_p = c.ut;
     return r;
 }
 
@@ -364,7 +380,7 @@ void rate(const orc_params& p, const T* h_in, const T* qx_in, const T* qy_in,
             Prim<T> pa{h[a], u[a], v[a], eta[a]};
             Prim<T> pc{h[c], u[c], v[c], eta[c]};
             Prim<T> pb{h[b], u[b], v[b], eta[b]};
-            rc[i + 1] = muscl(pa, pc, pb, h_eps);
+            rc[i + 1] = p.order == 1 ? piecewise_constant(pc) : muscl(pa, pc, pb, h_eps);
         }
         // faces i+1/2 for i = -1 .. nx-1
         std::vector<Face<T>> fc(nx + 1);
@@ -397,7 +413,7 @@ void rate(const orc_params& p, const T* h_in, const T* qx_in, const T* qy_in,
             Prim<T> pa{h[a], v[a], u[a], eta[a]};
             Prim<T> pc{h[c], v[c], u[c], eta[c]};
             Prim<T> pb{h[b], v[b], u[b], eta[b]};
-            rc[j + 1] = muscl(pa, pc, pb, h_eps);
+            rc[j + 1] = p.order == 1 ? piecewise_constant(pc) : muscl(pa, pc, pb, h_eps);
         }
         std::vector<Face<T>> fc(ny + 1);
         for (int j = -1; j < ny; ++j) {
@@ -543,7 +559,7 @@ inline void rain_infiltration(const orc_params& p, double dt, double r, size_t s
 }
 
 // One full time step from time t with a given dt (Algorithm 1: two stages,
-// then Heun).
+// then Heun; at first order one stage, the explicit Euler step).
 template <class T>
 void step_fixed(const orc_params& p, const T* fric, double t, double dt, T* h, T* qx,
                 T* qy, const double* z, T* vinf) {
@@ -551,6 +567,17 @@ void step_fixed(const orc_params& p, const T* fric, double t, double dt, T* h, T
     const double r = rain_rate(p, t);
     std::vector<T> h1(n), qx1(n), qy1(n), h2(n), qx2(n), qy2(n);
     stage(p, fric, dt, h, qx, qy, z, h1.data(), qx1.data(), qy1.data(), nullptr);
+    if (p.order == 1) {
+        for (size_t s = 0; s < n; ++s) {
+            T hn = h1[s], qxn = qx1[s], qyn = qy1[s];
+            T vdummy = T(0.0);
+            rain_infiltration(p, dt, r, s, hn, qxn, qyn, vinf ? &vinf[s] : &vdummy);
+            h[s] = hn;
+            qx[s] = qxn;
+            qy[s] = qyn;
+        }
+        return;
+    }
     stage(p, fric, dt, h1.data(), qx1.data(), qy1.data(), z, h2.data(), qx2.data(),
           qy2.data(), nullptr);
     for (size_t s = 0; s < n; ++s) {

@@ -93,6 +93,9 @@ class Workload:
     ks_f: Optional[np.ndarray] = None
     psi_f: Optional[np.ndarray] = None
     dtheta_f: Optional[np.ndarray] = None
+    # 2: MUSCL + Heun (the paper's scheme); 1: first order (piecewise
+    # constant, one Euler stage; the paper uses n_CFL = 1 with it)
+    order: int = 2
     t_end: float = math.inf
     nsteps: int = 0
     gauges: Optional[np.ndarray] = None  # flat cell indices
@@ -104,7 +107,7 @@ class Workload:
                     bc=tuple(self.bc), fric_law=self.fric_law,
                     fric_coef=self.fric_coef, rain=self.rain,
                     infil_on=self.infil_on, ks=self.ks, psi=self.psi,
-                    dtheta=self.dtheta)
+                    dtheta=self.dtheta, order=self.order)
 
     def copy(self) -> "Workload":
         out = dataclasses.replace(self)

@@ -38,6 +38,10 @@ MUTANTS = {
     "cfl_drop_y": ("double r = amax[0] / p.dx + amax[1] / p.dy;", "double r = amax[0] / p.dx;"),
     "green_ampt_sign": ("(T(psi) + h) / zf", "(T(psi) - h) / zf"),
     "rain_missing_dt": ("h = h + T(dt) * T(rate);", "h = h + T(rate);"),
+    "first_order_reconstructs": ("p.order == 1 ? piecewise_constant(pc) : muscl(pa, pc, pb, h_eps);\n        }\n        // faces i+1/2",
+                                 "muscl(pa, pc, pb, h_eps);\n        }\n        // faces i+1/2"),
+    "first_order_heun": ("    if (p.order == 1) {\n        for (size_t s = 0; s < n; ++s) {",
+                         "    if (p.order == 7) {\n        for (size_t s = 0; s < n; ++s) {"),
     "hyetograph_open_interval": ("if (p.rain_t[k] <= t) r = p.rain_r[k];",
                                  "if (p.rain_t[k] < t) r = p.rain_r[k];"),
     "hyetograph_next_value": ("if (p.rain_t[k] <= t) r = p.rain_r[k];",

@@ -365,6 +365,99 @@ def test_stoker_convergence():
 
 
 # ---------------------------------------------------------------------------
+# First order (Section 3.3: no reconstruction, n_CFL = 1; one Euler stage):
+# well-balanced, positive, equal to the literal 1D first-order scheme,
+# convergent on the Ritter dam break, and its CFL is eq. (cfl) on the cell
+# values.
+# ---------------------------------------------------------------------------
+
+def test_first_order_lake_at_rest():
+    # n_CFL = 0.9: at exactly 1 the 2D step sits on the stability limit of
+    # the unsplit first-order update (lambda_x A_x + lambda_y A_y = 1), where
+    # round-off is not damped (2e-10 after these 1000 steps, at either order)
+    C = 1.2
+    wl = _islands(40, 30, C, seed=12, bc=(0, 1, 1, 0))
+    wl.order, wl.cfl = 1, 0.9
+    s = oracle.State(wl)
+    assert s.run(1000) == 0
+    wet = wl.h > 0
+    H = wl.h.max()
+    assert np.abs((s.h + s.z)[wet] - C).max() <= 1e-12 * max(C, 1.0)
+    assert np.all(s.h[~wet] == 0.0)
+    assert np.abs(s.qx).max() <= 1e-12 * math.sqrt(G * H ** 3)
+    assert np.abs(s.qy).max() <= 1e-12 * math.sqrt(G * H ** 3)
+
+
+@pytest.mark.parametrize("law,coef", [(0, 0.0), (2, 0.2), (1, 0.03)])
+def test_first_order_one_dimensional_reduction(law, coef):
+    nx, ny = 120, 3
+    rng = np.random.default_rng(19)
+    x = (np.arange(nx) + 0.5)
+    z1 = 0.5 * np.exp(-((x - 70) / 8) ** 2) + 0.002 * (nx - x)
+    h1 = np.where(x < 40, 1.5, 0.0) + 0.0 * x
+    q1 = rng.uniform(-0.2, 0.2, nx) * (h1 > 0)
+    wl = I.Workload("1d", nx, ny, 1.0, 1.0, z=np.tile(z1, (ny, 1)), h=np.tile(h1, (ny, 1)),
+                    qx=np.tile(q1, (ny, 1)), qy=np.zeros((ny, nx)), bc=(0, 1, 0, 0),
+                    fric_law=law, fric_coef=coef, order=1, cfl=1.0)
+    s = oracle.State(wl)
+    assert s.run(150) == 0
+    assert np.all(s.qy == 0.0)
+    hh, qq = h1.copy(), q1.copy()
+    for dt in s.dts:
+        hh, qq = swe1d.euler_step(hh, qq, z1, dt, 1.0, bc=(0, 1), law=law, coef=coef)
+    assert np.abs(s.h[0] - hh).max() <= 1e-13 * np.abs(hh).max()
+    assert np.abs(s.qx[0] - qq).max() <= 1e-12 * np.abs(qq).max()
+    # and it is not the second-order scheme
+    wl.order = 2
+    s2 = oracle.State(wl)
+    s2.run(150)
+    assert np.abs(s2.h[0] - s.h[0]).max() > 1e-3
+
+
+def test_first_order_positivity_and_cfl_one():
+    for wl in (I.dam_break_200(), I.random_state(48, 40, 5, bc=(0, 1, 1, 0),
+                                                 fric_law=I.FRIC_DARCY, fric_coef=0.2)):
+        wl.order, wl.cfl = 1, 1.0
+        s = oracle.State(wl)
+        rc = s.run(300, wl.t_end)
+        assert rc in (0, 1), rc
+        assert s.h.min() >= 0.0 and np.isfinite(s.h).all()
+
+
+def test_first_order_cfl_on_cell_values():
+    # uniform state: dt = 1 / ((|u| + sqrt(gh))/dx + (|v| + sqrt(gh))/dy)
+    h0, u0, v0 = 0.8, 0.3, -0.2
+    wl = flat_workload(12, 9, dx=2.0, dy=0.5, bc=(1, 1, 1, 1))
+    wl.h[:] = h0
+    wl.qx[:] = h0 * u0
+    wl.qy[:] = h0 * v0
+    wl.order, wl.cfl = 1, 1.0
+    s = oracle.State(wl)
+    s.run(1)
+    c = math.sqrt(G * h0)
+    expect = 1.0 / ((abs(u0) + c) / 2.0 + (abs(v0) + c) / 0.5)
+    assert abs(s.dts[0] - expect) <= 1e-15 * expect
+
+
+def test_first_order_ritter_convergence():
+    errs = []
+    for n in (200, 400, 800):
+        dx = 200.0 / n
+        x = (np.arange(n) + 0.5) * dx
+        h = np.where(x < 100.0, 1.0, 0.0)
+        wl = I.Workload("db", n, 2, dx, 1e9, z=np.zeros((2, n)), h=np.tile(h, (2, 1)),
+                        qx=np.zeros((2, n)), qy=np.zeros((2, n)), bc=(1, 1, 0, 0),
+                        order=1, cfl=1.0)
+        s = oracle.State(wl)
+        assert s.run(10 ** 6, 10.0) == 1 and s.t == 10.0
+        errs.append(np.abs(s.h[0] - ritter_h(x, 10.0, 100.0, 1.0)).sum() * dx)
+    orders = [math.log2(errs[k] / errs[k + 1]) for k in range(2)]
+    assert min(orders) >= 0.5, (errs, orders)
+    # the second-order scheme is more accurate on the finest grid
+    assert errs[-1] > _dam_break_errors(0.0, lambda x, t: ritter_h(x, t, 100.0, 1.0), [800])[0]
+
+
+# ---------------------------------------------------------------------------
 # P11: friction alone on a uniform flat state (Section 2.1 laws, Section 3.2
 # semi-implicit treatment): converges to the ODE solution
 #   Manning: q(t) = q0 / (1 + g n^2 q0 t / h^{7/3}),
