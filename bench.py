@@ -236,6 +236,42 @@ def flow_dir_leg(wl, reps):
     return {"workload": f"{wl.name} terrain {wl.nx}x{wl.ny}", "launches": reps, **out}
 
 
+def first_order_leg(wl, warmup, steps):
+    """The same workload with the first-order scheme (Section 3.3: no
+    reconstruction, one Euler stage, n_CFL = 1): throughput and the average
+    duration of its two kernels (rate, then the cell-wise Euler update)."""
+    import torch
+
+    from paper_1307_4839_amd.solver import Solver
+    w1 = wl.copy()
+    w1.order, w1.cfl = 1, 1.0
+    g = Solver(w1, device="cuda:0")
+    g.step(warmup)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(g.stream)
+    g.step(steps)
+    e1.record(g.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    g.profile_begin(20)
+    g.step(20)
+    ms_rate, ms_upd, n = g.profile_end()
+    rc, _ = g.status()
+    t_sim = g.time()[0]
+    g.close()
+    del g
+    torch.cuda.empty_cache()
+    cells = wl.nx * wl.ny
+    print(f"[bench] first order: {steps} steps in {ms:.1f} ms, t = {t_sim:.1f} s",
+          file=sys.stderr, flush=True)
+    return {"workload": f"{wl.name} {wl.nx}x{wl.ny}, first order, cfl 1", "steps": steps,
+            "warmup": warmup, "ms_per_step": ms / steps, "value": cells * steps / (ms / 1e3),
+            "unit": "cell-updates/s", "rate_kernel_ms": ms_rate / n,
+            "euler_kernel_ms": ms_upd / n, "status": rc}
+
+
 def paper_runs_leg(iterations):
     """Wall time of whole runs of the 5120 x 5120 valley from its initial
     state, at the iteration counts of the scaling runs of Section 6.3 (one
@@ -294,6 +330,7 @@ def main(argv=None):
     ap.add_argument("--ensemble-steps", type=int, default=500)
     ap.add_argument("--no-paper-runs", action="store_true")
     ap.add_argument("--no-flow-dir", action="store_true")
+    ap.add_argument("--no-first-order", action="store_true")
     ap.add_argument("--flow-dir-reps", type=int, default=50)
     ap.add_argument("--paper-iterations", default="5000,20000")
     args = ap.parse_args(argv)
@@ -406,6 +443,10 @@ def main(argv=None):
     torch.cuda.empty_cache()
     print(f"[bench] 1 GiB device copy: {copy_gbps:.0f} GB/s", file=sys.stderr, flush=True)
 
+    order1 = None
+    if not args.no_first_order:
+        order1 = first_order_leg(wl, 300, 100)
+
     fdir = None
     if not args.no_flow_dir:
         fdir = flow_dir_leg(wl, args.flow_dir_reps)
@@ -463,6 +504,7 @@ def main(argv=None):
         "adjoint": adj,
         "paper_runs": paper,
         "flow_directions": fdir,
+        "first_order": order1,
         "sim_time_s": t_sim,
         "status_flags": flags,
     }

@@ -77,6 +77,9 @@ typedef struct swe_params {
     double ks;           /* saturated conductivity K_s [m/s] */
     double psi;          /* wetting-front suction head, magnitude >= 0 [m] */
     double dtheta;       /* theta_s - theta_i, > 0 */
+    int32_t order;       /* 1: first order (Section 3.3: no reconstruction,
+                            one explicit Euler stage per step; the paper
+                            pairs it with cfl = 1); 0 or 2: MUSCL + Heun */
 } swe_params;
 
 /* Optional per-cell fields below are read only, [ny][nx] FP64 device

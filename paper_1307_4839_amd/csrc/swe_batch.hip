@@ -123,20 +123,27 @@ void launch_batch_t(int tx, int grid, hipStream_t s, const MemberArgs* ms, const
 template <int STAGE>
 void launch_batch(bool fields, int tx, int grid, hipStream_t s, const MemberArgs* ms,
                   const int4* tiles, int ntiles, int phase, int slot, double t_end) {
-    if (STAGE == 2 && fields)
-        launch_batch_t<STAGE, true>(tx, grid, s, ms, tiles, ntiles, phase, slot, t_end);
-    else
-        launch_batch_t<STAGE, false>(tx, grid, s, ms, tiles, ntiles, phase, slot, t_end);
+    if constexpr (STAGE == 2) {
+        if (fields) {
+            launch_batch_t<2, true>(tx, grid, s, ms, tiles, ntiles, phase, slot, t_end);
+            return;
+        }
+    }
+    launch_batch_t<STAGE, false>(tx, grid, s, ms, tiles, ntiles, phase, slot, t_end);
 }
 
 template <int STAGE, int TXT>
 int resident_blocks(bool fields) {
     int nb = 0;
-    hipError_t e = STAGE == 2 && fields
-                       ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                             &nb, batch_stage_kernel<STAGE, TXT, true>, TXT, 0)
-                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                             &nb, batch_stage_kernel<STAGE, TXT, false>, TXT, 0);
+    hipError_t e;
+    if constexpr (STAGE == 2)
+        e = fields ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                         &nb, batch_stage_kernel<2, TXT, true>, TXT, 0)
+                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                         &nb, batch_stage_kernel<2, TXT, false>, TXT, 0);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &nb, batch_stage_kernel<STAGE, TXT, false>, TXT, 0);
     if (e != hipSuccess) return 1;
     return nb < 1 ? 1 : nb;
 }
@@ -342,6 +349,7 @@ int swe_batch_create(const swe_params* p, const swe_buffers* bufs, int32_t count
     for (int k = 0; k < count; ++k) {
         const swe_buffers& b = bufs[k];
         if (!b.h || !b.qx || !b.qy || !b.z) return SWE_EINVAL;
+        if (p[k].order == 1) return SWE_EINVAL;  // ensembles run the second-order scheme
         if (p[k].infil_on && !b.vinf) return SWE_EINVAL;
     }
     swe_batch* b = new (std::nothrow) swe_batch;

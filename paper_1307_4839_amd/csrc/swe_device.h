@@ -79,6 +79,8 @@ struct KParams {
     // g in (0, 2^10] and dx, dy in [2^-300, 2^300]: the shared-reciprocal
     // quotients may be used (their operand bounds are checked on the device)
     int fast_div;
+    // 2: MUSCL + Heun; 1: first order (no reconstruction, one Euler stage)
+    int order;
 };
 
 // ---------------------------------------------------------------------------
@@ -249,6 +251,24 @@ __host__ __device__ __forceinline__ Rec muscl(const Prim& a, const Prim& c, cons
                                               double h_eps) {
     ExactDiv d;
     return muscl(a, c, b, h_eps, d.rcp(c.h), d);
+}
+
+// Face values of a cell: MUSCL at second order; at first order (Section
+// 3.3) the cell's own values, i.e. the reconstruction above with zero
+// slopes (z still deduced from h and h+z).
+template <int ORDER, class D>
+__host__ __device__ __forceinline__ Rec reconstruct(const Prim& a, const Prim& c, const Prim& b,
+                                                    double h_eps, const Recip& rc, D& d) {
+    if constexpr (ORDER == 1) {
+        Rec r;
+        r.h_m = r.h_p = c.h;
+        r.z_m = r.z_p = c.eta - c.h;
+        r.un_m = r.un_p = c.un;
+        r.ut_m = r.ut_p = c.ut;
+        return r;
+    } else {
+        return muscl(a, c, b, h_eps, rc, d);
+    }
 }
 
 // Flux through one face: hydrostatic reconstruction (Section 3.1), HLL
@@ -704,7 +724,36 @@ template <int TXT> struct TileLds {
 // the caller to march on from row j with ExactDiv.  Thread 0 lowers the flag
 // of row j+1 after the first barrier of row j, when every lane has read it
 // for row j-1.  Returns y1 when the tile is done.
-template <int STAGE, int TXT, class D, bool FIELDS>
+// End of a step for cell idx: rain R = r(t) w and Green-Ampt with the
+// cell's soil (the optional fields are compiled in only for launches that
+// have some), then U^{n+1} and V_inf written and the sticky flags raised.
+template <bool FIELDS>
+__device__ __forceinline__ void finish_cell(const MemberArgs& m, const TileIO& io, size_t idx,
+                                            double dt, double rain, double hn, double qxn,
+                                            double qyn, double vi) {
+    const KParams& p = m.p;
+    double rate = rain, gks = p.ks, gpsi = p.psi, gdth = p.dtheta;
+    if constexpr (FIELDS) {
+        if (m.rain_w) rate = rain * m.rain_w[idx];
+        if (p.infil) {
+            if (m.ks_f) gks = m.ks_f[idx];
+            if (m.psi_f) gpsi = m.psi_f[idx];
+            if (m.dth_f) gdth = m.dth_f[idx];
+        }
+    }
+    rain_infiltration(p, dt, rate, gks, gpsi, gdth, hn, qxn, qyn, vi);
+    if (p.infil) m.vinf[idx] = vi;
+    io.ho[idx] = hn;
+    io.qxo[idx] = qxn;
+    io.qyo[idx] = qyn;
+    bool fin = (hn - hn) == 0.0 && (qxn - qxn) == 0.0 && (qyn - qyn) == 0.0;
+    if (!fin)
+        atomicOr(&m.sc->status, (unsigned)SWE_FLAG_NONFINITE);
+    else if (hn < 0.0)
+        atomicOr(&m.sc->status, (unsigned)SWE_FLAG_NEGDEPTH);
+}
+
+template <int STAGE, int TXT, class D, bool FIELDS, int ORDER>
 __device__ __forceinline__ int march(const MemberArgs& m, const TileIO& io, int strip, int y0,
                                      int y1, double dt, double rain, double& ax, double& ay,
                                      TileLds<TXT>& L) {
@@ -755,8 +804,8 @@ __device__ __forceinline__ int march(const MemberArgs& m, const TileIO& io, int 
     double n0h = fC.h, n0x = fC.qx, n0y = fC.qy, n1h = fD.h, n1x = fD.qx, n1y = fD.qy;
     double c0 = fC.coef, c1 = fD.coef;
 
-    Rec rprev = muscl(to_y(pA), to_y(pB), to_y(p0), p.h_eps, d.rcp(pB.h), d);
-    Rec rcur = muscl(to_y(pB), to_y(p0), to_y(p1), p.h_eps, R0, d);
+    Rec rprev = reconstruct<ORDER>(to_y(pA), to_y(pB), to_y(p0), p.h_eps, d.rcp(pB.h), d);
+    Rec rcur = reconstruct<ORDER>(to_y(pB), to_y(p0), to_y(p1), p.h_eps, R0, d);
     double gm0, gm1, gm2;  // face below the current row, as seen from above
     double gm_speed = 0.0;
     {
@@ -797,7 +846,7 @@ __device__ __forceinline__ int march(const MemberArgs& m, const TileIO& io, int 
         Prim p2 = prim_x(r2, p.h_eps, R2, d);
         note_cell(d, r2, p2);
         d.settle();
-        Rec rnext = muscl(to_y(p0), to_y(p1), to_y(p2), p.h_eps, R1, d);
+        Rec rnext = reconstruct<ORDER>(to_y(p0), to_y(p1), to_y(p2), p.h_eps, R1, d);
         FaceOut gp = face(p.g, rcur.h_p, rcur.z_p, rcur.un_p, rcur.ut_p, rnext.h_m, rnext.z_m,
                           rnext.un_m, rnext.ut_m, d);
         double gp_speed = 0.0;
@@ -821,7 +870,7 @@ __device__ __forceinline__ int march(const MemberArgs& m, const TileIO& io, int 
             pl.h = L.h[b][tl]; pl.un = L.u[b][tl]; pl.ut = L.v[b][tl]; pl.eta = L.e[b][tl];
             pr.h = L.h[b][tr]; pr.un = L.u[b][tr]; pr.ut = L.v[b][tr]; pr.eta = L.e[b][tr];
         }
-        Rec rx = muscl(pl, p0, pr, p.h_eps, R0, d);
+        Rec rx = reconstruct<ORDER>(pl, p0, pr, p.h_eps, R0, d);
         double hm_r, zm_r, unm_r, utm_r;
         if (WAVE) {
             hm_r = from_right(rx.h_m);
@@ -923,27 +972,7 @@ __device__ __forceinline__ int march(const MemberArgs& m, const TileIO& io, int 
                 double hn = 0.5 * (n0h + h2);
                 double qxn = 0.5 * (n0x + qx2);
                 double qyn = 0.5 * (n0y + qy2);
-                // R = r(t) w and the soil of the cell (the optional fields
-                // are compiled in only for launches that have some)
-                double rate = rain, gks = p.ks, gpsi = p.psi, gdth = p.dtheta;
-                if constexpr (FIELDS) {
-                    if (m.rain_w) rate = rain * m.rain_w[idx];
-                    if (p.infil) {
-                        if (m.ks_f) gks = m.ks_f[idx];
-                        if (m.psi_f) gpsi = m.psi_f[idx];
-                        if (m.dth_f) gdth = m.dth_f[idx];
-                    }
-                }
-                rain_infiltration(p, dt, rate, gks, gpsi, gdth, hn, qxn, qyn, vi);
-                if (p.infil) m.vinf[idx] = vi;
-                io.ho[idx] = hn;
-                io.qxo[idx] = qxn;
-                io.qyo[idx] = qyn;
-                bool fin = (hn - hn) == 0.0 && (qxn - qxn) == 0.0 && (qyn - qyn) == 0.0;
-                if (!fin)
-                    atomicOr(&m.sc->status, (unsigned)SWE_FLAG_NONFINITE);
-                else if (hn < 0.0)
-                    atomicOr(&m.sc->status, (unsigned)SWE_FLAG_NEGDEPTH);
+                finish_cell<FIELDS>(m, io, idx, dt, rain, hn, qxn, qyn, vi);
             }
         }
 
@@ -981,6 +1010,65 @@ __device__ __forceinline__ double rain_rate(const MemberArgs& m, double t) {
     return k == 0 ? 0.0 : m.sc->hy_r[k - 1];
 }
 
+// Start of the update of a step: dt from the wave-speed bounds of stage 1
+// (eq. cfl), the rain r(t) at the step's start time, and, by thread 0 of
+// the lead block, the time, step count and dt log of the next slot.
+// Returns false when no step is taken (dt not positive or not finite; the
+// latter raises the sticky DT flag).
+__device__ __forceinline__ bool begin_step(const MemberArgs& m, const TileIO& io, bool lead,
+                                           double& dt, double& rain) {
+    double ax, ay;
+    read_amax(&m.sc->amax[io.slot][0][0], ax, ay);
+    double tc = m.sc->t[io.slot];
+    rain = rain_rate(m, tc);
+    dt = io.dt_fixed > 0.0 ? io.dt_fixed : time_step(m.p, ax, ay, tc, io.t_end);
+    const bool finite = (dt - dt) == 0.0;  // false for inf and NaN
+    if (lead && threadIdx.x == 0) {
+        long long st = m.sc->steps[io.slot];
+        if (finite && dt > 0.0) {
+            m.sc->t[io.slot ^ 1] = tc + dt;
+            m.sc->steps[io.slot ^ 1] = st + 1;
+            m.sc->last_dt = dt;
+            if (m.dtlog && st < m.dtlog_cap) m.dtlog[st] = dt;
+        } else {
+            m.sc->t[io.slot ^ 1] = tc;
+            m.sc->steps[io.slot ^ 1] = st;
+            if (!finite) atomicOr(&m.sc->status, (unsigned)SWE_FLAG_DT);
+        }
+    }
+    return finite && dt > 0.0;
+}
+
+// First order (Section 3.3): the update of a step is one explicit Euler
+// stage, U^{n+1} = friction(U^n + dt Phi(U^n)) (the convective and
+// friction steps of Sections 3.1-3.2), then rain and Green-Ampt.  Cell by
+// cell (no stencil): cells first, first + stride, ...
+template <bool FIELDS>
+__device__ __forceinline__ void euler_cells(const MemberArgs& m, const TileIO& io, bool lead,
+                                            size_t first, size_t stride) {
+    const KParams& p = m.p;
+    const size_t n = (size_t)p.nx * (size_t)p.ny;
+    double dt, rain;
+    if (!begin_step(m, io, lead, dt, rain)) {
+        for (size_t i = first; i < n; i += stride) {
+            io.ho[i] = io.h[i];
+            io.qxo[i] = io.qx[i];
+            io.qyo[i] = io.qy[i];
+        }
+        return;
+    }
+    for (size_t i = first; i < n; i += stride) {
+        const double h0 = io.h[i], qx0 = io.qx[i], qy0 = io.qy[i];
+        double h1 = h0 + dt * io.ph[i];
+        double qx1 = qx0 + dt * io.pqx[i];
+        double qy1 = qy0 + dt * io.pqy[i];
+        const double coef = m.fric ? m.fric[i] : p.coef;
+        friction(p, coef, h0, qx0, qy0, h1, qx1, qy1, dt);
+        const double vi = p.infil ? m.vinf[i] : 0.0;
+        finish_cell<FIELDS>(m, io, i, dt, rain, h1, qx1, qy1, vi);
+    }
+}
+
 // Whether a simulation has any optional per-cell rain or soil field (its
 // stage-2 launches then take the FIELDS variant of the tile routine).
 __host__ __device__ __forceinline__ bool has_fields(const MemberArgs& m) {
@@ -994,8 +1082,9 @@ __host__ __device__ __forceinline__ bool has_fields(const MemberArgs& m) {
 // per simulation that does the scalar bookkeeping (time, step count, dt log,
 // clearing the next step's accumulators).
 // `spread` picks the accumulator pair of stage 1 (any block-dependent index).
-// FIELDS compiles in the reads of the optional rain and soil fields.
-template <int STAGE, int TXT, bool FIELDS = false>
+// FIELDS compiles in the reads of the optional rain and soil fields; ORDER 1
+// (stage 1 only) replaces MUSCL by the cell values (first order).
+template <int STAGE, int TXT, bool FIELDS = false, int ORDER = 2>
 __device__ __forceinline__ void stage_tile(const MemberArgs& m, const TileIO& io, int strip,
                                            int y0, int y1, bool lead, int spread) {
     constexpr int OUTW = TXT - 2 * HALO;
@@ -1008,26 +1097,7 @@ __device__ __forceinline__ void stage_tile(const MemberArgs& m, const TileIO& io
 
     double dt = 0.0, rain = 0.0;
     if (STAGE == 2) {
-        double ax, ay;
-        read_amax(&m.sc->amax[io.slot][0][0], ax, ay);
-        double tc = m.sc->t[io.slot];
-        rain = rain_rate(m, tc);
-        dt = io.dt_fixed > 0.0 ? io.dt_fixed : time_step(p, ax, ay, tc, io.t_end);
-        const bool finite = (dt - dt) == 0.0;  // false for inf and NaN
-        if (lead && t == 0) {
-            long long st = m.sc->steps[io.slot];
-            if (finite && dt > 0.0) {
-                m.sc->t[io.slot ^ 1] = tc + dt;
-                m.sc->steps[io.slot ^ 1] = st + 1;
-                m.sc->last_dt = dt;
-                if (m.dtlog && st < m.dtlog_cap) m.dtlog[st] = dt;
-            } else {
-                m.sc->t[io.slot ^ 1] = tc;
-                m.sc->steps[io.slot ^ 1] = st;
-                if (!finite) atomicOr(&m.sc->status, (unsigned)SWE_FLAG_DT);
-            }
-        }
-        if (!(finite && dt > 0.0)) {
+        if (!begin_step(m, io, lead, dt, rain)) {
             // no step: U^{n+1} = U^n
             if (out_col) {
                 for (int j = y0; j < y1; ++j) {
@@ -1049,9 +1119,10 @@ __device__ __forceinline__ void stage_tile(const MemberArgs& m, const TileIO& io
     double ax = 0.0, ay = 0.0;
     int stop = y0;
     if (p.fast_div)
-        stop = march<STAGE, TXT, FastDiv, FIELDS>(m, io, strip, y0, y1, dt, rain, ax, ay, L);
+        stop = march<STAGE, TXT, FastDiv, FIELDS, ORDER>(m, io, strip, y0, y1, dt, rain, ax, ay,
+                                                         L);
     if (stop < y1)
-        march<STAGE, TXT, ExactDiv, FIELDS>(m, io, strip, stop, y1, dt, rain, ax, ay, L);
+        march<STAGE, TXT, ExactDiv, FIELDS, ORDER>(m, io, strip, stop, y1, dt, rain, ax, ay, L);
     if (STAGE == 1) block_max2<TXT>(ax, ay, io.acc, spread);
 }
 

@@ -43,13 +43,22 @@ constexpr int DIAG_BLOCKS = 512;  // blocks of the diagnostics reduction
 constexpr int DIAG_T = 256;
 constexpr int GRAPH_STEPS = 16;   // steps per captured graph (even)
 
-template <int STAGE, int TXT, bool FIELDS>
+template <int STAGE, int TXT, bool FIELDS, int ORDER>
 __global__ __launch_bounds__(TXT) void stage_kernel(MemberArgs m, TileIO io, int ty) {
     const int y0 = blockIdx.y * ty;
     const int y1 = min(y0 + ty, m.p.ny);
-    stage_tile<STAGE, TXT, FIELDS>(m, io, blockIdx.x, y0, y1,
-                                   blockIdx.x == 0 && blockIdx.y == 0,
-                                   blockIdx.x + blockIdx.y * gridDim.x);
+    stage_tile<STAGE, TXT, FIELDS, ORDER>(m, io, blockIdx.x, y0, y1,
+                                          blockIdx.x == 0 && blockIdx.y == 0,
+                                          blockIdx.x + blockIdx.y * gridDim.x);
+}
+
+// First-order update (one Euler stage), cell by cell over a grid-stride loop.
+constexpr int EULER_T = 256;
+template <bool FIELDS>
+__global__ __launch_bounds__(EULER_T) void euler_kernel(MemberArgs m, TileIO io) {
+    euler_cells<FIELDS>(m, io, blockIdx.x == 0,
+                        (size_t)blockIdx.x * EULER_T + threadIdx.x,
+                        (size_t)gridDim.x * EULER_T);
 }
 
 // Deterministic diagnostics: block b reduces the cells b, b + B, b + 2B, ...
@@ -98,24 +107,41 @@ __global__ void diag_final_kernel(double* part, int nb) {
     }
 }
 
-template <int STAGE, bool FIELDS>
+template <int STAGE, bool FIELDS, int ORDER>
 void launch_stage_t(int tx, dim3 grid, hipStream_t s, const MemberArgs& m, const TileIO& io,
                     int ty) {
     switch (tx) {
-        case 64: hipLaunchKernelGGL((stage_kernel<STAGE, 64, FIELDS>), grid, dim3(64), 0, s, m, io, ty); break;
-        case 128: hipLaunchKernelGGL((stage_kernel<STAGE, 128, FIELDS>), grid, dim3(128), 0, s, m, io, ty); break;
-        default: hipLaunchKernelGGL((stage_kernel<STAGE, 256, FIELDS>), grid, dim3(256), 0, s, m, io, ty); break;
+        case 64: hipLaunchKernelGGL((stage_kernel<STAGE, 64, FIELDS, ORDER>), grid, dim3(64), 0, s, m, io, ty); break;
+        case 128: hipLaunchKernelGGL((stage_kernel<STAGE, 128, FIELDS, ORDER>), grid, dim3(128), 0, s, m, io, ty); break;
+        default: hipLaunchKernelGGL((stage_kernel<STAGE, 256, FIELDS, ORDER>), grid, dim3(256), 0, s, m, io, ty); break;
     }
 }
 
-// stage 1 never reads the rain and soil fields
+// Stage 1 never reads the rain and soil fields; the first-order scheme has
+// only stage 1 (its update is euler_kernel).
 template <int STAGE>
 void launch_stage(int tx, dim3 grid, hipStream_t s, const MemberArgs& m, const TileIO& io,
                   int ty) {
-    if (STAGE == 2 && has_fields(m))
-        launch_stage_t<STAGE, true>(tx, grid, s, m, io, ty);
+    if constexpr (STAGE == 1) {
+        if (m.p.order == 1)
+            launch_stage_t<1, false, 1>(tx, grid, s, m, io, ty);
+        else
+            launch_stage_t<1, false, 2>(tx, grid, s, m, io, ty);
+    } else {
+        if (has_fields(m))
+            launch_stage_t<2, true, 2>(tx, grid, s, m, io, ty);
+        else
+            launch_stage_t<2, false, 2>(tx, grid, s, m, io, ty);
+    }
+}
+
+void launch_euler(hipStream_t s, const MemberArgs& m, const TileIO& io) {
+    const size_t n = (size_t)m.p.nx * (size_t)m.p.ny;
+    const unsigned blocks = (unsigned)std::min<size_t>((n + EULER_T - 1) / EULER_T, 16384);
+    if (has_fields(m))
+        hipLaunchKernelGGL(euler_kernel<true>, dim3(blocks), dim3(EULER_T), 0, s, m, io);
     else
-        launch_stage_t<STAGE, false>(tx, grid, s, m, io, ty);
+        hipLaunchKernelGGL(euler_kernel<false>, dim3(blocks), dim3(EULER_T), 0, s, m, io);
 }
 
 }  // namespace
@@ -159,7 +185,10 @@ void enqueue_step(swe_ctx* c, int phase, double t_end, bool profile) {
     if (prof) (void)hipEventRecord(c->prof_ev[3 * c->prof_n], c->stream);
     launch_stage<1>(c->tx, grid, c->stream, c->m, io, c->ty);
     if (prof) (void)hipEventRecord(c->prof_ev[3 * c->prof_n + 1], c->stream);
-    launch_stage<2>(c->tx, grid, c->stream, c->m, io, c->ty);
+    if (c->m.p.order == 1)
+        launch_euler(c->stream, c->m, io);
+    else
+        launch_stage<2>(c->tx, grid, c->stream, c->m, io, c->ty);
     if (prof) (void)hipEventRecord(c->prof_ev[3 * c->prof_n++ + 2], c->stream);
     c->slot ^= 1;
 }

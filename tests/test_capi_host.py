@@ -117,3 +117,22 @@ def test_adjoint_rejects_rain_and_soil_fields_without_gpu():
         with pytest.raises(capi.SweError) as e:
             capi.swe_adj_create(p, b, 10, 3, 4096, 1, 5, 4096, 4096, 1 << 30, 0)
         assert e.value.code == capi.SWE_EINVAL
+
+
+def test_first_order_limits_without_gpu():
+    # ensembles and the adjoint run the second-order scheme only; an order
+    # outside {0, 1, 2} is invalid (all checked before any device work)
+    from paper_1307_4839_amd import capi
+    for order in (-1, 3):
+        with pytest.raises(capi.SweError):
+            capi.swe_workspace_bytes(capi.make_params(8, 8, 1.0, 1.0, order=order))
+    p1 = capi.make_params(16, 16, 1.0, 1.0, fric_law=capi.SWE_FRIC_MANNING, fric_coef=0.03,
+                          order=1)
+    b = capi.swe_buffers()
+    b.h = b.qx = b.qy = b.z = b.fric = 4096
+    with pytest.raises(capi.SweError) as e:
+        capi.swe_adj_create(p1, b, 10, 3, 4096, 1, 5, 4096, 4096, 1 << 30, 0)
+    assert e.value.code == capi.SWE_EINVAL
+    with pytest.raises(capi.SweError) as e:
+        capi.swe_batch_create([p1], [b], 4096, 1 << 30, 0)
+    assert e.value.code == capi.SWE_EINVAL

@@ -1,0 +1,134 @@
+"""GPU parity of the first-order scheme (Section 3.3: no reconstruction, one
+explicit Euler stage per step, n_CFL = 1) with the oracle, through the C
+ABI: single rates on random states, whole runs with wet/dry fronts, rain,
+Green-Ampt and the optional rain/soil fields, tile-shape invariance, and a
+lake at rest."""
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1307_4839_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def rel_err(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def first_order(wl, cfl=1.0):
+    wl = wl.copy()
+    wl.order, wl.cfl = 1, cfl
+    return wl
+
+
+def compare(wl, nsteps, t_end=math.inf, tiling=None):
+    from paper_1307_4839_amd.solver import Solver
+    say(f"[order1] {wl.name} {wl.nx}x{wl.ny} steps={nsteps} tiling={tiling}")
+    s = oracle.State(wl)
+    assert s.run(nsteps, t_end) in (0, 1)
+    g = Solver(wl, dt_log=s.steps + 1)
+    if tiling:
+        g.set_tiling(*tiling)
+    g.step(nsteps, t_end)
+    rc, flags = g.status()
+    assert rc == 0 and flags == 0, (rc, flags)
+    t, _, steps = g.time()
+    assert steps == s.steps
+    assert np.abs(g.dts()[:steps] - np.array(s.dts)).max() <= TOL * max(s.dts)
+    st = g.state()
+    same = True
+    for k in ("h", "qx", "qy", "vinf"):
+        if k in st:
+            e = rel_err(st[k], getattr(s, k))
+            same = same and np.array_equal(st[k], getattr(s, k))
+            assert e <= TOL, (k, e)
+    say(f"    bitwise={same} t={t}")
+    g.close()
+    return s, st
+
+
+@pytest.mark.parametrize("bc", [(0, 0, 0, 0), (1, 1, 1, 1), (0, 1, 1, 0)])
+@pytest.mark.parametrize("shape", [(37, 29), (300, 41), (253, 3), (2, 2)])
+def test_rate_random_state(torch_cuda, shape, bc):
+    from paper_1307_4839_amd.solver import Solver
+    nx, ny = shape
+    wl = first_order(I.random_state(nx, ny, seed=nx * 7 + ny, bc=bc))
+    p = oracle.params_of(wl)
+    ph, pqx, pqy, amax = oracle.rate(p, wl.h, wl.qx, wl.qy, wl.z)
+    g = Solver(wl)
+    gph, gpqx, gpqy, gamax = g.rate(g.h, g.qx, g.qy)
+    torch_cuda.cuda.synchronize()
+    for a, b in ((gph, ph), (gpqx, pqx), (gpqy, pqy)):
+        assert np.array_equal(a.cpu().numpy(), b)
+    assert gamax[0] == amax[0] and gamax[1] == amax[1]
+    g.close()
+
+
+def test_dam_break_200_to_30s(torch_cuda):
+    s, _ = compare(first_order(I.dam_break_200()), 10 ** 6, t_end=30.0)
+    assert s.t == 30.0
+
+
+def test_valley_small(torch_cuda):
+    compare(first_order(I.valley_2048(300, 320, dam_row=60)), 300)
+
+
+@pytest.mark.parametrize("tiling", [None, (64, 8), (128, 16)])
+def test_hillslope_rain_infiltration(torch_cuda, tiling):
+    compare(first_order(I.hillslope_8192(260, 200)), 400, tiling=tiling)
+
+
+def test_hillslope_with_rain_and_soil_fields(torch_cuda):
+    wl = first_order(I.hillslope_8192(200, 150))
+    rng = np.random.default_rng(8)
+    wl.rain_t = np.array([0.0, 100.0, 250.0])
+    wl.rain_r = np.array([80.0, 20.0, 60.0]) * I.MM_PER_HOUR
+    wl.rain_w = rng.uniform(0.3, 1.7, (wl.ny, wl.nx))
+    wl.ks_f = wl.ks * rng.uniform(0.5, 1.5, (wl.ny, wl.nx))
+    compare(wl, 450)
+
+
+@pytest.mark.parametrize("bc,cfl", [((0, 0, 0, 0), 1.0), ((0, 1, 1, 0), 0.5)])
+def test_lake_at_rest(torch_cuda, bc, cfl):
+    # walls at n_CFL = 1; free-outflow edges at 0.5 (against a zero-gradient
+    # edge a lake is only neutrally at rest, on both sides of the parity)
+    from paper_1307_4839_amd.solver import Solver
+    rng = np.random.default_rng(3)
+    nx, ny, C = 90, 70, 1.2
+    x = (np.arange(nx) + 0.5)[None, :]
+    y = (np.arange(ny) + 0.5)[:, None]
+    z = 0.3 * rng.uniform(0, 1, (ny, nx)) + 0.01 * x
+    for _ in range(5):
+        cx, cy = rng.uniform(0, nx), rng.uniform(0, ny)
+        z = z + 2.0 * np.exp(-((x - cx) ** 2 + (y - cy) ** 2) / 8.0)
+    h = np.maximum(C - z, 0.0)
+    wl = I.Workload("lake", nx, ny, 1.0, 1.0, z=z, h=h, qx=np.zeros_like(h),
+                    qy=np.zeros_like(h), bc=bc, fric_law=I.FRIC_MANNING,
+                    fric_coef=0.03, order=1, cfl=cfl)
+    g = Solver(wl)
+    g.step(1000)
+    st = g.state()
+    wet = h > 0
+    assert np.abs((st["h"] + z)[wet] - C).max() <= 1e-12 * C
+    assert np.all(st["h"][~wet] == 0.0)
+    assert np.abs(st["qx"]).max() <= 1e-12 * math.sqrt(9.81 * h.max() ** 3)
+    g.close()
