@@ -38,6 +38,7 @@
 #include <cstdint>
 #include <cstring>
 #include <new>
+#include <utility>
 #include <vector>
 
 #include "swe.h"
@@ -756,7 +757,9 @@ __global__ __launch_bounds__(T1) void stage_out_kernel(KParams p, const double* 
 
 // Reverse of a stage's friction and of C = U_in + dt Phi(U_in) up to the
 // rate: given the adjoint of the stage output (bo), writes
-//   lam_in  = (=|+=) bC + (friction-factor part)   [accumulate if acc]
+//   lam_in  = bC + (friction-factor part)           [mode 0]
+//   lam_in += the same                               [mode 1]
+//   lam_in  = base/2 + the same                      [mode 2: Heun's other half]
 //   mu      = dt * bC                              (seed for VJP_Phi)
 //   grad   += d/dcoef
 // STAGE 2 also forms the Heun split: its output adjoint is half of `lam`,
@@ -768,7 +771,8 @@ __global__ __launch_bounds__(T1) void adj_stage_kernel(
     const double* __restrict__ pqy, double dt, const double* __restrict__ bo_h,
     const double* __restrict__ bo_qx, const double* __restrict__ bo_qy, double bo_scale,
     double* __restrict__ lin_h, double* __restrict__ lin_qx, double* __restrict__ lin_qy,
-    int accumulate, double* __restrict__ mu_h, double* __restrict__ mu_qx,
+    int mode, const double* __restrict__ base_h, const double* __restrict__ base_qx,
+    const double* __restrict__ base_qy, double* __restrict__ mu_h, double* __restrict__ mu_qx,
     double* __restrict__ mu_qy, double* __restrict__ grad, size_t n) {
     size_t i = (size_t)blockIdx.x * T1 + threadIdx.x;
     if (i >= n) return;
@@ -782,10 +786,14 @@ __global__ __launch_bounds__(T1) void adj_stage_kernel(
                  bo_scale * bo_qx[i], bo_scale * bo_qy[i], bh1, bqx1, bqy1, bh0, bqx0, bqy0,
                  bc);
     double lh = bh1 + bh0, lqx = bqx1 + bqx0, lqy = bqy1 + bqy0;
-    if (accumulate) {
+    if (mode == 1) {
         lin_h[i] += lh;
         lin_qx[i] += lqx;
         lin_qy[i] += lqy;
+    } else if (mode == 2) {
+        lin_h[i] = 0.5 * base_h[i] + lh;
+        lin_qx[i] = 0.5 * base_qx[i] + lqx;
+        lin_qy[i] = 0.5 * base_qy[i] + lqy;
     } else {
         lin_h[i] = lh;
         lin_qx[i] = lqx;
@@ -795,19 +803,6 @@ __global__ __launch_bounds__(T1) void adj_stage_kernel(
     mu_qx[i] = dt * bqx1;
     mu_qy[i] = dt * bqy1;
     if (grad) grad[i] += bc;
-}
-
-// Heun split of stage 2: lam_n = lam/2 (the other half enters the stage).
-__global__ __launch_bounds__(T1) void half_kernel(const double* __restrict__ a,
-                                                  const double* __restrict__ b,
-                                                  const double* __restrict__ c,
-                                                  double* __restrict__ A, double* __restrict__ B,
-                                                  double* __restrict__ Cc, size_t n) {
-    size_t i = (size_t)blockIdx.x * T1 + threadIdx.x;
-    if (i >= n) return;
-    A[i] = 0.5 * a[i];
-    B[i] = 0.5 * b[i];
-    Cc[i] = 0.5 * c[i];
 }
 
 // h at the gauges -> row of the gauge series
@@ -902,6 +897,7 @@ struct swe_adj {
     double* series;        // device, nrows x ngauges
     double* ckpts;         // device, nckpt x 3N
     double* seg;           // device, (ckpt + 1) x 3N
+    double* segphi;        // Phi(U^k) of the recomputed segment steps, ckpt x 3N
     double* ust;           // U* (3N)
     double* phi;           // Phi (3N)
     double* phi0;          // Phi(U^k) kept for the reverse of stage 1 (3N)
@@ -921,25 +917,34 @@ size_t adj_bytes(const swe_params* p, int nsteps, int ckpt, int ngauges, int eve
     size_t rows = every > 0 ? nsteps / every : 0;
     return SCALAR_BYTES + 256 + align256(nsteps * sizeof(double)) +
            align256(rows * (size_t)ngauges * sizeof(double)) + 3 * an * nck +
-           3 * an * (ckpt + 1) + 3 * an * 7;
+           3 * an * (ckpt + 1) + 3 * an * ckpt + 3 * an * 7;
 }
 
 inline double* plane(double* base, size_t n, int k) { return base + (size_t)k * n; }
+inline const double* plane(const double* base, size_t n, int k) { return base + (size_t)k * n; }
 
 int blocks(size_t n) { return (int)((n + T1 - 1) / T1); }
 
 // One forward step U_in -> U_out with a frozen dt (dt_fixed > 0) or the CFL
-// dt (dt_fixed = 0, logged to dts[k]).
+// dt (dt_fixed = 0, logged to dts[k]).  phi_out (optional) receives
+// Phi(U_in), which stage 1 computes anyway.
 void fwd_step(swe_adj* A, const double* h, const double* qx, const double* qy, double* ho,
-              double* qxo, double* qyo, double dt_fixed, int k) {
+              double* qxo, double* qyo, double dt_fixed, int k, double* phi_out = nullptr) {
     MemberArgs m = A->m;
     m.h[0] = (double*)h; m.qx[0] = (double*)qx; m.qy[0] = (double*)qy;
     m.h[1] = ho; m.qx[1] = qxo; m.qy[1] = qyo;
     m.dtlog = dt_fixed > 0.0 ? nullptr : A->dts + k;
     m.dtlog_cap = dt_fixed > 0.0 ? 0 : 1;
+    if (phi_out) {
+        m.ph = plane(phi_out, A->n, 0);
+        m.pqx = plane(phi_out, A->n, 1);
+        m.pqy = plane(phi_out, A->n, 2);
+    }
     // the logged entry is indexed by the step count of the scalar block,
-    // which is reset to 0 before each step so that dts[k] receives it
-    hipLaunchKernelGGL(reset_step_kernel, dim3(1), dim3(64), 0, A->stream, m.sc);
+    // which is reset to 0 before each step so that dts[k] receives it; a
+    // frozen dt reads neither the count nor the wave-speed bounds
+    if (!(dt_fixed > 0.0))
+        hipLaunchKernelGGL(reset_step_kernel, dim3(1), dim3(64), 0, A->stream, m.sc);
     TileIO io = host_step_io(m, 0, 0, INFINITY);
     io.dt_fixed = dt_fixed;
     launch_fwd<1>(A->prm, A->stream, m, io);
@@ -955,10 +960,11 @@ void rate_into(swe_adj* A, const double* h, const double* qx, const double* qy, 
     io.ph = plane(dst, A->n, 0);
     io.pqx = plane(dst, A->n, 1);
     io.pqy = plane(dst, A->n, 2);
+    // the wave-speed bounds go to slot 2, which nothing reads here: it is
+    // not cleared
     io.acc = &m.sc->amax[2][0][0];
     io.clr = nullptr;
     io.slot = 2;
-    hipLaunchKernelGGL(swe_clear_amax_kernel, dim3(1), dim3(64), 0, A->stream, m.sc, 2);
     launch_fwd<1>(A->prm, A->stream, m, io);
 }
 
@@ -976,23 +982,22 @@ void vjp_rate(swe_adj* A, const double* h, const double* qx, const double* qy, d
 }
 
 // lamA <- adjoint of U^k given lam = adjoint of U^{k+1}; grad += dL/dn.
-void adj_step(swe_adj* A, const double* Uk, double dt, double* grad) {
+// phik: Phi(U^k) kept from the segment recompute, or null to recompute it.
+void adj_step(swe_adj* A, const double* Uk, double dt, double* grad, const double* phik) {
     const size_t n = A->n;
     const double* h = Uk;
     const double* qx = Uk + n;
     const double* qy = Uk + 2 * n;
     double* us = A->ust;
-    // recompute Phi(U^k) (kept for stage 1) and U*
-    rate_into(A, h, qx, qy, A->phi0);
+    // Phi(U^k) (kept for stage 1) and U*
+    if (!phik) {
+        rate_into(A, h, qx, qy, A->phi0);
+        phik = A->phi0;
+    }
     hipLaunchKernelGGL(stage_out_kernel, dim3(blocks(n)), dim3(T1), 0, A->stream, A->m.p,
-                       A->m.fric, h, qx, qy, (const double*)plane(A->phi0, n, 0),
-                       (const double*)plane(A->phi0, n, 1), (const double*)plane(A->phi0, n, 2),
-                       dt, plane(us, n, 0), plane(us, n, 1), plane(us, n, 2), n);
-    // Heun: lam_n = lam/2
-    hipLaunchKernelGGL(half_kernel, dim3(blocks(n)), dim3(T1), 0, A->stream,
-                       (const double*)plane(A->lam, n, 0), (const double*)plane(A->lam, n, 1),
-                       (const double*)plane(A->lam, n, 2), plane(A->lamA, n, 0),
-                       plane(A->lamA, n, 1), plane(A->lamA, n, 2), n);
+                       A->m.fric, h, qx, qy, plane(phik, n, 0), plane(phik, n, 1),
+                       plane(phik, n, 2), dt, plane(us, n, 0), plane(us, n, 1), plane(us, n, 2),
+                       n);
     // stage 2 on U*: Phi(U*), then its friction reversed with output
     // adjoint lam/2
     rate_into(A, plane(us, n, 0), plane(us, n, 1), plane(us, n, 2), A->phi);
@@ -1002,17 +1007,20 @@ void adj_step(swe_adj* A, const double* Uk, double dt, double* grad) {
                        (const double*)plane(A->phi, n, 1), (const double*)plane(A->phi, n, 2), dt,
                        (const double*)plane(A->lam, n, 0), (const double*)plane(A->lam, n, 1),
                        (const double*)plane(A->lam, n, 2), 0.5, plane(A->lamB, n, 0),
-                       plane(A->lamB, n, 1), plane(A->lamB, n, 2), 0, plane(A->mu, n, 0),
+                       plane(A->lamB, n, 1), plane(A->lamB, n, 2), 0, nullptr, nullptr, nullptr,
+                       plane(A->mu, n, 0),
                        plane(A->mu, n, 1), plane(A->mu, n, 2), grad, n);
     vjp_rate(A, plane(us, n, 0), plane(us, n, 1), plane(us, n, 2), A->lamB);
-    // stage 1 on U^k (Phi(U^k) kept above): friction reversed with output
-    // adjoint lamB, accumulated into lamA
+    // stage 1 on U^k: friction reversed with output adjoint lamB; lamA =
+    // lam/2 (Heun: lam_n takes half of lam directly) + that
     hipLaunchKernelGGL(adj_stage_kernel, dim3(blocks(n)), dim3(T1), 0, A->stream, A->m.p,
-                       A->m.fric, h, qx, qy, (const double*)plane(A->phi0, n, 0),
-                       (const double*)plane(A->phi0, n, 1), (const double*)plane(A->phi0, n, 2), dt,
+                       A->m.fric, h, qx, qy, plane(phik, n, 0), plane(phik, n, 1),
+                       plane(phik, n, 2), dt,
                        (const double*)plane(A->lamB, n, 0), (const double*)plane(A->lamB, n, 1),
                        (const double*)plane(A->lamB, n, 2), 1.0, plane(A->lamA, n, 0),
-                       plane(A->lamA, n, 1), plane(A->lamA, n, 2), 1, plane(A->mu, n, 0),
+                       plane(A->lamA, n, 1), plane(A->lamA, n, 2), 2,
+                       (const double*)plane(A->lam, n, 0), (const double*)plane(A->lam, n, 1),
+                       (const double*)plane(A->lam, n, 2), plane(A->mu, n, 0),
                        plane(A->mu, n, 1), plane(A->mu, n, 2), grad, n);
     vjp_rate(A, h, qx, qy, A->lamA);
 }
@@ -1083,6 +1091,7 @@ int swe_adj_create(const swe_params* p, const swe_buffers* b, int32_t nsteps,
     size_t nck = (nsteps + ckpt_every - 1) / ckpt_every;
     A->ckpts = (double*)w; w += 3 * an * nck;
     A->seg = (double*)w; w += 3 * an * (ckpt_every + 1);
+    A->segphi = (double*)w; w += 3 * an * ckpt_every;
     A->ust = (double*)w; w += 3 * an;
     A->phi = (double*)w; w += 3 * an;
     A->phi0 = (double*)w; w += 3 * an;
@@ -1207,7 +1216,8 @@ int swe_adj_backward(swe_adj* A, double* grad) {
         for (int k = s; k < e - 1; ++k) {
             double* in = A->seg + (size_t)(k - s) * 3 * n;
             double* o = in + 3 * n;
-            fwd_step(A, in, in + n, in + 2 * n, o, o + n, o + 2 * n, dts[k], k);
+            fwd_step(A, in, in + n, in + 2 * n, o, o + n, o + 2 * n, dts[k], k,
+                     A->segphi + (size_t)(k - s) * 3 * n);
         }
         for (int k = e - 1; k >= s; --k) {
             // loss term of U^{k+1}
@@ -1218,10 +1228,10 @@ int swe_adj_backward(swe_adj* A, double* grad) {
                                    A->ngauges, A->lam);
             }
             const double* Uk = A->seg + (size_t)(k - s) * 3 * n;
-            adj_step(A, Uk, dts[k], grad);
-            // lam <- lamA
-            (void)hipMemcpyAsync(A->lam, A->lamA, 3 * n * sizeof(double), hipMemcpyDeviceToDevice,
-                           A->stream);
+            adj_step(A, Uk, dts[k], grad,
+                     k < e - 1 ? A->segphi + (size_t)(k - s) * 3 * n : nullptr);
+            // lam <- lamA (the buffers trade places)
+            std::swap(A->lam, A->lamA);
         }
     }
     if (hipStreamSynchronize(A->stream) != hipSuccess) return SWE_EHIP;
