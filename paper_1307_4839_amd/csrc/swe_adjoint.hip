@@ -118,15 +118,18 @@ __host__ __device__ __forceinline__ void muscl_rev(const Prim& a, const Prim& c,
     cb.un += R.un_m + R.un_p;
     cb.ut += R.ut_m + R.ut_p;
     if (c.h > h_eps) {
-        double wp = h_p / c.h, wm = h_m / c.h;
+        // one reciprocal for the six quotients by h (the branches above are
+        // decided on the exact forward values; these are only arithmetic)
+        const double inv = 1.0 / c.h;
+        double wp = h_p * inv, wm = h_m * inv;
         double bwp = -(R.un_m * (0.5 * dun) + R.ut_m * (0.5 * dut));
         double bwm = R.un_p * (0.5 * dun) + R.ut_p * (0.5 * dut);
         double bdun = 0.5 * (wm * R.un_p - wp * R.un_m);
         double bdut = 0.5 * (wm * R.ut_p - wp * R.ut_m);
-        bh_p += bwp / c.h;
-        cb.h -= bwp * wp / c.h;
-        bh_m += bwm / c.h;
-        cb.h -= bwm * wm / c.h;
+        bh_p += bwp * inv;
+        cb.h -= bwp * wp * inv;
+        bh_m += bwm * inv;
+        cb.h -= bwm * wm * inv;
         route_minmod(su, bdun, ab.un, cb.un, bb.un);
         route_minmod(st, bdut, ab.ut, cb.ut, bb.ut);
     }
@@ -148,10 +151,11 @@ __host__ __device__ __forceinline__ void prim_rev(const RawCell& r, double h_eps
     bqx = 0.0;
     bqy = 0.0;
     if (r.h > h_eps) {
-        double u = r.qx / r.h, v = r.qy / r.h;
-        bqx = pb.un / r.h;
-        bqy = pb.ut / r.h;
-        bh -= (pb.un * u + pb.ut * v) / r.h;
+        const double inv = 1.0 / r.h;  // one reciprocal for the five quotients
+        double u = r.qx * inv, v = r.qy * inv;
+        bqx = pb.un * inv;
+        bqy = pb.ut * inv;
+        bh -= (pb.un * u + pb.ut * v) * inv;
     }
 }
 
@@ -201,18 +205,20 @@ __host__ __device__ __forceinline__ FaceBar face_rev(double g, double hm, double
     } else if (c2 <= 0.0) {
         for (int k = 0; k < 3; ++k) bFR[k] = bF[k];
     } else {
-        double D = c2 - c1;
-        double D2 = D * D;
+        // one reciprocal of D = c2 - c1 > 0 for every quotient of the branch
+        const double iD = 1.0 / (c2 - c1);
+        const double iD2 = iD * iD;
+        const double W = c1 * c2 * iD;
+        const double c2D = c2 * iD, c1D = c1 * iD, c12D2 = c1 * c2 * iD2;
         for (int k = 0; k < 3; ++k) {
             double A = c2 * FL[k] - c1 * FR[k];
             double dU = UR[k] - UL[k];
-            double W = c1 * c2 / D;
-            bFL[k] = bF[k] * c2 / D;
-            bFR[k] = -bF[k] * c1 / D;
+            bFL[k] = bF[k] * c2D;
+            bFR[k] = -bF[k] * c1D;
             bUR[k] = bF[k] * W;
             bUL[k] = -bF[k] * W;
-            bc2 += bF[k] * (FL[k] / D - A / D2 + (c1 / D - c1 * c2 / D2) * dU);
-            bc1 += bF[k] * (-FR[k] / D + A / D2 + (c2 / D + c1 * c2 / D2) * dU);
+            bc2 += bF[k] * (FL[k] * iD - A * iD2 + (c1D - c12D2) * dU);
+            bc1 += bF[k] * (-FR[k] * iD + A * iD2 + (c2D + c12D2) * dU);
         }
     }
     double bqL = 0.0, bqR = 0.0;
