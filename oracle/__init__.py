@@ -47,7 +47,8 @@ class OrcParams(C.Structure):
                 ("rain_n", C.c_int32), ("rain_t", C.POINTER(C.c_double)),
                 ("rain_r", C.POINTER(C.c_double)), ("rain_w", C.POINTER(C.c_double)),
                 ("ks_f", C.POINTER(C.c_double)), ("psi_f", C.POINTER(C.c_double)),
-                ("dtheta_f", C.POINTER(C.c_double)), ("order", C.c_int32)]
+                ("dtheta_f", C.POINTER(C.c_double)), ("order", C.c_int32),
+                ("flux", C.c_int32)]
 
 
 _lib = None
@@ -74,7 +75,7 @@ def lib(path: Optional[str] = None):
         l.orc_num_threads.restype = C.c_int
         l.orc_muscl.argtypes = [dp, dp, dp, C.c_double, dp]
         l.orc_hll.argtypes = [C.c_double] + [C.c_double] * 6 + [dp]
-        l.orc_face.argtypes = [C.c_double] + [C.c_double] * 8 + [dp]
+        l.orc_face.argtypes = [C.c_double] + [C.c_double] * 8 + [dp, C.c_int32]
         l.orc_tangent_run.argtypes = [pp, dp, dp, dp, dp, dp, dp, C.c_int32, dp,
                                       ip, C.c_int32, C.c_int32, dp, dp, dp]
         l.orc_gauge_run.argtypes = [pp, dp, dp, dp, dp, dp, C.c_int32, dp, ip,
@@ -101,9 +102,10 @@ def _ip(a: Optional[np.ndarray]):
 
 def params(nx, ny, dx, dy, g=9.81, cfl=0.5, dt_max=math.inf, h_eps=1e-12,
            bc=(0, 0, 0, 0), fric_law=0, fric_coef=0.0, rain=0.0, infil_on=0,
-           ks=0.0, psi=0.0, dtheta=0.0, order=2) -> OrcParams:
+           ks=0.0, psi=0.0, dtheta=0.0, order=2, flux=0) -> OrcParams:
     p = OrcParams()
     p.order = int(order)
+    p.flux = int(flux)
     p.nx, p.ny, p.dx, p.dy = nx, ny, dx, dy
     p.g, p.cfl, p.dt_max, p.h_eps = g, cfl, dt_max, h_eps
     for k in range(4):
@@ -241,10 +243,10 @@ def hll(g, hL, unL, utL, hR, unR, utR):
     return out
 
 
-def face(g, hm, zm, unm, utm, hp, zp, unp, utp):
-    """{F0, F1, F2, sL, sR, speed} of one face."""
+def face(g, hm, zm, unm, utm, hp, zp, unp, utp, flux=0):
+    """{F0, F1, F2, sL, sR, speed} of one face (flux 0 HLL, 1 Rusanov)."""
     out = np.zeros(6)
-    lib().orc_face(g, hm, zm, unm, utm, hp, zp, unp, utp, _dp(out))
+    lib().orc_face(g, hm, zm, unm, utm, hp, zp, unp, utp, _dp(out), flux)
     return out
 
 

@@ -8,7 +8,8 @@ formulas as printed, vectorised over cells and faces:
   U*_i = U^n_i - dt/dx [F_{i+1/2L} - F_{i-1/2R} - Fc_i];
 * hydrostatic reconstruction, S_{i+1/2L}, S_{i-1/2R} and Fc_i, Section 3.1;
 * HLL flux with c1 = min over U_L, U_R of u - sqrt(gh) and c2 = max of
-  u + sqrt(gh), Section 3.3;
+  u + sqrt(gh), Section 3.3 (or the Rusanov flux, another consistent flux
+  that section names);
 * MUSCL with minmod on h, h+z and u and the modified velocity, Section 3.4,
   written with divided differences exactly as printed;
 * semi-implicit friction and Heun's method, Section 3.2;
@@ -48,7 +49,7 @@ def _minmod(x, y):
     return out
 
 
-def convective_rate(h, q, z, dx, g, h_eps, bc, order=2):
+def convective_rate(h, q, z, dx, g, h_eps, bc, order=2, flux="hll"):
     """Returns the bracket [F_{i+1/2L} - F_{i-1/2R} - Fc_i] and max speed."""
     hp = _ghost(h, bc[0], bc[1], False)
     qp = _ghost(q, bc[0], bc[1], True)
@@ -86,11 +87,17 @@ def convective_rate(h, q, z, dx, g, h_eps, bc, order=2):
     c2 = np.maximum(um_ + cL, uq_ + cR)
     FL0, FL1 = hL * um_, hL * um_ * um_ + g * hL * hL / 2
     FR0, FR1 = hR * uq_, hR * uq_ * uq_ + g * hR * hR / 2
-    den = np.where((c1 < 0) & (c2 > 0), c2 - c1, 1.0)
-    mid0 = (c2 * FL0 - c1 * FR0) / den + c1 * c2 / den * (hR - hL)
-    mid1 = (c2 * FL1 - c1 * FR1) / den + c1 * c2 / den * (hR * uq_ - hL * um_)
-    F0 = np.where(c1 >= 0, FL0, np.where(c2 <= 0, FR0, mid0))
-    F1 = np.where(c1 >= 0, FL1, np.where(c2 <= 0, FR1, mid1))
+    if flux == "rusanov":
+        # local Lax-Friedrichs: (F(U_L) + F(U_R))/2 - c/2 (U_R - U_L)
+        c = np.maximum(np.abs(um_) + cL, np.abs(uq_) + cR)
+        F0 = (FL0 + FR0) / 2 - c / 2 * (hR - hL)
+        F1 = (FL1 + FR1) / 2 - c / 2 * (hR * uq_ - hL * um_)
+    else:
+        den = np.where((c1 < 0) & (c2 > 0), c2 - c1, 1.0)
+        mid0 = (c2 * FL0 - c1 * FR0) / den + c1 * c2 / den * (hR - hL)
+        mid1 = (c2 * FL1 - c1 * FR1) / den + c1 * c2 / den * (hR * uq_ - hL * um_)
+        F0 = np.where(c1 >= 0, FL0, np.where(c2 <= 0, FR0, mid0))
+        F1 = np.where(c1 >= 0, FL1, np.where(c2 <= 0, FR1, mid1))
     SL = g * (hm_ ** 2 - hL ** 2) / 2   # S_{i+1/2L}, momentum component
     SR = g * (hq_ ** 2 - hR ** 2) / 2   # S_{i+1/2R}
     speed = np.maximum(np.abs(um_) + np.sqrt(g * hm_),
@@ -119,9 +126,9 @@ def friction(h0, q0, h1, q1, dt, law, coef, g, h_eps):
 
 
 def heun_step(h, q, z, dt, dx, g=9.81, h_eps=1e-12, bc=(WALL, WALL), law=0,
-              coef=0.0):
+              coef=0.0, flux="hll"):
     def phi_stage(hh, qq):
-        B0, B1, _ = convective_rate(hh, qq, z, dx, g, h_eps, bc)
+        B0, B1, _ = convective_rate(hh, qq, z, dx, g, h_eps, bc, flux=flux)
         h1 = hh - dt / dx * B0
         q1 = qq - dt / dx * B1
         q1 = friction(hh, qq, h1, q1, dt, law, coef, g, h_eps)

@@ -130,6 +130,8 @@ struct orc_params {
     // 1: first order (Section 3.3: piecewise-constant reconstruction, one
     // explicit Euler stage per step); 0 or 2: the second-order scheme
     int32_t order;
+    // numerical flux (Section 3.3 allows any consistent one): 0 HLL, 1 Rusanov
+    int32_t flux;
 };
 }
 
@@ -236,8 +238,28 @@ inline void hll(double g, T hL, T unL, T utL, T hR, T unR, T utR, T F[3]) {
     }
 }
 
+// Rusanov (local Lax-Friedrichs) flux, one of the consistent fluxes
+// Section 3.3 lists: the centred average of the physical fluxes minus a
+// diffusion with the largest local wave speed,
+//   F = (F(U_L) + F(U_R))/2 - c/2 (U_R - U_L),
+//   c = max(|u_L| + sqrt(g h_L), |u_R| + sqrt(g h_R)).
+template <class T>
+inline void rusanov(double g, T hL, T unL, T utL, T hR, T unR, T utR, T F[3]) {
+    T cL = dsqrt(T(g) * hL);
+    T cR = dsqrt(T(g) * hR);
+    T c = vmax(dfabs(unL) + cL, dfabs(unR) + cR);
+    T qL = hL * unL;
+    T qR = hR * unR;
+    T FL[3] = {qL, qL * unL + T(0.5 * g) * hL * hL, qL * utL};
+    T FR[3] = {qR, qR * unR + T(0.5 * g) * hR * hR, qR * utR};
+    T UL[3] = {hL, qL, hL * utL};
+    T UR[3] = {hR, qR, hR * utR};
+    for (int k = 0; k < 3; ++k)
+        F[k] = T(0.5) * (FL[k] + FR[k]) - T(0.5) * c * (UR[k] - UL[k]);
+}
+
 // One face between a left cell (its "p" values) and a right cell (its "m"
-// values): hydrostatic reconstruction (Section 3.1), HLL flux and the two
+// values): hydrostatic reconstruction (Section 3.1), HLL (or Rusanov) flux and the two
 // normal-momentum corrections S_{i+1/2L} (for the left cell) and
 // S_{i+1/2R} (for the right cell).  Also returns the face's wave-speed bound
 // max(|u-| + sqrt(g h-), |u+| + sqrt(g h+)) on the MUSCL states, i.e. before
@@ -250,14 +272,17 @@ template <class T> struct Face {
 
 template <class T>
 inline Face<T> face(double g, T hm, T zm, T unm, T utm, T hp, T zp, T unp,
-                    T utp) {
+                    T utp, int flux = 0) {
     Face<T> f;
     T zs = vmax(zm, zp);
     T hL = vmax(hm + zm - zs, T(0.0));
     T hR = vmax(hp + zp - zs, T(0.0));
     // U_L = (h_L, h_L u-), U_R = (h_R, h_R u+); in 2D the tangential
     // velocity is carried the same way (reading).
-    hll(g, hL, unm, utm, hR, unp, utp, f.F);
+    if (flux == 1)
+        rusanov(g, hL, unm, utm, hR, unp, utp, f.F);
+    else
+        hll(g, hL, unm, utm, hR, unp, utp, f.F);
     f.sL = T(0.5 * g) * (hm * hm - hL * hL);
     f.sR = T(0.5 * g) * (hp * hp - hR * hR);
     double sm = std::fabs(val(unm)) + std::sqrt(g * val(hm));
@@ -388,7 +413,7 @@ void rate(const orc_params& p, const T* h_in, const T* qx_in, const T* qy_in,
             const Recon<T>& L = rc[i + 1];
             const Recon<T>& R = rc[i + 2];
             fc[i + 1] = face(g, L.h_p, L.z_p, L.un_p, L.ut_p, R.h_m, R.z_m,
-                             R.un_m, R.ut_m);
+                             R.un_m, R.ut_m, p.flux);
             if (fc[i + 1].speed > ax) ax = fc[i + 1].speed;
         }
         for (int i = 0; i < nx; ++i) {
@@ -420,7 +445,7 @@ void rate(const orc_params& p, const T* h_in, const T* qx_in, const T* qy_in,
             const Recon<T>& L = rc[j + 1];
             const Recon<T>& R = rc[j + 2];
             fc[j + 1] = face(g, L.h_p, L.z_p, L.un_p, L.ut_p, R.h_m, R.z_m,
-                             R.un_m, R.ut_m);
+                             R.un_m, R.ut_m, p.flux);
             if (fc[j + 1].speed > ay) ay = fc[j + 1].speed;
         }
         for (int j = 0; j < ny; ++j) {
@@ -705,8 +730,8 @@ void orc_hll(double g, double hL, double unL, double utL, double hR,
 
 // out: {F0, F1, F2, sL, sR, speed}
 void orc_face(double g, double hm, double zm, double unm, double utm,
-              double hp, double zp, double unp, double utp, double* out) {
-    Face<double> f = face(g, hm, zm, unm, utm, hp, zp, unp, utp);
+              double hp, double zp, double unp, double utp, double* out, int32_t flux) {
+    Face<double> f = face(g, hm, zm, unm, utm, hp, zp, unp, utp, flux);
     out[0] = f.F[0]; out[1] = f.F[1]; out[2] = f.F[2];
     out[3] = f.sL; out[4] = f.sR; out[5] = f.speed;
 }

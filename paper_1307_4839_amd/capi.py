@@ -41,7 +41,8 @@ class swe_params(C.Structure):
                 ("bc", C.c_int32 * 4), ("fric_law", C.c_int32),
                 ("fric_coef", C.c_double), ("rain", C.c_double),
                 ("infil_on", C.c_int32), ("ks", C.c_double),
-                ("psi", C.c_double), ("dtheta", C.c_double), ("order", C.c_int32)]
+                ("psi", C.c_double), ("dtheta", C.c_double), ("order", C.c_int32),
+                ("flux", C.c_int32)]
 
 
 class swe_buffers(C.Structure):
@@ -161,9 +162,11 @@ def check(code: int, where: str) -> int:
 
 def make_params(nx, ny, dx, dy, g=9.81, cfl=0.5, dt_max=float("inf"),
                 h_eps=1e-12, bc=(0, 0, 0, 0), fric_law=0, fric_coef=0.0,
-                rain=0.0, infil_on=0, ks=0.0, psi=0.0, dtheta=0.0, order=2) -> swe_params:
+                rain=0.0, infil_on=0, ks=0.0, psi=0.0, dtheta=0.0, order=2,
+                flux=0) -> swe_params:
     p = swe_params()
     p.order = int(order)
+    p.flux = int(flux)
     p.nx, p.ny, p.dx, p.dy = nx, ny, dx, dy
     p.g, p.cfl, p.dt_max, p.h_eps = g, cfl, dt_max, h_eps
     for k in range(4):

@@ -96,6 +96,8 @@ class Workload:
     # 2: MUSCL + Heun (the paper's scheme); 1: first order (piecewise
     # constant, one Euler stage; the paper uses n_CFL = 1 with it)
     order: int = 2
+    # numerical flux: 0 HLL (the paper's), 1 Rusanov
+    flux: int = 0
     t_end: float = math.inf
     nsteps: int = 0
     gauges: Optional[np.ndarray] = None  # flat cell indices
@@ -107,7 +109,7 @@ class Workload:
                     bc=tuple(self.bc), fric_law=self.fric_law,
                     fric_coef=self.fric_coef, rain=self.rain,
                     infil_on=self.infil_on, ks=self.ks, psi=self.psi,
-                    dtheta=self.dtheta, order=self.order)
+                    dtheta=self.dtheta, order=self.order, flux=self.flux)
 
     def copy(self) -> "Workload":
         out = dataclasses.replace(self)

@@ -42,6 +42,9 @@ MUTANTS = {
                                  "muscl(pa, pc, pb, h_eps);\n        }\n        // faces i+1/2"),
     "first_order_heun": ("    if (p.order == 1) {\n        for (size_t s = 0; s < n; ++s) {",
                          "    if (p.order == 7) {\n        for (size_t s = 0; s < n; ++s) {"),
+    "rusanov_speed_sign": ("T c = vmax(dfabs(unL) + cL, dfabs(unR) + cR);",
+                           "T c = vmax(dfabs(unL) - cL, dfabs(unR) + cR);"),
+    "rusanov_full_diffusion": ("- T(0.5) * c * (UR[k] - UL[k]);", "- c * (UR[k] - UL[k]);"),
     "hyetograph_open_interval": ("if (p.rain_t[k] <= t) r = p.rain_r[k];",
                                  "if (p.rain_t[k] < t) r = p.rain_r[k];"),
     "hyetograph_next_value": ("if (p.rain_t[k] <= t) r = p.rain_r[k];",

@@ -459,6 +459,83 @@ def test_first_order_ritter_convergence():
 
 
 # ---------------------------------------------------------------------------
+# Rusanov flux (Section 3.3 allows any consistent flux; the Rusanov flux is
+# one it names): consistency, equality with the literal 1D scheme, the
+# lake at rest, positivity and dam-break convergence.
+# ---------------------------------------------------------------------------
+
+def test_rusanov_face_consistency_and_wall():
+    rng = np.random.default_rng(31)
+    for _ in range(50):
+        h, z, u, v = rng.uniform(0.1, 3.0), rng.uniform(-1, 1), rng.normal(), rng.normal()
+        f = oracle.face(G, h, z, u, v, h, z, u, v, flux=1)
+        q = h * u
+        assert np.allclose(f[:3], [q, q * u + 0.5 * G * h * h, q * v], rtol=1e-14, atol=0)
+        # mirrored states (a wall): no mass through the face
+        f = oracle.face(G, h, z, u, v, h, z, -u, v, flux=1)
+        assert f[0] == 0.0
+    # it is not HLL
+    f1 = oracle.face(G, 1.0, 0.0, 0.5, 0.0, 0.4, 0.0, -0.2, 0.0, flux=1)
+    f0 = oracle.face(G, 1.0, 0.0, 0.5, 0.0, 0.4, 0.0, -0.2, 0.0, flux=0)
+    assert abs(f1[0] - f0[0]) > 1e-3
+
+
+@pytest.mark.parametrize("law,coef", [(0, 0.0), (1, 0.03)])
+def test_rusanov_one_dimensional_reduction(law, coef):
+    nx, ny = 120, 3
+    rng = np.random.default_rng(23)
+    x = (np.arange(nx) + 0.5)
+    z1 = 0.5 * np.exp(-((x - 70) / 8) ** 2) + 0.002 * (nx - x)
+    h1 = np.where(x < 40, 1.5, 0.0) + 0.0 * x
+    q1 = rng.uniform(-0.2, 0.2, nx) * (h1 > 0)
+    wl = I.Workload("1d", nx, ny, 1.0, 1.0, z=np.tile(z1, (ny, 1)), h=np.tile(h1, (ny, 1)),
+                    qx=np.tile(q1, (ny, 1)), qy=np.zeros((ny, nx)), bc=(0, 1, 0, 0),
+                    fric_law=law, fric_coef=coef, flux=1)
+    s = oracle.State(wl)
+    assert s.run(150) == 0
+    hh, qq = h1.copy(), q1.copy()
+    for dt in s.dts:
+        hh, qq = swe1d.heun_step(hh, qq, z1, dt, 1.0, bc=(0, 1), law=law, coef=coef,
+                                 flux="rusanov")
+    assert np.abs(s.h[0] - hh).max() <= 1e-13 * np.abs(hh).max()
+    assert np.abs(s.qx[0] - qq).max() <= 1e-12 * np.abs(qq).max()
+
+
+def test_rusanov_lake_at_rest_and_positivity():
+    C = 1.2
+    wl = _islands(40, 30, C, seed=13, bc=(0, 0, 0, 0))
+    wl.flux = 1
+    s = oracle.State(wl)
+    assert s.run(1000) == 0
+    wet = wl.h > 0
+    assert np.abs((s.h + s.z)[wet] - C).max() <= 1e-12 * C
+    assert np.abs(s.qx).max() <= 1e-12 * math.sqrt(G * wl.h.max() ** 3)
+    for wl in (I.dam_break_200(), I.random_state(48, 40, 6, bc=(0, 1, 1, 0),
+                                                 fric_law=I.FRIC_DARCY, fric_coef=0.2)):
+        wl.flux = 1
+        s = oracle.State(wl)
+        assert s.run(300, wl.t_end) in (0, 1)
+        assert s.h.min() >= 0.0
+
+
+def test_rusanov_dam_breaks_converge():
+    for h_down, exact in ((0.0, lambda x, t: ritter_h(x, t, 100.0, 1.0)),
+                          (0.1, lambda x, t: stoker_h(x, t, 100.0, 1.0, 0.1))):
+        errs = []
+        for n in (200, 400, 800):
+            dx = 200.0 / n
+            x = (np.arange(n) + 0.5) * dx
+            h = np.where(x < 100.0, 1.0, h_down)
+            wl = I.Workload("db", n, 2, dx, 1e9, z=np.zeros((2, n)), h=np.tile(h, (2, 1)),
+                            qx=np.zeros((2, n)), qy=np.zeros((2, n)), bc=(1, 1, 0, 0), flux=1)
+            s = oracle.State(wl)
+            assert s.run(10 ** 6, 10.0) == 1
+            errs.append(np.abs(s.h[0] - exact(x, 10.0)).sum() * dx)
+        orders = [math.log2(errs[k] / errs[k + 1]) for k in range(2)]
+        assert min(orders) >= 0.7, (h_down, errs, orders)
+
+
+# ---------------------------------------------------------------------------
 # P11: friction alone on a uniform flat state (Section 2.1 laws, Section 3.2
 # semi-implicit treatment): converges to the ODE solution
 #   Manning: q(t) = q0 / (1 + g n^2 q0 t / h^{7/3}),
