@@ -236,15 +236,18 @@ def flow_dir_leg(wl, reps):
     return {"workload": f"{wl.name} terrain {wl.nx}x{wl.ny}", "launches": reps, **out}
 
 
-def first_order_leg(wl, warmup, steps):
-    """The same workload with the first-order scheme (Section 3.3: no
-    reconstruction, one Euler stage, n_CFL = 1): throughput and the average
-    duration of its two kernels (rate, then the cell-wise Euler update)."""
+def variant_leg(wl, warmup, steps, order, flux):
+    """The same workload with another scheme of Section 3.3: the first-order
+    scheme (no reconstruction, one Euler stage, n_CFL = 1) and/or the
+    Rusanov flux.  Throughput and the average durations of the two kernels
+    of a step (rate, then the update)."""
     import torch
 
     from paper_1307_4839_amd.solver import Solver
     w1 = wl.copy()
-    w1.order, w1.cfl = 1, 1.0
+    w1.order, w1.flux = order, flux
+    if order == 1:
+        w1.cfl = 1.0
     g = Solver(w1, device="cuda:0")
     g.step(warmup)
     e0 = torch.cuda.Event(enable_timing=True)
@@ -264,12 +267,13 @@ def first_order_leg(wl, warmup, steps):
     del g
     torch.cuda.empty_cache()
     cells = wl.nx * wl.ny
-    print(f"[bench] first order: {steps} steps in {ms:.1f} ms, t = {t_sim:.1f} s",
+    name = f"{'first' if order == 1 else 'second'} order, {'Rusanov' if flux else 'HLL'}"
+    print(f"[bench] {name}: {steps} steps in {ms:.1f} ms, t = {t_sim:.1f} s",
           file=sys.stderr, flush=True)
-    return {"workload": f"{wl.name} {wl.nx}x{wl.ny}, first order, cfl 1", "steps": steps,
+    return {"workload": f"{wl.name} {wl.nx}x{wl.ny}, {name}, cfl {w1.cfl}", "steps": steps,
             "warmup": warmup, "ms_per_step": ms / steps, "value": cells * steps / (ms / 1e3),
             "unit": "cell-updates/s", "rate_kernel_ms": ms_rate / n,
-            "euler_kernel_ms": ms_upd / n, "status": rc}
+            "update_kernel_ms": ms_upd / n, "status": rc}
 
 
 def paper_runs_leg(iterations):
@@ -330,7 +334,8 @@ def main(argv=None):
     ap.add_argument("--ensemble-steps", type=int, default=500)
     ap.add_argument("--no-paper-runs", action="store_true")
     ap.add_argument("--no-flow-dir", action="store_true")
-    ap.add_argument("--no-first-order", action="store_true")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the first-order and Rusanov runs")
     ap.add_argument("--flow-dir-reps", type=int, default=50)
     ap.add_argument("--paper-iterations", default="5000,20000")
     args = ap.parse_args(argv)
@@ -443,9 +448,10 @@ def main(argv=None):
     torch.cuda.empty_cache()
     print(f"[bench] 1 GiB device copy: {copy_gbps:.0f} GB/s", file=sys.stderr, flush=True)
 
-    order1 = None
-    if not args.no_first_order:
-        order1 = first_order_leg(wl, 300, 100)
+    variants = None
+    if not args.no_variants:
+        variants = {"first_order_hll": variant_leg(wl, 300, 100, 1, 0),
+                    "second_order_rusanov": variant_leg(wl, 300, 100, 2, 1)}
 
     fdir = None
     if not args.no_flow_dir:
@@ -504,7 +510,7 @@ def main(argv=None):
         "adjoint": adj,
         "paper_runs": paper,
         "flow_directions": fdir,
-        "first_order": order1,
+        "scheme_variants": variants,
         "sim_time_s": t_sim,
         "status_flags": flags,
     }

@@ -80,6 +80,8 @@ typedef struct swe_params {
     int32_t order;       /* 1: first order (Section 3.3: no reconstruction,
                             one explicit Euler stage per step; the paper
                             pairs it with cfl = 1); 0 or 2: MUSCL + Heun */
+    int32_t flux;        /* numerical flux (Section 3.3): 0 HLL (the
+                            paper's), 1 Rusanov (local Lax-Friedrichs) */
 } swe_params;
 
 /* Optional per-cell fields below are read only, [ny][nx] FP64 device

@@ -1052,7 +1052,8 @@ int swe_adj_create(const swe_params* p, const swe_buffers* b, int32_t nsteps,
     if (rc) return rc;
     if (!b || !out || !workspace || !b->h || !b->qx || !b->qy || !b->z || !b->fric)
         return SWE_EINVAL;
-    if (p->infil_on || p->fric_law == SWE_FRIC_NONE || p->order == 1) return SWE_EINVAL;
+    if (p->infil_on || p->fric_law == SWE_FRIC_NONE || p->order == 1 || p->flux != 0)
+        return SWE_EINVAL;
     // uniform rain only: the reverse pass has no rain or soil fields
     if (b->rain_w || b->ks || b->psi || b->dtheta) return SWE_EINVAL;
     if (nsteps < 1 || ckpt_every < 1 || ngauges < 1 || every < 1 || !gauges || !obs)

@@ -349,7 +349,8 @@ int swe_batch_create(const swe_params* p, const swe_buffers* bufs, int32_t count
     for (int k = 0; k < count; ++k) {
         const swe_buffers& b = bufs[k];
         if (!b.h || !b.qx || !b.qy || !b.z) return SWE_EINVAL;
-        if (p[k].order == 1) return SWE_EINVAL;  // ensembles run the second-order scheme
+        // ensembles run the second-order scheme with the HLL flux
+        if (p[k].order == 1 || p[k].flux != 0) return SWE_EINVAL;
         if (p[k].infil_on && !b.vinf) return SWE_EINVAL;
     }
     swe_batch* b = new (std::nothrow) swe_batch;

@@ -81,6 +81,8 @@ struct KParams {
     int fast_div;
     // 2: MUSCL + Heun; 1: first order (no reconstruction, one Euler stage)
     int order;
+    // 0: HLL; 1: Rusanov
+    int flux;
 };
 
 // ---------------------------------------------------------------------------
@@ -272,7 +274,8 @@ __host__ __device__ __forceinline__ Rec reconstruct(const Prim& a, const Prim& c
 }
 
 // Flux through one face: hydrostatic reconstruction (Section 3.1), HLL
-// (Section 3.3), and the normal-momentum corrections S_L (left cell) and
+// (Section 3.3; FLUX 1: the Rusanov flux, another consistent flux that
+// section lists), and the normal-momentum corrections S_L (left cell) and
 // S_R (right cell).  fl = flux seen by the left cell, fr = by the right one.
 // face_speed = max(|u-| + sqrt(g h-), |u+| + sqrt(g h+)) on the MUSCL
 // states (stage 1 only).
@@ -282,8 +285,8 @@ struct FaceOut {
 
 // With depths, velocities and z capped at 2^60 and g at most 2^10, c1 and c2
 // stay below 2^62 and the HLL numerators below 2^251; den and the
-// numerators are bounded below here.
-template <class D>
+// numerators are bounded below here.  The Rusanov flux divides by nothing.
+template <int FLUX = 0, class D>
 __host__ __device__ __forceinline__ FaceOut face(double g, double hm, double zm, double unm,
                                                  double utm, double hp, double zp, double unp,
                                                  double utp, D& d) {
@@ -302,7 +305,13 @@ __host__ __device__ __forceinline__ FaceOut face(double g, double hm, double zm,
     double FL0 = qL, FL1 = qL * unm + hg * hL * hL, FL2 = qL * utm;
     double FR0 = qR, FR1 = qR * unp + hg * hR * hR, FR2 = qR * utp;
     double F0, F1, F2;
-    if (0.0 <= c1) {
+    if constexpr (FLUX == 1) {
+        // (F(U_L) + F(U_R))/2 - c/2 (U_R - U_L), c the largest local speed
+        double c = vmax(fabs(unm) + cL, fabs(unp) + cR);
+        F0 = 0.5 * (FL0 + FR0) - 0.5 * c * (hR - hL);
+        F1 = 0.5 * (FL1 + FR1) - 0.5 * c * (qR - qL);
+        F2 = 0.5 * (FL2 + FR2) - 0.5 * c * (hR * utp - hL * utm);
+    } else if (0.0 <= c1) {
         F0 = FL0; F1 = FL1; F2 = FL2;
     } else if (c2 <= 0.0) {
         F0 = FR0; F1 = FR1; F2 = FR2;
@@ -753,7 +762,7 @@ __device__ __forceinline__ void finish_cell(const MemberArgs& m, const TileIO& i
         atomicOr(&m.sc->status, (unsigned)SWE_FLAG_NEGDEPTH);
 }
 
-template <int STAGE, int TXT, class D, bool FIELDS, int ORDER>
+template <int STAGE, int TXT, class D, bool FIELDS, int ORDER, int FLUX>
 __device__ __forceinline__ int march(const MemberArgs& m, const TileIO& io, int strip, int y0,
                                      int y1, double dt, double rain, double& ax, double& ay,
                                      TileLds<TXT>& L) {
@@ -809,7 +818,7 @@ __device__ __forceinline__ int march(const MemberArgs& m, const TileIO& io, int 
     double gm0, gm1, gm2;  // face below the current row, as seen from above
     double gm_speed = 0.0;
     {
-        FaceOut gm = face(p.g, rprev.h_p, rprev.z_p, rprev.un_p, rprev.ut_p, rcur.h_m,
+        FaceOut gm = face<FLUX>(p.g, rprev.h_p, rprev.z_p, rprev.un_p, rprev.ut_p, rcur.h_m,
                           rcur.z_m, rcur.un_m, rcur.ut_m, d);
         if (STAGE == 1 && y0 == 0)
             gm_speed = face_speed(p.g, rprev.h_p, rprev.un_p, rcur.h_m, rcur.un_m, d);
@@ -847,7 +856,7 @@ __device__ __forceinline__ int march(const MemberArgs& m, const TileIO& io, int 
         note_cell(d, r2, p2);
         d.settle();
         Rec rnext = reconstruct<ORDER>(to_y(p0), to_y(p1), to_y(p2), p.h_eps, R1, d);
-        FaceOut gp = face(p.g, rcur.h_p, rcur.z_p, rcur.un_p, rcur.ut_p, rnext.h_m, rnext.z_m,
+        FaceOut gp = face<FLUX>(p.g, rcur.h_p, rcur.z_p, rcur.un_p, rcur.ut_p, rnext.h_m, rnext.z_m,
                           rnext.un_m, rnext.ut_m, d);
         double gp_speed = 0.0;
         if (STAGE == 1)
@@ -889,7 +898,7 @@ __device__ __forceinline__ int march(const MemberArgs& m, const TileIO& io, int 
             unm_r = L.unm[tr];
             utm_r = L.utm[tr];
         }
-        FaceOut fp = face(p.g, rx.h_p, rx.z_p, rx.un_p, rx.ut_p, hm_r, zm_r, unm_r, utm_r, d);
+        FaceOut fp = face<FLUX>(p.g, rx.h_p, rx.z_p, rx.un_p, rx.ut_p, hm_r, zm_r, unm_r, utm_r, d);
         double fp_speed = 0.0;
         if (STAGE == 1) fp_speed = face_speed(p.g, rx.h_p, rx.un_p, hm_r, unm_r, d);
         d.settle();
@@ -1083,8 +1092,9 @@ __host__ __device__ __forceinline__ bool has_fields(const MemberArgs& m) {
 // clearing the next step's accumulators).
 // `spread` picks the accumulator pair of stage 1 (any block-dependent index).
 // FIELDS compiles in the reads of the optional rain and soil fields; ORDER 1
-// (stage 1 only) replaces MUSCL by the cell values (first order).
-template <int STAGE, int TXT, bool FIELDS = false, int ORDER = 2>
+// (stage 1 only) replaces MUSCL by the cell values (first order); FLUX 1
+// takes the Rusanov flux instead of HLL.
+template <int STAGE, int TXT, bool FIELDS = false, int ORDER = 2, int FLUX = 0>
 __device__ __forceinline__ void stage_tile(const MemberArgs& m, const TileIO& io, int strip,
                                            int y0, int y1, bool lead, int spread) {
     constexpr int OUTW = TXT - 2 * HALO;
@@ -1119,10 +1129,11 @@ __device__ __forceinline__ void stage_tile(const MemberArgs& m, const TileIO& io
     double ax = 0.0, ay = 0.0;
     int stop = y0;
     if (p.fast_div)
-        stop = march<STAGE, TXT, FastDiv, FIELDS, ORDER>(m, io, strip, y0, y1, dt, rain, ax, ay,
-                                                         L);
+        stop = march<STAGE, TXT, FastDiv, FIELDS, ORDER, FLUX>(m, io, strip, y0, y1, dt, rain,
+                                                               ax, ay, L);
     if (stop < y1)
-        march<STAGE, TXT, ExactDiv, FIELDS, ORDER>(m, io, strip, stop, y1, dt, rain, ax, ay, L);
+        march<STAGE, TXT, ExactDiv, FIELDS, ORDER, FLUX>(m, io, strip, stop, y1, dt, rain, ax,
+                                                         ay, L);
     if (STAGE == 1) block_max2<TXT>(ax, ay, io.acc, spread);
 }
 

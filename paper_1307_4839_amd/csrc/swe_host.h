@@ -35,6 +35,7 @@ inline int check_params(const swe_params* p) {
     if (!(p->rain >= 0.0) || !std::isfinite(p->rain)) return SWE_EINVAL;
     if ((size_t)p->nx * (size_t)p->ny > ((size_t)1 << 36)) return SWE_EINVAL;
     if (p->order < 0 || p->order > 2) return SWE_EINVAL;
+    if (p->flux < 0 || p->flux > 1) return SWE_EINVAL;
     return SWE_OK;
 }
 
@@ -56,6 +57,7 @@ inline KParams to_kparams(const swe_params& p) {
     k.law = p.fric_law; k.coef = p.fric_coef; k.rain = p.rain;
     k.infil = p.infil_on; k.ks = p.ks; k.psi = p.psi; k.dtheta = p.dtheta;
     k.order = p.order == 1 ? 1 : 2;
+    k.flux = p.flux;
     double ix = 0.0, iy = 0.0;
     k.dxy_pow2 = exact_pow2(p.dx, ix) && exact_pow2(p.dy, iy);
     k.inv_dx = k.dxy_pow2 ? ix : 0.0;

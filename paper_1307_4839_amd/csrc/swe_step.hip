@@ -43,13 +43,13 @@ constexpr int DIAG_BLOCKS = 512;  // blocks of the diagnostics reduction
 constexpr int DIAG_T = 256;
 constexpr int GRAPH_STEPS = 16;   // steps per captured graph (even)
 
-template <int STAGE, int TXT, bool FIELDS, int ORDER>
+template <int STAGE, int TXT, bool FIELDS, int ORDER, int FLUX>
 __global__ __launch_bounds__(TXT) void stage_kernel(MemberArgs m, TileIO io, int ty) {
     const int y0 = blockIdx.y * ty;
     const int y1 = min(y0 + ty, m.p.ny);
-    stage_tile<STAGE, TXT, FIELDS, ORDER>(m, io, blockIdx.x, y0, y1,
-                                          blockIdx.x == 0 && blockIdx.y == 0,
-                                          blockIdx.x + blockIdx.y * gridDim.x);
+    stage_tile<STAGE, TXT, FIELDS, ORDER, FLUX>(m, io, blockIdx.x, y0, y1,
+                                                blockIdx.x == 0 && blockIdx.y == 0,
+                                                blockIdx.x + blockIdx.y * gridDim.x);
 }
 
 // First-order update (one Euler stage), cell by cell over a grid-stride loop.
@@ -107,14 +107,23 @@ __global__ void diag_final_kernel(double* part, int nb) {
     }
 }
 
+template <int STAGE, bool FIELDS, int ORDER, int FLUX>
+void launch_stage_tf(int tx, dim3 grid, hipStream_t s, const MemberArgs& m, const TileIO& io,
+                     int ty) {
+    switch (tx) {
+        case 64: hipLaunchKernelGGL((stage_kernel<STAGE, 64, FIELDS, ORDER, FLUX>), grid, dim3(64), 0, s, m, io, ty); break;
+        case 128: hipLaunchKernelGGL((stage_kernel<STAGE, 128, FIELDS, ORDER, FLUX>), grid, dim3(128), 0, s, m, io, ty); break;
+        default: hipLaunchKernelGGL((stage_kernel<STAGE, 256, FIELDS, ORDER, FLUX>), grid, dim3(256), 0, s, m, io, ty); break;
+    }
+}
+
 template <int STAGE, bool FIELDS, int ORDER>
 void launch_stage_t(int tx, dim3 grid, hipStream_t s, const MemberArgs& m, const TileIO& io,
                     int ty) {
-    switch (tx) {
-        case 64: hipLaunchKernelGGL((stage_kernel<STAGE, 64, FIELDS, ORDER>), grid, dim3(64), 0, s, m, io, ty); break;
-        case 128: hipLaunchKernelGGL((stage_kernel<STAGE, 128, FIELDS, ORDER>), grid, dim3(128), 0, s, m, io, ty); break;
-        default: hipLaunchKernelGGL((stage_kernel<STAGE, 256, FIELDS, ORDER>), grid, dim3(256), 0, s, m, io, ty); break;
-    }
+    if (m.p.flux == 1)
+        launch_stage_tf<STAGE, FIELDS, ORDER, 1>(tx, grid, s, m, io, ty);
+    else
+        launch_stage_tf<STAGE, FIELDS, ORDER, 0>(tx, grid, s, m, io, ty);
 }
 
 // Stage 1 never reads the rain and soil fields; the first-order scheme has

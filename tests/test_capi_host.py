@@ -136,3 +136,22 @@ def test_first_order_limits_without_gpu():
     with pytest.raises(capi.SweError) as e:
         capi.swe_batch_create([p1], [b], 4096, 1 << 30, 0)
     assert e.value.code == capi.SWE_EINVAL
+
+
+def test_rusanov_limits_without_gpu():
+    # flux outside {0, 1} is invalid; ensembles and the adjoint take HLL only
+    from paper_1307_4839_amd import capi
+    for flux in (-1, 2):
+        with pytest.raises(capi.SweError):
+            capi.swe_workspace_bytes(capi.make_params(8, 8, 1.0, 1.0, flux=flux))
+    capi.swe_workspace_bytes(capi.make_params(8, 8, 1.0, 1.0, flux=1))
+    p1 = capi.make_params(16, 16, 1.0, 1.0, fric_law=capi.SWE_FRIC_MANNING, fric_coef=0.03,
+                          flux=1)
+    b = capi.swe_buffers()
+    b.h = b.qx = b.qy = b.z = b.fric = 4096
+    with pytest.raises(capi.SweError) as e:
+        capi.swe_adj_create(p1, b, 10, 3, 4096, 1, 5, 4096, 4096, 1 << 30, 0)
+    assert e.value.code == capi.SWE_EINVAL
+    with pytest.raises(capi.SweError) as e:
+        capi.swe_batch_create([p1], [b], 4096, 1 << 30, 0)
+    assert e.value.code == capi.SWE_EINVAL
