@@ -331,12 +331,14 @@ struct AdjArgs {
     const double* fric;
 };
 
-// one-wave tiles for the VJP kernel, about 2048 of them (the 1024^2 grids of
-// a calibration are small): 4 to 32 rows each
+// one-wave tiles for the VJP kernel, about 4096 of them, 4 to 32 rows each:
+// at 1024^2 the reverse ran fastest with 4-row tiles (18 x 256 tiles; the
+// halo rows of the y march cost less than the latency fewer waves leave
+// exposed: 8, 2 and 1 rows were 3%, 10% and 33% slower)
 constexpr int VJP_TX = 64;
 inline int vjp_rows(int nx, int ny) {
     long long strips = (nx + VJP_TX - 7) / (VJP_TX - 6);
-    long long ty = strips * (long long)ny / 2048;
+    long long ty = strips * (long long)ny / 4096;
     if (ty > 32) ty = 32;
     if (ty < 4) ty = 4;
     while ((ny + ty - 1) / ty > 65535) ty *= 2;
@@ -529,19 +531,23 @@ __host__ __device__ __forceinline__ void gather_cell(const KParams& p, const dou
     }
 }
 
-// VJP of Phi over one tile (TXT lanes, rows y0 .. y1-1), summed per cell in
-// the order of gather_cell: x-faces left to right, the x ghost folds, then
-// y-faces bottom to top, the y ghost folds; lambda += the sum.  Each face of
-// the tile's stencil is evaluated once per tile (faces on a tile's border by
-// both tiles), and no per-face contribution goes to HBM.
+// VJP of Phi over one tile (64 lanes = columns, rows y0 .. y1-1), cell by
+// cell: the bars of each face (face_rev: the hydrostatic reconstruction and
+// the flux reversed) go to the reconstructions of its two cells; each
+// cell's reconstruction is reversed once (muscl_rev) with the bars of both
+// its faces and of its centred source; the resulting bars of the
+// primitives are summed per cell (from the reconstructions of the cell and
+// of its two neighbours) and reversed once (prim_rev).  Ghost positions
+// (-2, -1, n, n+1 along a sweep) carry their bars to the cells they mirror,
+// discharge sign included.  lambda += x part + y part.
 //
-// Lane t owns column c = strip * (TXT - 6) - 3 + t; lanes 3 .. TXT-4 are
-// outputs.  The x-face c (between columns c-1 and c) is evaluated by lane t
-// from the cells of lanes t-2 .. t+1 (LDS); its 12 contributions go through
-// LDS to the lanes of the four cells.  Down the column, the march at step k
-// loads row k+1, forms the x-part of row k+1, evaluates the y-face k (rows
-// k-2 .. k+1, a register window) and completes row k-2, which no later face
-// touches.
+// x: lane t owns column c = strip * (64 - 6) - 3 + t (outputs: lanes
+// 3 .. 60); neighbours exchange by DPP lane shifts, ghost columns fold by
+// lane shuffles.  y: down the column, iteration n loads row n, forms the
+// reconstruction of row n-1, reverses face n-1 (between rows n-2 and n-1)
+// and the reconstruction of row n-2, and completes row n-3, which no later
+// reconstruction touches.  Faces with no real cell on either side get zero
+// seeds, so their bars are exactly zero.
 template <int TXT>
 __global__ __launch_bounds__(TXT) void adj_vjp_kernel(AdjArgs a, const double* __restrict__ h,
                                                       const double* __restrict__ qx,
@@ -552,6 +558,7 @@ __global__ __launch_bounds__(TXT) void adj_vjp_kernel(AdjArgs a, const double* _
                                                       double* __restrict__ lh,
                                                       double* __restrict__ lqx,
                                                       double* __restrict__ lqy, int ty) {
+    static_assert(TXT == 64, "one wave per tile: neighbours move by DPP lane shifts");
     constexpr int H = 3, OUTW = TXT - 2 * H;
     const KParams& p = a.p;
     const int nx = p.nx, ny = p.ny;
@@ -563,18 +570,21 @@ __global__ __launch_bounds__(TXT) void adj_vjp_kernel(AdjArgs a, const double* _
     const int cs = map_index(c, nx, p.bcw, p.bce, sx);
     const bool col_real = c >= 0 && c < nx;
     const bool out = t >= H && t < TXT - H && col_real;
-    const bool xface = t >= 2 && t <= TXT - 2 && c >= 0 && c <= nx;
 
-    __shared__ double Lc[4][TXT];   // cell of the row (h, qx, qy, z)
-    __shared__ double Lm[3][TXT];   // its adjoint seed
-    __shared__ double Ls[TXT];      // ghost sign of the column
-    __shared__ double Lx[12][TXT];  // x-face contributions
-    // y contributions to ghost rows (each lane its own column), folded into
-    // the rows they mirror: 0, 1 = face 0 to rows -2, -1; 2 = face 1 to row
-    // -1; 3 = face ny-1 to row ny; 4, 5 = face ny to rows ny, ny+1
-    __shared__ double Lg[6][3][TXT];
+    // lanes whose ghost columns fold into this column: west (w1, w2) and
+    // east (e1, e2); a lane with none reads itself with weight 0
+    const bool wall_w = p.bcw == SWE_BC_WALL, wall_e = p.bce == SWE_BC_WALL;
+    int w1 = t, w2 = t, e1 = t, e2 = t;
+    double kw1 = 0.0, kw2 = 0.0, ke1 = 0.0, ke2 = 0.0;
+    if (c == 0) { w1 = t - 1; kw1 = 1.0; if (!wall_w) { w2 = t - 2; kw2 = 1.0; } }
+    if (c == 1 && wall_w) { w2 = t - 3; kw2 = 1.0; }
+    if (c == nx - 1) { e1 = t + 1; ke1 = 1.0; if (!wall_e) { e2 = t + 2; ke2 = 1.0; } }
+    if (c == nx - 2 && wall_e) { e2 = t + 3; ke2 = 1.0; }
+    w1 = w1 < 0 ? 0 : w1; w2 = w2 < 0 ? 0 : w2;
+    e1 = e1 > TXT - 1 ? TXT - 1 : e1; e2 = e2 > TXT - 1 ? TXT - 1 : e2;
 
-    // load row r of this column (ghost rows mapped, discharge signs applied)
+    // row r of this column as loaded (ghost rows mapped, discharge signs
+    // applied) and its seed (0 off the grid)
     auto load = [&](int r, RawCell& cell, double& sy, double m[3]) {
         const int rs = map_index(r, ny, p.bcs, p.bcn, sy);
         cell = load_raw(h, qx, qy, a.z, nx, rs, cs, sx, sy);
@@ -584,157 +594,177 @@ __global__ __launch_bounds__(TXT) void adj_vjp_kernel(AdjArgs a, const double* _
         m[1] = real ? mu_qx[idx] : 0.0;
         m[2] = real ? mu_qy[idx] : 0.0;
     };
+    auto shl = [](const Prim& v) {
+        Prim o;
+        o.h = from_left(v.h); o.un = from_left(v.un); o.ut = from_left(v.ut);
+        o.eta = from_left(v.eta);
+        return o;
+    };
+    auto shr = [](const Prim& v) {
+        Prim o;
+        o.h = from_right(v.h); o.un = from_right(v.un); o.ut = from_right(v.ut);
+        o.eta = from_right(v.eta);
+        return o;
+    };
 
-    // window: rows k-2, k-1, k (+ k+1 loaded at step k)
-    RawCell w0, w1, w2;
-    double s0, s1, s2;
-    double m0[3], m1[3], m2[3];  // seeds of rows k-2 (unused), k-1, k
-    load(y0 - 3, w0, s0, m0);
-    load(y0 - 2, w1, s1, m1);
-    load(y0 - 1, w2, s2, m2);
-    // sums of rows k-2 .. k+1 (a0 .. a3)
-    double a0[3] = {0.0, 0.0, 0.0}, a1[3] = {0.0, 0.0, 0.0}, a2[3] = {0.0, 0.0, 0.0};
-    double a3[3];
-
-    for (int k = y0 - 1; k <= y1 + 1; ++k) {
-        const int r = k + 1;
-        RawCell w3;
-        double s3, m3[3];
-        load(r, w3, s3, m3);
-
-        // ---- x-part of row r ----
-        a3[0] = a3[1] = a3[2] = 0.0;
-        if (r >= y0 && r < y1) {
-            Lc[0][t] = w3.h;
-            Lc[1][t] = w3.qx;
-            Lc[2][t] = w3.qy;
-            Lc[3][t] = w3.z;
-            Lm[0][t] = m3[0];
-            Lm[1][t] = m3[1];
-            Lm[2][t] = m3[2];
-            Ls[t] = sx;
-            __syncthreads();
-            if (xface) {
-                RawCell rc[4];
-                double sg[4];
+    // x part of a row (all lanes; the row is the same for the whole wave)
+    auto xpart = [&](const RawCell& w, const double m[3], double o[3]) {
+        const Prim P = prim_x(w, p.h_eps);
+        const Prim Pl = shl(P), Pr = shr(P);
+        const Rec R = muscl(Pl, P, Pr, p.h_eps);
+        // X_i enters Phi_i as -X_i / dx
+        const double b0 = -m[0] / p.dx, b1 = -m[1] / p.dx, b2 = -m[2] / p.dx;
+        const double l0 = from_left(b0), l1 = from_left(b1), l2 = from_left(b2);
+        // face c, between column c-1 (lane t-1, its p side) and c
+        const FaceBar fb = face_rev(p.g, from_left(R.h_p), from_left(R.z_p), from_left(R.un_p),
+                                    from_left(R.ut_p), R.h_m, R.z_m, R.un_m, R.ut_m, l0 - b0,
+                                    l1 - b1, l2 - b2, l1, -b1);
+        // this cell's reconstruction: m side from face c, p side from face
+        // c+1 (lane t+1), and its centred source
+        RecBar rb;
+        rb.h_m = fb.hp; rb.z_m = fb.zp; rb.un_m = fb.unp; rb.ut_m = fb.utp;
+        rb.h_p = from_right(fb.hm); rb.z_p = from_right(fb.zm);
+        rb.un_p = from_right(fb.unm); rb.ut_p = from_right(fb.utm);
+        centred_rev(p.g, R, -b1, rb);
+        PrimBar pa, pc, pb;
+        zero(pa); zero(pc); zero(pb);
+        muscl_rev(Pl, P, Pr, p.h_eps, rb, pa, pc, pb);
+        // bars of this cell's primitives: from the reconstruction of the
+        // left neighbour (its b), its own (c) and the right one's (a)
+        PrimBar s;
+        s.h = from_left(pb.h) + pc.h + from_right(pa.h);
+        s.un = from_left(pb.un) + pc.un + from_right(pa.un);
+        s.ut = from_left(pb.ut) + pc.ut + from_right(pa.ut);
+        s.eta = from_left(pb.eta) + pc.eta + from_right(pa.eta);
+        double bh, bqx, bqy;
+        prim_rev(w, p.h_eps, s, bh, bqx, bqy);
+        bqx *= sx;
+        // ghost columns fold into the columns they mirror
+        const double v[3] = {bh, bqx, bqy};
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int l = t - 2 + q;
-                    rc[q].h = Lc[0][l];
-                    rc[q].qx = Lc[1][l];
-                    rc[q].qy = Lc[2][l];
-                    rc[q].z = Lc[3][l];
-                    sg[q] = Ls[l];
-                }
-                const double muL[3] = {Lm[0][t - 1], Lm[1][t - 1], Lm[2][t - 1]};
-                const double muR[3] = {m3[0], m3[1], m3[2]};
-                double o[12];
-                face_contrib_cells<0>(p, rc, sg, c - 1 >= 0 && c - 1 < nx, c < nx, muL, muR, o);
-#pragma unroll
-                for (int q = 0; q < 12; ++q) Lx[q][t] = o[q];
-            }
-            __syncthreads();
-            if (out) {
-                // faces f = max(c-1, 0) .. min(c+2, nx), slot c - f + 2
-                const int f0 = c - 1 > 0 ? c - 1 : 0;
-                const int f1 = c + 2 < nx ? c + 2 : nx;
-                for (int f = f0; f <= f1; ++f) {
-                    const int l = t + (f - c), sl = c - f + 2;
-                    a3[0] += Lx[3 * sl + 0][l];
-                    a3[1] += Lx[3 * sl + 1][l];
-                    a3[2] += Lx[3 * sl + 2][l];
-                }
-                auto add = [&](int l, int sl) {
-                    a3[0] += Lx[3 * sl + 0][l];
-                    a3[1] += Lx[3 * sl + 1][l];
-                    a3[2] += Lx[3 * sl + 2][l];
-                };
-                if (c == 0) {
-                    add(t, 1);      // column -1 (face 0)
-                    add(t + 1, 0);  // column -1 (face 1)
-                    if (p.bcw == SWE_BC_OUTFLOW) add(t, 0);
-                }
-                if (c == 1 && p.bcw == SWE_BC_WALL) add(t - 1, 0);
-                if (c == nx - 1) {
-                    add(t, 3);      // column nx (face nx-1)
-                    add(t + 1, 2);  // column nx (face nx)
-                    if (p.bce == SWE_BC_OUTFLOW) add(t + 1, 3);
-                }
-                if (c == nx - 2 && p.bce == SWE_BC_WALL) add(t + 2, 3);
+        for (int q = 0; q < 3; ++q) {
+            const double gw1 = __shfl(v[q], w1, TXT), gw2 = __shfl(v[q], w2, TXT);
+            const double ge1 = __shfl(v[q], e1, TXT), ge2 = __shfl(v[q], e2, TXT);
+            o[q] = v[q] + kw1 * gw1 + kw2 * gw2 + ke1 * ge1 + ke2 * ge2;
+        }
+    };
+
+    // per-lane slots (no lane reads another's): the x parts of the last
+    // four rows (slot n & 3) and the y bars of the ghost rows -1 and -2
+    __shared__ double Xs[4][3][TXT];
+    __shared__ double Gs[2][3][TXT];
+
+    // ---- y window (rows relative to the iteration's new row n) ----
+    RawCell r3, r2, r1;                  // rows n-3, n-2, n-1 as loaded (z unused)
+    Prim P3, P2, P1;                     // y-view primitives of rows n-3 .. n-1
+    Rec R2;                              // reconstruction of row n-2
+    RecBar M2;                           // its m-side bars (face n-2)
+    double bY2[3] = {0.0, 0.0, 0.0}, bY1[3] = {0.0, 0.0, 0.0};  // seeds (y view)
+    PrimBar A, B;                        // partial bars of rows n-3 and n-2
+    zero(A); zero(B); zero(M2);
+    R2.h_m = R2.h_p = R2.z_m = R2.z_p = R2.un_m = R2.un_p = R2.ut_m = R2.ut_p = 0.0;
+    P3.h = P3.un = P3.ut = P3.eta = 0.0;
+    P2 = P1 = P3;
+    r3.h = r3.qx = r3.qy = r3.z = 0.0;
+    r2 = r1 = r3;
+
+    const int n_end = y1 == ny ? y1 + 4 : y1 + 2;
+    for (int n = y0 - 3; n <= n_end; ++n) {
+        RawCell r0;
+        double s0, m0[3];
+        load(n, r0, s0, m0);
+        const Prim P0 = to_y(prim_x(r0, p.h_eps));
+        const double bY0[3] = {-m0[0] / p.dy, -m0[2] / p.dy, -m0[1] / p.dy};
+
+        // x part of row n
+        if (n >= y0 && n < y1) {
+            double X0[3];
+            xpart(r0, m0, X0);
+            Xs[n & 3][0][t] = X0[0];
+            Xs[n & 3][1][t] = X0[1];
+            Xs[n & 3][2][t] = X0[2];
+        }
+
+        Rec R1;
+        R1.h_m = R1.h_p = R1.z_m = R1.z_p = R1.un_m = R1.un_p = R1.ut_m = R1.ut_p = 0.0;
+        RecBar M1;
+        zero(M1);
+        PrimBar C;  // bars of row n-1 from the reconstruction of row n-2
+        zero(C);
+        if (n >= y0 - 1) R1 = muscl(P2, P1, P0, p.h_eps);
+        if (n >= y0) {
+            // face n-1, between rows n-2 (p side of R2) and n-1 (m side of R1)
+            const FaceBar fb = face_rev(p.g, R2.h_p, R2.z_p, R2.un_p, R2.ut_p, R1.h_m, R1.z_m,
+                                        R1.un_m, R1.ut_m, bY2[0] - bY1[0], bY2[1] - bY1[1],
+                                        bY2[2] - bY1[2], bY2[1], -bY1[1]);
+            M1.h_m = fb.hp; M1.z_m = fb.zp; M1.un_m = fb.unp; M1.ut_m = fb.utp;
+            if (n >= y0 + 1) {
+                // row n-2's reconstruction: m side (face n-2), p side (face
+                // n-1), centred source; reversed once
+                RecBar rb = M2;
+                rb.h_p = fb.hm; rb.z_p = fb.zm; rb.un_p = fb.unm; rb.ut_p = fb.utm;
+                centred_rev(p.g, R2, -bY2[1], rb);
+                PrimBar pa, pc;
+                zero(pa); zero(pc);
+                muscl_rev(P3, P2, P1, p.h_eps, rb, pa, pc, C);
+                A.h += pa.h; A.un += pa.un; A.ut += pa.ut; A.eta += pa.eta;
+                B.h += pc.h; B.un += pc.un; B.ut += pc.ut; B.eta += pc.eta;
             }
         }
 
-        // ---- y-face k of this column (rows k-2 .. k+1) ----
-        if (k >= 0 && k <= ny && col_real) {
-            const RawCell rc[4] = {w0, w1, w2, w3};
-            const double sg[4] = {s0, s1, s2, s3};
-            double o[12];
-            face_contrib_cells<1>(p, rc, sg, k - 1 >= 0 && k - 1 < ny, k < ny, m1, m2, o);
-            // contributions to rows k-2+q, q = 0..3, in the order of the faces
-            auto addq = [&](double s[3], int q) {
-                if (k - 2 + q >= y0 && k - 2 + q < y1) {
-                    s[0] += o[3 * q + 0];
-                    s[1] += o[3 * q + 1];
-                    s[2] += o[3 * q + 2];
+        // ---- row n-3 is complete ----
+        const int jd = n - 3;
+        if (n >= y0 + 1) {
+            PrimBar xb;  // back to the x view of the primitives
+            xb.h = A.h; xb.un = A.ut; xb.ut = A.un; xb.eta = A.eta;
+            double yb[3], s3;
+            prim_rev(r3, p.h_eps, xb, yb[0], yb[1], yb[2]);
+            (void)map_index(jd, ny, p.bcs, p.bcn, s3);
+            yb[2] *= s3;
+            if (jd == -1 || jd == -2) {
+#pragma unroll
+                for (int q = 0; q < 3; ++q) Gs[-1 - jd][q][t] = yb[q];
+            }
+            if (jd >= y0 && jd < y1 && out) {
+                double tot[3];
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    tot[q] = Xs[jd & 3][q][t] + yb[q];
+                    // ghost rows below fold into rows 0 and 1
+                    if (jd == 0)
+                        tot[q] += Gs[0][q][t] + (p.bcs != SWE_BC_WALL ? Gs[1][q][t] : 0.0);
+                    if (jd == 1 && p.bcs == SWE_BC_WALL) tot[q] += Gs[1][q][t];
                 }
-            };
-            addq(a0, 0);
-            addq(a1, 1);
-            addq(a2, 2);
-            addq(a3, 3);
-            auto keep = [&](int g, int q) {
-                Lg[g][0][t] = o[3 * q + 0];
-                Lg[g][1][t] = o[3 * q + 1];
-                Lg[g][2][t] = o[3 * q + 2];
-            };
-            if (k == 0) {
-                keep(0, 0);
-                keep(1, 1);
+                const size_t idx = (size_t)jd * nx + c;
+                lh[idx] += tot[0];
+                lqx[idx] += tot[1];
+                lqy[idx] += tot[2];
             }
-            if (k == 1) keep(2, 0);
-            if (k == ny - 1) keep(3, 3);
-            if (k == ny) {
-                keep(4, 2);
-                keep(5, 3);
+            // ghost rows above fold into rows ny-1 and ny-2 (written before)
+            if (out && (jd == ny || jd == ny + 1)) {
+                int dst = -1;
+                if (jd == ny) dst = ny - 1;
+                if (jd == ny + 1) dst = p.bcn == SWE_BC_WALL ? ny - 2 : ny - 1;
+                if (dst >= y0 && dst < y1) {
+                    const size_t idx = (size_t)dst * nx + c;
+                    lh[idx] += yb[0];
+                    lqx[idx] += yb[1];
+                    lqy[idx] += yb[2];
+                }
             }
-        }
-
-        // ---- row k-2 is complete: ghost folds, then lambda += sum ----
-        const int jd = k - 2;
-        if (jd >= y0 && jd < y1 && out) {
-            auto add = [&](int g) {
-                a0[0] += Lg[g][0][t];
-                a0[1] += Lg[g][1][t];
-                a0[2] += Lg[g][2][t];
-            };
-            if (jd == 0) {
-                add(1);  // row -1 (face 0)
-                add(2);  // row -1 (face 1)
-                if (p.bcs == SWE_BC_OUTFLOW) add(0);
-            }
-            if (jd == 1 && p.bcs == SWE_BC_WALL) add(0);
-            if (jd == ny - 1) {
-                add(3);  // row ny (face ny-1)
-                add(4);  // row ny (face ny)
-                if (p.bcn == SWE_BC_OUTFLOW) add(5);
-            }
-            if (jd == ny - 2 && p.bcn == SWE_BC_WALL) add(5);
-            const size_t idx = (size_t)jd * nx + c;
-            lh[idx] += a0[0];
-            lqx[idx] += a0[1];
-            lqy[idx] += a0[2];
         }
 
         // ---- shift the window ----
-        w0 = w1; w1 = w2; w2 = w3;
-        s0 = s1; s1 = s2; s2 = s3;
+        r3 = r2; r2 = r1; r1 = r0;
+        P3 = P2; P2 = P1; P1 = P0;
+        R2 = R1;
+        M2 = M1;
+        A = B;
+        B = C;
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-            m1[q] = m2[q];
-            m2[q] = m3[q];
-            a0[q] = a1[q];
-            a1[q] = a2[q];
-            a2[q] = a3[q];
+            bY2[q] = bY1[q];
+            bY1[q] = bY0[q];
         }
     }
 }
