@@ -872,24 +872,27 @@ __global__ void loss_kernel(const double* __restrict__ series, const double* __r
 
 // Forward stages of one tile grid (the same tile routine as the
 // single-simulation context).
-template <int STAGE, int TXT>
+template <int STAGE, int TXT, bool PHI2>
 __global__ __launch_bounds__(TXT) void fwd_stage_kernel(MemberArgs m, TileIO io, int ty) {
     const int y0 = blockIdx.y * ty;
     const int y1 = min(y0 + ty, m.p.ny);
-    stage_tile<STAGE, TXT>(m, io, blockIdx.x, y0, y1, blockIdx.x == 0 && blockIdx.y == 0,
-                           blockIdx.x + blockIdx.y * gridDim.x);
+    stage_tile<STAGE, TXT, false, 2, 0, PHI2>(m, io, blockIdx.x, y0, y1,
+                                              blockIdx.x == 0 && blockIdx.y == 0,
+                                              blockIdx.x + blockIdx.y * gridDim.x);
 }
 
-// One stage over the whole grid with the default tiling of its size.
-template <int STAGE>
+// One stage over the whole grid with the default tiling of its size; PHI2:
+// stage 2 also writes Phi(U*) to io.ph2/pqx2/pqy2.
+template <int STAGE, bool PHI2 = false>
 void launch_fwd(const swe_params& prm, hipStream_t s, const MemberArgs& m, const TileIO& io) {
     const int tx = default_tx(prm.nx, prm.ny);
     const int ty = auto_rows(prm.nx, prm.ny, tx);
     const dim3 grid(strips_of(prm.nx, tx), (prm.ny + ty - 1) / ty);
     if (tx == 64)
-        hipLaunchKernelGGL((fwd_stage_kernel<STAGE, 64>), grid, dim3(64), 0, s, m, io, ty);
+        hipLaunchKernelGGL((fwd_stage_kernel<STAGE, 64, PHI2>), grid, dim3(64), 0, s, m, io, ty);
     else
-        hipLaunchKernelGGL((fwd_stage_kernel<STAGE, 256>), grid, dim3(256), 0, s, m, io, ty);
+        hipLaunchKernelGGL((fwd_stage_kernel<STAGE, 256, PHI2>), grid, dim3(256), 0, s, m, io,
+                           ty);
 }
 
 // Per-step reset of the time bookkeeping (the status flags stay sticky).
@@ -934,6 +937,7 @@ struct swe_adj {
     double* ckpts;         // device, nckpt x 3N
     double* seg;           // device, (ckpt + 1) x 3N
     double* segphi;        // Phi(U^k) of the recomputed segment steps, ckpt x 3N
+    double* segphi2;       // Phi(U*) of the same steps, ckpt x 3N
     double* ust;           // U* (3N)
     double* phi;           // Phi (3N)
     double* phi0;          // Phi(U^k) kept for the reverse of stage 1 (3N)
@@ -953,7 +957,7 @@ size_t adj_bytes(const swe_params* p, int nsteps, int ckpt, int ngauges, int eve
     size_t rows = every > 0 ? nsteps / every : 0;
     return SCALAR_BYTES + 256 + align256(nsteps * sizeof(double)) +
            align256(rows * (size_t)ngauges * sizeof(double)) + 3 * an * nck +
-           3 * an * (ckpt + 1) + 3 * an * ckpt + 3 * an * 7;
+           3 * an * (ckpt + 1) + 2 * 3 * an * ckpt + 3 * an * 7;
 }
 
 inline double* plane(double* base, size_t n, int k) { return base + (size_t)k * n; }
@@ -962,10 +966,11 @@ inline const double* plane(const double* base, size_t n, int k) { return base + 
 int blocks(size_t n) { return (int)((n + T1 - 1) / T1); }
 
 // One forward step U_in -> U_out with a frozen dt (dt_fixed > 0) or the CFL
-// dt (dt_fixed = 0, logged to dts[k]).  phi_out (optional) receives
-// Phi(U_in), which stage 1 computes anyway.
+// dt (dt_fixed = 0, logged to dts[k]).  phi_out and phi2_out (optional)
+// receive Phi(U_in) and Phi(U*), which the two stages compute anyway.
 void fwd_step(swe_adj* A, const double* h, const double* qx, const double* qy, double* ho,
-              double* qxo, double* qyo, double dt_fixed, int k, double* phi_out = nullptr) {
+              double* qxo, double* qyo, double dt_fixed, int k, double* phi_out = nullptr,
+              double* phi2_out = nullptr) {
     MemberArgs m = A->m;
     m.h[0] = (double*)h; m.qx[0] = (double*)qx; m.qy[0] = (double*)qy;
     m.h[1] = ho; m.qx[1] = qxo; m.qy[1] = qyo;
@@ -984,7 +989,14 @@ void fwd_step(swe_adj* A, const double* h, const double* qx, const double* qy, d
     TileIO io = host_step_io(m, 0, 0, INFINITY);
     io.dt_fixed = dt_fixed;
     launch_fwd<1>(A->prm, A->stream, m, io);
-    launch_fwd<2>(A->prm, A->stream, m, io);
+    if (phi2_out) {
+        io.ph2 = plane(phi2_out, A->n, 0);
+        io.pqx2 = plane(phi2_out, A->n, 1);
+        io.pqy2 = plane(phi2_out, A->n, 2);
+        launch_fwd<2, true>(A->prm, A->stream, m, io);
+    } else {
+        launch_fwd<2>(A->prm, A->stream, m, io);
+    }
 }
 
 // Phi(U) into dst (stage 1 kernel with a scratch accumulator).
@@ -1018,8 +1030,10 @@ void vjp_rate(swe_adj* A, const double* h, const double* qx, const double* qy, d
 }
 
 // lamA <- adjoint of U^k given lam = adjoint of U^{k+1}; grad += dL/dn.
-// phik: Phi(U^k) kept from the segment recompute, or null to recompute it.
-void adj_step(swe_adj* A, const double* Uk, double dt, double* grad, const double* phik) {
+// phik, phi2k: Phi(U^k) and Phi(U*) kept from the segment recompute, or
+// null to recompute them.
+void adj_step(swe_adj* A, const double* Uk, double dt, double* grad, const double* phik,
+              const double* phi2k) {
     const size_t n = A->n;
     const double* h = Uk;
     const double* qx = Uk + n;
@@ -1036,11 +1050,14 @@ void adj_step(swe_adj* A, const double* Uk, double dt, double* grad, const doubl
                        n);
     // stage 2 on U*: Phi(U*), then its friction reversed with output
     // adjoint lam/2
-    rate_into(A, plane(us, n, 0), plane(us, n, 1), plane(us, n, 2), A->phi);
+    if (!phi2k) {
+        rate_into(A, plane(us, n, 0), plane(us, n, 1), plane(us, n, 2), A->phi);
+        phi2k = A->phi;
+    }
     hipLaunchKernelGGL(adj_stage_kernel, dim3(blocks(n)), dim3(T1), 0, A->stream, A->m.p,
                        A->m.fric, (const double*)plane(us, n, 0), (const double*)plane(us, n, 1),
-                       (const double*)plane(us, n, 2), (const double*)plane(A->phi, n, 0),
-                       (const double*)plane(A->phi, n, 1), (const double*)plane(A->phi, n, 2), dt,
+                       (const double*)plane(us, n, 2), plane(phi2k, n, 0), plane(phi2k, n, 1),
+                       plane(phi2k, n, 2), dt,
                        (const double*)plane(A->lam, n, 0), (const double*)plane(A->lam, n, 1),
                        (const double*)plane(A->lam, n, 2), 0.5, plane(A->lamB, n, 0),
                        plane(A->lamB, n, 1), plane(A->lamB, n, 2), 0, nullptr, nullptr, nullptr,
@@ -1129,6 +1146,7 @@ int swe_adj_create(const swe_params* p, const swe_buffers* b, int32_t nsteps,
     A->ckpts = (double*)w; w += 3 * an * nck;
     A->seg = (double*)w; w += 3 * an * (ckpt_every + 1);
     A->segphi = (double*)w; w += 3 * an * ckpt_every;
+    A->segphi2 = (double*)w; w += 3 * an * ckpt_every;
     A->ust = (double*)w; w += 3 * an;
     A->phi = (double*)w; w += 3 * an;
     A->phi0 = (double*)w; w += 3 * an;
@@ -1254,7 +1272,7 @@ int swe_adj_backward(swe_adj* A, double* grad) {
             double* in = A->seg + (size_t)(k - s) * 3 * n;
             double* o = in + 3 * n;
             fwd_step(A, in, in + n, in + 2 * n, o, o + n, o + 2 * n, dts[k], k,
-                     A->segphi + (size_t)(k - s) * 3 * n);
+                     A->segphi + (size_t)(k - s) * 3 * n, A->segphi2 + (size_t)(k - s) * 3 * n);
         }
         for (int k = e - 1; k >= s; --k) {
             // loss term of U^{k+1}
@@ -1265,8 +1283,9 @@ int swe_adj_backward(swe_adj* A, double* grad) {
                                    A->ngauges, A->lam);
             }
             const double* Uk = A->seg + (size_t)(k - s) * 3 * n;
-            adj_step(A, Uk, dts[k], grad,
-                     k < e - 1 ? A->segphi + (size_t)(k - s) * 3 * n : nullptr);
+            const bool kept = k < e - 1;  // the recompute stopped before the last step
+            adj_step(A, Uk, dts[k], grad, kept ? A->segphi + (size_t)(k - s) * 3 * n : nullptr,
+                     kept ? A->segphi2 + (size_t)(k - s) * 3 * n : nullptr);
             // lam <- lamA (the buffers trade places)
             std::swap(A->lam, A->lamA);
         }

@@ -509,6 +509,9 @@ struct TileIO {
     int slot;                 // step parity (time buffer, accumulator slot)
     double t_end;
     double dt_fixed;          // > 0: use this time step instead of the CFL bound
+    double* ph2;              // stage 2 with PHI2 only: Phi(U*) out
+    double* pqx2;
+    double* pqy2;
 };
 
 __device__ __forceinline__ TileIO step_io(const MemberArgs& m, int phase, int slot,
@@ -528,6 +531,7 @@ __device__ __forceinline__ TileIO step_io(const MemberArgs& m, int phase, int sl
     io.slot = slot;
     io.t_end = t_end;
     io.dt_fixed = 0.0;
+    io.ph2 = io.pqx2 = io.pqy2 = nullptr;
     return io;
 }
 
@@ -762,7 +766,7 @@ __device__ __forceinline__ void finish_cell(const MemberArgs& m, const TileIO& i
         atomicOr(&m.sc->status, (unsigned)SWE_FLAG_NEGDEPTH);
 }
 
-template <int STAGE, int TXT, class D, bool FIELDS, int ORDER, int FLUX>
+template <int STAGE, int TXT, class D, bool FIELDS, int ORDER, int FLUX, bool PHI2>
 __device__ __forceinline__ int march(const MemberArgs& m, const TileIO& io, int strip, int y0,
                                      int y1, double dt, double rain, double& ax, double& ay,
                                      TileLds<TXT>& L) {
@@ -977,6 +981,11 @@ __device__ __forceinline__ int march(const MemberArgs& m, const TileIO& io, int 
                 io.pqx[idx] = rqx;
                 io.pqy[idx] = rqy;
             } else {
+                if constexpr (PHI2) {
+                    io.ph2[idx] = rh;
+                    io.pqx2[idx] = rqx;
+                    io.pqy2[idx] = rqy;
+                }
                 // Heun: U^{n+1} = (U^n + U**)/2
                 double hn = 0.5 * (n0h + h2);
                 double qxn = 0.5 * (n0x + qx2);
@@ -1093,8 +1102,10 @@ __host__ __device__ __forceinline__ bool has_fields(const MemberArgs& m) {
 // `spread` picks the accumulator pair of stage 1 (any block-dependent index).
 // FIELDS compiles in the reads of the optional rain and soil fields; ORDER 1
 // (stage 1 only) replaces MUSCL by the cell values (first order); FLUX 1
-// takes the Rusanov flux instead of HLL.
-template <int STAGE, int TXT, bool FIELDS = false, int ORDER = 2, int FLUX = 0>
+// takes the Rusanov flux instead of HLL; PHI2 (stage 2) also writes Phi(U*)
+// to io.ph2/pqx2/pqy2 (the adjoint keeps it).
+template <int STAGE, int TXT, bool FIELDS = false, int ORDER = 2, int FLUX = 0,
+          bool PHI2 = false>
 __device__ __forceinline__ void stage_tile(const MemberArgs& m, const TileIO& io, int strip,
                                            int y0, int y1, bool lead, int spread) {
     constexpr int OUTW = TXT - 2 * HALO;
@@ -1129,11 +1140,11 @@ __device__ __forceinline__ void stage_tile(const MemberArgs& m, const TileIO& io
     double ax = 0.0, ay = 0.0;
     int stop = y0;
     if (p.fast_div)
-        stop = march<STAGE, TXT, FastDiv, FIELDS, ORDER, FLUX>(m, io, strip, y0, y1, dt, rain,
-                                                               ax, ay, L);
+        stop = march<STAGE, TXT, FastDiv, FIELDS, ORDER, FLUX, PHI2>(m, io, strip, y0, y1, dt,
+                                                                     rain, ax, ay, L);
     if (stop < y1)
-        march<STAGE, TXT, ExactDiv, FIELDS, ORDER, FLUX>(m, io, strip, stop, y1, dt, rain, ax,
-                                                         ay, L);
+        march<STAGE, TXT, ExactDiv, FIELDS, ORDER, FLUX, PHI2>(m, io, strip, stop, y1, dt, rain,
+                                                               ax, ay, L);
     if (STAGE == 1) block_max2<TXT>(ax, ay, io.acc, spread);
 }
 
