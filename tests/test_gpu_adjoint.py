@@ -63,7 +63,26 @@ def case_darcy():
     return wl, 0.3 + 0.1 * wl.extra["fric_obs"] / 0.03
 
 
-@pytest.mark.parametrize("make", [case_calibration, case_random_bcs, case_darcy])
+def _small(nx, ny, bc, seed):
+    def make():
+        rng = np.random.default_rng(seed)
+        wl = I.random_state(nx, ny, seed=seed, bc=bc, fric_law=I.FRIC_MANNING, fric_coef=0.04)
+        wl.fric = 0.04 * (1.0 + 0.2 * rng.uniform(-1.0, 1.0, (ny, nx)))
+        k = min(4, nx * ny)
+        wl.gauges = np.sort(rng.choice(nx * ny, k, replace=False)).astype(np.int32)
+        return wl, 0.04 * (1.0 + 0.2 * rng.uniform(-1.0, 1.0, (ny, nx)))
+    make.__name__ = f"case_{nx}x{ny}_bc{''.join(map(str, bc))}"
+    return make
+
+
+# small grids: every ghost fold lands on a cell that also has other folds
+# (nx or ny of 2 or 3), a strip narrower than one tile, one row of tiles
+SMALL = [_small(2, 2, (0, 0, 0, 0), 41), _small(3, 5, (1, 1, 1, 1), 42),
+         _small(2, 7, (0, 1, 1, 0), 43), _small(5, 3, (1, 0, 0, 1), 44),
+         _small(130, 9, (0, 1, 0, 1), 45)]
+
+
+@pytest.mark.parametrize("make", [case_calibration, case_random_bcs, case_darcy] + SMALL)
 def test_adjoint_against_oracle_tangent(torch_cuda, make):
     from paper_1307_4839_amd.solver import Calibration
     wl, fric_obs = make()
