@@ -48,7 +48,7 @@ class OrcParams(C.Structure):
                 ("rain_r", C.POINTER(C.c_double)), ("rain_w", C.POINTER(C.c_double)),
                 ("ks_f", C.POINTER(C.c_double)), ("psi_f", C.POINTER(C.c_double)),
                 ("dtheta_f", C.POINTER(C.c_double)), ("order", C.c_int32),
-                ("flux", C.c_int32)]
+                ("flux", C.c_int32), ("bc_h", C.c_double * 4), ("bc_q", C.c_double * 4)]
 
 
 _lib = None
@@ -102,10 +102,14 @@ def _ip(a: Optional[np.ndarray]):
 
 def params(nx, ny, dx, dy, g=9.81, cfl=0.5, dt_max=math.inf, h_eps=1e-12,
            bc=(0, 0, 0, 0), fric_law=0, fric_coef=0.0, rain=0.0, infil_on=0,
-           ks=0.0, psi=0.0, dtheta=0.0, order=2, flux=0) -> OrcParams:
+           ks=0.0, psi=0.0, dtheta=0.0, order=2, flux=0, bc_h=(0.0,) * 4,
+           bc_q=(0.0,) * 4) -> OrcParams:
     p = OrcParams()
     p.order = int(order)
     p.flux = int(flux)
+    for k in range(4):
+        p.bc_h[k] = float(bc_h[k])
+        p.bc_q[k] = float(bc_q[k])
     p.nx, p.ny, p.dx, p.dy = nx, ny, dx, dy
     p.g, p.cfl, p.dt_max, p.h_eps = g, cfl, dt_max, h_eps
     for k in range(4):

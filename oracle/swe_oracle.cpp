@@ -97,7 +97,7 @@ template <class T> inline T vmin(T a, T b) { return (b < a) ? b : a; }
 // Parameters (own definition; mirrors nothing)
 // ---------------------------------------------------------------------------
 
-enum { BC_WALL = 0, BC_OUTFLOW = 1 };
+enum { BC_WALL = 0, BC_OUTFLOW = 1, BC_IMPOSED_H = 2, BC_IMPOSED_Q = 3, BC_IMPOSED_HQ = 4 };
 enum { LAW_NONE = 0, LAW_MANNING = 1, LAW_DARCY = 2 };
 
 }  // namespace
@@ -132,6 +132,10 @@ struct orc_params {
     int32_t order;
     // numerical flux (Section 3.3 allows any consistent one): 0 HLL, 1 Rusanov
     int32_t flux;
+    // imposed boundaries (bc 2: depth h_b, 3: inflow discharge q_b per unit
+    // width, 4: both), per side west, east, south, north
+    double bc_h[4];
+    double bc_q[4];
 };
 }
 
@@ -305,29 +309,104 @@ struct Grid {
     size_t size() const { return (size_t)px * py; }
 };
 
+// Imposed boundary (Section 2.2): the ghost state comes from the Riemann
+// invariants.  With w the outward normal velocity of the boundary cell and
+// c = sqrt(g h), the invariant w + 2c is carried out of the domain by the
+// characteristic w + c, so the ghost keeps it.  In fluvial flow one
+// variable is imposed: the depth h_b (w of the ghost from the invariant) or
+// the inflow discharge q_b (the depth from the invariant); with both
+// imposed (supercritical inflow) the ghost is (h_b, q_b); a boundary cell in
+// supercritical outflow (w > c) is free (the ghost copies it).  The ghost
+// keeps the boundary cell's tangential velocity.  Inputs and outputs: depth,
+// outward normal discharge, tangential discharge.
+template <class T>
+inline void imposed_ghost(const orc_params& p, int side, T hb, T qo, T qt, T& hg, T& qog,
+                          T& qtg) {
+    const double g = p.g;
+    const bool wet = hb > T(p.h_eps);
+    T w = wet ? qo / hb : T(0.0);
+    T vt = wet ? qt / hb : T(0.0);
+    T c = dsqrt(T(g) * hb);
+    if (w > c) {  // supercritical outflow: free
+        hg = hb;
+        qog = qo;
+        qtg = qt;
+        return;
+    }
+    const int type = p.bc[side];
+    if (type == BC_IMPOSED_HQ) {
+        hg = T(p.bc_h[side]);
+        qog = -T(p.bc_q[side]);
+    } else if (type == BC_IMPOSED_H) {
+        hg = T(p.bc_h[side]);
+        T wg = (w + T(2.0) * c) - T(2.0) * dsqrt(T(g) * hg);
+        qog = hg * wg;
+    } else {
+        // depth of the ghost: 2 sqrt(g h) - q_b / h = w + 2c, increasing in
+        // h for q_b >= 0; bisection (bracket doubled from 1 m, then halved
+        // 100 times), which only compares, adds, divides and takes roots
+        const double qb = p.bc_q[side];
+        const double R = val(w + T(2.0) * c);
+        auto F = [&](double x) { return 2.0 * std::sqrt(g * x) - qb / x; };
+        double hi = 1.0;
+        for (int k = 0; k < 200 && F(hi) < R; ++k) hi = 2.0 * hi;
+        double lo = 0.0;
+        for (int k = 0; k < 100; ++k) {
+            double mid = 0.5 * (lo + hi);
+            if (F(mid) < R) lo = mid; else hi = mid;
+        }
+        hg = T(hi);
+        qog = -T(qb);
+    }
+    qtg = hg * vt;
+}
+
 // Ghost cells (reading of Section 2.2).  Wall: ghost k mirrors interior
 // cell k (h, z and tangential discharge), normal discharge negated.  Free
-// outflow: ghosts copy the boundary cell (zero gradient).  The x-sweep reads
-// only x-ghosts and the y-sweep only y-ghosts, so corners are never used.
+// outflow: ghosts copy the boundary cell (zero gradient).  Imposed: both
+// ghosts take imposed_ghost() of the boundary cell, z copied.  The x-sweep
+// reads only x-ghosts and the y-sweep only y-ghosts, so corners are never
+// used.
 template <class T>
 void fill_ghosts(const orc_params& p, const Grid& gr, std::vector<T>& h,
                  std::vector<T>& qx, std::vector<T>& qy, std::vector<T>& z) {
     const int nx = gr.nx, ny = gr.ny;
+    auto imposed = [&](int side, size_t dst, size_t src) {
+        // outward normal: -x, +x, -y, +y for west, east, south, north
+        const bool xn = side < 2;
+        const double sg = (side == 0 || side == 2) ? -1.0 : 1.0;
+        T qn = xn ? qx[src] : qy[src];
+        T qt = xn ? qy[src] : qx[src];
+        T hg, qog, qtg;
+        imposed_ghost(p, side, h[src], T(sg) * qn, qt, hg, qog, qtg);
+        h[dst] = hg;
+        z[dst] = z[src];
+        if (xn) { qx[dst] = T(sg) * qog; qy[dst] = qtg; }
+        else { qy[dst] = T(sg) * qog; qx[dst] = qtg; }
+    };
     for (int j = 0; j < ny; ++j) {
         for (int k = 0; k < G; ++k) {
             // west: ghost -1-k
             {
                 size_t dst = gr.at(-1 - k, j);
                 size_t src = p.bc[0] == BC_WALL ? gr.at(k, j) : gr.at(0, j);
-                h[dst] = h[src]; z[dst] = z[src]; qy[dst] = qy[src];
-                qx[dst] = p.bc[0] == BC_WALL ? -qx[src] : qx[src];
+                if (p.bc[0] >= BC_IMPOSED_H) {
+                    imposed(0, dst, src);
+                } else {
+                    h[dst] = h[src]; z[dst] = z[src]; qy[dst] = qy[src];
+                    qx[dst] = p.bc[0] == BC_WALL ? -qx[src] : qx[src];
+                }
             }
             // east: ghost nx+k
             {
                 size_t dst = gr.at(nx + k, j);
                 size_t src = p.bc[1] == BC_WALL ? gr.at(nx - 1 - k, j) : gr.at(nx - 1, j);
-                h[dst] = h[src]; z[dst] = z[src]; qy[dst] = qy[src];
-                qx[dst] = p.bc[1] == BC_WALL ? -qx[src] : qx[src];
+                if (p.bc[1] >= BC_IMPOSED_H) {
+                    imposed(1, dst, src);
+                } else {
+                    h[dst] = h[src]; z[dst] = z[src]; qy[dst] = qy[src];
+                    qx[dst] = p.bc[1] == BC_WALL ? -qx[src] : qx[src];
+                }
             }
         }
     }
@@ -337,15 +416,23 @@ void fill_ghosts(const orc_params& p, const Grid& gr, std::vector<T>& h,
             {
                 size_t dst = gr.at(i, -1 - k);
                 size_t src = p.bc[2] == BC_WALL ? gr.at(i, k) : gr.at(i, 0);
-                h[dst] = h[src]; z[dst] = z[src]; qx[dst] = qx[src];
-                qy[dst] = p.bc[2] == BC_WALL ? -qy[src] : qy[src];
+                if (p.bc[2] >= BC_IMPOSED_H) {
+                    imposed(2, dst, src);
+                } else {
+                    h[dst] = h[src]; z[dst] = z[src]; qx[dst] = qx[src];
+                    qy[dst] = p.bc[2] == BC_WALL ? -qy[src] : qy[src];
+                }
             }
             // north: ghost ny+k
             {
                 size_t dst = gr.at(i, ny + k);
                 size_t src = p.bc[3] == BC_WALL ? gr.at(i, ny - 1 - k) : gr.at(i, ny - 1);
-                h[dst] = h[src]; z[dst] = z[src]; qx[dst] = qx[src];
-                qy[dst] = p.bc[3] == BC_WALL ? -qy[src] : qy[src];
+                if (p.bc[3] >= BC_IMPOSED_H) {
+                    imposed(3, dst, src);
+                } else {
+                    h[dst] = h[src]; z[dst] = z[src]; qx[dst] = qx[src];
+                    qy[dst] = p.bc[3] == BC_WALL ? -qy[src] : qy[src];
+                }
             }
         }
     }

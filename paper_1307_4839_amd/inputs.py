@@ -48,6 +48,9 @@ import numpy as np
 
 WALL = 0
 OUTFLOW = 1
+IMPOSED_H = 2   # depth imposed (Riemann invariant for the velocity)
+IMPOSED_Q = 3   # inflow discharge imposed (Riemann invariant for the depth)
+IMPOSED_HQ = 4  # both (supercritical inflow)
 
 FRIC_NONE = 0
 FRIC_MANNING = 1
@@ -70,6 +73,8 @@ class Workload:
     qx: np.ndarray
     qy: np.ndarray
     bc: tuple = (WALL, WALL, WALL, WALL)  # west, east, south, north
+    bc_h: tuple = (0.0, 0.0, 0.0, 0.0)    # imposed depth per side [m]
+    bc_q: tuple = (0.0, 0.0, 0.0, 0.0)    # imposed inflow discharge per side [m^2/s]
     g: float = 9.81
     cfl: float = 0.5
     dt_max: float = math.inf
@@ -109,7 +114,8 @@ class Workload:
                     bc=tuple(self.bc), fric_law=self.fric_law,
                     fric_coef=self.fric_coef, rain=self.rain,
                     infil_on=self.infil_on, ks=self.ks, psi=self.psi,
-                    dtheta=self.dtheta, order=self.order, flux=self.flux)
+                    dtheta=self.dtheta, order=self.order, flux=self.flux,
+                    bc_h=tuple(self.bc_h), bc_q=tuple(self.bc_q))
 
     def copy(self) -> "Workload":
         out = dataclasses.replace(self)

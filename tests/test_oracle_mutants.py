@@ -57,6 +57,22 @@ MUTANTS = {
                              "const double psi = p.psi;"),
     "ga_dtheta_field_ignored": ("const double dtheta = p.dtheta_f ? p.dtheta_f[s] : p.dtheta;",
                                 "const double dtheta = p.dtheta;"),
+    "imposed_outward_velocity_sign": ("T w = wet ? qo / hb : T(0.0);",
+                                      "T w = wet ? -qo / hb : T(0.0);"),
+    "imposed_h_invariant_dropped": ("T wg = (w + T(2.0) * c) - T(2.0) * dsqrt(T(g) * hg);",
+                                    "T wg = w;"),
+    "imposed_h_invariant_sign": ("T wg = (w + T(2.0) * c) - T(2.0) * dsqrt(T(g) * hg);",
+                                 "T wg = (w - T(2.0) * c) + T(2.0) * dsqrt(T(g) * hg);"),
+    "imposed_q_discharge_sign": ("        qog = -T(qb);", "        qog = T(qb);"),
+    "imposed_q_invariant_term": ("return 2.0 * std::sqrt(g * x) - qb / x;",
+                                 "return 2.0 * std::sqrt(g * x) + qb / x;"),
+    "imposed_hq_discharge_sign": ("qog = -T(p.bc_q[side]);", "qog = T(p.bc_q[side]);"),
+    "imposed_supercritical_test": ("if (w > c) {  // supercritical outflow: free",
+                                   "if (w < -c) {  // supercritical outflow: free"),
+    "imposed_side_signs": ("const double sg = (side == 0 || side == 2) ? -1.0 : 1.0;",
+                           "const double sg = (side == 0 || side == 3) ? -1.0 : 1.0;"),
+    "imposed_tangential_dropped": ("    qtg = hg * vt;", "    qtg = T(0.0);"),
+    "imposed_ghost_not_wet_tested": ("const bool wet = hb > T(p.h_eps);", "const bool wet = true;"),
 }
 
 

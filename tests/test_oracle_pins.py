@@ -742,3 +742,196 @@ def test_restart_bit_identical():
     assert np.array_equal(a.h, c.h) and np.array_equal(a.qx, c.qx)
     assert np.array_equal(a.qy, c.qy) and np.array_equal(a.vinf, c.vinf)
     assert a.t == c.t
+
+
+# ---------------------------------------------------------------------------
+# P-imposed: boundaries with an imposed depth or inflow discharge, the ghost
+# state from the Riemann invariants (Section 2.2).  Pinned to the steady
+# Bernoulli solution of subcritical flow over a bump, to exact preservation
+# of uniform flows and of a lake at rest, to the free exit of supercritical
+# outflow, and to mirror and transposition symmetry.
+# ---------------------------------------------------------------------------
+
+def _bump(nx, ny=2, q0=4.42, hb=2.0, flip=False):
+    """25 m channel, parabolic bump 0.2 - 0.05 (x - 10)^2 on 8 < x < 12, at
+    rest with h + z = hb; discharge q0 imposed upstream, depth hb
+    downstream (walls on the channel sides).  flip: the mirror image."""
+    dx = 25.0 / nx
+    x = (np.arange(nx) + 0.5) * dx
+    z1 = np.where((x > 8) & (x < 12), 0.2 - 0.05 * (x - 10) ** 2, 0.0)
+    if flip:
+        z1 = z1[::-1].copy()
+    z = np.tile(z1, (ny, 1))
+    h = hb - z
+    bc = (I.IMPOSED_H, I.IMPOSED_Q, 0, 0) if flip else (I.IMPOSED_Q, I.IMPOSED_H, 0, 0)
+    bc_h = (hb, 0, 0, 0) if flip else (0, hb, 0, 0)
+    bc_q = (0, q0, 0, 0) if flip else (q0, 0, 0, 0)
+    wl = I.Workload("bump", nx, ny, dx, dx, z=z, h=h, qx=np.zeros_like(h),
+                    qy=np.zeros_like(h), bc=bc, bc_h=bc_h, bc_q=bc_q)
+    return wl, z1
+
+
+def _bernoulli_depth(z1, q0, hb):
+    # steady frictionless flow: q = q0 and q^2 / (2 g h^2) + h + z equal to
+    # its value at the outlet (z = 0, h = hb); the fluvial root of the cubic
+    H = q0 ** 2 / (2 * G * hb ** 2) + hb
+    hc = (q0 ** 2 / G) ** (1.0 / 3.0)
+    out = []
+    for zz in z1:
+        r = np.roots([1.0, zz - H, 0.0, q0 ** 2 / (2 * G)])
+        r = r[np.abs(r.imag) < 1e-9].real
+        out.append(r[r > hc].min())
+    return np.array(out)
+
+
+def test_imposed_subcritical_bump_reaches_bernoulli():
+    q0, hb = 4.42, 2.0
+    errs = []
+    for nx in (50, 100):
+        wl, z1 = _bump(nx, q0=q0, hb=hb)
+        s = oracle.State(wl)
+        assert s.run(10 ** 8, 150.0) == 1 and s.t == 150.0
+        he = _bernoulli_depth(z1, q0, hb)
+        eh = np.abs(s.h - he[None, :]).max()
+        eq = np.abs(s.qx - q0).max()
+        assert np.all(s.qy == 0.0)
+        assert eh <= 0.03 and eq <= 0.06, (nx, eh, eq)
+        errs.append((eh, eq))
+    # the error falls with the mesh
+    assert errs[1][0] <= 0.7 * errs[0][0] and errs[1][1] <= 0.7 * errs[0][1], errs
+
+
+def test_imposed_bump_mirror_and_transpose():
+    wl, _ = _bump(60)
+    wm, _ = _bump(60, flip=True)
+    a, m = oracle.State(wl), oracle.State(wm)
+    assert a.run(400) == 0 and m.run(400) == 0
+    assert a.dts == m.dts
+    scale = 4.42
+    assert np.abs(m.h[:, ::-1] - a.h).max() <= 1e-12 * 2.0
+    assert np.abs(-m.qx[:, ::-1] - a.qx).max() <= 1e-12 * scale
+    # the same channel along y: q imposed on the south, depth on the north
+    wt = I.Workload("bump_y", wl.ny, wl.nx, wl.dy, wl.dx, z=wl.z.T.copy(), h=wl.h.T.copy(),
+                    qx=np.zeros((wl.nx, wl.ny)), qy=np.zeros((wl.nx, wl.ny)),
+                    bc=(0, 0, I.IMPOSED_Q, I.IMPOSED_H), bc_h=(0, 0, 0, 2.0),
+                    bc_q=(0, 0, 4.42, 0))
+    b = oracle.State(wt)
+    assert b.run(400) == 0 and b.dts == a.dts
+    assert np.abs(b.h.T - a.h).max() <= 1e-12 * 2.0
+    assert np.abs(b.qy.T - a.qx).max() <= 1e-12 * scale
+    assert np.all(b.qx == 0.0)
+    # and mirrored along y: q imposed on the north
+    wtm = I.Workload("bump_y_flip", wl.ny, wl.nx, wl.dy, wl.dx, z=wm.z.T.copy(),
+                     h=wm.h.T.copy(), qx=np.zeros((wl.nx, wl.ny)), qy=np.zeros((wl.nx, wl.ny)),
+                     bc=(0, 0, I.IMPOSED_H, I.IMPOSED_Q), bc_h=(0, 0, 2.0, 0),
+                     bc_q=(0, 0, 0, 4.42))
+    c = oracle.State(wtm)
+    assert c.run(400) == 0 and c.dts == a.dts
+    assert np.abs(c.h.T[:, ::-1] - a.h).max() <= 1e-12 * 2.0
+    assert np.abs(-c.qy.T[:, ::-1] - a.qx).max() <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("order", [2, 1])
+def test_imposed_uniform_flow_is_kept(order):
+    # uniform fluvial flow (h0, u0, 0) along x on a flat bed: discharge
+    # imposed upstream, depth downstream, depth on the south side and zero
+    # inflow on the north side (both tangential to the flow): the ghosts
+    # equal the boundary cells, so the flow stays uniform to round-off
+    h0, u0 = 1.3, 0.7
+    wl = flat_workload(40, 12, dx=0.5, dy=0.5, bc=(I.IMPOSED_Q, I.IMPOSED_H, I.IMPOSED_H, I.IMPOSED_Q),
+                       bc_h=(0, h0, h0, 0), bc_q=(h0 * u0, 0, 0, 0), order=order,
+                       cfl=0.5 if order == 2 else 1.0)
+    wl.h[:] = h0
+    wl.qx[:] = h0 * u0
+    s = oracle.State(wl)
+    assert s.run(300) == 0
+    assert np.abs(s.h - h0).max() <= 1e-12 * h0
+    assert np.abs(s.qx - h0 * u0).max() <= 1e-12 * h0 * u0
+    assert np.abs(s.qy).max() <= 1e-12 * h0 * u0
+
+
+def test_imposed_supercritical_outflow_is_free():
+    # uniform torrential flow (Froude 4.5): the downstream imposed depth is
+    # ignored (the ghost copies the cell), bit for bit as a free outflow;
+    # the upstream ghost with (h, q) imposed equals the cell
+    h0, q0 = 0.5, 5.0
+    runs = []
+    for east in ((I.IMPOSED_H, 2.0), (I.OUTFLOW, 0.0)):
+        wl = flat_workload(50, 3, bc=(I.IMPOSED_HQ, east[0], 0, 0),
+                           bc_h=(h0, east[1], 0, 0), bc_q=(q0, 0, 0, 0))
+        wl.h[:] = h0
+        wl.qx[:] = q0
+        s = oracle.State(wl)
+        assert s.run(200) == 0
+        runs.append(s)
+    assert np.array_equal(runs[0].h, runs[1].h) and np.array_equal(runs[0].qx, runs[1].qx)
+    assert np.all(runs[0].h == h0) and np.all(runs[0].qx == q0)
+
+
+@pytest.mark.parametrize("depth0", [0.5, 0.0])
+def test_imposed_supercritical_inflow_fills_channel(depth0):
+    # torrential inflow (h, q) = (0.5, 5) into a channel at rest (depth 0.5,
+    # or dry) with a free outlet: once the front has left, the flow is
+    # uniform
+    h0, q0 = 0.5, 5.0
+    wl = flat_workload(60, 2, bc=(I.IMPOSED_HQ, I.OUTFLOW, 0, 0), bc_h=(h0, 0, 0, 0),
+                       bc_q=(q0, 0, 0, 0))
+    wl.h[:] = depth0
+    s = oracle.State(wl)
+    assert s.run(10 ** 6, 40.0) == 1
+    assert np.abs(s.h - h0).max() <= 1e-9 and np.abs(s.qx - q0).max() <= 1e-8
+
+
+@pytest.mark.parametrize("kind", [I.IMPOSED_H, I.IMPOSED_Q])
+def test_imposed_lake_at_rest(kind):
+    # the level C on every side, zero inflow: a lake at rest over bumps
+    # (bed 0 along the edges) stays at rest
+    C = 1.2
+    nx, ny = 40, 30
+    x = (np.arange(nx) + 0.5)[None, :]
+    y = (np.arange(ny) + 0.5)[:, None]
+    z = 1.5 * np.exp(-((x - 20) ** 2 + (y - 14) ** 2) / 20.0)
+    z = z * (x > 2) * (x < nx - 2) * (y > 2) * (y < ny - 2)
+    h = np.maximum(C - z, 0.0)
+    wl = I.Workload("lake", nx, ny, 1.0, 1.0, z=z, h=h, qx=np.zeros_like(h), qy=np.zeros_like(h),
+                    bc=(kind,) * 4, bc_h=(C,) * 4, bc_q=(0.0,) * 4,
+                    fric_law=I.FRIC_MANNING, fric_coef=0.03)
+    assert (h == 0).any()
+    s = oracle.State(wl)
+    assert s.run(500) == 0
+    wet = h > 0
+    assert np.abs((s.h + z)[wet] - C).max() <= 1e-12 * C
+    assert np.all(s.h[~wet] == 0.0)
+    assert np.abs(s.qx).max() <= 1e-12 and np.abs(s.qy).max() <= 1e-12
+
+
+def test_imposed_depth_rarefaction_closed_form():
+    # a channel at rest at depth h1 whose outlet imposes h2 < h1: a
+    # rarefaction enters the domain.  Across it u + 2c = 2 c1 (the invariant
+    # of the waves it does not belong to) and u - c = (x - L) / t, and next
+    # to the outlet the state is (h2, 2 (c1 - c2)) (fluvial here).
+    h1, h2, L, nx = 2.0, 1.5, 100.0, 400
+    dx = L / nx
+    wl = flat_workload(nx, 2, dx=dx, dy=dx, bc=(0, I.IMPOSED_H, 0, 0), bc_h=(0, h2, 0, 0))
+    wl.h[:] = h1
+    s = oracle.State(wl)
+    c1, c2 = math.sqrt(G * h1), math.sqrt(G * h2)
+    ub = 2.0 * (c1 - c2)
+    assert ub < c2
+    # the invariant gives the ghost the plateau state from the first step:
+    # within 45 steps the outlet cell holds it to 1e-3 (a ghost that takes
+    # the cell's velocity instead needs several times longer)
+    assert s.run(10 ** 6, 0.6) == 1
+    assert abs(s.h[0, -1] - h2) <= 1e-3 and abs(s.qx[0, -1] - h2 * ub) <= 0.02
+    assert s.run(10 ** 6, 4.0) == 1
+    x = (np.arange(nx) + 0.5) * dx
+    xi = (x - L) / s.t
+    c = np.clip((2.0 * c1 - xi) / 3.0, c2, c1)
+    he = c * c / G
+    qe = he * (2.0 * c1 - 2.0 * c)
+    plateau = x > L + (ub - c2) * s.t + 1.0
+    assert plateau.sum() >= 10
+    assert np.abs(s.h[:, plateau] - h2).max() <= 0.02
+    assert np.abs(s.qx[:, plateau] - h2 * ub).max() <= 0.04
+    assert np.abs(s.h - he[None, :]).mean() <= 0.004
+    assert np.abs(s.qx - qe[None, :]).mean() <= 0.01
