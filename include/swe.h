@@ -53,9 +53,26 @@ extern "C" {
 
 /* boundary types, Section 2.2: ghost cells.  WALL mirrors the boundary
  * cells (normal discharge negated); OUTFLOW copies the boundary cell (free,
- * zero-gradient outflow). */
+ * zero-gradient outflow).  The imposed types take the ghost state from the
+ * Riemann invariants (Section 2.2: one variable is imposed in fluvial flow,
+ * both in supercritical inflow, none in supercritical outflow).  With w the
+ * outward normal velocity of the boundary cell and c = sqrt(g h), the
+ * invariant w + 2c leaves the domain and the ghost keeps it:
+ *   IMPOSED_H   depth bc_h; the ghost's normal velocity from the invariant;
+ *   IMPOSED_Q   inflow discharge bc_q >= 0 per unit width; the ghost's depth
+ *               solves 2 sqrt(g h) - bc_q / h = w + 2c (fixed bisection);
+ *   IMPOSED_HQ  both (supercritical inflow).
+ * A boundary cell in supercritical outflow (w > c) has a free ghost (the
+ * copy) under every imposed type.  The tangential velocity is the cell's.
+ * Both ghost layers are equal; the bed of the ghosts is the cell's.  A
+ * supercritical inflow needs IMPOSED_HQ: under IMPOSED_H or IMPOSED_Q the
+ * invariant is still used but is then not carried out of the domain.
+ * Single contexts only (ensembles and the adjoint reject them). */
 #define SWE_BC_WALL 0
 #define SWE_BC_OUTFLOW 1
+#define SWE_BC_IMPOSED_H 2
+#define SWE_BC_IMPOSED_Q 3
+#define SWE_BC_IMPOSED_HQ 4
 
 /* friction laws, Section 2.1 */
 #define SWE_FRIC_NONE 0
@@ -82,6 +99,12 @@ typedef struct swe_params {
                             pairs it with cfl = 1); 0 or 2: MUSCL + Heun */
     int32_t flux;        /* numerical flux (Section 3.3): 0 HLL (the
                             paper's), 1 Rusanov (local Lax-Friedrichs) */
+    double bc_h[4];      /* imposed depth [m] per side (west, east, south,
+                            north), finite and > 0 where bc is IMPOSED_H or
+                            IMPOSED_HQ; ignored elsewhere */
+    double bc_q[4];      /* imposed inflow discharge [m^2/s] per side,
+                            finite and >= 0 where bc is IMPOSED_Q or
+                            IMPOSED_HQ; ignored elsewhere */
 } swe_params;
 
 /* Optional per-cell fields below are read only, [ny][nx] FP64 device

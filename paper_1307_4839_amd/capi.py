@@ -28,6 +28,9 @@ SWE_FLAG_DT = 4
 
 SWE_BC_WALL = 0
 SWE_BC_OUTFLOW = 1
+SWE_BC_IMPOSED_H = 2
+SWE_BC_IMPOSED_Q = 3
+SWE_BC_IMPOSED_HQ = 4
 SWE_FRIC_NONE = 0
 SWE_FRIC_MANNING = 1
 SWE_FRIC_DARCY = 2
@@ -42,7 +45,7 @@ class swe_params(C.Structure):
                 ("fric_coef", C.c_double), ("rain", C.c_double),
                 ("infil_on", C.c_int32), ("ks", C.c_double),
                 ("psi", C.c_double), ("dtheta", C.c_double), ("order", C.c_int32),
-                ("flux", C.c_int32)]
+                ("flux", C.c_int32), ("bc_h", C.c_double * 4), ("bc_q", C.c_double * 4)]
 
 
 class swe_buffers(C.Structure):
@@ -163,10 +166,13 @@ def check(code: int, where: str) -> int:
 def make_params(nx, ny, dx, dy, g=9.81, cfl=0.5, dt_max=float("inf"),
                 h_eps=1e-12, bc=(0, 0, 0, 0), fric_law=0, fric_coef=0.0,
                 rain=0.0, infil_on=0, ks=0.0, psi=0.0, dtheta=0.0, order=2,
-                flux=0) -> swe_params:
+                flux=0, bc_h=(0.0,) * 4, bc_q=(0.0,) * 4) -> swe_params:
     p = swe_params()
     p.order = int(order)
     p.flux = int(flux)
+    for k in range(4):
+        p.bc_h[k] = float(bc_h[k])
+        p.bc_q[k] = float(bc_q[k])
     p.nx, p.ny, p.dx, p.dy = nx, ny, dx, dy
     p.g, p.cfl, p.dt_max, p.h_eps = g, cfl, dt_max, h_eps
     for k in range(4):

@@ -1101,6 +1101,9 @@ int swe_adj_create(const swe_params* p, const swe_buffers* b, int32_t nsteps,
         return SWE_EINVAL;
     if (p->infil_on || p->fric_law == SWE_FRIC_NONE || p->order == 1 || p->flux != 0)
         return SWE_EINVAL;
+    // walls and free outflow only: the reverse pass has no imposed ghosts
+    for (int s = 0; s < 4; ++s)
+        if (p->bc[s] >= SWE_BC_IMPOSED_H) return SWE_EINVAL;
     // uniform rain only: the reverse pass has no rain or soil fields
     if (b->rain_w || b->ks || b->psi || b->dtheta) return SWE_EINVAL;
     if (nsteps < 1 || ckpt_every < 1 || ngauges < 1 || every < 1 || !gauges || !obs)

@@ -351,6 +351,8 @@ int swe_batch_create(const swe_params* p, const swe_buffers* bufs, int32_t count
         if (!b.h || !b.qx || !b.qy || !b.z) return SWE_EINVAL;
         // ensembles run the second-order scheme with the HLL flux
         if (p[k].order == 1 || p[k].flux != 0) return SWE_EINVAL;
+        for (int s = 0; s < 4; ++s)
+            if (p[k].bc[s] >= SWE_BC_IMPOSED_H) return SWE_EINVAL;
         if (p[k].infil_on && !b.vinf) return SWE_EINVAL;
     }
     swe_batch* b = new (std::nothrow) swe_batch;

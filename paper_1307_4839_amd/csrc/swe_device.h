@@ -83,6 +83,10 @@ struct KParams {
     int order;
     // 0: HLL; 1: Rusanov
     int flux;
+    // some side has an imposed depth or discharge; its values per side
+    // (west, east, south, north)
+    int imposed;
+    double bc_h[4], bc_q[4];
 };
 
 // ---------------------------------------------------------------------------
@@ -545,6 +549,7 @@ template <int STAGE> struct Fetch {
     double h, qx, qy, z;
     double ph, pqx, pqy, coef;
     double sy;  // sign applied to qy (wall ghost rows)
+    int ys;     // ghost row of an imposed south (2) or north (3) side, else -1
 };
 
 // rh = d.rcp(c.h); the numerators are bounded by the caller (note_cell)
@@ -593,12 +598,83 @@ __host__ __device__ __forceinline__ Prim to_y(const Prim& px) {
     return p;
 }
 
+// Ghost of a side with an imposed depth or inflow discharge (Section 2.2:
+// the ghost state from the Riemann invariants).  `o` holds the stage input
+// of the boundary cell and becomes the ghost.  w is the outward normal
+// velocity and c = sqrt(g h); the invariant w + 2c leaves the domain with
+// the characteristic w + c and the ghost keeps it.  A boundary cell in
+// supercritical outflow (w > c) keeps a free ghost (the copy).  Otherwise:
+// depth imposed, the ghost's w from the invariant; inflow discharge q_b
+// imposed, the ghost's depth h from 2 sqrt(g h) - q_b / h = w + 2c (increasing
+// in h) by a fixed bisection; both imposed (supercritical inflow), the
+// ghost is (h_b, q_b).  The tangential velocity is the cell's.  Every
+// operation is a correctly rounded IEEE one (plain quotients and roots), so
+// the ghost is reproducible bit for bit.
+__device__ __forceinline__ RawCell imposed_ghost(const KParams& p, int side, RawCell o) {
+    const bool xn = side < 2;
+    const double sg = (side & 1) ? 1.0 : -1.0;  // outward normal: -x, +x, -y, +y
+    const double hb = o.h;
+    const double qo = sg * (xn ? o.qx : o.qy);
+    const double qt = xn ? o.qy : o.qx;
+    const bool wet = hb > p.h_eps;
+    const double w = wet ? qo / hb : 0.0;
+    const double vt = wet ? qt / hb : 0.0;
+    const double c = sqrt(p.g * hb);
+    if (w > c) return o;
+    // constant indices only: a dynamic index into the kernel argument would
+    // copy it to scratch memory
+    const int type = side == 0 ? p.bcw : side == 1 ? p.bce : side == 2 ? p.bcs : p.bcn;
+    const double hbc = side == 0   ? p.bc_h[0]
+                       : side == 1 ? p.bc_h[1]
+                       : side == 2 ? p.bc_h[2]
+                                   : p.bc_h[3];
+    const double qbc = side == 0   ? p.bc_q[0]
+                       : side == 1 ? p.bc_q[1]
+                       : side == 2 ? p.bc_q[2]
+                                   : p.bc_q[3];
+    double hg, qog;
+    if (type == SWE_BC_IMPOSED_HQ) {
+        hg = hbc;
+        qog = -qbc;
+    } else if (type == SWE_BC_IMPOSED_H) {
+        hg = hbc;
+        const double wg = (w + 2.0 * c) - 2.0 * sqrt(p.g * hg);
+        qog = hg * wg;
+    } else {
+        const double qb = qbc;
+        const double R = w + 2.0 * c;
+        double hi = 1.0;
+        for (int k = 0; k < 200 && 2.0 * sqrt(p.g * hi) - qb / hi < R; ++k) hi = 2.0 * hi;
+        double lo = 0.0;
+        for (int k = 0; k < 100; ++k) {
+            const double mid = 0.5 * (lo + hi);
+            if (2.0 * sqrt(p.g * mid) - qb / mid < R) lo = mid;
+            else hi = mid;
+        }
+        hg = hi;
+        qog = -qb;
+    }
+    const double qtg = hg * vt;
+    o.h = hg;
+    if (xn) {
+        o.qx = sg * qog;
+        o.qy = qtg;
+    } else {
+        o.qy = sg * qog;
+        o.qx = qtg;
+    }
+    return o;
+}
+
 // Issue the loads of cell (row r, mapped column cs).
 template <int STAGE>
 __device__ __forceinline__ Fetch<STAGE> fetch(const MemberArgs& m, const TileIO& io, int r,
                                               int cs) {
     Fetch<STAGE> f;
     int rs = map_index(r, m.p.ny, m.p.bcs, m.p.bcn, f.sy);
+    f.ys = (r < 0 && r >= -HALO && m.p.bcs >= SWE_BC_IMPOSED_H)                ? 2
+           : (r >= m.p.ny && r < m.p.ny + HALO && m.p.bcn >= SWE_BC_IMPOSED_H) ? 3
+                                                                               : -1;
     size_t idx = (size_t)rs * m.p.nx + cs;
     f.h = io.h[idx];
     f.qx = io.qx[idx];
@@ -786,7 +862,21 @@ __device__ __forceinline__ int march(const MemberArgs& m, const TileIO& io, int 
 
     double sx;
     const int cs = map_index(c, p.nx, p.bcw, p.bce, sx);
+    // x-ghost column of an imposed west (0) or east (1) side
+    const int xside = !(FIELDS && p.imposed)                               ? -1
+                      : (c < 0 && p.bcw >= SWE_BC_IMPOSED_H)               ? 0
+                      : (c >= p.nx && c < p.nx + HALO && p.bce >= SWE_BC_IMPOSED_H) ? 1
+                                                                                    : -1;
     D d;
+    // stage input of a fetched cell, ghosts of imposed sides transformed
+    auto cell = [&](const Fetch<STAGE>& f) {
+        RawCell r = build<STAGE>(p, f, sx, dt, d);
+        if (FIELDS) {
+            const int side = xside >= 0 ? xside : (p.imposed ? f.ys : -1);
+            if (side >= 0) r = imposed_ghost(p, side, r);
+        }
+        return r;
+    };
     // X / dx and Y / dy: exact products when dx and dy are powers of two,
     // else quotients sharing the reciprocals of dx and dy
     const Recip Rdx = d.rcp(p.dx), Rdy = d.rcp(p.dy);
@@ -797,10 +887,10 @@ __device__ __forceinline__ int march(const MemberArgs& m, const TileIO& io, int 
     Fetch<STAGE> fC = fetch<STAGE>(m, io, y0, cs);
     Fetch<STAGE> fD = fetch<STAGE>(m, io, y0 + 1, cs);
     Fetch<STAGE> fnext = fetch<STAGE>(m, io, y0 + 2, cs);
-    RawCell rA = build<STAGE>(p, fA, sx, dt, d);
-    RawCell rB = build<STAGE>(p, fB, sx, dt, d);
-    RawCell rC = build<STAGE>(p, fC, sx, dt, d);
-    RawCell rD = build<STAGE>(p, fD, sx, dt, d);
+    RawCell rA = cell(fA);
+    RawCell rB = cell(fB);
+    RawCell rC = cell(fC);
+    RawCell rD = cell(fD);
     // reciprocals of the depths of rows j and j+1, shared by the velocities
     // and by both reconstructions of the cell
     Recip R0 = d.rcp(rC.h), R1 = d.rcp(rD.h);
@@ -854,7 +944,7 @@ __device__ __forceinline__ int march(const MemberArgs& m, const TileIO& io, int 
         if (STAGE == 2 && p.infil && out_col) vi = m.vinf[(size_t)j * p.nx + c];
 
         // ---- y direction, all in registers ----
-        RawCell r2 = build<STAGE>(p, f2, sx, dt, d);
+        RawCell r2 = cell(f2);
         Recip R2 = d.rcp(r2.h);
         Prim p2 = prim_x(r2, p.h_eps, R2, d);
         note_cell(d, r2, p2);
@@ -1088,7 +1178,8 @@ __device__ __forceinline__ void euler_cells(const MemberArgs& m, const TileIO& i
 }
 
 // Whether a simulation has any optional per-cell rain or soil field (its
-// stage-2 launches then take the FIELDS variant of the tile routine).
+// stage-2 launches then take the FIELDS variant of the tile routine, as do
+// both stages of a simulation with an imposed side).
 __host__ __device__ __forceinline__ bool has_fields(const MemberArgs& m) {
     return m.rain_w || m.ks_f || m.psi_f || m.dth_f;
 }
@@ -1100,7 +1191,8 @@ __host__ __device__ __forceinline__ bool has_fields(const MemberArgs& m) {
 // per simulation that does the scalar bookkeeping (time, step count, dt log,
 // clearing the next step's accumulators).
 // `spread` picks the accumulator pair of stage 1 (any block-dependent index).
-// FIELDS compiles in the reads of the optional rain and soil fields; ORDER 1
+// FIELDS compiles in the reads of the optional rain and soil fields and the
+// ghosts of imposed sides (imposed_ghost, when KParams::imposed); ORDER 1
 // (stage 1 only) replaces MUSCL by the cell values (first order); FLUX 1
 // takes the Rusanov flux instead of HLL; PHI2 (stage 2) also writes Phi(U*)
 // to io.ph2/pqx2/pqy2 (the adjoint keeps it).

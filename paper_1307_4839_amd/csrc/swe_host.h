@@ -28,8 +28,13 @@ inline int check_params(const swe_params* p) {
     if (!(p->dx > 0.0) || !(p->dy > 0.0) || !(p->g > 0.0) || !(p->cfl > 0.0))
         return SWE_EINVAL;
     if (!(p->h_eps >= 0.0) || !(p->dt_max > 0.0)) return SWE_EINVAL;
-    for (int k = 0; k < 4; ++k)
-        if (p->bc[k] != SWE_BC_WALL && p->bc[k] != SWE_BC_OUTFLOW) return SWE_EINVAL;
+    for (int k = 0; k < 4; ++k) {
+        if (p->bc[k] < SWE_BC_WALL || p->bc[k] > SWE_BC_IMPOSED_HQ) return SWE_EINVAL;
+        if (p->bc[k] == SWE_BC_IMPOSED_H || p->bc[k] == SWE_BC_IMPOSED_HQ)
+            if (!(p->bc_h[k] > 0.0) || !std::isfinite(p->bc_h[k])) return SWE_EINVAL;
+        if (p->bc[k] == SWE_BC_IMPOSED_Q || p->bc[k] == SWE_BC_IMPOSED_HQ)
+            if (!(p->bc_q[k] >= 0.0) || !std::isfinite(p->bc_q[k])) return SWE_EINVAL;
+    }
     if (p->fric_law < SWE_FRIC_NONE || p->fric_law > SWE_FRIC_DARCY) return SWE_EINVAL;
     if (p->infil_on && !(p->dtheta > 0.0)) return SWE_EINVAL;
     if (!(p->rain >= 0.0) || !std::isfinite(p->rain)) return SWE_EINVAL;
@@ -54,6 +59,12 @@ inline KParams to_kparams(const swe_params& p) {
     k.dx = p.dx; k.dy = p.dy; k.g = p.g; k.cfl = p.cfl; k.dt_max = p.dt_max;
     k.h_eps = p.h_eps;
     k.bcw = p.bc[0]; k.bce = p.bc[1]; k.bcs = p.bc[2]; k.bcn = p.bc[3];
+    k.imposed = 0;
+    for (int s = 0; s < 4; ++s) {
+        k.bc_h[s] = p.bc_h[s];
+        k.bc_q[s] = p.bc_q[s];
+        if (p.bc[s] >= SWE_BC_IMPOSED_H) k.imposed = 1;
+    }
     k.law = p.fric_law; k.coef = p.fric_coef; k.rain = p.rain;
     k.infil = p.infil_on; k.ks = p.ks; k.psi = p.psi; k.dtheta = p.dtheta;
     k.order = p.order == 1 ? 1 : 2;

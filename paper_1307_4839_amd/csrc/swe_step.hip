@@ -126,18 +126,24 @@ void launch_stage_t(int tx, dim3 grid, hipStream_t s, const MemberArgs& m, const
         launch_stage_tf<STAGE, FIELDS, ORDER, 0>(tx, grid, s, m, io, ty);
 }
 
-// Stage 1 never reads the rain and soil fields; the first-order scheme has
-// only stage 1 (its update is euler_kernel).
+// Stage 1 never reads the rain and soil fields: its FIELDS variant only
+// adds the ghosts of imposed sides.  The first-order scheme has only stage 1
+// (its update is euler_kernel).
 template <int STAGE>
 void launch_stage(int tx, dim3 grid, hipStream_t s, const MemberArgs& m, const TileIO& io,
                   int ty) {
     if constexpr (STAGE == 1) {
-        if (m.p.order == 1)
+        if (m.p.imposed) {
+            if (m.p.order == 1)
+                launch_stage_t<1, true, 1>(tx, grid, s, m, io, ty);
+            else
+                launch_stage_t<1, true, 2>(tx, grid, s, m, io, ty);
+        } else if (m.p.order == 1)
             launch_stage_t<1, false, 1>(tx, grid, s, m, io, ty);
         else
             launch_stage_t<1, false, 2>(tx, grid, s, m, io, ty);
     } else {
-        if (has_fields(m))
+        if (has_fields(m) || m.p.imposed)
             launch_stage_t<2, true, 2>(tx, grid, s, m, io, ty);
         else
             launch_stage_t<2, false, 2>(tx, grid, s, m, io, ty);

@@ -1,5 +1,6 @@
 """Host-side checks of the C-ABI library (no GPU needed, no compute calls)."""
 
+import math
 import os
 import re
 
@@ -147,6 +148,39 @@ def test_rusanov_limits_without_gpu():
     capi.swe_workspace_bytes(capi.make_params(8, 8, 1.0, 1.0, flux=1))
     p1 = capi.make_params(16, 16, 1.0, 1.0, fric_law=capi.SWE_FRIC_MANNING, fric_coef=0.03,
                           flux=1)
+    b = capi.swe_buffers()
+    b.h = b.qx = b.qy = b.z = b.fric = 4096
+    with pytest.raises(capi.SweError) as e:
+        capi.swe_adj_create(p1, b, 10, 3, 4096, 1, 5, 4096, 4096, 1 << 30, 0)
+    assert e.value.code == capi.SWE_EINVAL
+    with pytest.raises(capi.SweError) as e:
+        capi.swe_batch_create([p1], [b], 4096, 1 << 30, 0)
+    assert e.value.code == capi.SWE_EINVAL
+
+
+def test_imposed_boundary_limits_without_gpu():
+    # imposed depth finite and > 0, imposed discharge finite and >= 0 on the
+    # sides that use them; other sides ignore the values; ensembles and the
+    # adjoint reject imposed sides
+    from paper_1307_4839_amd import capi
+    H, Q, HQ = capi.SWE_BC_IMPOSED_H, capi.SWE_BC_IMPOSED_Q, capi.SWE_BC_IMPOSED_HQ
+    good = [dict(bc=(H, Q, HQ, 0), bc_h=(1.0, 0.0, 0.5, -3.0), bc_q=(-1.0, 2.0, 0.0, math.nan)),
+            dict(bc=(0, 1, Q, H), bc_h=(math.nan, 0, 0, 2.0), bc_q=(0, 0, 0.0, -1.0))]
+    for kw in good:
+        capi.swe_workspace_bytes(capi.make_params(8, 8, 1.0, 1.0, **kw))
+    bad = [dict(bc=(H, 0, 0, 0), bc_h=(0.0, 1, 1, 1)),
+           dict(bc=(0, HQ, 0, 0), bc_h=(1, -1.0, 1, 1), bc_q=(0, 1.0, 0, 0)),
+           dict(bc=(0, 0, H, 0), bc_h=(1, 1, math.inf, 1)),
+           dict(bc=(0, 0, 0, Q), bc_q=(0, 0, 0, -0.5)),
+           dict(bc=(0, 0, 0, HQ), bc_h=(0, 0, 0, 1.0), bc_q=(0, 0, 0, math.nan)),
+           dict(bc=(5, 0, 0, 0)),
+           dict(bc=(0, -1, 0, 0))]
+    for kw in bad:
+        with pytest.raises(capi.SweError) as e:
+            capi.swe_workspace_bytes(capi.make_params(8, 8, 1.0, 1.0, **kw))
+        assert e.value.code == capi.SWE_EINVAL
+    p1 = capi.make_params(16, 16, 1.0, 1.0, fric_law=capi.SWE_FRIC_MANNING, fric_coef=0.03,
+                          bc=(Q, H, 0, 0), bc_h=(0, 1.0, 0, 0), bc_q=(0.5, 0, 0, 0))
     b = capi.swe_buffers()
     b.h = b.qx = b.qy = b.z = b.fric = 4096
     with pytest.raises(capi.SweError) as e:
