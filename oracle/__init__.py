@@ -248,7 +248,8 @@ def hll(g, hL, unL, utL, hR, unR, utR):
 
 
 def face(g, hm, zm, unm, utm, hp, zp, unp, utp, flux=0):
-    """{F0, F1, F2, sL, sR, speed} of one face (flux 0 HLL, 1 Rusanov)."""
+    """{F0, F1, F2, sL, sR, speed} of one face (flux 0 HLL, 1 Rusanov,
+    2 kinetic)."""
     out = np.zeros(6)
     lib().orc_face(g, hm, zm, unm, utm, hp, zp, unp, utp, _dp(out), flux)
     return out

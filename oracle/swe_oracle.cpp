@@ -130,7 +130,8 @@ struct orc_params {
     // 1: first order (Section 3.3: piecewise-constant reconstruction, one
     // explicit Euler stage per step); 0 or 2: the second-order scheme
     int32_t order;
-    // numerical flux (Section 3.3 allows any consistent one): 0 HLL, 1 Rusanov
+    // numerical flux (Section 3.3 allows any consistent one): 0 HLL, 1 Rusanov,
+    // 2 kinetic
     int32_t flux;
     // imposed boundaries (bc 2: depth h_b, 3: inflow discharge q_b per unit
     // width, 4: both), per side west, east, south, north
@@ -262,12 +263,56 @@ inline void rusanov(double g, T hL, T unL, T utL, T hR, T unR, T utR, T F[3]) {
         F[k] = T(0.5) * (FL[k] + FR[k]) - T(0.5) * c * (UR[k] - UL[k]);
 }
 
+// Kinetic flux (Perthame and Simeoni, 2001; Audusse, Bristeau and Perthame,
+// 2000), another flux Section 3.3 lists.  A state (h, u) is the mean of
+// particles whose velocities xi spread uniformly over [u - s, u + s],
+// s = sqrt(3 g h / 2), with density h / (2 s): their moments are h, h u and
+// h u^2 + g h^2 / 2.  Particles with xi > 0 cross the face from the left
+// state and those with xi < 0 from the right one:
+//   F_h = int_{xi > 0} xi M_L + int_{xi < 0} xi M_R,
+//   F_q = int_{xi > 0} xi^2 M_L + int_{xi < 0} xi^2 M_R,
+// and the tangential momentum rides with the mass each side sends.  Over
+// [a, b]: int xi = (b^2 - a^2) / 2 and int xi^2 = (b^3 - a^3) / 3.  A dry
+// side (h = 0) sends nothing.
+template <class T>
+inline void kinetic_half(double g, T h, T un, bool left, T& m0, T& m1) {
+    if (!(h > T(0.0))) {
+        m0 = T(0.0);
+        m1 = T(0.0);
+        return;
+    }
+    T s = dsqrt(T(1.5 * g) * h);
+    T a = un - s;
+    T b = un + s;
+    if (left) {
+        a = vmax(a, T(0.0));
+        b = vmax(b, T(0.0));
+    } else {
+        a = vmin(a, T(0.0));
+        b = vmin(b, T(0.0));
+    }
+    m0 = (h * (b * b - a * a)) / (T(4.0) * s);
+    m1 = (h * (b * b * b - a * a * a)) / (T(6.0) * s);
+}
+
+template <class T>
+inline void kinetic(double g, T hL, T unL, T utL, T hR, T unR, T utR, T F[3]) {
+    T m0L, m1L, m0R, m1R;
+    kinetic_half(g, hL, unL, true, m0L, m1L);
+    kinetic_half(g, hR, unR, false, m0R, m1R);
+    F[0] = m0L + m0R;
+    F[1] = m1L + m1R;
+    F[2] = m0L * utL + m0R * utR;
+}
+
 // One face between a left cell (its "p" values) and a right cell (its "m"
-// values): hydrostatic reconstruction (Section 3.1), HLL (or Rusanov) flux and the two
+// values): hydrostatic reconstruction (Section 3.1), HLL (Rusanov, kinetic) flux and the two
 // normal-momentum corrections S_{i+1/2L} (for the left cell) and
 // S_{i+1/2R} (for the right cell).  Also returns the face's wave-speed bound
 // max(|u-| + sqrt(g h-), |u+| + sqrt(g h+)) on the MUSCL states, i.e. before
-// the hydrostatic reconstruction (eq. cfl and the remark after it).
+// the hydrostatic reconstruction (eq. cfl and the remark after it); with
+// the kinetic flux the bound is the particles' largest speed,
+// max(|u-| + sqrt(3 g h- / 2), |u+| + sqrt(3 g h+ / 2)).
 template <class T> struct Face {
     T F[3];
     T sL, sR;
@@ -285,12 +330,15 @@ inline Face<T> face(double g, T hm, T zm, T unm, T utm, T hp, T zp, T unp,
     // velocity is carried the same way (reading).
     if (flux == 1)
         rusanov(g, hL, unm, utm, hR, unp, utp, f.F);
+    else if (flux == 2)
+        kinetic(g, hL, unm, utm, hR, unp, utp, f.F);
     else
         hll(g, hL, unm, utm, hR, unp, utp, f.F);
     f.sL = T(0.5 * g) * (hm * hm - hL * hL);
     f.sR = T(0.5 * g) * (hp * hp - hR * hR);
-    double sm = std::fabs(val(unm)) + std::sqrt(g * val(hm));
-    double sp = std::fabs(val(unp)) + std::sqrt(g * val(hp));
+    const double gs = flux == 2 ? 1.5 * g : g;
+    double sm = std::fabs(val(unm)) + std::sqrt(gs * val(hm));
+    double sp = std::fabs(val(unp)) + std::sqrt(gs * val(hp));
     f.speed = sm < sp ? sp : sm;
     return f;
 }

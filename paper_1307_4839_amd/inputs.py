@@ -101,7 +101,7 @@ class Workload:
     # 2: MUSCL + Heun (the paper's scheme); 1: first order (piecewise
     # constant, one Euler stage; the paper uses n_CFL = 1 with it)
     order: int = 2
-    # numerical flux: 0 HLL (the paper's), 1 Rusanov
+    # numerical flux: 0 HLL (the paper's), 1 Rusanov, 2 kinetic
     flux: int = 0
     t_end: float = math.inf
     nsteps: int = 0

@@ -57,6 +57,11 @@ MUTANTS = {
                              "const double psi = p.psi;"),
     "ga_dtheta_field_ignored": ("const double dtheta = p.dtheta_f ? p.dtheta_f[s] : p.dtheta;",
                                 "const double dtheta = p.dtheta;"),
+    "kinetic_support_width": ("T s = dsqrt(T(1.5 * g) * h);", "T s = dsqrt(T(g) * h);"),
+    "kinetic_right_side_bound": ("        a = vmin(a, T(0.0));", "        a = vmax(a, T(0.0));"),
+    "kinetic_third_moment": ("/ (T(6.0) * s);", "/ (T(4.0) * s);"),
+    "kinetic_tangential_side": ("F[2] = m0L * utL + m0R * utR;", "F[2] = m0L * utL + m0R * utL;"),
+    "kinetic_cfl_speed": ("const double gs = flux == 2 ? 1.5 * g : g;", "const double gs = g;"),
     "imposed_outward_velocity_sign": ("T w = wet ? qo / hb : T(0.0);",
                                       "T w = wet ? -qo / hb : T(0.0);"),
     "imposed_h_invariant_dropped": ("T wg = (w + T(2.0) * c) - T(2.0) * dsqrt(T(g) * hg);",

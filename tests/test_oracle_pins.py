@@ -536,6 +536,92 @@ def test_rusanov_dam_breaks_converge():
 
 
 # ---------------------------------------------------------------------------
+# Kinetic flux (Section 3.3 lists it; the definition is Perthame and
+# Simeoni's with particle velocities uniform on [u - s, u + s],
+# s = sqrt(3 g h / 2)): the closed form against numerical quadrature of its
+# defining integrals, consistency, the lake at rest, positivity and
+# dam-break convergence.
+# ---------------------------------------------------------------------------
+
+def _kinetic_by_quadrature(hL, uL, vL, hR, uR, vR):
+    from scipy.integrate import quad
+    out = np.zeros(3)
+    for h, u, v, lo, hi in ((hL, uL, vL, 0.0, np.inf), (hR, uR, vR, -np.inf, 0.0)):
+        if h <= 0:
+            continue
+        s = math.sqrt(1.5 * G * h)
+        a, b = max(u - s, lo), min(u + s, hi)
+        if a >= b:
+            continue
+        rho = h / (2.0 * s)
+        m0 = quad(lambda x: x * rho, a, b, epsabs=0, epsrel=1e-13)[0]
+        m1 = quad(lambda x: x * x * rho, a, b, epsabs=0, epsrel=1e-13)[0]
+        out += (m0, m1, m0 * v)
+    return out
+
+
+def test_kinetic_face_against_quadrature_and_consistency():
+    rng = np.random.default_rng(41)
+    for k in range(60):
+        hL, hR = rng.uniform(0.01, 3.0, 2)
+        if k % 10 == 0:
+            hR = 0.0                               # dry right side
+        uL, uR = rng.normal(0, 4, 2)               # sub- and supercritical
+        vL, vR = rng.normal(0, 1, 2)
+        f = oracle.face(G, hL, 0.0, uL, vL, hR, 0.0, uR, vR, flux=2)
+        ref = _kinetic_by_quadrature(hL, uL, vL, hR, uR, vR)
+        scale = max(np.abs(ref).max(), 1e-12)
+        assert np.abs(f[:3] - ref).max() <= 1e-12 * scale, (k, f[:3], ref)
+        # the particles' largest speed bounds the time step
+        sp = max(abs(uL) + math.sqrt(1.5 * G * hL), abs(uR) + math.sqrt(1.5 * G * hR))
+        assert abs(f[5] - sp) <= 1e-15 * sp
+        # consistency: F(U, U) is the physical flux
+        h, u, v = hL, uL, vL
+        f = oracle.face(G, h, 0.3, u, v, h, 0.3, u, v, flux=2)
+        q = h * u
+        assert np.allclose(f[:3], [q, q * u + 0.5 * G * h * h, q * v], rtol=1e-13,
+                           atol=1e-14 * (abs(q) + G * h * h))
+        # mirrored states (a wall): no mass through the face
+        f = oracle.face(G, h, 0.3, u, v, h, 0.3, -u, v, flux=2)
+        assert abs(f[0]) <= 1e-15 * (abs(q) + h * math.sqrt(G * h))
+
+
+def test_kinetic_lake_at_rest_and_positivity():
+    C = 1.2
+    wl = _islands(40, 30, C, seed=13, bc=(0, 0, 0, 0))
+    wl.flux = 2
+    s = oracle.State(wl)
+    assert s.run(1000) == 0
+    wet = wl.h > 0
+    assert np.abs((s.h + s.z)[wet] - C).max() <= 1e-12 * C
+    assert np.abs(s.qx).max() <= 1e-12 * math.sqrt(G * wl.h.max() ** 3)
+    for wl in (I.dam_break_200(), I.random_state(48, 40, 6, bc=(0, 1, 1, 0),
+                                                 fric_law=I.FRIC_DARCY, fric_coef=0.2)):
+        for order, cfl in ((2, 0.5), (1, 1.0)):
+            wl.flux, wl.order, wl.cfl = 2, order, cfl
+            s = oracle.State(wl)
+            assert s.run(300, wl.t_end) in (0, 1)
+            assert s.h.min() >= 0.0
+
+
+def test_kinetic_dam_breaks_converge():
+    for h_down, exact in ((0.0, lambda x, t: ritter_h(x, t, 100.0, 1.0)),
+                          (0.1, lambda x, t: stoker_h(x, t, 100.0, 1.0, 0.1))):
+        errs = []
+        for n in (200, 400, 800):
+            dx = 200.0 / n
+            x = (np.arange(n) + 0.5) * dx
+            h = np.where(x < 100.0, 1.0, h_down)
+            wl = I.Workload("db", n, 2, dx, 1e9, z=np.zeros((2, n)), h=np.tile(h, (2, 1)),
+                            qx=np.zeros((2, n)), qy=np.zeros((2, n)), bc=(1, 1, 0, 0), flux=2)
+            s = oracle.State(wl)
+            assert s.run(10 ** 6, 10.0) == 1
+            errs.append(np.abs(s.h[0] - exact(x, 10.0)).sum() * dx)
+        orders = [math.log2(errs[k] / errs[k + 1]) for k in range(2)]
+        assert min(orders) >= 0.7, (h_down, errs, orders)
+
+
+# ---------------------------------------------------------------------------
 # P11: friction alone on a uniform flat state (Section 2.1 laws, Section 3.2
 # semi-implicit treatment): converges to the ODE solution
 #   Manning: q(t) = q0 / (1 + g n^2 q0 t / h^{7/3}),
