@@ -239,7 +239,7 @@ def flow_dir_leg(wl, reps):
 def variant_leg(wl, warmup, steps, order, flux):
     """The same workload with another scheme of Section 3.3: the first-order
     scheme (no reconstruction, one Euler stage, n_CFL = 1) and/or the
-    Rusanov flux.  Throughput and the average durations of the two kernels
+    Rusanov or kinetic flux.  Throughput and the average durations of the two kernels
     of a step (rate, then the update)."""
     import torch
 
@@ -267,7 +267,7 @@ def variant_leg(wl, warmup, steps, order, flux):
     del g
     torch.cuda.empty_cache()
     cells = wl.nx * wl.ny
-    name = f"{'first' if order == 1 else 'second'} order, {'Rusanov' if flux else 'HLL'}"
+    name = f"{'first' if order == 1 else 'second'} order, {('HLL', 'Rusanov', 'kinetic')[flux]}"
     print(f"[bench] {name}: {steps} steps in {ms:.1f} ms, t = {t_sim:.1f} s",
           file=sys.stderr, flush=True)
     return {"workload": f"{wl.name} {wl.nx}x{wl.ny}, {name}, cfl {w1.cfl}", "steps": steps,
@@ -335,7 +335,7 @@ def main(argv=None):
     ap.add_argument("--no-paper-runs", action="store_true")
     ap.add_argument("--no-flow-dir", action="store_true")
     ap.add_argument("--no-variants", action="store_true",
-                    help="skip the first-order and Rusanov runs")
+                    help="skip the first-order, Rusanov and kinetic runs")
     ap.add_argument("--flow-dir-reps", type=int, default=50)
     ap.add_argument("--paper-iterations", default="5000,20000")
     args = ap.parse_args(argv)
@@ -451,7 +451,8 @@ def main(argv=None):
     variants = None
     if not args.no_variants:
         variants = {"first_order_hll": variant_leg(wl, 300, 100, 1, 0),
-                    "second_order_rusanov": variant_leg(wl, 300, 100, 2, 1)}
+                    "second_order_rusanov": variant_leg(wl, 300, 100, 2, 1),
+                    "second_order_kinetic": variant_leg(wl, 300, 100, 2, 2)}
 
     fdir = None
     if not args.no_flow_dir:

@@ -98,7 +98,11 @@ typedef struct swe_params {
                             one explicit Euler stage per step; the paper
                             pairs it with cfl = 1); 0 or 2: MUSCL + Heun */
     int32_t flux;        /* numerical flux (Section 3.3): 0 HLL (the
-                            paper's), 1 Rusanov (local Lax-Friedrichs) */
+                            paper's), 1 Rusanov (local Lax-Friedrichs),
+                            2 kinetic (Perthame-Simeoni, particle velocities
+                            uniform on [u - s, u + s], s = sqrt(3gh/2); the
+                            time step then uses |u| + s as the speed).
+                            Ensembles and the adjoint take HLL only. */
     double bc_h[4];      /* imposed depth [m] per side (west, east, south,
                             north), finite and > 0 where bc is IMPOSED_H or
                             IMPOSED_HQ; ignored elsewhere */

@@ -278,14 +278,42 @@ __host__ __device__ __forceinline__ Rec reconstruct(const Prim& a, const Prim& c
 }
 
 // Flux through one face: hydrostatic reconstruction (Section 3.1), HLL
-// (Section 3.3; FLUX 1: the Rusanov flux, another consistent flux that
-// section lists), and the normal-momentum corrections S_L (left cell) and
-// S_R (right cell).  fl = flux seen by the left cell, fr = by the right one.
-// face_speed = max(|u-| + sqrt(g h-), |u+| + sqrt(g h+)) on the MUSCL
-// states (stage 1 only).
+// (Section 3.3; FLUX 1: the Rusanov flux, FLUX 2: the kinetic flux, two
+// other consistent fluxes that section lists), and the normal-momentum
+// corrections S_L (left cell) and S_R (right cell).  fl = flux seen by the
+// left cell, fr = by the right one.  face_speed = max(|u-| + sqrt(g h-),
+// |u+| + sqrt(g h+)) on the MUSCL states (stage 1 only); with the kinetic
+// flux, g is replaced by 3g/2 (the particles' largest speed).
 struct FaceOut {
     double f0, fl1, fr1, f2;
 };
+
+// Kinetic flux (Perthame and Simeoni, 2001): one side's share.  The state
+// (h, u) is the mean of particles with velocities uniform on [u - s, u + s],
+// s = sqrt(3 g h / 2), density h / (2 s); the left state sends those with
+// xi > 0, the right one those with xi < 0.  m0 = int xi M = h (b^2 - a^2) /
+// (4 s) and m1 = int xi^2 M = h (b^3 - a^3) / (6 s) over the part [a, b] of
+// the support on the sending side; a dry side sends nothing.  Plain
+// quotients and roots (correctly rounded), no shared reciprocals.
+template <bool LEFT>
+__host__ __device__ __forceinline__ void kinetic_half(double g, double h, double un, double& m0,
+                                                      double& m1) {
+    const double s = sqrt((1.5 * g) * h);
+    double a = un - s;
+    double b = un + s;
+    if (LEFT) {
+        a = fmax(a, 0.0);
+        b = fmax(b, 0.0);
+    } else {
+        a = fmin(a, 0.0);
+        b = fmin(b, 0.0);
+    }
+    const double n0 = h * (b * b - a * a);
+    const double n1 = h * (b * b * b - a * a * a);
+    const bool wet = h > 0.0;
+    m0 = wet ? n0 / (4.0 * s) : 0.0;
+    m1 = wet ? n1 / (6.0 * s) : 0.0;
+}
 
 // With depths, velocities and z capped at 2^60 and g at most 2^10, c1 and c2
 // stay below 2^62 and the HLL numerators below 2^251; den and the
@@ -309,7 +337,14 @@ __host__ __device__ __forceinline__ FaceOut face(double g, double hm, double zm,
     double FL0 = qL, FL1 = qL * unm + hg * hL * hL, FL2 = qL * utm;
     double FR0 = qR, FR1 = qR * unp + hg * hR * hR, FR2 = qR * utp;
     double F0, F1, F2;
-    if constexpr (FLUX == 1) {
+    if constexpr (FLUX == 2) {
+        double m0L, m1L, m0R, m1R;
+        kinetic_half<true>(g, hL, unm, m0L, m1L);
+        kinetic_half<false>(g, hR, unp, m0R, m1R);
+        F0 = m0L + m0R;
+        F1 = m1L + m1R;
+        F2 = m0L * utm + m0R * utp;
+    } else if constexpr (FLUX == 1) {
         // (F(U_L) + F(U_R))/2 - c/2 (U_R - U_L), c the largest local speed
         double c = vmax(fabs(unm) + cL, fabs(unp) + cR);
         F0 = 0.5 * (FL0 + FR0) - 0.5 * c * (hR - hL);
@@ -344,10 +379,11 @@ __host__ __device__ __forceinline__ FaceOut face(double g, double hm, double zm,
     return o;
 }
 
-template <class D>
+template <int FLUX, class D>
 __device__ __forceinline__ double face_speed(double g, double hm, double unm, double hp,
                                              double unp, D& d) {
-    double gm = g * hm, gp = g * hp;
+    const double gs = FLUX == 2 ? 1.5 * g : g;
+    double gm = gs * hm, gp = gs * hp;
     d.low2(gm, gp);
     double sm = fabs(unm) + d.root(gm);
     double sp = fabs(unp) + d.root(gp);
@@ -915,7 +951,7 @@ __device__ __forceinline__ int march(const MemberArgs& m, const TileIO& io, int 
         FaceOut gm = face<FLUX>(p.g, rprev.h_p, rprev.z_p, rprev.un_p, rprev.ut_p, rcur.h_m,
                           rcur.z_m, rcur.un_m, rcur.ut_m, d);
         if (STAGE == 1 && y0 == 0)
-            gm_speed = face_speed(p.g, rprev.h_p, rprev.un_p, rcur.h_m, rcur.un_m, d);
+            gm_speed = face_speed<FLUX>(p.g, rprev.h_p, rprev.un_p, rcur.h_m, rcur.un_m, d);
         gm0 = gm.f0;
         gm1 = gm.fr1;
         gm2 = gm.f2;
@@ -954,7 +990,7 @@ __device__ __forceinline__ int march(const MemberArgs& m, const TileIO& io, int 
                           rnext.un_m, rnext.ut_m, d);
         double gp_speed = 0.0;
         if (STAGE == 1)
-            gp_speed = face_speed(p.g, rcur.h_p, rcur.un_p, rnext.h_m, rnext.un_m, d);
+            gp_speed = face_speed<FLUX>(p.g, rcur.h_p, rcur.un_p, rnext.h_m, rnext.un_m, d);
         d.settle();
         double fcy = centred(p.g, rcur);
         double Y0 = gp.f0 - gm0;
@@ -994,7 +1030,7 @@ __device__ __forceinline__ int march(const MemberArgs& m, const TileIO& io, int 
         }
         FaceOut fp = face<FLUX>(p.g, rx.h_p, rx.z_p, rx.un_p, rx.ut_p, hm_r, zm_r, unm_r, utm_r, d);
         double fp_speed = 0.0;
-        if (STAGE == 1) fp_speed = face_speed(p.g, rx.h_p, rx.un_p, hm_r, unm_r, d);
+        if (STAGE == 1) fp_speed = face_speed<FLUX>(p.g, rx.h_p, rx.un_p, hm_r, unm_r, d);
         d.settle();
         double fm0, fm1, fm2;
         if (WAVE) {
@@ -1194,8 +1230,8 @@ __host__ __device__ __forceinline__ bool has_fields(const MemberArgs& m) {
 // FIELDS compiles in the reads of the optional rain and soil fields and the
 // ghosts of imposed sides (imposed_ghost, when KParams::imposed); ORDER 1
 // (stage 1 only) replaces MUSCL by the cell values (first order); FLUX 1
-// takes the Rusanov flux instead of HLL; PHI2 (stage 2) also writes Phi(U*)
-// to io.ph2/pqx2/pqy2 (the adjoint keeps it).
+// takes the Rusanov flux instead of HLL, FLUX 2 the kinetic flux; PHI2
+// (stage 2) also writes Phi(U*) to io.ph2/pqx2/pqy2 (the adjoint keeps it).
 template <int STAGE, int TXT, bool FIELDS = false, int ORDER = 2, int FLUX = 0,
           bool PHI2 = false>
 __device__ __forceinline__ void stage_tile(const MemberArgs& m, const TileIO& io, int strip,

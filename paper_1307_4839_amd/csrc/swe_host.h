@@ -40,7 +40,7 @@ inline int check_params(const swe_params* p) {
     if (!(p->rain >= 0.0) || !std::isfinite(p->rain)) return SWE_EINVAL;
     if ((size_t)p->nx * (size_t)p->ny > ((size_t)1 << 36)) return SWE_EINVAL;
     if (p->order < 0 || p->order > 2) return SWE_EINVAL;
-    if (p->flux < 0 || p->flux > 1) return SWE_EINVAL;
+    if (p->flux < 0 || p->flux > 2) return SWE_EINVAL;
     return SWE_OK;
 }
 

@@ -120,7 +120,9 @@ void launch_stage_tf(int tx, dim3 grid, hipStream_t s, const MemberArgs& m, cons
 template <int STAGE, bool FIELDS, int ORDER>
 void launch_stage_t(int tx, dim3 grid, hipStream_t s, const MemberArgs& m, const TileIO& io,
                     int ty) {
-    if (m.p.flux == 1)
+    if (m.p.flux == 2)
+        launch_stage_tf<STAGE, FIELDS, ORDER, 2>(tx, grid, s, m, io, ty);
+    else if (m.p.flux == 1)
         launch_stage_tf<STAGE, FIELDS, ORDER, 1>(tx, grid, s, m, io, ty);
     else
         launch_stage_tf<STAGE, FIELDS, ORDER, 0>(tx, grid, s, m, io, ty);

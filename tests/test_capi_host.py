@@ -139,15 +139,17 @@ def test_first_order_limits_without_gpu():
     assert e.value.code == capi.SWE_EINVAL
 
 
-def test_rusanov_limits_without_gpu():
-    # flux outside {0, 1} is invalid; ensembles and the adjoint take HLL only
+@pytest.mark.parametrize("flux", [1, 2])
+def test_flux_variant_limits_without_gpu(flux):
+    # flux outside {0, 1, 2} is invalid; ensembles and the adjoint take HLL
+    # only (Rusanov and kinetic are refused)
     from paper_1307_4839_amd import capi
-    for flux in (-1, 2):
+    for bad in (-1, 3):
         with pytest.raises(capi.SweError):
-            capi.swe_workspace_bytes(capi.make_params(8, 8, 1.0, 1.0, flux=flux))
-    capi.swe_workspace_bytes(capi.make_params(8, 8, 1.0, 1.0, flux=1))
+            capi.swe_workspace_bytes(capi.make_params(8, 8, 1.0, 1.0, flux=bad))
+    capi.swe_workspace_bytes(capi.make_params(8, 8, 1.0, 1.0, flux=flux))
     p1 = capi.make_params(16, 16, 1.0, 1.0, fric_law=capi.SWE_FRIC_MANNING, fric_coef=0.03,
-                          flux=1)
+                          flux=flux)
     b = capi.swe_buffers()
     b.h = b.qx = b.qy = b.z = b.fric = 4096
     with pytest.raises(capi.SweError) as e:

@@ -1,7 +1,7 @@
-"""GPU parity of the Rusanov flux (the alternative consistent flux of
-Section 3.3) with the oracle, through the C ABI: single rates on random
-states, whole runs at second and first order, with rain, Green-Ampt and the
-optional fields, over several tile shapes."""
+"""GPU parity of the Rusanov and kinetic fluxes (two other consistent
+fluxes Section 3.3 lists beside HLL) with the oracle, through the C ABI:
+single rates on random states, whole runs at second and first order, with
+rain, Green-Ampt and the optional fields, over several tile shapes."""
 
 import math
 import sys
@@ -33,9 +33,13 @@ def rel_err(a, b):
     return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
 
 
-def rusanov(wl, order=2):
+RUSANOV, KINETIC = 1, 2
+FLUXES = pytest.mark.parametrize("flux", [RUSANOV, KINETIC])
+
+
+def variant(wl, flux, order=2):
     wl = wl.copy()
-    wl.flux = 1
+    wl.flux = flux
     if order == 1:
         wl.order, wl.cfl = 1, 1.0
     return wl
@@ -43,7 +47,8 @@ def rusanov(wl, order=2):
 
 def compare(wl, nsteps, t_end=math.inf, tiling=None):
     from paper_1307_4839_amd.solver import Solver
-    say(f"[rusanov] {wl.name} {wl.nx}x{wl.ny} order={wl.order} steps={nsteps} tiling={tiling}")
+    say(f"[flux {wl.flux}] {wl.name} {wl.nx}x{wl.ny} order={wl.order} steps={nsteps} "
+        f"tiling={tiling}")
     s = oracle.State(wl)
     assert s.run(nsteps, t_end) in (0, 1)
     g = Solver(wl, dt_log=s.steps + 1)
@@ -67,13 +72,14 @@ def compare(wl, nsteps, t_end=math.inf, tiling=None):
     return s, st
 
 
+@FLUXES
 @pytest.mark.parametrize("order", [2, 1])
 @pytest.mark.parametrize("bc", [(0, 0, 0, 0), (1, 1, 1, 1), (0, 1, 1, 0)])
 @pytest.mark.parametrize("shape", [(37, 29), (300, 41), (2, 2)])
-def test_rate_random_state(torch_cuda, shape, bc, order):
+def test_rate_random_state(torch_cuda, shape, bc, order, flux):
     from paper_1307_4839_amd.solver import Solver
     nx, ny = shape
-    wl = rusanov(I.random_state(nx, ny, seed=nx * 5 + ny, bc=bc, dx=1.5, dy=0.7), order)
+    wl = variant(I.random_state(nx, ny, seed=nx * 5 + ny, bc=bc, dx=1.5, dy=0.7), flux, order)
     p = oracle.params_of(wl)
     ph, pqx, pqy, amax = oracle.rate(p, wl.h, wl.qx, wl.qy, wl.z)
     g = Solver(wl)
@@ -85,23 +91,32 @@ def test_rate_random_state(torch_cuda, shape, bc, order):
     g.close()
 
 
+@FLUXES
 @pytest.mark.parametrize("order", [2, 1])
-def test_dam_break_200_to_30s(torch_cuda, order):
-    s, _ = compare(rusanov(I.dam_break_200(), order), 10 ** 6, t_end=30.0)
+def test_dam_break_200_to_30s(torch_cuda, order, flux):
+    s, _ = compare(variant(I.dam_break_200(), flux, order), 10 ** 6, t_end=30.0)
     assert s.t == 30.0
 
 
+@FLUXES
 @pytest.mark.parametrize("tiling", [None, (64, 8), (128, 16)])
-def test_hillslope_rain_infiltration(torch_cuda, tiling):
-    compare(rusanov(I.hillslope_8192(260, 200)), 400, tiling=tiling)
+def test_hillslope_rain_infiltration(torch_cuda, tiling, flux):
+    compare(variant(I.hillslope_8192(260, 200), flux), 400, tiling=tiling)
 
 
-def test_valley_first_order(torch_cuda):
-    compare(rusanov(I.valley_2048(300, 320, dam_row=60), order=1), 300)
+@FLUXES
+def test_valley_first_order(torch_cuda, flux):
+    compare(variant(I.valley_2048(300, 320, dam_row=60), flux, order=1), 300)
 
 
-def test_fields_and_hyetograph(torch_cuda):
-    wl = rusanov(I.hillslope_8192(200, 150))
+@FLUXES
+def test_valley_second_order(torch_cuda, flux):
+    compare(variant(I.valley_2048(300, 320, dam_row=60), flux), 300)
+
+
+@FLUXES
+def test_fields_and_hyetograph(torch_cuda, flux):
+    wl = variant(I.hillslope_8192(200, 150), flux)
     rng = np.random.default_rng(9)
     wl.rain_t = np.array([0.0, 120.0])
     wl.rain_r = np.array([90.0, 30.0]) * I.MM_PER_HOUR

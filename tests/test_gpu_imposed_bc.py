@@ -2,9 +2,9 @@
 discharge or both imposed, the ghost from the Riemann invariants) with the
 oracle, through the C ABI: single rates on random states with every type on
 every side (fluvial, torrential and dry boundary cells), whole runs of the
-channel over a bump on all four sides and at both orders and fluxes,
-torrential inflow into a dry channel, a 2D valley with rain fields, and
-tile-shape invariance."""
+channel over a bump on all four sides, at both orders and with the three
+fluxes, torrential inflow into a dry channel, a 2D valley with rain fields,
+and tile-shape invariance."""
 
 import math
 import sys
@@ -95,7 +95,7 @@ BC_MIXES = [((H, Q, HQ, H), (1.2, 0.0, 0.4, 0.9), (0.0, 1.5, 2.5, 0.0)),
 
 
 @pytest.mark.parametrize("order", [2, 1])
-@pytest.mark.parametrize("flux", [0, 1])
+@pytest.mark.parametrize("flux", [0, 1, 2])
 @pytest.mark.parametrize("mix", range(len(BC_MIXES)))
 @pytest.mark.parametrize("shape", [(37, 29), (300, 41), (2, 2)])
 def test_rate_random_state(torch_cuda, shape, mix, flux, order):
@@ -122,7 +122,7 @@ def test_bump_every_side(torch_cuda, axis, flip):
     compare(bump(100, axis=axis, flip=flip), 10 ** 6, t_end=20.0)
 
 
-@pytest.mark.parametrize("order,flux", [(1, 0), (2, 1), (1, 1)])
+@pytest.mark.parametrize("order,flux", [(1, 0), (2, 1), (1, 1), (2, 2), (1, 2)])
 def test_bump_scheme_variants(torch_cuda, order, flux):
     compare(bump(100, order=order, flux=flux, cfl=1.0 if order == 1 else 0.5), 1500)
 
