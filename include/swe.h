@@ -318,6 +318,24 @@ int swe_adj_backward(swe_adj* a, double* grad);
  * (device, row-major), stream-ordered. */
 int swe_adj_get_series(swe_adj* a, double* out);
 
+/* Gauge recorder of a single context (Section 4.2: the water depth at
+ * gauges over time is the output the Malpasset validation compares).
+ * After every step that advances the simulation, when the number of steps
+ * taken since this call is a positive multiple k * every, h of the new state
+ * at each gauge cell goes to series[(k - 1) * ngauges + m] for k <= max_samples
+ * (later samples are dropped).  cells (int32 flat indices j * nx + i) and
+ * series (FP64, max_samples * ngauges) are caller-owned device arrays that
+ * must stay valid while recording; a cell index outside the grid records
+ * NaN.  ngauges = 0 stops recording.  Synchronizes (it reads the step
+ * count). */
+int swe_set_gauges(swe_ctx* ctx, const int32_t* cells, int32_t ngauges, int32_t every,
+                   double* series, int64_t max_samples);
+
+/* Number of samples recorded since swe_set_gauges (at most max_samples);
+ * copies min(that, max_copy) samples (ngauges values each) to the host
+ * array out when out is not NULL.  Synchronizes. */
+int swe_get_gauges(swe_ctx* ctx, double* out, int64_t max_copy, int64_t* nsamples);
+
 /* Human-readable text for an error code. */
 const char* swe_strerror(int code);
 

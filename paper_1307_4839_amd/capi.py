@@ -10,6 +10,9 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+from typing import Optional
+
+import numpy as np
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("SWE_LIB") or os.path.join(_PKG, "libswe_mi355x.so")
@@ -78,6 +81,9 @@ EXPORTS = {
                                      C.POINTER(C.c_double), C.c_int32]),
     "swe_set_dt_log": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64]),
     "swe_step": (C.c_int, [C.c_void_p, C.c_int32, C.c_double]),
+    "swe_set_gauges": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p,
+                                 C.c_int64]),
+    "swe_get_gauges": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(C.c_int64)]),
     "swe_get_time": (C.c_int, [C.c_void_p, C.POINTER(C.c_double),
                                C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "swe_get_status": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint32)]),
@@ -256,6 +262,25 @@ def swe_batch_set_hyetograph(b: int, member: int, t_pts, r) -> None:
 def swe_set_dt_log(ctx: int, ptr: int, capacity: int) -> None:
     check(lib().swe_set_dt_log(C.c_void_p(ctx), C.c_void_p(ptr), capacity),
           "swe_set_dt_log")
+
+
+def swe_set_gauges(ctx: int, cells_ptr: int, ngauges: int, every: int, series_ptr: int,
+                   max_samples: int) -> None:
+    check(lib().swe_set_gauges(C.c_void_p(ctx), C.c_void_p(cells_ptr), ngauges, every,
+                               C.c_void_p(series_ptr), max_samples), "swe_set_gauges")
+
+
+def swe_get_gauges(ctx: int, out: Optional[np.ndarray] = None) -> int:
+    """Samples recorded so far; fills out (float64, C-contiguous, rows of
+    ngauges values) with as many as fit."""
+    n = C.c_int64(0)
+    if out is None:
+        check(lib().swe_get_gauges(C.c_void_p(ctx), None, 0, C.byref(n)), "swe_get_gauges")
+    else:
+        assert out.dtype == np.float64 and out.flags.c_contiguous and out.ndim == 2
+        check(lib().swe_get_gauges(C.c_void_p(ctx), out.ctypes.data_as(C.c_void_p),
+                                   out.shape[0], C.byref(n)), "swe_get_gauges")
+    return n.value
 
 
 def swe_step(ctx: int, nsteps: int, t_end: float = float("inf")) -> None:

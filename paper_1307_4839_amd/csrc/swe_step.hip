@@ -186,9 +186,39 @@ struct swe_ctx {
     hipEvent_t* prof_ev;
     int prof_cap;
     int prof_n;
+    // gauge recorder (caller-owned device arrays); g_n = 0: off
+    const int32_t* g_cells;
+    int32_t g_n;
+    int32_t g_every;
+    double* g_series;
+    int64_t g_cap;
+    long long g_base;  // step count when the gauges were set
 };
 
 namespace {
+
+constexpr int GAUGE_T = 256;
+
+// Gauge samples after a step that read slot `slot`: the step advanced the
+// simulation when steps[slot ^ 1] (its count after) differs from
+// steps[slot] (before).  A count d = after - base that is a positive
+// multiple of `every` records sample k = d / every - 1 of h (the step's
+// output) at every gauge, while k < cap; a cell outside the grid records NaN.
+__global__ __launch_bounds__(GAUGE_T) void gauge_record_kernel(
+    const double* __restrict__ h, const int32_t* __restrict__ cells, int n, int every,
+    double* __restrict__ series, long long cap, const DevScalars* __restrict__ sc, int slot,
+    long long base, long long ncell) {
+    const long long after = sc->steps[slot ^ 1];
+    if (after == sc->steps[slot]) return;
+    const long long d = after - base;
+    if (d <= 0 || d % every != 0) return;
+    const long long k = d / every - 1;
+    if (k >= cap) return;
+    const int g = blockIdx.x * GAUGE_T + threadIdx.x;
+    if (g >= n) return;
+    const long long cell = cells[g];
+    series[k * n + g] = (cell >= 0 && cell < ncell) ? h[cell] : __builtin_nan("");
+}
 
 dim3 stage_grid(const swe_ctx* c) {
     return dim3(strips_of(c->prm.nx, c->tx), (c->prm.ny + c->ty - 1) / c->ty);
@@ -207,6 +237,12 @@ void enqueue_step(swe_ctx* c, int phase, double t_end, bool profile) {
     else
         launch_stage<2>(c->tx, grid, c->stream, c->m, io, c->ty);
     if (prof) (void)hipEventRecord(c->prof_ev[3 * c->prof_n++ + 2], c->stream);
+    if (c->g_n > 0)
+        hipLaunchKernelGGL(gauge_record_kernel, dim3((c->g_n + GAUGE_T - 1) / GAUGE_T),
+                           dim3(GAUGE_T), 0, c->stream, (const double*)io.ho, c->g_cells, c->g_n,
+                           c->g_every, c->g_series, (long long)c->g_cap,
+                           (const DevScalars*)c->m.sc, c->slot, c->g_base,
+                           (long long)ncells(&c->prm));
     c->slot ^= 1;
 }
 
@@ -408,6 +444,52 @@ int swe_set_dt_log(swe_ctx* c, double* dev_log, int64_t capacity) {
     c->m.dtlog = dev_log;
     c->m.dtlog_cap = dev_log ? capacity : 0;
     c->epoch++;
+    return SWE_OK;
+}
+
+int swe_set_gauges(swe_ctx* c, const int32_t* cells, int32_t ngauges, int32_t every,
+                   double* series, int64_t max_samples) {
+    if (!c || ngauges < 0) return SWE_EINVAL;
+    if (ngauges > 0 && (!cells || !series || every < 1 || max_samples < 1)) return SWE_EINVAL;
+    long long st = 0;
+    if (ngauges > 0) {
+        if (hipMemcpyAsync(&st, &c->m.sc->steps[c->slot], sizeof st, hipMemcpyDeviceToHost,
+                           c->stream) != hipSuccess ||
+            hipStreamSynchronize(c->stream) != hipSuccess)
+            return SWE_EHIP;
+    }
+    c->g_cells = ngauges > 0 ? cells : nullptr;
+    c->g_n = ngauges;
+    c->g_every = ngauges > 0 ? every : 1;
+    c->g_series = ngauges > 0 ? series : nullptr;
+    c->g_cap = ngauges > 0 ? max_samples : 0;
+    c->g_base = st;
+    c->epoch++;
+    return SWE_OK;
+}
+
+int swe_get_gauges(swe_ctx* c, double* out, int64_t max_copy, int64_t* nsamples) {
+    if (!c || max_copy < 0) return SWE_EINVAL;
+    if (c->g_n == 0) {
+        if (nsamples) *nsamples = 0;
+        return SWE_OK;
+    }
+    long long st = 0;
+    if (hipMemcpyAsync(&st, &c->m.sc->steps[c->slot], sizeof st, hipMemcpyDeviceToHost,
+                       c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+        return SWE_EHIP;
+    long long k = (st - c->g_base) / c->g_every;
+    if (k > c->g_cap) k = c->g_cap;
+    if (k < 0) k = 0;
+    if (nsamples) *nsamples = k;
+    const long long ncopy = k < max_copy ? k : max_copy;
+    if (out && ncopy > 0) {
+        if (hipMemcpyAsync(out, c->g_series, (size_t)ncopy * c->g_n * sizeof(double),
+                           hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+            hipStreamSynchronize(c->stream) != hipSuccess)
+            return SWE_EHIP;
+    }
     return SWE_OK;
 }
 

@@ -151,6 +151,29 @@ class Solver:
         if vinf is not None and self.vinf is not None:
             self.vinf.copy_(torch.as_tensor(np.asarray(vinf, dtype=np.float64)))
 
+    def set_gauges(self, cells, every: int, max_samples: int) -> None:
+        """Record h at the flat cell indices `cells` after every `every`
+        steps from now on (at most max_samples samples); empty cells stop
+        recording."""
+        cells = np.asarray(cells, dtype=np.int32).ravel()
+        if cells.size == 0:
+            capi.swe_set_gauges(self.ctx, 0, 0, 1, 0, 0)
+            self._gauge_cells = self._gauge_series = None
+            return
+        self._gauge_cells = torch.from_numpy(cells.copy()).to(self.device)
+        self._gauge_series = torch.full((max_samples, cells.size), math.nan,
+                                        dtype=torch.float64, device=self.device)
+        capi.swe_set_gauges(self.ctx, self._gauge_cells.data_ptr(), cells.size, every,
+                            self._gauge_series.data_ptr(), max_samples)
+
+    def gauges(self) -> np.ndarray:
+        """The samples recorded so far, one row of gauge depths each."""
+        if getattr(self, "_gauge_series", None) is None:
+            return np.zeros((0, 0))
+        out = np.empty(tuple(self._gauge_series.shape), dtype=np.float64)
+        n = capi.swe_get_gauges(self.ctx, out)
+        return out[:n]
+
     def dts(self, n: Optional[int] = None) -> np.ndarray:
         if self.dt_log is None:
             raise RuntimeError("no dt log")

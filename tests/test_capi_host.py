@@ -191,3 +191,14 @@ def test_imposed_boundary_limits_without_gpu():
     with pytest.raises(capi.SweError) as e:
         capi.swe_batch_create([p1], [b], 4096, 1 << 30, 0)
     assert e.value.code == capi.SWE_EINVAL
+
+
+def test_gauge_arguments_without_gpu():
+    # a null context or negative sizes are refused before any device work
+    from paper_1307_4839_amd import capi
+    with pytest.raises(capi.SweError) as e:
+        capi.swe_set_gauges(0, 4096, 3, 1, 4096, 10)
+    assert e.value.code == capi.SWE_EINVAL
+    with pytest.raises(capi.SweError) as e:
+        capi.swe_get_gauges(0)
+    assert e.value.code == capi.SWE_EINVAL
