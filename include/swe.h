@@ -141,6 +141,12 @@ typedef struct swe_diag {
     double infiltrated;  /* sum of vinf dx dy [m^3] */
     double h_min, h_max; /* extrema of h */
     int64_t wet_cells;   /* cells with h > h_eps */
+    double rain_in;      /* rain fallen on the domain since creation,
+                            sum over steps of dt r(t^n) sum(w) dx dy [m^3] */
+    double outflow;      /* net volume that left through the sides since
+                            creation: the balance water at creation + rain_in
+                            - (mass + infiltrated) of the conservative scheme
+                            (valid while only swe_step changes the state) */
 } swe_diag;
 
 /* Size in bytes of the device workspace a context needs for these

@@ -64,7 +64,8 @@ SWE_HYETO_MAX = 128
 class swe_diag(C.Structure):
     _fields_ = [("mass", C.c_double), ("infiltrated", C.c_double),
                 ("h_min", C.c_double), ("h_max", C.c_double),
-                ("wet_cells", C.c_int64)]
+                ("wet_cells", C.c_int64), ("rain_in", C.c_double),
+                ("outflow", C.c_double)]
 
 
 EXPORTS = {

@@ -53,6 +53,8 @@ struct DevScalars {
     double last_dt;
     unsigned int status;            // sticky SWE_FLAG_* bits
     unsigned int pad;
+    double rain_depth;              // sum over the steps taken of dt r(t^n)
+    double water0;                  // sum of h + V_inf when the context was made
     // hyetograph r(t): hy_r[k] from hy_t[k] (strictly increasing) up to the
     // next breakpoint, 0 before hy_t[0]; hy_n = 0: the constant rain of the
     // parameters
@@ -1173,6 +1175,7 @@ __device__ __forceinline__ bool begin_step(const MemberArgs& m, const TileIO& io
             m.sc->t[io.slot ^ 1] = tc + dt;
             m.sc->steps[io.slot ^ 1] = st + 1;
             m.sc->last_dt = dt;
+            m.sc->rain_depth += dt * rain;
             if (m.dtlog && st < m.dtlog_cap) m.dtlog[st] = dt;
         } else {
             m.sc->t[io.slot ^ 1] = tc;

@@ -186,6 +186,8 @@ static __global__ void swe_init_scalars_kernel(swe_dev::DevScalars* sc, double t
         sc->steps[1] = 0;
         sc->last_dt = 0.0;
         sc->status = 0u;
+        sc->rain_depth = 0.0;
+        sc->water0 = 0.0;
         sc->hy_n = 0;
     }
 }

@@ -63,11 +63,14 @@ __global__ __launch_bounds__(EULER_T) void euler_kernel(MemberArgs m, TileIO io)
 
 // Deterministic diagnostics: block b reduces the cells b, b + B, b + 2B, ...
 // in a fixed tree; a single block then combines the partials in order.
+// Also sums the rain weight (1 per cell without a weight field).
+constexpr int DIAG_N = 6;  // values per block: mass, V_inf, min, max, wet, weight
 __global__ __launch_bounds__(DIAG_T) void diag_partial_kernel(
-    const double* __restrict__ h, const double* __restrict__ vinf, double h_eps,
-    size_t n, double* __restrict__ part) {
-    __shared__ double s_m[DIAG_T], s_v[DIAG_T], s_lo[DIAG_T], s_hi[DIAG_T], s_w[DIAG_T];
-    double m = 0.0, v = 0.0, lo = INFINITY, hi = -INFINITY, w = 0.0;
+    const double* __restrict__ h, const double* __restrict__ vinf,
+    const double* __restrict__ rain_w, double h_eps, size_t n, double* __restrict__ part) {
+    __shared__ double s_m[DIAG_T], s_v[DIAG_T], s_lo[DIAG_T], s_hi[DIAG_T], s_w[DIAG_T],
+        s_r[DIAG_T];
+    double m = 0.0, v = 0.0, lo = INFINITY, hi = -INFINITY, w = 0.0, r = 0.0;
     for (size_t i = (size_t)blockIdx.x * DIAG_T + threadIdx.x; i < n;
          i += (size_t)gridDim.x * DIAG_T) {
         double x = h[i];
@@ -76,9 +79,10 @@ __global__ __launch_bounds__(DIAG_T) void diag_partial_kernel(
         lo = fmin(lo, x);
         hi = fmax(hi, x);
         if (x > h_eps) w += 1.0;
+        r += rain_w ? rain_w[i] : 1.0;
     }
     int t = threadIdx.x;
-    s_m[t] = m; s_v[t] = v; s_lo[t] = lo; s_hi[t] = hi; s_w[t] = w;
+    s_m[t] = m; s_v[t] = v; s_lo[t] = lo; s_hi[t] = hi; s_w[t] = w; s_r[t] = r;
     __syncthreads();
     for (int off = DIAG_T / 2; off > 0; off >>= 1) {
         if (t < off) {
@@ -87,23 +91,29 @@ __global__ __launch_bounds__(DIAG_T) void diag_partial_kernel(
             s_lo[t] = fmin(s_lo[t], s_lo[t + off]);
             s_hi[t] = fmax(s_hi[t], s_hi[t + off]);
             s_w[t] += s_w[t + off];
+            s_r[t] += s_r[t + off];
         }
         __syncthreads();
     }
     if (t == 0) {
-        double* o = part + (size_t)blockIdx.x * 5;
+        double* o = part + (size_t)blockIdx.x * DIAG_N;
         o[0] = s_m[0]; o[1] = s_v[0]; o[2] = s_lo[0]; o[3] = s_hi[0]; o[4] = s_w[0];
+        o[5] = s_r[0];
     }
 }
 
-__global__ void diag_final_kernel(double* part, int nb) {
+// Combines the partials in block order; with `sc`, also keeps the initial
+// water (h + V_inf) in the scalar block (the reference of the outflow).
+__global__ void diag_final_kernel(double* part, int nb, DevScalars* sc) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
-        double m = 0.0, v = 0.0, lo = INFINITY, hi = -INFINITY, w = 0.0;
+        double m = 0.0, v = 0.0, lo = INFINITY, hi = -INFINITY, w = 0.0, r = 0.0;
         for (int b = 0; b < nb; ++b) {
-            const double* o = part + (size_t)b * 5;
+            const double* o = part + (size_t)b * DIAG_N;
             m += o[0]; v += o[1]; lo = fmin(lo, o[2]); hi = fmax(hi, o[3]); w += o[4];
+            r += o[5];
         }
-        part[0] = m; part[1] = v; part[2] = lo; part[3] = hi; part[4] = w;
+        part[0] = m; part[1] = v; part[2] = lo; part[3] = hi; part[4] = w; part[5] = r;
+        if (sc) sc->water0 = m + v;
     }
 }
 
@@ -302,7 +312,7 @@ int swe_workspace_bytes(const swe_params* p, size_t* bytes) {
     if (!bytes) return SWE_EINVAL;
     size_t n = ncells(p);
     *bytes = SCALAR_BYTES + 6 * align256(n * sizeof(double)) +
-             align256((size_t)DIAG_BLOCKS * 5 * sizeof(double));
+             align256((size_t)DIAG_BLOCKS * DIAG_N * sizeof(double));
     return SWE_OK;
 }
 
@@ -343,6 +353,12 @@ int swe_create(const swe_params* p, const swe_buffers* b, void* workspace,
     c->tx = default_tx(p->nx, p->ny);
     c->ty = auto_rows(p->nx, p->ny, c->tx);
     hipLaunchKernelGGL(swe_init_scalars_kernel, dim3(1), dim3(64), 0, c->stream, m.sc, 0.0);
+    // the initial water, kept on the device for the outflow diagnostic
+    hipLaunchKernelGGL(diag_partial_kernel, dim3(DIAG_BLOCKS), dim3(DIAG_T), 0, c->stream,
+                       (const double*)m.h[0], (const double*)m.vinf, m.rain_w, p->h_eps, n,
+                       c->diag);
+    hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(64), 0, c->stream, c->diag,
+                       DIAG_BLOCKS, m.sc);
     rc = hip_ok(hipGetLastError());
     if (rc) { delete c; return rc; }
     *out = c;
@@ -553,12 +569,14 @@ int swe_get_diagnostics(swe_ctx* c, swe_diag* d) {
     if (!c || !d) return SWE_EINVAL;
     size_t n = ncells(&c->prm);
     hipLaunchKernelGGL(diag_partial_kernel, dim3(DIAG_BLOCKS), dim3(DIAG_T), 0, c->stream,
-                       (const double*)c->m.h[0], (const double*)c->m.vinf, c->prm.h_eps, n,
-                       c->diag);
+                       (const double*)c->m.h[0], (const double*)c->m.vinf, c->m.rain_w,
+                       c->prm.h_eps, n, c->diag);
     hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(64), 0, c->stream, c->diag,
-                       DIAG_BLOCKS);
-    double r[5];
-    if (hipMemcpyAsync(r, c->diag, sizeof r, hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+                       DIAG_BLOCKS, (DevScalars*)nullptr);
+    double r[DIAG_N];
+    DevScalars s;
+    if (hipMemcpyAsync(r, c->diag, sizeof r, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipMemcpyAsync(&s, c->m.sc, sizeof s, hipMemcpyDeviceToHost, c->stream) != hipSuccess)
         return SWE_EHIP;
     if (hipStreamSynchronize(c->stream) != hipSuccess) return SWE_EHIP;
     double area = c->prm.dx * c->prm.dy;
@@ -567,6 +585,8 @@ int swe_get_diagnostics(swe_ctx* c, swe_diag* d) {
     d->h_min = r[2];
     d->h_max = r[3];
     d->wet_cells = (int64_t)r[4];
+    d->rain_in = s.rain_depth * r[5] * area;
+    d->outflow = (s.water0 + s.rain_depth * r[5] - (r[0] + r[1])) * area;
     return SWE_OK;
 }
 

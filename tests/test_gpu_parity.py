@@ -207,6 +207,44 @@ def test_diagnostics(torch_cuda):
     assert d.wet_cells == int((st["h"] > 1e-12).sum())
 
 
+def _rain_rate(t_pts, r_pts, t):
+    # the hyetograph: the value of the last breakpoint at or before t
+    k = np.searchsorted(np.asarray(t_pts), t, side="right")
+    return 0.0 if k == 0 else float(r_pts[k - 1])
+
+
+@pytest.mark.parametrize("bc", [(0, 0, 0, 0), (0, 1, 0, 0)])
+def test_rain_in_and_outflow(torch_cuda, bc):
+    # rain fallen = sum of dt r(t) over the steps times the summed weight;
+    # outflow = the water balance; a walled basin loses nothing
+    wl = I.hillslope_8192(130, 90)
+    wl.bc = bc
+    rng = np.random.default_rng(4)
+    wl.rain_t = np.array([0.0, 40.0, 90.0])
+    wl.rain_r = np.array([200.0, 20.0, 120.0]) * I.MM_PER_HOUR
+    wl.rain_w = rng.uniform(0.5, 1.5, (wl.ny, wl.nx))
+    s = oracle.State(wl)
+    assert s.run(300) == 0
+    g = gpu_solver(wl)
+    g.step(300)
+    d = g.diagnostics()
+    area = wl.dx * wl.dy
+    t, depth = 0.0, 0.0
+    for dt in s.dts:
+        depth += dt * _rain_rate(wl.rain_t, wl.rain_r, t)
+        t += dt
+    rain_in = depth * wl.rain_w.sum() * area
+    assert abs(d.rain_in - rain_in) <= 1e-12 * rain_in
+    water0 = (wl.h.sum() + wl.vinf.sum()) * area
+    water = (s.h.sum() + s.vinf.sum()) * area
+    out = water0 + rain_in - water
+    assert abs(d.outflow - out) <= 1e-10 * (water0 + rain_in)
+    if bc[1] == 0:
+        assert abs(d.outflow) <= 1e-10 * (water0 + rain_in)
+    else:
+        assert d.outflow > 1e-3 * rain_in
+
+
 def test_status_flags(torch_cuda):
     from paper_1307_4839_amd import capi
     # non-finite input poisons dt and the state: sticky flag
