@@ -67,7 +67,7 @@ extern "C" {
  * Both ghost layers are equal; the bed of the ghosts is the cell's.  A
  * supercritical inflow needs IMPOSED_HQ: under IMPOSED_H or IMPOSED_Q the
  * invariant is still used but is then not carried out of the domain.
- * Single contexts only (ensembles and the adjoint reject them). */
+ * Single contexts and ensemble members (the adjoint rejects them). */
 #define SWE_BC_WALL 0
 #define SWE_BC_OUTFLOW 1
 #define SWE_BC_IMPOSED_H 2

@@ -121,29 +121,23 @@ void launch_batch_t(int tx, int grid, hipStream_t s, const MemberArgs* ms, const
 // stage 2 of an ensemble with any rain or soil field takes the FIELDS
 // variant (stage 1 never reads them)
 template <int STAGE>
+// `fields`: the FIELDS variant of the tile routine (some member has a rain
+// or soil field, stage 2 only, or an imposed side, both stages).
 void launch_batch(bool fields, int tx, int grid, hipStream_t s, const MemberArgs* ms,
                   const int4* tiles, int ntiles, int phase, int slot, double t_end) {
-    if constexpr (STAGE == 2) {
-        if (fields) {
-            launch_batch_t<2, true>(tx, grid, s, ms, tiles, ntiles, phase, slot, t_end);
-            return;
-        }
-    }
-    launch_batch_t<STAGE, false>(tx, grid, s, ms, tiles, ntiles, phase, slot, t_end);
+    if (fields)
+        launch_batch_t<STAGE, true>(tx, grid, s, ms, tiles, ntiles, phase, slot, t_end);
+    else
+        launch_batch_t<STAGE, false>(tx, grid, s, ms, tiles, ntiles, phase, slot, t_end);
 }
 
 template <int STAGE, int TXT>
 int resident_blocks(bool fields) {
     int nb = 0;
-    hipError_t e;
-    if constexpr (STAGE == 2)
-        e = fields ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                         &nb, batch_stage_kernel<2, TXT, true>, TXT, 0)
-                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                         &nb, batch_stage_kernel<2, TXT, false>, TXT, 0);
-    else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &nb, batch_stage_kernel<STAGE, TXT, false>, TXT, 0);
+    hipError_t e = fields ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                                &nb, batch_stage_kernel<STAGE, TXT, true>, TXT, 0)
+                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                                &nb, batch_stage_kernel<STAGE, TXT, false>, TXT, 0);
     if (e != hipSuccess) return 1;
     return nb < 1 ? 1 : nb;
 }
@@ -167,6 +161,7 @@ struct swe_batch {
     int slot;
     size_t max_cells;
     bool any_fields;              // some member has a rain or soil field
+    bool any_imposed;             // some member has an imposed side
     hipGraphExec_t graph;
     hipStream_t cap_stream;  // private stream used only to capture graphs
     int graph_slot;
@@ -203,12 +198,13 @@ int upload_members(swe_batch* b) {
 int persistent_grid(const swe_batch* b, int stage) {
     int nb;
     if (stage == 1)
-        nb = b->tx == 64 ? resident_blocks<1, 64>(false)
-             : b->tx == 128 ? resident_blocks<1, 128>(false) : resident_blocks<1, 256>(false);
+        nb = b->tx == 64 ? resident_blocks<1, 64>(b->any_imposed)
+             : b->tx == 128 ? resident_blocks<1, 128>(b->any_imposed)
+                            : resident_blocks<1, 256>(b->any_imposed);
     else
-        nb = b->tx == 64 ? resident_blocks<2, 64>(b->any_fields)
-             : b->tx == 128 ? resident_blocks<2, 128>(b->any_fields)
-                            : resident_blocks<2, 256>(b->any_fields);
+        nb = b->tx == 64 ? resident_blocks<2, 64>(b->any_fields || b->any_imposed)
+             : b->tx == 128 ? resident_blocks<2, 128>(b->any_fields || b->any_imposed)
+                            : resident_blocks<2, 256>(b->any_fields || b->any_imposed);
     long long g = (long long)nb * b->cus;
     if (g > b->ntiles) g = b->ntiles;
     return g < 1 ? 1 : (int)g;
@@ -246,10 +242,10 @@ int build_tiles(swe_batch* b, int tx, int ty) {
 }
 
 void enqueue_step(swe_batch* b, int phase, double t_end) {
-    launch_batch<1>(false, b->tx, b->grid1, b->stream, b->md, b->tiles, b->ntiles, phase, b->slot,
-                    t_end);
-    launch_batch<2>(b->any_fields, b->tx, b->grid2, b->stream, b->md, b->tiles, b->ntiles, phase, b->slot,
-                    t_end);
+    launch_batch<1>(b->any_imposed, b->tx, b->grid1, b->stream, b->md, b->tiles, b->ntiles,
+                    phase, b->slot, t_end);
+    launch_batch<2>(b->any_fields || b->any_imposed, b->tx, b->grid2, b->stream, b->md,
+                    b->tiles, b->ntiles, phase, b->slot, t_end);
     b->slot ^= 1;
 }
 
@@ -351,8 +347,6 @@ int swe_batch_create(const swe_params* p, const swe_buffers* bufs, int32_t count
         if (!b.h || !b.qx || !b.qy || !b.z) return SWE_EINVAL;
         // ensembles run the second-order scheme with the HLL flux
         if (p[k].order == 1 || p[k].flux != 0) return SWE_EINVAL;
-        for (int s = 0; s < 4; ++s)
-            if (p[k].bc[s] >= SWE_BC_IMPOSED_H) return SWE_EINVAL;
         if (p[k].infil_on && !b.vinf) return SWE_EINVAL;
     }
     swe_batch* b = new (std::nothrow) swe_batch;
@@ -369,6 +363,7 @@ int swe_batch_create(const swe_params* p, const swe_buffers* bufs, int32_t count
     b->graph_epoch = 0;
     b->max_cells = 0;
     b->any_fields = false;
+    b->any_imposed = false;
     char* w = (char*)workspace;
     b->md = (MemberArgs*)w;
     w += align256(sizeof(MemberArgs) * count);
@@ -388,6 +383,7 @@ int swe_batch_create(const swe_params* p, const swe_buffers* bufs, int32_t count
         m.vinf = p[k].infil_on ? bufs[k].vinf : nullptr;
         attach_fields(m, bufs[k]);
         if (has_fields(m)) b->any_fields = true;
+        if (m.p.imposed) b->any_imposed = true;
         m.sc = (DevScalars*)w; w += SCALAR_BYTES;
         m.h[0] = bufs[k].h; m.qx[0] = bufs[k].qx; m.qy[0] = bufs[k].qy;
         m.h[1] = (double*)w; w += an;

@@ -162,8 +162,8 @@ def test_flux_variant_limits_without_gpu(flux):
 
 def test_imposed_boundary_limits_without_gpu():
     # imposed depth finite and > 0, imposed discharge finite and >= 0 on the
-    # sides that use them; other sides ignore the values; ensembles and the
-    # adjoint reject imposed sides
+    # sides that use them; other sides ignore the values; the adjoint
+    # rejects imposed sides (ensembles take them)
     from paper_1307_4839_amd import capi
     H, Q, HQ = capi.SWE_BC_IMPOSED_H, capi.SWE_BC_IMPOSED_Q, capi.SWE_BC_IMPOSED_HQ
     good = [dict(bc=(H, Q, HQ, 0), bc_h=(1.0, 0.0, 0.5, -3.0), bc_q=(-1.0, 2.0, 0.0, math.nan)),
@@ -187,9 +187,6 @@ def test_imposed_boundary_limits_without_gpu():
     b.h = b.qx = b.qy = b.z = b.fric = 4096
     with pytest.raises(capi.SweError) as e:
         capi.swe_adj_create(p1, b, 10, 3, 4096, 1, 5, 4096, 4096, 1 << 30, 0)
-    assert e.value.code == capi.SWE_EINVAL
-    with pytest.raises(capi.SweError) as e:
-        capi.swe_batch_create([p1], [b], 4096, 1 << 30, 0)
     assert e.value.code == capi.SWE_EINVAL
 
 

@@ -4,7 +4,8 @@ oracle, through the C ABI: single rates on random states with every type on
 every side (fluvial, torrential and dry boundary cells), whole runs of the
 channel over a bump on all four sides, at both orders and with the three
 fluxes, torrential inflow into a dry channel, a 2D valley with rain fields,
-and tile-shape invariance."""
+tile-shape invariance, and ensemble members bit-identical to their own
+runs."""
 
 import math
 import sys
@@ -165,3 +166,25 @@ def test_valley_with_rain_fields_and_imposed_sides(torch_cuda):
     wl.rain_r = np.array([100.0, 300.0, 50.0]) * I.MM_PER_HOUR
     wl.rain_w = rng.uniform(0.5, 1.5, (wl.ny, wl.nx))
     compare(wl, 400)
+
+
+def test_ensemble_members_with_imposed_sides(torch_cuda):
+    # members with imposed sides (and one without) evolve in the ensemble
+    # exactly as in their own contexts
+    from paper_1307_4839_amd.solver import Ensemble, Solver
+    v = I.valley_2048(90, 110, dam_row=30)
+    v.bc, v.bc_h, v.bc_q = (0, 0, H, Q), (0.0, 0.0, 0.5, 0.0), (0.0, 0.0, 0.0, 0.2)
+    v.rain_w = np.random.default_rng(5).uniform(0.5, 1.5, (v.ny, v.nx))
+    wls = [bump(120, ny=9), I.ensemble_member(2, n=100), v, bump(70, ny=5, axis="y", flip=True)]
+    e = Ensemble(wls)
+    e.step(200)
+    rc, _ = e.status()
+    assert rc == 0
+    for k, wl in enumerate(wls):
+        g = Solver(wl)
+        g.step(200)
+        a, b = e.state(k), g.state()
+        for f in b:
+            assert np.array_equal(a[f], b[f]), (k, f)
+        g.close()
+    e.close()
