@@ -83,7 +83,7 @@ struct KParams {
     int fast_div;
     // 2: MUSCL + Heun; 1: first order (no reconstruction, one Euler stage)
     int order;
-    // 0: HLL; 1: Rusanov
+    // 0: HLL; 1: Rusanov; 2: kinetic
     int flux;
     // some side has an imposed depth or discharge; its values per side
     // (west, east, south, north)
