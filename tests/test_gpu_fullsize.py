@@ -45,7 +45,7 @@ def window_step(wl, st, j, i, dt):
                    fric_law=wl.fric_law, fric_coef=wl.fric_coef,
                    fric=None if wl.fric is None else np.ascontiguousarray(wl.fric[j0:j1, i0:i1]),
                    rain=wl.rain, infil_on=wl.infil_on, ks=wl.ks, psi=wl.psi,
-                   dtheta=wl.dtheta,
+                   dtheta=wl.dtheta, order=wl.order, flux=wl.flux,
                    vinf=None if "vinf" not in st else np.ascontiguousarray(st["vinf"][j0:j1, i0:i1]))
     s = oracle.State(w)
     s.step_fixed(dt)
@@ -103,6 +103,17 @@ def check_fullsize(wl, pre_steps, nsamples, seed):
 def test_fullsize_hillslope_8192():
     wl = I.hillslope_8192()
     check_fullsize(wl, 300, 200, seed=1)
+
+
+@pytest.mark.parametrize("order,flux", [(1, 0), (2, 1), (2, 2)])
+def test_fullsize_hillslope_8192_scheme_variants(order, flux):
+    # the variants bench.py times on the same workload: first order with HLL
+    # (n_CFL = 1), and the Rusanov and kinetic fluxes at second order
+    wl = I.hillslope_8192()
+    wl.order, wl.flux = order, flux
+    if order == 1:
+        wl.cfl = 1.0
+    check_fullsize(wl, 300, 100, seed=10 + 3 * order + flux)
 
 
 def test_fullsize_valley_2048():
