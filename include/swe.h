@@ -102,7 +102,9 @@ typedef struct swe_params {
                             2 kinetic (Perthame-Simeoni, particle velocities
                             uniform on [u - s, u + s], s = sqrt(3gh/2); the
                             time step then uses |u| + s as the speed).
-                            Ensembles and the adjoint take HLL only. */
+                            The adjoint takes the second-order HLL scheme
+                            only; the members of an ensemble share order
+                            and flux. */
     double bc_h[4];      /* imposed depth [m] per side (west, east, south,
                             north), finite and > 0 where bc is IMPOSED_H or
                             IMPOSED_HQ; ignored elsewhere */
@@ -237,7 +239,8 @@ int swe_profile_end(swe_ctx* ctx, double* ms_rate, double* ms_update,
  * Ensembles: `count` independent simulations of arbitrary (uneven) sizes
  * stepped together.  Member k has its own swe_params p[k] and caller-owned
  * buffers b[k] (same conventions as swe_create), its own time, time step
- * (its own CFL bound), status flags and rain.  One step of the ensemble is
+ * (its own CFL bound), status flags and rain; all members share the
+ * scheme (order and flux: SWE_EINVAL otherwise).  One step of the ensemble is
  * one persistent launch per stage over a work list of (member, strip, row
  * range) tiles; runs of 16 steps replay a captured HIP graph.  Every member
  * evolves exactly (bit for bit) as it would in its own context.

@@ -33,7 +33,7 @@ namespace {
 constexpr int GRAPH_STEPS = 16;  // steps per captured graph (even)
 constexpr int MIN_TY = 4;        // smallest rows per tile the work list is sized for
 
-template <int STAGE, int TXT, bool FIELDS>
+template <int STAGE, int TXT, bool FIELDS, int ORDER, int FLUX>
 __global__ __launch_bounds__(TXT) void batch_stage_kernel(const MemberArgs* __restrict__ ms,
                                                           const int4* __restrict__ tiles,
                                                           int ntiles, int phase, int slot,
@@ -44,7 +44,48 @@ __global__ __launch_bounds__(TXT) void batch_stage_kernel(const MemberArgs* __re
         // live in scratch memory, since its buffer pairs are indexed by phase
         const MemberArgs& m = ms[tl.x];
         const TileIO io = step_io(m, phase, slot, t_end);
-        stage_tile<STAGE, TXT, FIELDS>(m, io, tl.y, tl.z, tl.w, tl.y == 0 && tl.z == 0, k);
+        stage_tile<STAGE, TXT, FIELDS, ORDER, FLUX>(m, io, tl.y, tl.z, tl.w,
+                                                    tl.y == 0 && tl.z == 0, k);
+    }
+}
+
+// Update of the first-order scheme (Section 3.3: one explicit Euler stage,
+// U^{n+1} = friction(U^n + dt Phi(U^n)), then rain and Green-Ampt), tile by
+// tile over the same work list: the strip's output columns of each row.
+// The arithmetic is that of the single-context update (euler_cells).
+template <int TXT, bool FIELDS>
+__global__ __launch_bounds__(TXT) void batch_euler_kernel(const MemberArgs* __restrict__ ms,
+                                                          const int4* __restrict__ tiles,
+                                                          int ntiles, int phase, int slot,
+                                                          double t_end) {
+    constexpr int OUTW = TXT - 2 * HALO;
+    for (int k = blockIdx.x; k < ntiles; k += gridDim.x) {
+        const int4 tl = tiles[k];
+        const MemberArgs& m = ms[tl.x];
+        const KParams& p = m.p;
+        const TileIO io = step_io(m, phase, slot, t_end);
+        double dt, rain;
+        // every lane takes part (the hyetograph lookup uses wave ballots)
+        const bool go = begin_step(m, io, tl.y == 0 && tl.z == 0, dt, rain);
+        const int c = tl.y * OUTW + (int)threadIdx.x;
+        if ((int)threadIdx.x >= OUTW || c >= p.nx) continue;
+        for (int j = tl.z; j < tl.w; ++j) {
+            const size_t i = (size_t)j * p.nx + c;
+            if (!go) {
+                io.ho[i] = io.h[i];
+                io.qxo[i] = io.qx[i];
+                io.qyo[i] = io.qy[i];
+                continue;
+            }
+            const double h0 = io.h[i], qx0 = io.qx[i], qy0 = io.qy[i];
+            double h1 = h0 + dt * io.ph[i];
+            double qx1 = qx0 + dt * io.pqx[i];
+            double qy1 = qy0 + dt * io.pqy[i];
+            const double coef = m.fric ? m.fric[i] : p.coef;
+            friction(p, coef, h0, qx0, qy0, h1, qx1, qy1, dt);
+            const double vi = p.infil ? m.vinf[i] : 0.0;
+            finish_cell<FIELDS>(m, io, i, dt, rain, h1, qx1, qy1, vi);
+        }
     }
 }
 
@@ -99,45 +140,56 @@ __global__ void batch_backup_kernel(const MemberArgs* __restrict__ ms,
     }
 }
 
-template <int STAGE, bool FIELDS>
-void launch_batch_t(int tx, int grid, hipStream_t s, const MemberArgs* ms, const int4* tiles,
-                    int ntiles, int phase, int slot, double t_end) {
-    switch (tx) {
-        case 64:
-            hipLaunchKernelGGL((batch_stage_kernel<STAGE, 64, FIELDS>), dim3(grid), dim3(64), 0,
-                               s, ms, tiles, ntiles, phase, slot, t_end);
-            break;
-        case 128:
-            hipLaunchKernelGGL((batch_stage_kernel<STAGE, 128, FIELDS>), dim3(grid), dim3(128),
-                               0, s, ms, tiles, ntiles, phase, slot, t_end);
-            break;
-        default:
-            hipLaunchKernelGGL((batch_stage_kernel<STAGE, 256, FIELDS>), dim3(grid), dim3(256),
-                               0, s, ms, tiles, ntiles, phase, slot, t_end);
-            break;
+// The scheme of an ensemble (shared by its members) and whether the
+// FIELDS variant of the tile routine is needed: some member has a rain or
+// soil field (stage 2) or an imposed side (both stages).
+struct Variant {
+    bool fields;
+    int order;  // 1 or 2
+    int flux;   // 0 HLL, 1 Rusanov, 2 kinetic
+};
+
+using BatchKernel = void (*)(const MemberArgs*, const int4*, int, int, int, double);
+
+template <int STAGE, int TXT, bool FIELDS, int ORDER>
+BatchKernel pick_flux(int flux) {
+    if constexpr (STAGE == 2 && ORDER == 1) {
+        return batch_euler_kernel<TXT, FIELDS>;
+    } else {
+        switch (flux) {
+            case 1: return batch_stage_kernel<STAGE, TXT, FIELDS, ORDER, 1>;
+            case 2: return batch_stage_kernel<STAGE, TXT, FIELDS, ORDER, 2>;
+            default: return batch_stage_kernel<STAGE, TXT, FIELDS, ORDER, 0>;
+        }
     }
 }
 
-// stage 2 of an ensemble with any rain or soil field takes the FIELDS
-// variant (stage 1 never reads them)
-template <int STAGE>
-// `fields`: the FIELDS variant of the tile routine (some member has a rain
-// or soil field, stage 2 only, or an imposed side, both stages).
-void launch_batch(bool fields, int tx, int grid, hipStream_t s, const MemberArgs* ms,
-                  const int4* tiles, int ntiles, int phase, int slot, double t_end) {
-    if (fields)
-        launch_batch_t<STAGE, true>(tx, grid, s, ms, tiles, ntiles, phase, slot, t_end);
-    else
-        launch_batch_t<STAGE, false>(tx, grid, s, ms, tiles, ntiles, phase, slot, t_end);
+template <int STAGE, int TXT>
+BatchKernel pick_t(const Variant& v) {
+    if (v.fields)
+        return v.order == 1 ? pick_flux<STAGE, TXT, true, 1>(v.flux)
+                            : pick_flux<STAGE, TXT, true, 2>(v.flux);
+    return v.order == 1 ? pick_flux<STAGE, TXT, false, 1>(v.flux)
+                        : pick_flux<STAGE, TXT, false, 2>(v.flux);
 }
 
-template <int STAGE, int TXT>
-int resident_blocks(bool fields) {
+template <int STAGE>
+BatchKernel pick(int tx, const Variant& v) {
+    return tx == 64 ? pick_t<STAGE, 64>(v) : tx == 128 ? pick_t<STAGE, 128>(v)
+                                                       : pick_t<STAGE, 256>(v);
+}
+
+template <int STAGE>
+void launch_batch(const Variant& v, int tx, int grid, hipStream_t s, const MemberArgs* ms,
+                  const int4* tiles, int ntiles, int phase, int slot, double t_end) {
+    hipLaunchKernelGGL(pick<STAGE>(tx, v), dim3(grid), dim3(tx), 0, s, ms, tiles, ntiles, phase,
+                       slot, t_end);
+}
+
+template <int STAGE>
+int resident_blocks(int tx, const Variant& v) {
     int nb = 0;
-    hipError_t e = fields ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                                &nb, batch_stage_kernel<STAGE, TXT, true>, TXT, 0)
-                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                                &nb, batch_stage_kernel<STAGE, TXT, false>, TXT, 0);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pick<STAGE>(tx, v), tx, 0);
     if (e != hipSuccess) return 1;
     return nb < 1 ? 1 : nb;
 }
@@ -162,6 +214,7 @@ struct swe_batch {
     size_t max_cells;
     bool any_fields;              // some member has a rain or soil field
     bool any_imposed;             // some member has an imposed side
+    int order, flux;              // the members' scheme (shared)
     hipGraphExec_t graph;
     hipStream_t cap_stream;  // private stream used only to capture graphs
     int graph_slot;
@@ -195,16 +248,14 @@ int upload_members(swe_batch* b) {
     return SWE_OK;
 }
 
+Variant variant(const swe_batch* b, int stage) {
+    return Variant{stage == 1 ? b->any_imposed : (b->any_fields || b->any_imposed), b->order,
+                   b->flux};
+}
+
 int persistent_grid(const swe_batch* b, int stage) {
-    int nb;
-    if (stage == 1)
-        nb = b->tx == 64 ? resident_blocks<1, 64>(b->any_imposed)
-             : b->tx == 128 ? resident_blocks<1, 128>(b->any_imposed)
-                            : resident_blocks<1, 256>(b->any_imposed);
-    else
-        nb = b->tx == 64 ? resident_blocks<2, 64>(b->any_fields || b->any_imposed)
-             : b->tx == 128 ? resident_blocks<2, 128>(b->any_fields || b->any_imposed)
-                            : resident_blocks<2, 256>(b->any_fields || b->any_imposed);
+    const int nb = stage == 1 ? resident_blocks<1>(b->tx, variant(b, 1))
+                              : resident_blocks<2>(b->tx, variant(b, 2));
     long long g = (long long)nb * b->cus;
     if (g > b->ntiles) g = b->ntiles;
     return g < 1 ? 1 : (int)g;
@@ -242,10 +293,10 @@ int build_tiles(swe_batch* b, int tx, int ty) {
 }
 
 void enqueue_step(swe_batch* b, int phase, double t_end) {
-    launch_batch<1>(b->any_imposed, b->tx, b->grid1, b->stream, b->md, b->tiles, b->ntiles,
+    launch_batch<1>(variant(b, 1), b->tx, b->grid1, b->stream, b->md, b->tiles, b->ntiles,
                     phase, b->slot, t_end);
-    launch_batch<2>(b->any_fields || b->any_imposed, b->tx, b->grid2, b->stream, b->md,
-                    b->tiles, b->ntiles, phase, b->slot, t_end);
+    launch_batch<2>(variant(b, 2), b->tx, b->grid2, b->stream, b->md, b->tiles, b->ntiles,
+                    phase, b->slot, t_end);
     b->slot ^= 1;
 }
 
@@ -345,8 +396,9 @@ int swe_batch_create(const swe_params* p, const swe_buffers* bufs, int32_t count
     for (int k = 0; k < count; ++k) {
         const swe_buffers& b = bufs[k];
         if (!b.h || !b.qx || !b.qy || !b.z) return SWE_EINVAL;
-        // ensembles run the second-order scheme with the HLL flux
-        if (p[k].order == 1 || p[k].flux != 0) return SWE_EINVAL;
+        // the members share the scheme (order and flux): one kernel per stage
+        if ((p[k].order == 1) != (p[0].order == 1) || p[k].flux != p[0].flux)
+            return SWE_EINVAL;
         if (p[k].infil_on && !b.vinf) return SWE_EINVAL;
     }
     swe_batch* b = new (std::nothrow) swe_batch;
@@ -364,6 +416,8 @@ int swe_batch_create(const swe_params* p, const swe_buffers* bufs, int32_t count
     b->max_cells = 0;
     b->any_fields = false;
     b->any_imposed = false;
+    b->order = p[0].order == 1 ? 1 : 2;
+    b->flux = p[0].flux;
     char* w = (char*)workspace;
     b->md = (MemberArgs*)w;
     w += align256(sizeof(MemberArgs) * count);

@@ -121,8 +121,9 @@ def test_adjoint_rejects_rain_and_soil_fields_without_gpu():
 
 
 def test_first_order_limits_without_gpu():
-    # ensembles and the adjoint run the second-order scheme only; an order
-    # outside {0, 1, 2} is invalid (all checked before any device work)
+    # the adjoint runs the second-order scheme only and the members of an
+    # ensemble share it; an order outside {0, 1, 2} is invalid (all checked
+    # before any device work)
     from paper_1307_4839_amd import capi
     for order in (-1, 3):
         with pytest.raises(capi.SweError):
@@ -134,15 +135,16 @@ def test_first_order_limits_without_gpu():
     with pytest.raises(capi.SweError) as e:
         capi.swe_adj_create(p1, b, 10, 3, 4096, 1, 5, 4096, 4096, 1 << 30, 0)
     assert e.value.code == capi.SWE_EINVAL
+    p2 = capi.make_params(16, 16, 1.0, 1.0, fric_law=capi.SWE_FRIC_MANNING, fric_coef=0.03)
     with pytest.raises(capi.SweError) as e:
-        capi.swe_batch_create([p1], [b], 4096, 1 << 30, 0)
+        capi.swe_batch_create([p2, p1], [b, b], 4096, 1 << 30, 0)
     assert e.value.code == capi.SWE_EINVAL
 
 
 @pytest.mark.parametrize("flux", [1, 2])
 def test_flux_variant_limits_without_gpu(flux):
-    # flux outside {0, 1, 2} is invalid; ensembles and the adjoint take HLL
-    # only (Rusanov and kinetic are refused)
+    # flux outside {0, 1, 2} is invalid; the adjoint takes HLL only and the
+    # members of an ensemble share one flux
     from paper_1307_4839_amd import capi
     for bad in (-1, 3):
         with pytest.raises(capi.SweError):
@@ -155,8 +157,9 @@ def test_flux_variant_limits_without_gpu(flux):
     with pytest.raises(capi.SweError) as e:
         capi.swe_adj_create(p1, b, 10, 3, 4096, 1, 5, 4096, 4096, 1 << 30, 0)
     assert e.value.code == capi.SWE_EINVAL
+    p2 = capi.make_params(16, 16, 1.0, 1.0, fric_law=capi.SWE_FRIC_MANNING, fric_coef=0.03)
     with pytest.raises(capi.SweError) as e:
-        capi.swe_batch_create([p1], [b], 4096, 1 << 30, 0)
+        capi.swe_batch_create([p1, p2], [b, b], 4096, 1 << 30, 0)
     assert e.value.code == capi.SWE_EINVAL
 
 

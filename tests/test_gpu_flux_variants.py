@@ -123,3 +123,32 @@ def test_fields_and_hyetograph(torch_cuda, flux):
     wl.rain_w = rng.uniform(0.3, 1.7, (wl.ny, wl.nx))
     wl.psi_f = wl.psi * rng.uniform(0.5, 1.5, (wl.ny, wl.nx))
     compare(wl, 400)
+
+
+@pytest.mark.parametrize("order,flux", [(1, 0), (1, 1), (1, 2), (2, 1), (2, 2)])
+def test_ensemble_members_bit_identical(torch_cuda, order, flux):
+    # ensembles whose members share a scheme variant: each member evolves as
+    # in its own context (graph replays, an autotuned tiling, a member
+    # with rain and soil fields, one with imposed sides)
+    from paper_1307_4839_amd.solver import Ensemble, Solver
+    rng = np.random.default_rng(order * 10 + flux)
+    a = I.hillslope_8192(150, 90)
+    a.rain_w = rng.uniform(0.5, 1.5, (a.ny, a.nx))
+    a.ks_f = a.ks * rng.uniform(0.5, 1.5, (a.ny, a.nx))
+    c = I.valley_2048(90, 110, dam_row=30)
+    c.bc, c.bc_h, c.bc_q = (0, 0, I.IMPOSED_H, I.IMPOSED_Q), (0, 0, 0.5, 0), (0, 0, 0, 0.2)
+    wls = [variant(w, flux, order) for w in (a, I.ensemble_member(3, n=100), c)]
+    e = Ensemble(wls)
+    if order == 1:
+        e.autotune(4)
+    e.step(150)
+    rc, _ = e.status()
+    assert rc == 0
+    for k, wl in enumerate(wls):
+        g = Solver(wl)
+        g.step(150)
+        a_, b_ = e.state(k), g.state()
+        for f in b_:
+            assert np.array_equal(a_[f], b_[f]), (k, f)
+        g.close()
+    e.close()

@@ -181,6 +181,25 @@ def test_restart_bit_identical_gpu(torch_cuda):
     assert a.time()[0] == c.time()[0]
 
 
+def test_run_to_run_bit_identical(torch_cuda):
+    # the same run twice (thousands of blocks racing on the wave-speed
+    # accumulators, graph replays) gives the same bits, for every flux
+    for flux in (0, 1, 2):
+        wl = I.hillslope_8192(1500, 1100)
+        wl.rain = 150 * I.MM_PER_HOUR
+        wl.flux = flux
+        runs = []
+        for _ in range(2):
+            g = gpu_solver(wl)
+            g.step(330)
+            runs.append((g.state(), g.time()))
+            g.close()
+        (sa, ta), (sb, tb) = runs
+        assert ta == tb
+        for k in ("h", "qx", "qy", "vinf"):
+            assert np.array_equal(sa[k], sb[k]), (flux, k)
+
+
 def test_stop_at_t_end_and_odd_even_steps(torch_cuda):
     wl = I.dam_break_200(60, 50)
     s = oracle.State(wl)
