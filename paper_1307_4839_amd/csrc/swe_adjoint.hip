@@ -165,6 +165,7 @@ struct FaceBar {
     double hm, zm, unm, utm, hp, zp, unp, utp;
 };
 
+template <int FLUX = 0>
 __host__ __device__ __forceinline__ FaceBar face_rev(double g, double hm, double zm, double unm,
                                             double utm, double hp, double zp, double unp,
                                             double utp, double bF0, double bF1, double bF2,
@@ -200,7 +201,30 @@ __host__ __device__ __forceinline__ FaceBar face_rev(double g, double hm, double
     double bFL[3] = {0.0, 0.0, 0.0}, bFR[3] = {0.0, 0.0, 0.0};
     double bUL[3] = {0.0, 0.0, 0.0}, bUR[3] = {0.0, 0.0, 0.0};
     double bc1 = 0.0, bc2 = 0.0;
-    if (0.0 <= c1) {
+    double bcL = 0.0, bcR = 0.0;
+    if constexpr (FLUX == 1) {
+        // Rusanov: F = (F(U_L) + F(U_R))/2 - c/2 (U_R - U_L),
+        // c = max(|unm| + cL, |unp| + cR) (the first on ties; |x| takes the
+        // derivative sign(x), +1 at 0)
+        const double aL = fabs(unm) + cL, aR = fabs(unp) + cR;
+        const bool right = aL < aR;
+        const double c = right ? aR : aL;
+        double bc = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            bFL[k] = 0.5 * bF[k];
+            bFR[k] = 0.5 * bF[k];
+            bUR[k] = -0.5 * c * bF[k];
+            bUL[k] = 0.5 * c * bF[k];
+            bc -= 0.5 * bF[k] * (UR[k] - UL[k]);
+        }
+        if (right) {
+            o.unp += unp < 0.0 ? -bc : bc;
+            bcR += bc;
+        } else {
+            o.unm += unm < 0.0 ? -bc : bc;
+            bcL += bc;
+        }
+    } else if (0.0 <= c1) {
         for (int k = 0; k < 3; ++k) bFL[k] = bF[k];
     } else if (c2 <= 0.0) {
         for (int k = 0; k < 3; ++k) bFR[k] = bF[k];
@@ -245,8 +269,7 @@ __host__ __device__ __forceinline__ FaceBar face_rev(double g, double hm, double
     o.unm += bqL * hL;
     bhR += bqR * unp;
     o.unp += bqR * hR;
-    // c1 = min(unm - cL, unp - cR), c2 = max(unm + cL, unp + cR)
-    double bcL = 0.0, bcR = 0.0;
+    // c1 = min(unm - cL, unp - cR), c2 = max(unm + cL, unp + cR) (HLL)
     if (c1_b) { o.unp += bc1; bcR -= bc1; } else { o.unm += bc1; bcL -= bc1; }
     if (c2_b) { o.unp += bc2; bcR += bc2; } else { o.unm += bc2; bcL += bc2; }
     if (cL > 0.0) bhL += bcL * g / (2.0 * cL);
@@ -365,7 +388,7 @@ __host__ __device__ __forceinline__ RawCell load_raw(const double* h, const doub
 // contribution to component c (h, qx, qy) of the cell at position f-2+k
 // (ghost positions carry it to the cell they mirror, sign included): the
 // face itself and the centred source of its lower/left cell.
-template <int DIR>
+template <int DIR, int FLUX = 0>
 __host__ __device__ __forceinline__ void face_contrib_cells(const KParams& p, const RawCell r[4],
                                                             const double sgn[4], bool L_real,
                                                             bool R_real, const double muL[3],
@@ -391,8 +414,9 @@ __host__ __device__ __forceinline__ void face_contrib_cells(const KParams& p, co
         bR[1] = -(DIR == 0 ? muR[1] : muR[2]) / d;
         bR[2] = -(DIR == 0 ? muR[2] : muR[1]) / d;
     }
-    FaceBar fb = face_rev(p.g, RL.h_p, RL.z_p, RL.un_p, RL.ut_p, RR.h_m, RR.z_m, RR.un_m,
-                          RR.ut_m, bL[0] - bR[0], bL[1] - bR[1], bL[2] - bR[2], bL[1], -bR[1]);
+    FaceBar fb = face_rev<FLUX>(p.g, RL.h_p, RL.z_p, RL.un_p, RL.ut_p, RR.h_m, RR.z_m,
+                                RR.un_m, RR.ut_m, bL[0] - bR[0], bL[1] - bR[1], bL[2] - bR[2],
+                                bL[1], -bR[1]);
     RecBar RLb, RRb;
     zero(RLb);
     zero(RRb);
@@ -432,7 +456,7 @@ __host__ __device__ __forceinline__ void face_contrib_cells(const KParams& p, co
 // The same, loading the stencil: DIR 0: x-face f of row `line` (between
 // columns f-1 and f, f = 0..nx); DIR 1: y-face f of column `line` (between
 // rows f-1 and f, f = 0..ny).
-template <int DIR>
+template <int DIR, int FLUX = 0>
 __host__ __device__ __forceinline__ void face_contrib(const KParams& p, const double* z,
                                                       const double* h, const double* qx,
                                                       const double* qy, const double* mu_h,
@@ -470,7 +494,7 @@ __host__ __device__ __forceinline__ void face_contrib(const KParams& p, const do
         muR[1] = mu_qx[idx];
         muR[2] = mu_qy[idx];
     }
-    face_contrib_cells<DIR>(p, r, sgn, L_real, R_real, muL, muR, out);
+    face_contrib_cells<DIR, FLUX>(p, r, sgn, L_real, R_real, muL, muR, out);
 }
 
 // The face contributions addressed to cell (i, j), summed in a fixed order:
@@ -548,7 +572,7 @@ __host__ __device__ __forceinline__ void gather_cell(const KParams& p, const dou
 // and the reconstruction of row n-2, and completes row n-3, which no later
 // reconstruction touches.  Faces with no real cell on either side get zero
 // seeds, so their bars are exactly zero.
-template <int TXT>
+template <int TXT, int FLUX>
 __global__ __launch_bounds__(TXT) void adj_vjp_kernel(AdjArgs a, const double* __restrict__ h,
                                                       const double* __restrict__ qx,
                                                       const double* __restrict__ qy,
@@ -616,9 +640,9 @@ __global__ __launch_bounds__(TXT) void adj_vjp_kernel(AdjArgs a, const double* _
         const double b0 = -m[0] / p.dx, b1 = -m[1] / p.dx, b2 = -m[2] / p.dx;
         const double l0 = from_left(b0), l1 = from_left(b1), l2 = from_left(b2);
         // face c, between column c-1 (lane t-1, its p side) and c
-        const FaceBar fb = face_rev(p.g, from_left(R.h_p), from_left(R.z_p), from_left(R.un_p),
-                                    from_left(R.ut_p), R.h_m, R.z_m, R.un_m, R.ut_m, l0 - b0,
-                                    l1 - b1, l2 - b2, l1, -b1);
+        const FaceBar fb = face_rev<FLUX>(p.g, from_left(R.h_p), from_left(R.z_p),
+                                          from_left(R.un_p), from_left(R.ut_p), R.h_m, R.z_m,
+                                          R.un_m, R.ut_m, l0 - b0, l1 - b1, l2 - b2, l1, -b1);
         // this cell's reconstruction: m side from face c, p side from face
         // c+1 (lane t+1), and its centred source
         RecBar rb;
@@ -694,9 +718,10 @@ __global__ __launch_bounds__(TXT) void adj_vjp_kernel(AdjArgs a, const double* _
         if (n >= y0 - 1) R1 = muscl(P2, P1, P0, p.h_eps);
         if (n >= y0) {
             // face n-1, between rows n-2 (p side of R2) and n-1 (m side of R1)
-            const FaceBar fb = face_rev(p.g, R2.h_p, R2.z_p, R2.un_p, R2.ut_p, R1.h_m, R1.z_m,
-                                        R1.un_m, R1.ut_m, bY2[0] - bY1[0], bY2[1] - bY1[1],
-                                        bY2[2] - bY1[2], bY2[1], -bY1[1]);
+            const FaceBar fb = face_rev<FLUX>(p.g, R2.h_p, R2.z_p, R2.un_p, R2.ut_p, R1.h_m,
+                                              R1.z_m, R1.un_m, R1.ut_m, bY2[0] - bY1[0],
+                                              bY2[1] - bY1[1], bY2[2] - bY1[2], bY2[1],
+                                              -bY1[1]);
             M1.h_m = fb.hp; M1.z_m = fb.zp; M1.un_m = fb.unp; M1.ut_m = fb.utp;
             if (n >= y0 + 1) {
                 // row n-2's reconstruction: m side (face n-2), p side (face
@@ -872,11 +897,11 @@ __global__ void loss_kernel(const double* __restrict__ series, const double* __r
 
 // Forward stages of one tile grid (the same tile routine as the
 // single-simulation context).
-template <int STAGE, int TXT, bool PHI2>
+template <int STAGE, int TXT, bool PHI2, int FLUX>
 __global__ __launch_bounds__(TXT) void fwd_stage_kernel(MemberArgs m, TileIO io, int ty) {
     const int y0 = blockIdx.y * ty;
     const int y1 = min(y0 + ty, m.p.ny);
-    stage_tile<STAGE, TXT, false, 2, 0, PHI2>(m, io, blockIdx.x, y0, y1,
+    stage_tile<STAGE, TXT, false, 2, FLUX, PHI2>(m, io, blockIdx.x, y0, y1,
                                               blockIdx.x == 0 && blockIdx.y == 0,
                                               blockIdx.x + blockIdx.y * gridDim.x);
 }
@@ -888,11 +913,20 @@ void launch_fwd(const swe_params& prm, hipStream_t s, const MemberArgs& m, const
     const int tx = default_tx(prm.nx, prm.ny);
     const int ty = auto_rows(prm.nx, prm.ny, tx);
     const dim3 grid(strips_of(prm.nx, tx), (prm.ny + ty - 1) / ty);
-    if (tx == 64)
-        hipLaunchKernelGGL((fwd_stage_kernel<STAGE, 64, PHI2>), grid, dim3(64), 0, s, m, io, ty);
-    else
-        hipLaunchKernelGGL((fwd_stage_kernel<STAGE, 256, PHI2>), grid, dim3(256), 0, s, m, io,
+    if (prm.flux == 1) {
+        if (tx == 64)
+            hipLaunchKernelGGL((fwd_stage_kernel<STAGE, 64, PHI2, 1>), grid, dim3(64), 0, s, m,
+                               io, ty);
+        else
+            hipLaunchKernelGGL((fwd_stage_kernel<STAGE, 256, PHI2, 1>), grid, dim3(256), 0, s, m,
+                               io, ty);
+    } else if (tx == 64) {
+        hipLaunchKernelGGL((fwd_stage_kernel<STAGE, 64, PHI2, 0>), grid, dim3(64), 0, s, m, io,
                            ty);
+    } else {
+        hipLaunchKernelGGL((fwd_stage_kernel<STAGE, 256, PHI2, 0>), grid, dim3(256), 0, s, m, io,
+                           ty);
+    }
 }
 
 // Per-step reset of the time bookkeeping (the status flags stay sticky).
@@ -1023,10 +1057,16 @@ void vjp_rate(swe_adj* A, const double* h, const double* qx, const double* qy, d
     const int ty = vjp_rows(nx, ny);
     dim3 grid((nx + VJP_TX - 7) / (VJP_TX - 6), (ny + ty - 1) / ty);
     double* mu = A->mu;
-    hipLaunchKernelGGL(adj_vjp_kernel<VJP_TX>, grid, dim3(VJP_TX), 0, A->stream, A->aa, h, qx,
-                       qy, (const double*)plane(mu, n, 0), (const double*)plane(mu, n, 1),
-                       (const double*)plane(mu, n, 2), plane(lam, n, 0), plane(lam, n, 1),
-                       plane(lam, n, 2), ty);
+    if (A->prm.flux == 1)
+        hipLaunchKernelGGL((adj_vjp_kernel<VJP_TX, 1>), grid, dim3(VJP_TX), 0, A->stream, A->aa,
+                           h, qx, qy, (const double*)plane(mu, n, 0),
+                           (const double*)plane(mu, n, 1), (const double*)plane(mu, n, 2),
+                           plane(lam, n, 0), plane(lam, n, 1), plane(lam, n, 2), ty);
+    else
+        hipLaunchKernelGGL((adj_vjp_kernel<VJP_TX, 0>), grid, dim3(VJP_TX), 0, A->stream, A->aa,
+                           h, qx, qy, (const double*)plane(mu, n, 0),
+                           (const double*)plane(mu, n, 1), (const double*)plane(mu, n, 2),
+                           plane(lam, n, 0), plane(lam, n, 1), plane(lam, n, 2), ty);
 }
 
 // lamA <- adjoint of U^k given lam = adjoint of U^{k+1}; grad += dL/dn.
@@ -1099,7 +1139,8 @@ int swe_adj_create(const swe_params* p, const swe_buffers* b, int32_t nsteps,
     if (rc) return rc;
     if (!b || !out || !workspace || !b->h || !b->qx || !b->qy || !b->z || !b->fric)
         return SWE_EINVAL;
-    if (p->infil_on || p->fric_law == SWE_FRIC_NONE || p->order == 1 || p->flux != 0)
+    // the second-order scheme with the HLL or Rusanov flux
+    if (p->infil_on || p->fric_law == SWE_FRIC_NONE || p->order == 1 || p->flux > 1)
         return SWE_EINVAL;
     // walls and free outflow only: the reverse pass has no imposed ghosts
     for (int s = 0; s < 4; ++s)

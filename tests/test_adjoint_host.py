@@ -2,7 +2,7 @@
 
 The per-face and per-cell functions of the adjoint are __host__ __device__;
 tests/adjoint_host_emu.hip builds them for the CPU.  Checked against the
-oracle (no GPU needed):
+oracle (no GPU needed), with the HLL and the Rusanov flux:
   * the vector-Jacobian product of the convective rate equals central
     differences of the oracle's rate (three boundary mixes, ghost folding);
   * one full reverse step (Heun split, both frictions, both VJPs) gives
@@ -50,10 +50,12 @@ def vjp(L, cp, wl, U, mu):
     return out
 
 
+@pytest.mark.parametrize("flux", [0, 1])
 @pytest.mark.parametrize("bc", [(0, 0, 0, 0), (1, 1, 1, 1), (0, 1, 1, 0)])
-def test_rate_vjp_matches_oracle_differences(emu, bc):
+def test_rate_vjp_matches_oracle_differences(emu, bc, flux):
     rng = np.random.default_rng(0)
-    wl = I.random_state(23, 19, seed=4, bc=bc, dx=1.3, dy=0.8, dry_frac=0.0, film_frac=0.0)
+    wl = I.random_state(23, 19, seed=4, bc=bc, dx=1.3, dy=0.8, dry_frac=0.0, film_frac=0.0,
+                        flux=flux)
     p = oracle.params_of(wl)
     cp = capi.make_params(**wl.params())
     mu = [rng.standard_normal((wl.ny, wl.nx)) for _ in range(3)]
@@ -67,16 +69,19 @@ def test_rate_vjp_matches_oracle_differences(emu, bc):
     assert abs(lhs - rhs) <= 1e-6 * abs(lhs)
 
 
+@pytest.mark.parametrize("flux", [0, 1])
 @pytest.mark.parametrize("case", ["valley", "random"])
-def test_one_reverse_step_matches_oracle_tangent(emu, case):
+def test_one_reverse_step_matches_oracle_tangent(emu, case, flux):
     L = emu
     if case == "valley":
         wl = I.calibration_1024(40, 36, dam_row=10, ngauges=4, sigma_cells=3)
+        wl.flux = flux
         s = oracle.State(wl)
         s.run(15)
         wl.h, wl.qx, wl.qy = s.h.copy(), s.qx.copy(), s.qy.copy()
     else:
-        wl = I.random_state(30, 26, seed=3, bc=(1, 0, 0, 1), fric_law=1, fric_coef=0.04)
+        wl = I.random_state(30, 26, seed=3, bc=(1, 0, 0, 1), fric_law=1, fric_coef=0.04,
+                            flux=flux)
         wl.fric = 0.04 * (1 + 0.2 * I.smooth_field(np.random.default_rng(2), 30, 26, 3.0))
     p = oracle.params_of(wl)
     cp = capi.make_params(**wl.params())

@@ -63,6 +63,18 @@ def case_darcy():
     return wl, 0.3 + 0.1 * wl.extra["fric_obs"] / 0.03
 
 
+def case_rusanov_calibration():
+    wl = I.calibration_1024(96, 80, dam_row=20, ngauges=10, sigma_cells=4)
+    wl.flux = 1
+    return wl, wl.extra["fric_obs"]
+
+
+def case_rusanov_random_bcs():
+    wl, obs = case_random_bcs()
+    wl.flux = 1
+    return wl, obs
+
+
 def _small(nx, ny, bc, seed):
     def make():
         rng = np.random.default_rng(seed)
@@ -82,7 +94,8 @@ SMALL = [_small(2, 2, (0, 0, 0, 0), 41), _small(3, 5, (1, 1, 1, 1), 42),
          _small(130, 9, (0, 1, 0, 1), 45)]
 
 
-@pytest.mark.parametrize("make", [case_calibration, case_random_bcs, case_darcy] + SMALL)
+@pytest.mark.parametrize("make", [case_calibration, case_random_bcs, case_darcy,
+                                  case_rusanov_calibration, case_rusanov_random_bcs] + SMALL)
 def test_adjoint_against_oracle_tangent(torch_cuda, make):
     from paper_1307_4839_amd.solver import Calibration
     wl, fric_obs = make()
