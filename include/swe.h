@@ -102,9 +102,9 @@ typedef struct swe_params {
                             2 kinetic (Perthame-Simeoni, particle velocities
                             uniform on [u - s, u + s], s = sqrt(3gh/2); the
                             time step then uses |u| + s as the speed).
-                            The adjoint takes the second-order scheme with
-                            the HLL or Rusanov flux; the members of an
-                            ensemble share order and flux. */
+                            The adjoint takes the second-order scheme
+                            (any flux); the members of an ensemble share
+                            order and flux. */
     double bc_h[4];      /* imposed depth [m] per side (west, east, south,
                             north), finite and > 0 where bc is IMPOSED_H or
                             IMPOSED_HQ; ignored elsewhere */

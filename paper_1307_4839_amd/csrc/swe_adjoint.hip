@@ -159,6 +159,34 @@ __host__ __device__ __forceinline__ void prim_rev(const RawCell& r, double h_eps
     }
 }
 
+// Reverse of kinetic_half (one side of the kinetic flux): given the bars of
+// its two moments, adds those of the side's depth and normal velocity.  The
+// clamps of the support's ends at 0 take the derivative of the end itself
+// when it is kept (ties included, as the first argument of max/min).
+template <bool LEFT>
+__host__ __device__ __forceinline__ void kinetic_half_rev(double g, double h, double un,
+                                                          double bm0, double bm1, double& bh,
+                                                          double& bun) {
+    if (!(h > 0.0)) return;
+    const double g15 = 1.5 * g;
+    const double s = sqrt(g15 * h);
+    const double a0 = un - s, b0 = un + s;
+    const bool keep_a = LEFT ? !(a0 < 0.0) : !(0.0 < a0);
+    const bool keep_b = LEFT ? !(b0 < 0.0) : !(0.0 < b0);
+    const double a = keep_a ? a0 : 0.0, b = keep_b ? b0 : 0.0;
+    const double w2 = b * b - a * a, w3 = b * b * b - a * a * a;
+    const double i4 = 1.0 / (4.0 * s), i6 = 1.0 / (6.0 * s);
+    // m0 = h w2 / (4 s), m1 = h w3 / (6 s)
+    const double bw2 = bm0 * h * i4, bw3 = bm1 * h * i6;
+    double bs = -(bm0 * h * w2 * i4 + bm1 * h * w3 * i6) / s;
+    const double ba = -2.0 * a * bw2 - 3.0 * a * a * bw3;
+    const double bb = 2.0 * b * bw2 + 3.0 * b * b * bw3;
+    if (keep_a) { bun += ba; bs -= ba; }
+    if (keep_b) { bun += bb; bs += bb; }
+    // s = sqrt(3 g h / 2)
+    bh += bm0 * w2 * i4 + bm1 * w3 * i6 + bs * g15 / (2.0 * s);
+}
+
 // Reverse of face(): adjoints of the eight inputs given those of
 // (F0, F1, F2, s_L, s_R).
 struct FaceBar {
@@ -202,7 +230,16 @@ __host__ __device__ __forceinline__ FaceBar face_rev(double g, double hm, double
     double bUL[3] = {0.0, 0.0, 0.0}, bUR[3] = {0.0, 0.0, 0.0};
     double bc1 = 0.0, bc2 = 0.0;
     double bcL = 0.0, bcR = 0.0;
-    if constexpr (FLUX == 1) {
+    if constexpr (FLUX == 2) {
+        // kinetic: F0 = m0L + m0R, F1 = m1L + m1R, F2 = m0L utm + m0R utp
+        double m0L, m1L, m0R, m1R;
+        kinetic_half<true>(g, hL, unm, m0L, m1L);
+        kinetic_half<false>(g, hR, unp, m0R, m1R);
+        o.utm += bF[2] * m0L;
+        o.utp += bF[2] * m0R;
+        kinetic_half_rev<true>(g, hL, unm, bF[0] + bF[2] * utm, bF[1], bhL, o.unm);
+        kinetic_half_rev<false>(g, hR, unp, bF[0] + bF[2] * utp, bF[1], bhR, o.unp);
+    } else if constexpr (FLUX == 1) {
         // Rusanov: F = (F(U_L) + F(U_R))/2 - c/2 (U_R - U_L),
         // c = max(|unm| + cL, |unp| + cR) (the first on ties; |x| takes the
         // derivative sign(x), +1 at 0)
@@ -913,7 +950,14 @@ void launch_fwd(const swe_params& prm, hipStream_t s, const MemberArgs& m, const
     const int tx = default_tx(prm.nx, prm.ny);
     const int ty = auto_rows(prm.nx, prm.ny, tx);
     const dim3 grid(strips_of(prm.nx, tx), (prm.ny + ty - 1) / ty);
-    if (prm.flux == 1) {
+    if (prm.flux == 2) {
+        if (tx == 64)
+            hipLaunchKernelGGL((fwd_stage_kernel<STAGE, 64, PHI2, 2>), grid, dim3(64), 0, s, m,
+                               io, ty);
+        else
+            hipLaunchKernelGGL((fwd_stage_kernel<STAGE, 256, PHI2, 2>), grid, dim3(256), 0, s, m,
+                               io, ty);
+    } else if (prm.flux == 1) {
         if (tx == 64)
             hipLaunchKernelGGL((fwd_stage_kernel<STAGE, 64, PHI2, 1>), grid, dim3(64), 0, s, m,
                                io, ty);
@@ -1057,7 +1101,12 @@ void vjp_rate(swe_adj* A, const double* h, const double* qx, const double* qy, d
     const int ty = vjp_rows(nx, ny);
     dim3 grid((nx + VJP_TX - 7) / (VJP_TX - 6), (ny + ty - 1) / ty);
     double* mu = A->mu;
-    if (A->prm.flux == 1)
+    if (A->prm.flux == 2)
+        hipLaunchKernelGGL((adj_vjp_kernel<VJP_TX, 2>), grid, dim3(VJP_TX), 0, A->stream, A->aa,
+                           h, qx, qy, (const double*)plane(mu, n, 0),
+                           (const double*)plane(mu, n, 1), (const double*)plane(mu, n, 2),
+                           plane(lam, n, 0), plane(lam, n, 1), plane(lam, n, 2), ty);
+    else if (A->prm.flux == 1)
         hipLaunchKernelGGL((adj_vjp_kernel<VJP_TX, 1>), grid, dim3(VJP_TX), 0, A->stream, A->aa,
                            h, qx, qy, (const double*)plane(mu, n, 0),
                            (const double*)plane(mu, n, 1), (const double*)plane(mu, n, 2),
@@ -1139,9 +1188,8 @@ int swe_adj_create(const swe_params* p, const swe_buffers* b, int32_t nsteps,
     if (rc) return rc;
     if (!b || !out || !workspace || !b->h || !b->qx || !b->qy || !b->z || !b->fric)
         return SWE_EINVAL;
-    // the second-order scheme with the HLL or Rusanov flux
-    if (p->infil_on || p->fric_law == SWE_FRIC_NONE || p->order == 1 || p->flux > 1)
-        return SWE_EINVAL;
+    // the second-order scheme (any of the three fluxes)
+    if (p->infil_on || p->fric_law == SWE_FRIC_NONE || p->order == 1) return SWE_EINVAL;
     // walls and free outflow only: the reverse pass has no imposed ghosts
     for (int s = 0; s < 4; ++s)
         if (p->bc[s] >= SWE_BC_IMPOSED_H) return SWE_EINVAL;

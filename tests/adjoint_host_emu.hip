@@ -13,16 +13,18 @@ int emu_vjp(const swe_params* prm, const double* z, const double* h, const doubl
     size_t px = (size_t)ny * (nx + 1), py = (size_t)(ny + 1) * nx;
     std::vector<double> xc(12 * px), yc(12 * py);
     double out[12];
-    const bool rus = prm->flux == 1;
+    const int fl = prm->flux;
     for (int j = 0; j < ny; ++j)
         for (int f = 0; f <= nx; ++f) {
-            if (rus) face_contrib<0, 1>(p, z, h, qx, qy, mh, mqx, mqy, f, j, out);
+            if (fl == 2) face_contrib<0, 2>(p, z, h, qx, qy, mh, mqx, mqy, f, j, out);
+            else if (fl == 1) face_contrib<0, 1>(p, z, h, qx, qy, mh, mqx, mqy, f, j, out);
             else face_contrib<0, 0>(p, z, h, qx, qy, mh, mqx, mqy, f, j, out);
             for (int k = 0; k < 12; ++k) xc[k * px + (size_t)j * (nx + 1) + f] = out[k];
         }
     for (int i = 0; i < nx; ++i)
         for (int f = 0; f <= ny; ++f) {
-            if (rus) face_contrib<1, 1>(p, z, h, qx, qy, mh, mqx, mqy, f, i, out);
+            if (fl == 2) face_contrib<1, 2>(p, z, h, qx, qy, mh, mqx, mqy, f, i, out);
+            else if (fl == 1) face_contrib<1, 1>(p, z, h, qx, qy, mh, mqx, mqy, f, i, out);
             else face_contrib<1, 0>(p, z, h, qx, qy, mh, mqx, mqy, f, i, out);
             for (int k = 0; k < 12; ++k) yc[k * py + (size_t)f * nx + i] = out[k];
         }

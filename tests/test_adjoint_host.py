@@ -2,7 +2,7 @@
 
 The per-face and per-cell functions of the adjoint are __host__ __device__;
 tests/adjoint_host_emu.hip builds them for the CPU.  Checked against the
-oracle (no GPU needed), with the HLL and the Rusanov flux:
+oracle (no GPU needed), with the HLL, Rusanov and kinetic fluxes:
   * the vector-Jacobian product of the convective rate equals central
     differences of the oracle's rate (three boundary mixes, ghost folding);
   * one full reverse step (Heun split, both frictions, both VJPs) gives
@@ -50,7 +50,7 @@ def vjp(L, cp, wl, U, mu):
     return out
 
 
-@pytest.mark.parametrize("flux", [0, 1])
+@pytest.mark.parametrize("flux", [0, 1, 2])
 @pytest.mark.parametrize("bc", [(0, 0, 0, 0), (1, 1, 1, 1), (0, 1, 1, 0)])
 def test_rate_vjp_matches_oracle_differences(emu, bc, flux):
     rng = np.random.default_rng(0)
@@ -69,7 +69,7 @@ def test_rate_vjp_matches_oracle_differences(emu, bc, flux):
     assert abs(lhs - rhs) <= 1e-6 * abs(lhs)
 
 
-@pytest.mark.parametrize("flux", [0, 1])
+@pytest.mark.parametrize("flux", [0, 1, 2])
 @pytest.mark.parametrize("case", ["valley", "random"])
 def test_one_reverse_step_matches_oracle_tangent(emu, case, flux):
     L = emu

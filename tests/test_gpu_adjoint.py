@@ -75,6 +75,18 @@ def case_rusanov_random_bcs():
     return wl, obs
 
 
+def case_kinetic_calibration():
+    wl = I.calibration_1024(96, 80, dam_row=20, ngauges=10, sigma_cells=4)
+    wl.flux = 2
+    return wl, wl.extra["fric_obs"]
+
+
+def case_kinetic_random_bcs():
+    wl, obs = case_random_bcs()
+    wl.flux = 2
+    return wl, obs
+
+
 def _small(nx, ny, bc, seed):
     def make():
         rng = np.random.default_rng(seed)
@@ -95,7 +107,8 @@ SMALL = [_small(2, 2, (0, 0, 0, 0), 41), _small(3, 5, (1, 1, 1, 1), 42),
 
 
 @pytest.mark.parametrize("make", [case_calibration, case_random_bcs, case_darcy,
-                                  case_rusanov_calibration, case_rusanov_random_bcs] + SMALL)
+                                  case_rusanov_calibration, case_rusanov_random_bcs,
+                                  case_kinetic_calibration, case_kinetic_random_bcs] + SMALL)
 def test_adjoint_against_oracle_tangent(torch_cuda, make):
     from paper_1307_4839_amd.solver import Calibration
     wl, fric_obs = make()
