@@ -233,6 +233,34 @@ def flow_dir_leg(wl, reps):
               file=sys.stderr, flush=True)
         del z, code
     torch.cuda.empty_cache()
+    # the paper's own flow-direction size (14786 x 10086 float DEM; it
+    # reports 31 s with SkelGIS and 101 s with SkeTo on hardware it does not
+    # name): a seeded ramp with noise, timed the same way
+    ny, nx = 10086, 14786
+    gen = torch.Generator(device="cuda:0")
+    gen.manual_seed(1307)
+    z = torch.rand((ny, nx), generator=gen, device="cuda:0", dtype=torch.float32)
+    z += torch.linspace(0.0, 50.0, nx, device="cuda:0", dtype=torch.float32)[None, :]
+    code = torch.empty((ny, nx), dtype=torch.uint8, device="cuda:0")
+    for _ in range(3):
+        flow_directions(z, out=code)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        flow_directions(z, out=code)
+    e1.record()
+    torch.cuda.synchronize()
+    avg = e0.elapsed_time(e1) / reps
+    out["paper_size_f32"] = {"workload": f"seeded ramp + noise {nx}x{ny}", "avg_ms": avg,
+                             "cells_per_s": nx * ny / (avg / 1e3),
+                             "GBps": 5 * nx * ny / (avg / 1e3) / 1e9,
+                             "paper_s_context": {"SkelGIS": 31.0, "SkeTo": 101.0}}
+    print(f"[bench] flow directions f32 at the paper's {nx}x{ny}: {avg * 1e3:.1f} us/launch "
+          f"(the paper: 31 s SkelGIS, 101 s SkeTo, other hardware)", file=sys.stderr, flush=True)
+    del z, code
+    torch.cuda.empty_cache()
     return {"workload": f"{wl.name} terrain {wl.nx}x{wl.ny}", "launches": reps, **out}
 
 
