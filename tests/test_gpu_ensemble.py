@@ -152,3 +152,31 @@ def test_single_tiling_invariance_and_graph_replay(torch_cuda):
             b.step(1)
         assert same(sa, b.state()), rep
         assert a.time() == b.time()
+
+
+def test_bench_ensemble_configuration(torch_cuda):
+    # the 256-member ensemble bench.py times (autotuned tiling, graph
+    # replay): sampled members bit-identical to their own runs and, for the
+    # smallest, within 1e-12 of the oracle
+    from paper_1307_4839_amd.solver import Ensemble
+    wls = I.ensemble(256)
+    e = Ensemble(wls)
+    e.autotune(4)
+    n = 40
+    e.step(n)
+    rc, flags = e.status()
+    assert rc == 0 and not any(flags)
+    sizes = [wl.nx * wl.ny for wl in wls]
+    picks = sorted({int(np.argmax(sizes)), int(np.argmin(sizes)), 0, 17, 128, 255})
+    for k in picks:
+        ref = run_single(wls[k], n)
+        assert same(e.state(k), ref), k
+        assert e.time(k)[0] == ref["t"]
+    k = int(np.argmin(sizes))
+    s = oracle.State(wls[k])
+    assert s.run(n) == 0
+    st = e.state(k)
+    for f in ("h", "qx", "qy"):
+        ref = getattr(s, f)
+        assert np.abs(st[f] - ref).max() <= 1e-12 * max(np.abs(ref).max(), 1e-300), f
+    e.close()
