@@ -182,6 +182,13 @@ int swe_set_time(swe_ctx* ctx, double t);
  * hyetograph is set). */
 int swe_set_rain(swe_ctx* ctx, double rain);
 
+/* New imposed values of one side (0 west, 1 east, 2 south, 3 north) for the
+ * steps enqueued after this call: a hydrograph or a varying level is fed
+ * this way between calls of swe_step (Section 2.2; the values are constant
+ * over a step).  The side must have an imposed type; the values follow the
+ * rules of swe_params.bc_h / bc_q for that type, else SWE_EINVAL. */
+int swe_set_boundary_values(swe_ctx* ctx, int32_t side, double h_b, double q_b);
+
 /* Hyetograph r(t) (Section 2.1: R depends on t): a step from time t rains
  * r[k] for the last k with t_pts[k] <= t (rain is explicit, so the rate at
  * the start of the step holds for the whole step), and 0 when t < t_pts[0].
@@ -269,6 +276,9 @@ int swe_batch_autotune(swe_batch* b, int32_t trial_steps, int32_t* tx, int32_t* 
                        double* ms_per_step);
 
 int swe_batch_set_rain(swe_batch* b, int32_t member, double rain);
+/* swe_set_boundary_values for one member (same rules; synchronizes). */
+int swe_batch_set_boundary_values(swe_batch* b, int32_t member, int32_t side, double h_b,
+                                  double q_b);
 /* swe_set_hyetograph for one member (same rules; synchronizes). */
 int swe_batch_set_hyetograph(swe_batch* b, int32_t member, const double* t_pts,
                              const double* r, int32_t n);

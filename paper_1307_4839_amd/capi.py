@@ -82,6 +82,9 @@ EXPORTS = {
                                      C.POINTER(C.c_double), C.c_int32]),
     "swe_set_dt_log": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64]),
     "swe_step": (C.c_int, [C.c_void_p, C.c_int32, C.c_double]),
+    "swe_set_boundary_values": (C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.c_double]),
+    "swe_batch_set_boundary_values": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_double,
+                                                C.c_double]),
     "swe_set_gauges": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p,
                                  C.c_int64]),
     "swe_get_gauges": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(C.c_int64)]),
@@ -282,6 +285,17 @@ def swe_get_gauges(ctx: int, out: Optional[np.ndarray] = None) -> int:
         check(lib().swe_get_gauges(C.c_void_p(ctx), out.ctypes.data_as(C.c_void_p),
                                    out.shape[0], C.byref(n)), "swe_get_gauges")
     return n.value
+
+
+def swe_set_boundary_values(ctx: int, side: int, h_b: float, q_b: float) -> None:
+    check(lib().swe_set_boundary_values(C.c_void_p(ctx), side, h_b, q_b),
+          "swe_set_boundary_values")
+
+
+def swe_batch_set_boundary_values(b: int, member: int, side: int, h_b: float,
+                                  q_b: float) -> None:
+    check(lib().swe_batch_set_boundary_values(C.c_void_p(b), member, side, h_b, q_b),
+          "swe_batch_set_boundary_values")
 
 
 def swe_step(ctx: int, nsteps: int, t_end: float = float("inf")) -> None:

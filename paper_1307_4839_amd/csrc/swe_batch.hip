@@ -552,6 +552,18 @@ int swe_batch_autotune(swe_batch* b, int32_t trial_steps, int32_t* tx_out, int32
     return rc;
 }
 
+int swe_batch_set_boundary_values(swe_batch* b, int32_t member, int32_t side, double h_b,
+                                  double q_b) {
+    if (!b || member < 0 || member >= b->count || side < 0 || side > 3) return SWE_EINVAL;
+    const int type = b->prm[member].bc[side];
+    if (type < SWE_BC_IMPOSED_H || !imposed_values_ok(type, h_b, q_b)) return SWE_EINVAL;
+    b->prm[member].bc_h[side] = h_b;
+    b->prm[member].bc_q[side] = q_b;
+    b->mh[member].p.bc_h[side] = h_b;
+    b->mh[member].p.bc_q[side] = q_b;
+    return upload_members(b);
+}
+
 int swe_batch_set_rain(swe_batch* b, int32_t member, double rain) {
     if (!b || member < 0 || member >= b->count || !(rain >= 0.0) || !std::isfinite(rain))
         return SWE_EINVAL;

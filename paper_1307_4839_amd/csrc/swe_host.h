@@ -22,6 +22,16 @@ inline size_t ncells(const swe_params* p) { return (size_t)p->nx * (size_t)p->ny
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// The imposed values of a side of type `type`: a depth finite and > 0 where
+// it is imposed, a discharge finite and >= 0 where it is imposed.
+inline bool imposed_values_ok(int type, double h_b, double q_b) {
+    if (type == SWE_BC_IMPOSED_H || type == SWE_BC_IMPOSED_HQ)
+        if (!(h_b > 0.0) || !std::isfinite(h_b)) return false;
+    if (type == SWE_BC_IMPOSED_Q || type == SWE_BC_IMPOSED_HQ)
+        if (!(q_b >= 0.0) || !std::isfinite(q_b)) return false;
+    return true;
+}
+
 inline int check_params(const swe_params* p) {
     if (!p) return SWE_EINVAL;
     if (p->nx < 2 || p->ny < 2) return SWE_EINVAL;
@@ -30,10 +40,7 @@ inline int check_params(const swe_params* p) {
     if (!(p->h_eps >= 0.0) || !(p->dt_max > 0.0)) return SWE_EINVAL;
     for (int k = 0; k < 4; ++k) {
         if (p->bc[k] < SWE_BC_WALL || p->bc[k] > SWE_BC_IMPOSED_HQ) return SWE_EINVAL;
-        if (p->bc[k] == SWE_BC_IMPOSED_H || p->bc[k] == SWE_BC_IMPOSED_HQ)
-            if (!(p->bc_h[k] > 0.0) || !std::isfinite(p->bc_h[k])) return SWE_EINVAL;
-        if (p->bc[k] == SWE_BC_IMPOSED_Q || p->bc[k] == SWE_BC_IMPOSED_HQ)
-            if (!(p->bc_q[k] >= 0.0) || !std::isfinite(p->bc_q[k])) return SWE_EINVAL;
+        if (!imposed_values_ok(p->bc[k], p->bc_h[k], p->bc_q[k])) return SWE_EINVAL;
     }
     if (p->fric_law < SWE_FRIC_NONE || p->fric_law > SWE_FRIC_DARCY) return SWE_EINVAL;
     if (p->infil_on && !(p->dtheta > 0.0)) return SWE_EINVAL;

@@ -447,6 +447,18 @@ int swe_set_rain(swe_ctx* c, double rain) {
     return SWE_OK;
 }
 
+int swe_set_boundary_values(swe_ctx* c, int32_t side, double h_b, double q_b) {
+    if (!c || side < 0 || side > 3) return SWE_EINVAL;
+    const int type = c->prm.bc[side];
+    if (type < SWE_BC_IMPOSED_H || !imposed_values_ok(type, h_b, q_b)) return SWE_EINVAL;
+    c->prm.bc_h[side] = h_b;
+    c->prm.bc_q[side] = q_b;
+    c->m.p.bc_h[side] = h_b;
+    c->m.p.bc_q[side] = q_b;
+    c->epoch++;
+    return SWE_OK;
+}
+
 int swe_set_hyetograph(swe_ctx* c, const double* t_pts, const double* r, int32_t n) {
     if (!c) return SWE_EINVAL;
     HyetoStage st;

@@ -151,6 +151,11 @@ class Solver:
         if vinf is not None and self.vinf is not None:
             self.vinf.copy_(torch.as_tensor(np.asarray(vinf, dtype=np.float64)))
 
+    def set_boundary_values(self, side: int, h_b: float = 0.0, q_b: float = 0.0) -> None:
+        """New imposed depth / inflow discharge of an imposed side (0 west,
+        1 east, 2 south, 3 north) for the steps that follow."""
+        capi.swe_set_boundary_values(self.ctx, side, h_b, q_b)
+
     def set_gauges(self, cells, every: int, max_samples: int) -> None:
         """Record h at the flat cell indices `cells` after every `every`
         steps from now on (at most max_samples samples); empty cells stop
@@ -248,6 +253,10 @@ class Ensemble:
 
     def set_rain(self, member: int, rain: float) -> None:
         capi.swe_batch_set_rain(self.handle, member, rain)
+
+    def set_boundary_values(self, member: int, side: int, h_b: float = 0.0,
+                            q_b: float = 0.0) -> None:
+        capi.swe_batch_set_boundary_values(self.handle, member, side, h_b, q_b)
 
     def set_hyetograph(self, member: int, t_pts, r) -> None:
         capi.swe_batch_set_hyetograph(self.handle, member, t_pts, r)

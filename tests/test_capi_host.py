@@ -199,3 +199,13 @@ def test_gauge_arguments_without_gpu():
     with pytest.raises(capi.SweError) as e:
         capi.swe_get_gauges(0)
     assert e.value.code == capi.SWE_EINVAL
+
+
+def test_boundary_value_arguments_without_gpu():
+    from paper_1307_4839_amd import capi
+    with pytest.raises(capi.SweError) as e:
+        capi.swe_set_boundary_values(0, 0, 1.0, 1.0)
+    assert e.value.code == capi.SWE_EINVAL
+    with pytest.raises(capi.SweError) as e:
+        capi.swe_batch_set_boundary_values(0, 0, 0, 1.0, 1.0)
+    assert e.value.code == capi.SWE_EINVAL

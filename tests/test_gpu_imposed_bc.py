@@ -188,3 +188,44 @@ def test_ensemble_members_with_imposed_sides(torch_cuda):
             assert np.array_equal(a[f], b[f]), (k, f)
         g.close()
     e.close()
+
+
+def test_hydrograph_by_boundary_value_updates(torch_cuda):
+    # the inflow discharge and the outlet level changed between calls of
+    # swe_step (a stepwise hydrograph): the same as the oracle with the
+    # parameters changed at the same steps, in a context and in an ensemble
+    from paper_1307_4839_amd import capi
+    from paper_1307_4839_amd.solver import Ensemble, Solver
+    wl = bump(120, ny=5)
+    plan = [(200, 4.42, 2.0), (150, 3.1, 1.9), (170, 5.0, 2.05)]
+    s = oracle.State(wl)
+    g = Solver(wl, dt_log=600)
+    e = Ensemble([wl, I.ensemble_member(1, n=80)])
+    for n, q, h in plan:
+        w2 = wl.copy()
+        w2.bc_q, w2.bc_h = (q, 0, 0, 0), (0, h, 0, 0)
+        s.p = oracle.params_of(w2)
+        assert s.run(n) == 0
+        g.set_boundary_values(0, q_b=q)
+        g.set_boundary_values(1, h_b=h)
+        g.step(n)
+        e.set_boundary_values(0, 0, q_b=q)
+        e.set_boundary_values(0, 1, h_b=h)
+        e.step(n)
+    st = g.state()
+    assert g.time()[2] == s.steps
+    for k in ("h", "qx", "qy"):
+        assert rel_err(st[k], getattr(s, k)) <= TOL, k
+    es = e.state(0)
+    for k in ("h", "qx", "qy"):
+        assert np.array_equal(es[k], st[k]), k
+    # the side must be imposed and the values valid for its type
+    for side, hb, qb in ((2, 1.0, 0.0), (0, 0.0, -1.0), (1, 0.0, 0.0), (1, math.nan, 0.0),
+                         (4, 1.0, 1.0)):
+        with pytest.raises(capi.SweError) as err:
+            g.set_boundary_values(side, h_b=hb, q_b=qb)
+        assert err.value.code == capi.SWE_EINVAL
+    with pytest.raises(capi.SweError):
+        e.set_boundary_values(1, 0, q_b=1.0)     # member 1 has no imposed side
+    g.close()
+    e.close()
