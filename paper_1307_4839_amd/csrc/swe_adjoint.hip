@@ -862,6 +862,49 @@ __global__ __launch_bounds__(T1) void stage_out_kernel(KParams p, const double* 
 //   grad   += d/dcoef
 // STAGE 2 also forms the Heun split: its output adjoint is half of `lam`,
 // and the other half seeds lam_n.
+// Stage 2 of the reverse of a step, fused with the rebuild of its input: U*
+// = friction(U^k + dt Phi(U^k)) (what stage_out_kernel computes) is formed
+// per cell, written to us (the VJP that follows reads it) and used as the
+// stage input of the friction reversal with output adjoint lam/2, as in
+// adj_stage_kernel (mode 0).  One kernel and one pass over U* fewer.
+__global__ __launch_bounds__(T1) void adj_stage2_kernel(
+    KParams p, const double* __restrict__ fric, const double* __restrict__ h,
+    const double* __restrict__ qx, const double* __restrict__ qy,
+    const double* __restrict__ ph, const double* __restrict__ pqx,
+    const double* __restrict__ pqy, const double* __restrict__ ph2,
+    const double* __restrict__ pqx2, const double* __restrict__ pqy2, double dt,
+    const double* __restrict__ bo_h, const double* __restrict__ bo_qx,
+    const double* __restrict__ bo_qy, double* __restrict__ us_h, double* __restrict__ us_qx,
+    double* __restrict__ us_qy, double* __restrict__ lin_h, double* __restrict__ lin_qx,
+    double* __restrict__ lin_qy, double* __restrict__ mu_h, double* __restrict__ mu_qx,
+    double* __restrict__ mu_qy, double* __restrict__ grad, size_t n) {
+    size_t i = (size_t)blockIdx.x * T1 + threadIdx.x;
+    if (i >= n) return;
+    const double coef = fric ? fric[i] : p.coef;
+    // U*
+    double h0 = h[i] + dt * ph[i];
+    double qx0 = qx[i] + dt * pqx[i];
+    double qy0 = qy[i] + dt * pqy[i];
+    friction(p, coef, h[i], qx[i], qy[i], h0, qx0, qy0, dt);
+    us_h[i] = h0;
+    us_qx[i] = qx0;
+    us_qy[i] = qy0;
+    // stage 2 from U*
+    double h1 = h0 + dt * ph2[i];
+    double qx1 = qx0 + dt * pqx2[i];
+    double qy1 = qy0 + dt * pqy2[i];
+    double bh1, bqx1, bqy1, bh0, bqx0, bqy0, bc;
+    friction_rev(p, coef, h0, qx0, qy0, h1, qx1, qy1, dt, 0.5 * bo_h[i], 0.5 * bo_qx[i],
+                 0.5 * bo_qy[i], bh1, bqx1, bqy1, bh0, bqx0, bqy0, bc);
+    lin_h[i] = bh1 + bh0;
+    lin_qx[i] = bqx1 + bqx0;
+    lin_qy[i] = bqy1 + bqy0;
+    mu_h[i] = dt * bh1;
+    mu_qx[i] = dt * bqx1;
+    mu_qy[i] = dt * bqy1;
+    if (grad) grad[i] += bc;
+}
+
 __global__ __launch_bounds__(T1) void adj_stage_kernel(
     KParams p, const double* __restrict__ fric, const double* __restrict__ h,
     const double* __restrict__ qx, const double* __restrict__ qy,
@@ -1133,25 +1176,36 @@ void adj_step(swe_adj* A, const double* Uk, double dt, double* grad, const doubl
         rate_into(A, h, qx, qy, A->phi0);
         phik = A->phi0;
     }
-    hipLaunchKernelGGL(stage_out_kernel, dim3(blocks(n)), dim3(T1), 0, A->stream, A->m.p,
-                       A->m.fric, h, qx, qy, plane(phik, n, 0), plane(phik, n, 1),
-                       plane(phik, n, 2), dt, plane(us, n, 0), plane(us, n, 1), plane(us, n, 2),
-                       n);
     // stage 2 on U*: Phi(U*), then its friction reversed with output
     // adjoint lam/2
     if (!phi2k) {
+        hipLaunchKernelGGL(stage_out_kernel, dim3(blocks(n)), dim3(T1), 0, A->stream, A->m.p,
+                           A->m.fric, h, qx, qy, plane(phik, n, 0), plane(phik, n, 1),
+                           plane(phik, n, 2), dt, plane(us, n, 0), plane(us, n, 1),
+                           plane(us, n, 2), n);
         rate_into(A, plane(us, n, 0), plane(us, n, 1), plane(us, n, 2), A->phi);
-        phi2k = A->phi;
+        hipLaunchKernelGGL(adj_stage_kernel, dim3(blocks(n)), dim3(T1), 0, A->stream, A->m.p,
+                           A->m.fric, (const double*)plane(us, n, 0),
+                           (const double*)plane(us, n, 1), (const double*)plane(us, n, 2),
+                           plane(A->phi, n, 0), plane(A->phi, n, 1), plane(A->phi, n, 2), dt,
+                           (const double*)plane(A->lam, n, 0),
+                           (const double*)plane(A->lam, n, 1),
+                           (const double*)plane(A->lam, n, 2), 0.5, plane(A->lamB, n, 0),
+                           plane(A->lamB, n, 1), plane(A->lamB, n, 2), 0, nullptr, nullptr,
+                           nullptr, plane(A->mu, n, 0), plane(A->mu, n, 1), plane(A->mu, n, 2),
+                           grad, n);
+    } else {
+        // U* rebuilt and stage 2 reversed in one pass
+        hipLaunchKernelGGL(adj_stage2_kernel, dim3(blocks(n)), dim3(T1), 0, A->stream, A->m.p,
+                           A->m.fric, h, qx, qy, plane(phik, n, 0), plane(phik, n, 1),
+                           plane(phik, n, 2), plane(phi2k, n, 0), plane(phi2k, n, 1),
+                           plane(phi2k, n, 2), dt, (const double*)plane(A->lam, n, 0),
+                           (const double*)plane(A->lam, n, 1),
+                           (const double*)plane(A->lam, n, 2), plane(us, n, 0), plane(us, n, 1),
+                           plane(us, n, 2), plane(A->lamB, n, 0), plane(A->lamB, n, 1),
+                           plane(A->lamB, n, 2), plane(A->mu, n, 0), plane(A->mu, n, 1),
+                           plane(A->mu, n, 2), grad, n);
     }
-    hipLaunchKernelGGL(adj_stage_kernel, dim3(blocks(n)), dim3(T1), 0, A->stream, A->m.p,
-                       A->m.fric, (const double*)plane(us, n, 0), (const double*)plane(us, n, 1),
-                       (const double*)plane(us, n, 2), plane(phi2k, n, 0), plane(phi2k, n, 1),
-                       plane(phi2k, n, 2), dt,
-                       (const double*)plane(A->lam, n, 0), (const double*)plane(A->lam, n, 1),
-                       (const double*)plane(A->lam, n, 2), 0.5, plane(A->lamB, n, 0),
-                       plane(A->lamB, n, 1), plane(A->lamB, n, 2), 0, nullptr, nullptr, nullptr,
-                       plane(A->mu, n, 0),
-                       plane(A->mu, n, 1), plane(A->mu, n, 2), grad, n);
     vjp_rate(A, plane(us, n, 0), plane(us, n, 1), plane(us, n, 2), A->lamB);
     // stage 1 on U^k: friction reversed with output adjoint lamB; lamA =
     // lam/2 (Heun: lam_n takes half of lam directly) + that
