@@ -4,10 +4,10 @@
 // Every member runs the same two stages as a single simulation (the tile
 // routine of swe_device.h; the members share the scheme, order and flux, so
 // that one kernel serves each stage), with its own grid, parameters, time,
-// time step (its own CFL bound, Section 3.3), status flags and buffers.  A step of the
-// whole ensemble is ONE persistent launch per stage: a grid sized to the
-// resident capacity of the GPU walks a work list of (member, strip, row
-// range) tiles, largest members first.  Runs of 16 steps replay a captured
+// time step (its own CFL bound, Section 3.3), status flags and buffers.  A
+// step of the whole ensemble is ONE persistent launch per stage: a grid
+// sized to the resident capacity of the GPU walks a work list of (member,
+// strip, row range) tiles, largest members first.  Runs of 16 steps replay a captured
 // HIP graph.  The tile shape (strip width x rows) is chosen by a measuring
 // autotuner that times the candidates on the live state and restores it
 // bit for bit afterwards; results never depend on the tile shape.
