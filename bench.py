@@ -369,8 +369,8 @@ def main(argv=None):
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); "
-              "the multi-GPU decomposition is a design, not an implementation",
+        print(f"bench.py: the library runs on one GPU (got --gpus {args.gpus}); "
+              "its multi-GPU decomposition is designed, not implemented",
               file=sys.stderr, flush=True)
         return 2
 
