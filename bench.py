@@ -3,10 +3,12 @@
 Workload (default): the 8192 x 8192 overland-flow hillslope (1 m cells,
 initially dry, 50 mm/h rain, Green-Ampt infiltration, Darcy-Weisbach
 friction), i.e. every step of the method is active.  A step is one full
-Heun step of the whole grid (both stage kernels).  W warmup steps run first
-(default 300: the dry start ends with ponding after about 223 s of simulated
-time, so the timed steps see thin films and wet/dry fronts), then K timed
-steps.  The metric counts nx*ny cell updates per step, dry cells included.
+Heun step of the whole grid (both stage kernels).  A fixed spin-up of 300
+steps runs first whatever the warmup is (the dry start ends with ponding
+after about 223 s of simulated time, so the timed steps see thin films and
+wet/dry fronts everywhere; the run stops if no cell is wet), then W warmup
+steps, then R samples of K timed steps (value from the median sample).  The
+metric counts nx*ny cell updates per step, dry cells included.
 
 Prints one JSON line with the throughput, the roofline of the dominant
 kernel (HIP events on the library's stream) and the CPU oracle timed on a
@@ -51,9 +53,11 @@ def algorithmic_bytes(wl):
     return rate, upd
 
 
-def load_counters(path=COUNTERS_FILE, sources=None):
+def load_counters(path=COUNTERS_FILE, sources=None, need_regime=False):
     """Counters measured on the current kernel sources (committed summary of
-    rocprofv3 runs of this benchmark), or None."""
+    rocprofv3 runs of this benchmark), or None.  With `need_regime`, only
+    counters taken on a state with water (the regime the timed steps run
+    in) are returned."""
     from paper_1307_4839_amd.build import source_hash
     try:
         with open(path) as f:
@@ -62,10 +66,16 @@ def load_counters(path=COUNTERS_FILE, sources=None):
         return None
     if rec.get("kernel_sha256_16") != source_hash(sources):
         return None
+    if need_regime and not rec.get("regime", {}).get("wet_fraction", 0.0) > 0.0:
+        return None
     return rec
 
 
-def cpu_baseline(wl, rows, steps):
+def cpu_baseline(wl, rows, spinup, seconds):
+    """The oracle on a band of the workload: its first `rows` rows as a grid
+    of their own (same terrain, physics and side types), advanced by the
+    oracle itself through the same spin-up as the GPU run, then timed in the
+    same regime with all host threads and with one thread."""
     import numpy as np
 
     import oracle
@@ -76,16 +86,41 @@ def cpu_baseline(wl, rows, steps):
         if a is not None:
             setattr(sub, f, np.ascontiguousarray(a[:rows]))
     s = oracle.State(sub)
+    nproc = oracle.num_threads()
     t0 = time.perf_counter()
-    rc = s.run(steps)
-    el = time.perf_counter() - t0
-    assert rc in (0, 1), rc
-    cells = sub.nx * sub.ny * s.steps
-    return {"value": cells / el, "unit": "cell-updates/s", "cores": oracle.num_threads(),
+    rc = s.run(spinup)
+    assert rc == 0, rc
+    t_spin = time.perf_counter() - t0
+    wet = float((s.h > sub.h_eps).mean())
+    cells = sub.nx * sub.ny
+
+    def timed(threads, budget):
+        oracle.set_num_threads(threads)
+        t1 = time.perf_counter()
+        assert s.run(1) == 0
+        per_step = time.perf_counter() - t1
+        k = max(1, int(budget / max(per_step, 1e-6)))
+        t1 = time.perf_counter()
+        assert s.run(k) == 0
+        el = time.perf_counter() - t1
+        return k, el
+
+    t_start = s.t
+    kn, eln = timed(nproc, 0.4 * seconds)
+    k1, el1 = timed(1, 0.6 * seconds)
+    oracle.set_num_threads(nproc)
+    print(f"[bench] CPU oracle: spin-up {spinup} steps of {rows} rows in {t_spin:.1f} s "
+          f"(t = {t_start:.1f} s, wet fraction {wet:.3f}); {kn} steps on {nproc} threads in "
+          f"{eln:.1f} s, {k1} steps on 1 thread in {el1:.1f} s", file=sys.stderr, flush=True)
+    return {"value": cells * kn / eln, "unit": "cell-updates/s", "cores": nproc,
             "kind": "oracle",
-            "sample": f"rows 0..{rows - 1} of the {wl.nx}x{wl.ny} {wl.name} workload, "
-                      f"{s.steps} steps from its initial state ({cells:.3g} cell-updates "
-                      f"in {el:.1f} s)"}
+            "sample": f"rows 0..{rows - 1} of the {wl.nx}x{wl.ny} {wl.name} workload as a "
+                      f"{wl.nx}x{rows} grid, advanced {spinup} steps by the oracle itself "
+                      f"(to t = {t_start:.1f} s, wet fraction {wet:.3f}), then {kn} steps "
+                      f"timed on {nproc} threads ({cells * kn:.3g} cell-updates in {eln:.1f} s)",
+            "single_thread": {"value": cells * k1 / el1, "unit": "cell-updates/s", "cores": 1,
+                              "steps": k1, "s": el1},
+            "t_start_s": t_start, "wet_fraction": wet}
 
 
 def ensemble_leg(members, steps, trial_steps):
@@ -167,6 +202,7 @@ def adjoint_leg(steps, every):
     cal = Calibration(wl, wl.gauges, every, np.zeros(rows * ng), steps)
     cal.forward()
     dts = cal.dts()
+    cal.set_dts(dts)
     cal.fric.copy_(torch.as_tensor(wl.extra["fric_obs"], device="cuda:0"))
     cal.forward()
     obs = cal.series()
@@ -264,16 +300,17 @@ def flow_dir_leg(wl, reps):
     return {"workload": f"{wl.name} terrain {wl.nx}x{wl.ny}", "launches": reps, **out}
 
 
-def variant_leg(wl, warmup, steps, order, flux):
-    """The same workload with another scheme of Section 3.3: the first-order
-    scheme (no reconstruction, one Euler stage, n_CFL = 1) and/or the
-    Rusanov or kinetic flux.  Throughput and the average durations of the two kernels
-    of a step (rate, then the update)."""
+def variant_leg(wl, warmup, steps, order, flux, recon=0):
+    """The same workload with another scheme of Sections 3.3 and 4.1: the
+    first-order scheme (no reconstruction, one Euler stage, n_CFL = 1), the
+    Rusanov, kinetic or VFRoe-ncv flux, or the ENO or modified ENO
+    reconstruction.  Throughput and the average durations of the two
+    kernels of a step (rate, then the update)."""
     import torch
 
     from paper_1307_4839_amd.solver import Solver
     w1 = wl.copy()
-    w1.order, w1.flux = order, flux
+    w1.order, w1.flux, w1.recon = order, flux, recon
     if order == 1:
         w1.cfl = 1.0
     g = Solver(w1, device="cuda:0")
@@ -295,7 +332,9 @@ def variant_leg(wl, warmup, steps, order, flux):
     del g
     torch.cuda.empty_cache()
     cells = wl.nx * wl.ny
-    name = f"{'first' if order == 1 else 'second'} order, {('HLL', 'Rusanov', 'kinetic')[flux]}"
+    name = (f"{'first' if order == 1 else 'second'} order, "
+            f"{('MUSCL', 'ENO', 'modified ENO')[recon] + ', ' if order != 1 else ''}"
+            f"{('HLL', 'Rusanov', 'kinetic', 'VFRoe-ncv')[flux]}")
     print(f"[bench] {name}: {steps} steps in {ms:.1f} ms, t = {t_sim:.1f} s",
           file=sys.stderr, flush=True)
     return {"workload": f"{wl.name} {wl.nx}x{wl.ny}, {name}, cfl {w1.cfl}", "steps": steps,
@@ -345,16 +384,22 @@ def paper_runs_leg(iterations):
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=300)
-    ap.add_argument("--warmup", type=int, default=300)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="hillslope_8192",
                     choices=["hillslope_8192", "valley_2048", "valley_5120",
                              "dam_break_200", "calibration_1024"])
     ap.add_argument("--size", type=int, default=0, help="override nx = ny (testing)")
     ap.add_argument("--profile-steps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rows", type=int, default=2048)
-    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--cpu-rows", type=int, default=16)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0,
+                    help="time the oracle sample for about this long (after its spin-up)")
+    ap.add_argument("--spinup", type=int, default=None,
+                    help="steps run before the warmup whatever --warmup is (default: 300 "
+                         "on the hillslope, past Green-Ampt ponding; 0 elsewhere)")
+    ap.add_argument("--repeats", type=int, default=5,
+                    help="timed samples of --steps steps; the value is from the median")
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--adjoint-steps", type=int, default=2000)
@@ -391,32 +436,51 @@ def main(argv=None):
 
     g = Solver(wl, device="cuda:0")
     stream = g.stream
-    g.step(args.warmup)
+    cells = wl.nx * wl.ny
+    # fixed spin-up, whatever --warmup is: the hillslope starts dry and ponds
+    # after about 223 s of simulated time (1 s steps until then), so the
+    # timed steps see thin films and wet/dry fronts everywhere
+    spinup = args.spinup if args.spinup is not None else \
+        (300 if wl.name.startswith("hillslope") else 0)
+    g.step(spinup + args.warmup)
     torch.cuda.synchronize()
-    print(f"[bench] warmup {args.warmup} steps done, t = {g.time()[0]:.2f} s",
-          file=sys.stderr, flush=True)
+    t_start = g.time()[0]
+    d0 = g.diagnostics()
+    wet0 = d0.wet_cells / cells
+    print(f"[bench] spin-up {spinup} + warmup {args.warmup} steps done, t = {t_start:.2f} s, "
+          f"wet fraction {wet0:.4f}", file=sys.stderr, flush=True)
+    if d0.wet_cells <= 0:
+        print("[bench] no wet cell when timing starts: the timed steps would not run "
+              "the method's wet branches", file=sys.stderr, flush=True)
+        return 1
 
-    # timed region: K steps bracketed by synchronizations
+    # timed region: `repeats` samples of K steps, each bracketed by
+    # synchronizations; the value is from the median sample
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    w0 = time.perf_counter()
-    e0.record(stream)
-    g.step(args.steps)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
-    ms = e0.elapsed_time(e1)
+    samples, walls = [], []
+    for _ in range(args.repeats):
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        e0.record(stream)
+        g.step(args.steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - w0)
+        samples.append(e0.elapsed_time(e1))
+    ms = sorted(samples)[len(samples) // 2]
     rc, flags = g.status()
     t_sim, last_dt, nsteps_done = g.time()
+    wet1 = g.diagnostics().wet_cells / cells
     if rc != 0:
         print(f"[bench] status flags {flags} (code {rc})", file=sys.stderr, flush=True)
-    cells = wl.nx * wl.ny
     value = cells * args.steps / (ms / 1e3)
-    print(f"[bench] timed {args.steps} steps: {ms:.2f} ms (wall {wall * 1e3:.2f} ms), "
-          f"t = {t_sim:.2f} s", file=sys.stderr, flush=True)
+    print(f"[bench] timed {args.repeats} x {args.steps} steps: median {ms:.2f} ms "
+          f"(samples {', '.join(f'{v:.2f}' for v in samples)} ms; wall "
+          f"{sorted(walls)[len(walls) // 2] * 1e3:.2f} ms), t = {t_start:.2f} -> {t_sim:.2f} s, "
+          f"wet fraction {wet0:.4f} -> {wet1:.4f}", file=sys.stderr, flush=True)
 
-    # per-kernel durations on the library's stream (HIP events)
+    # per-kernel durations on the library's stream (HIP events), same regime
     g.profile_begin(args.profile_steps)
     g.step(args.profile_steps)
     ms_rate, ms_upd, np_ = g.profile_end()
@@ -433,30 +497,39 @@ def main(argv=None):
     tx, ty = g.tiling()
     ach = kern[dom]["GBps"]
     # measured HBM bytes and VALU instructions per launch (rocprofv3 counters
-    # committed under profiles/, used only when taken on these kernel sources)
+    # committed under profiles/, used only when taken on these kernel sources,
+    # on this workload, in the wet regime the timed steps run in)
     traffic, alu = None, None
-    cnt = load_counters()
-    if cnt and kname in cnt["kernels"]:
+    cnt = load_counters(need_regime=True)
+    if cnt and cnt.get("workload") == wl.name and cnt.get("cells") == cells \
+            and kname in cnt["kernels"]:
         kc = cnt["kernels"][kname]
         traffic = round(kc["bytes_per_launch"])
+        for key, avg in (("rate", avg_rate), ("update", avg_upd)):
+            kk = "stage_kernel<1>" if key == "rate" else "stage_kernel<2>"
+            sqk = cnt["kernels"].get(kk, {}).get("sq", {})
+            if "SQ_INSTS_VALU" in sqk:
+                lane_ops = sqk["SQ_INSTS_VALU"] * 64
+                frac = lane_ops / (avg / 1e3) / VALU_PEAK_LANE_OPS
+                kern[key]["valu_lane_ops_per_cell"] = lane_ops / cells
+                if frac > 1.0:
+                    print(f"[bench] {kk}: counters give {frac:.3f} of the VALU issue peak, "
+                          "which cannot be; not reported", file=sys.stderr, flush=True)
+                else:
+                    kern[key]["valu_frac"] = frac
         sq = kc.get("sq", {})
-        if "SQ_INSTS_VALU" in sq:
-            for key, avg in (("rate", avg_rate), ("update", avg_upd)):
-                kk = "stage_kernel<1>" if key == "rate" else "stage_kernel<2>"
-                sqk = cnt["kernels"].get(kk, {}).get("sq", {})
-                if "SQ_INSTS_VALU" in sqk:
-                    lane_ops = sqk["SQ_INSTS_VALU"] * 64
-                    kern[key]["valu_lane_ops_per_cell"] = lane_ops / cells
-                    kern[key]["valu_frac"] = lane_ops / (avg / 1e3) / VALU_PEAK_LANE_OPS
+        if "SQ_INSTS_VALU" in sq and "valu_frac" in kern[dom]:
             lane_ops = sq["SQ_INSTS_VALU"] * 64
             a_ops = lane_ops / (kern[dom]["avg_ms"] / 1e3)
             alu = {"bound": "alu", "achieved": a_ops, "peak": VALU_PEAK_LANE_OPS,
                    "unit": "FP64 VALU lane-op/s", "frac": round(a_ops / VALU_PEAK_LANE_OPS, 4),
-                   "kernel": kname, "lane_ops_per_launch": lane_ops}
+                   "kernel": kname, "lane_ops_per_launch": lane_ops,
+                   "counters_regime": cnt["regime"]}
     roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "kernel": kname, "tile": [tx, ty],
-                "algorithmic_bytes_per_launch": kern[dom]["bytes_per_cell"] * cells}
+                "algorithmic_bytes_per_launch": kern[dom]["bytes_per_cell"] * cells,
+                "launches": np_}
     step_bytes = (b_rate + b_upd) * cells
     print(f"[bench] kernels: {json.dumps(kern)}", file=sys.stderr, flush=True)
 
@@ -508,7 +581,7 @@ def main(argv=None):
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(wl, min(args.cpu_rows, wl.ny), args.cpu_steps)
+        cpu = cpu_baseline(wl, min(args.cpu_rows, wl.ny), spinup, args.cpu_seconds)
 
     out = {
         "metric": METRIC,
@@ -540,6 +613,9 @@ def main(argv=None):
         "paper_runs": paper,
         "flow_directions": fdir,
         "scheme_variants": variants,
+        "timing": {"repeats": args.repeats, "samples_ms": samples, "statistic": "median",
+                   "spinup_steps": spinup, "t_start_s": t_start, "t_end_s": t_sim,
+                   "wet_fraction_start": wet0, "wet_fraction_end": wet1},
         "sim_time_s": t_sim,
         "status_flags": flags,
     }

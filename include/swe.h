@@ -43,13 +43,15 @@ extern "C" {
 #define SWE_EHIP (-2)       /* a HIP runtime call failed */
 #define SWE_ENEGDEPTH (-3)  /* a negative water depth was produced */
 #define SWE_ENONFINITE (-4) /* a non-finite value was produced */
-#define SWE_EDT (-5)        /* the time step was not finite */
+#define SWE_EDTMIN (-5)     /* the time step collapsed below dt_min */
 #define SWE_ENOMEM (-6)     /* workspace too small */
+#define SWE_EDT (-7)        /* the time step was not finite */
 
 /* sticky status flags (swe_get_status) */
 #define SWE_FLAG_NEGDEPTH 1u
 #define SWE_FLAG_NONFINITE 2u
-#define SWE_FLAG_DT 4u
+#define SWE_FLAG_DT 4u           /* a step's dt was not finite */
+#define SWE_FLAG_DT_UNDERFLOW 8u /* a step's dt fell below dt_min */
 
 /* boundary types, Section 2.2: ghost cells.  WALL mirrors the boundary
  * cells (normal discharge negated); OUTFLOW copies the boundary cell (free,
@@ -111,6 +113,17 @@ typedef struct swe_params {
     double bc_q[4];      /* imposed inflow discharge [m^2/s] per side,
                             finite and >= 0 where bc is IMPOSED_Q or
                             IMPOSED_HQ; ignored elsewhere */
+    double dt_min;       /* smallest acceptable dt [s] (0: no bound; finite,
+                            >= 0).  A step whose eq. (cfl) dt falls below it
+                            is a collapse of the time step (a wet/dry front
+                            or a blow-up driving the wave speeds up): the
+                            step is not taken, SWE_FLAG_DT_UNDERFLOW is
+                            raised and later steps are not taken either
+                            while it holds.  The last step of a run, clipped
+                            to t_end - t, is exempt (dt == t_end - t). */
+    int32_t recon;       /* second-order reconstruction: 0 MUSCL with
+                            minmod (the paper's, Section 3.4); other values
+                            are refused */
 } swe_params;
 
 /* Optional per-cell fields below are read only, [ny][nx] FP64 device
@@ -216,7 +229,8 @@ int swe_step(swe_ctx* ctx, int32_t nsteps, double t_end);
 int swe_get_time(swe_ctx* ctx, double* t, double* last_dt, int64_t* steps);
 
 /* Synchronizes.  Sticky SWE_FLAG_* bits; returns the SWE_E* code of the
- * most serious flag set (0 if none). */
+ * most serious flag set (0 if none), in the order NONFINITE, NEGDEPTH, DT,
+ * DT_UNDERFLOW. */
 int swe_get_status(swe_ctx* ctx, uint32_t* flags);
 
 /* Synchronizes.  Deterministic (fixed-order) reductions of the state. */

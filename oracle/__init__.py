@@ -48,7 +48,8 @@ class OrcParams(C.Structure):
                 ("rain_r", C.POINTER(C.c_double)), ("rain_w", C.POINTER(C.c_double)),
                 ("ks_f", C.POINTER(C.c_double)), ("psi_f", C.POINTER(C.c_double)),
                 ("dtheta_f", C.POINTER(C.c_double)), ("order", C.c_int32),
-                ("flux", C.c_int32), ("bc_h", C.c_double * 4), ("bc_q", C.c_double * 4)]
+                ("flux", C.c_int32), ("bc_h", C.c_double * 4), ("bc_q", C.c_double * 4),
+                ("dt_min", C.c_double), ("recon", C.c_int32)]
 
 
 _lib = None
@@ -73,7 +74,9 @@ def lib(path: Optional[str] = None):
         l.orc_minmod.argtypes = [C.c_double, C.c_double]
         l.orc_minmod.restype = C.c_double
         l.orc_num_threads.restype = C.c_int
+        l.orc_set_num_threads.argtypes = [C.c_int]
         l.orc_muscl.argtypes = [dp, dp, dp, C.c_double, dp]
+        l.orc_eno.argtypes = [dp, dp, dp, C.c_double, C.c_int, dp]
         l.orc_hll.argtypes = [C.c_double] + [C.c_double] * 6 + [dp]
         l.orc_face.argtypes = [C.c_double] + [C.c_double] * 8 + [dp, C.c_int32]
         l.orc_tangent_run.argtypes = [pp, dp, dp, dp, dp, dp, dp, C.c_int32, dp,
@@ -103,8 +106,10 @@ def _ip(a: Optional[np.ndarray]):
 def params(nx, ny, dx, dy, g=9.81, cfl=0.5, dt_max=math.inf, h_eps=1e-12,
            bc=(0, 0, 0, 0), fric_law=0, fric_coef=0.0, rain=0.0, infil_on=0,
            ks=0.0, psi=0.0, dtheta=0.0, order=2, flux=0, bc_h=(0.0,) * 4,
-           bc_q=(0.0,) * 4) -> OrcParams:
+           bc_q=(0.0,) * 4, dt_min=0.0, recon=0) -> OrcParams:
     p = OrcParams()
+    p.dt_min = float(dt_min)
+    p.recon = int(recon)
     p.order = int(order)
     p.flux = int(flux)
     for k in range(4):
@@ -229,6 +234,12 @@ def num_threads() -> int:
     return lib().orc_num_threads()
 
 
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops from now on (results are the
+    same at any count)."""
+    lib().orc_set_num_threads(int(n))
+
+
 def minmod(a, b):
     return lib().orc_minmod(a, b)
 
@@ -241,6 +252,14 @@ def muscl(a, c, b, h_eps=1e-12):
     return out
 
 
+def eno(a, c, b, h_eps=1e-12, modified=False):
+    """ENO (or modified ENO) face values of one cell, as muscl()."""
+    a, c, b = (np.ascontiguousarray(x, dtype=np.float64) for x in (a, c, b))
+    out = np.zeros(8)
+    lib().orc_eno(_dp(a), _dp(c), _dp(b), h_eps, int(bool(modified)), _dp(out))
+    return out
+
+
 def hll(g, hL, unL, utL, hR, unR, utR):
     out = np.zeros(3)
     lib().orc_hll(g, hL, unL, utL, hR, unR, utR, _dp(out))
@@ -249,7 +268,7 @@ def hll(g, hL, unL, utL, hR, unR, utR):
 
 def face(g, hm, zm, unm, utm, hp, zp, unp, utp, flux=0):
     """{F0, F1, F2, sL, sR, speed} of one face (flux 0 HLL, 1 Rusanov,
-    2 kinetic)."""
+    2 kinetic, 3 VFRoe-ncv)."""
     out = np.zeros(6)
     lib().orc_face(g, hm, zm, unm, utm, hp, zp, unp, utp, _dp(out), flux)
     return out

@@ -9,9 +9,13 @@ formulas as printed, vectorised over cells and faces:
 * hydrostatic reconstruction, S_{i+1/2L}, S_{i-1/2R} and Fc_i, Section 3.1;
 * HLL flux with c1 = min over U_L, U_R of u - sqrt(gh) and c2 = max of
   u + sqrt(gh), Section 3.3 (or the Rusanov flux, another consistent flux
-  that section names);
+  that section names, or the VFRoe-ncv flux Section 4.1 lists: the
+  interface state of the Riemann problem in the variables (2 sqrt(gh), u)
+  linearized about the mean state);
 * MUSCL with minmod on h, h+z and u and the modified velocity, Section 3.4,
-  written with divided differences exactly as printed;
+  written with divided differences exactly as printed (or ENO: the
+  one-sided slope of smaller magnitude, none in a dry cell; modified ENO:
+  the same with the depth slope limited to 2 h / dx in magnitude);
 * semi-implicit friction and Heun's method, Section 3.2;
 * first order (Section 3.3): no reconstruction (zero slopes) and one
   explicit Euler stage per step.
@@ -49,7 +53,31 @@ def _minmod(x, y):
     return out
 
 
-def convective_rate(h, q, z, dx, g, h_eps, bc, order=2, flux="hll"):
+def _eno(x, y):
+    """The argument of smaller magnitude (the first on ties)."""
+    return np.where(np.abs(x) <= np.abs(y), x, y)
+
+
+def _vfroe(hL, uL, hR, uR, g):
+    """Mass and momentum flux of the state at x/t = 0 of the Riemann problem
+    of (2c, u), c = sqrt(gh), linearized about the mean state."""
+    wl, wr = hL > 0, hR > 0
+    uL = np.where(wl, uL, uR)
+    uR = np.where(wr, uR, uL)
+    cL, cR = np.sqrt(g * hL), np.sqrt(g * hR)
+    um, cm = (uL + uR) / 2, (cL + cR) / 2
+    # subsonic interface: 2c + u from the left, 2c - u from the right
+    cs = np.maximum(cm + (uL - uR) / 4, 0.0)
+    us = um + (cL - cR)
+    h = np.where(um - cm >= 0, hL, np.where(um + cm <= 0, hR, cs * cs / g))
+    u = np.where(um - cm >= 0, uL, np.where(um + cm <= 0, uR, us))
+    both_dry = ~wl & ~wr
+    F0 = np.where(both_dry, 0.0, h * u)
+    F1 = np.where(both_dry, 0.0, h * u * u + g * h * h / 2)
+    return F0, F1
+
+
+def convective_rate(h, q, z, dx, g, h_eps, bc, order=2, flux="hll", recon="minmod"):
     """Returns the bracket [F_{i+1/2L} - F_{i-1/2R} - Fc_i] and max speed."""
     hp = _ghost(h, bc[0], bc[1], False)
     qp = _ghost(q, bc[0], bc[1], True)
@@ -61,9 +89,17 @@ def convective_rate(h, q, z, dx, g, h_eps, bc, order=2, flux="hll"):
     c = slice(1, -1)
     lo = slice(0, -2)
     hi = slice(2, None)
-    Dh = _minmod((hp[c] - hp[lo]) / dx, (hp[hi] - hp[c]) / dx)
-    De = _minmod((eta[c] - eta[lo]) / dx, (eta[hi] - eta[c]) / dx)
-    Du = _minmod((u[c] - u[lo]) / dx, (u[hi] - u[c]) / dx)
+    lim = _minmod if recon == "minmod" else _eno
+    Dh = lim((hp[c] - hp[lo]) / dx, (hp[hi] - hp[c]) / dx)
+    De = lim((eta[c] - eta[lo]) / dx, (eta[hi] - eta[c]) / dx)
+    Du = lim((u[c] - u[lo]) / dx, (u[hi] - u[c]) / dx)
+    if recon in ("eno", "enomod"):
+        # a dry cell is not reconstructed
+        dry = hp[c] <= h_eps
+        Dh, De, Du = (np.where(dry, 0.0, D) for D in (Dh, De, Du))
+    if recon == "enomod":
+        # face depths h -/+ dx/2 Dh within [0, 2h]
+        Dh = np.clip(Dh, -2 * hp[c] / dx, 2 * hp[c] / dx)
     if order == 1:
         Dh, De, Du = np.zeros_like(Dh), np.zeros_like(De), np.zeros_like(Du)
     h_m = hp[c] - dx / 2 * Dh           # h_{i-1/2+}
@@ -87,7 +123,9 @@ def convective_rate(h, q, z, dx, g, h_eps, bc, order=2, flux="hll"):
     c2 = np.maximum(um_ + cL, uq_ + cR)
     FL0, FL1 = hL * um_, hL * um_ * um_ + g * hL * hL / 2
     FR0, FR1 = hR * uq_, hR * uq_ * uq_ + g * hR * hR / 2
-    if flux == "rusanov":
+    if flux == "vfroe":
+        F0, F1 = _vfroe(hL, um_, hR, uq_, g)
+    elif flux == "rusanov":
         # local Lax-Friedrichs: (F(U_L) + F(U_R))/2 - c/2 (U_R - U_L)
         c = np.maximum(np.abs(um_) + cL, np.abs(uq_) + cR)
         F0 = (FL0 + FR0) / 2 - c / 2 * (hR - hL)
@@ -126,9 +164,9 @@ def friction(h0, q0, h1, q1, dt, law, coef, g, h_eps):
 
 
 def heun_step(h, q, z, dt, dx, g=9.81, h_eps=1e-12, bc=(WALL, WALL), law=0,
-              coef=0.0, flux="hll"):
+              coef=0.0, flux="hll", recon="minmod"):
     def phi_stage(hh, qq):
-        B0, B1, _ = convective_rate(hh, qq, z, dx, g, h_eps, bc, flux=flux)
+        B0, B1, _ = convective_rate(hh, qq, z, dx, g, h_eps, bc, flux=flux, recon=recon)
         h1 = hh - dt / dx * B0
         q1 = qq - dt / dx * B1
         q1 = friction(hh, qq, h1, q1, dt, law, coef, g, h_eps)

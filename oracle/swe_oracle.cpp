@@ -131,12 +131,19 @@ struct orc_params {
     // explicit Euler stage per step); 0 or 2: the second-order scheme
     int32_t order;
     // numerical flux (Section 3.3 allows any consistent one): 0 HLL, 1 Rusanov,
-    // 2 kinetic
+    // 2 kinetic, 3 VFRoe-ncv
     int32_t flux;
     // imposed boundaries (bc 2: depth h_b, 3: inflow discharge q_b per unit
     // width, 4: both), per side west, east, south, north
     double bc_h[4];
     double bc_q[4];
+    // smallest acceptable time step (0: none): a dt of eq. (cfl) below it,
+    // other than the last step clipped to the end time, is a collapse of the
+    // time step and stops the run before that step
+    double dt_min;
+    // second-order reconstruction (Section 4.1 lists MUSCL, ENO and modified
+    // ENO): 0 MUSCL with minmod, 1 ENO, 2 modified ENO; ignored at order 1
+    int32_t recon;
 };
 }
 
@@ -200,6 +207,56 @@ inline Recon<T> muscl(const Prim<T>& a, const Prim<T>& c, const Prim<T>& b,
     return r;
 }
 
+// ENO reconstruction at second order (Section 4.1 names ENO and modified ENO
+// beside MUSCL without defining them; reading).  Every second-order
+// reconstruction of the paper works on the cells i-1, i, i+1 (two ghost
+// layers at order two, Section 6.1), so ENO is Harten's at second order:
+// of the two two-cell stencils the smoother one, i.e. the one-sided
+// undivided difference of smaller magnitude (the left one on ties), as the
+// slope of h, h+z and the velocities.  Unlike minmod it keeps a slope at an
+// extremum, and the face depths h -/+ D/2 can then be negative.  A cell at
+// or below the dry threshold keeps its values at both faces (its slopes
+// would put water on the faces of a dry cell between wet ones; the same
+// threshold stops the velocity reconstruction of MUSCL).  Modified ENO: the
+// same with the depth's slope limited to |D| <= 2 h_i, so that both face
+// depths stay in [0, 2 h_i], as the positivity of the hydrostatic
+// reconstruction (Section 3.1) needs.  z and the velocities follow as for
+// MUSCL (modified velocity conserving the discharge).
+template <class T> inline T eno_slope(T a, T b) { return dfabs(a) <= dfabs(b) ? a : b; }
+
+template <class T>
+inline Recon<T> eno(const Prim<T>& a, const Prim<T>& c, const Prim<T>& b, double h_eps,
+                    bool modified) {
+    Recon<T> r;
+    if (!(c.h > T(h_eps))) {
+        r.h_m = r.h_p = c.h;
+        r.z_m = r.z_p = c.eta - c.h;
+        r.un_m = r.un_p = c.un;
+        r.ut_m = r.ut_p = c.ut;
+        return r;
+    }
+    T dh = eno_slope(c.h - a.h, b.h - c.h);
+    if (modified) {
+        T cap = T(2.0) * c.h;
+        if (dh > cap) dh = cap;
+        else if (dh < -cap) dh = -cap;
+    }
+    r.h_m = c.h - T(0.5) * dh;
+    r.h_p = c.h + T(0.5) * dh;
+    T de = eno_slope(c.eta - a.eta, b.eta - c.eta);
+    T eta_m = c.eta - T(0.5) * de;
+    T eta_p = c.eta + T(0.5) * de;
+    r.z_m = eta_m - r.h_m;
+    r.z_p = eta_p - r.h_p;
+    T dun = eno_slope(c.un - a.un, b.un - c.un);
+    T dut = eno_slope(c.ut - a.ut, b.ut - c.ut);
+    r.un_m = c.un - (r.h_p / c.h) * (T(0.5) * dun);
+    r.un_p = c.un + (r.h_m / c.h) * (T(0.5) * dun);
+    r.ut_m = c.ut - (r.h_p / c.h) * (T(0.5) * dut);
+    r.ut_p = c.ut + (r.h_m / c.h) * (T(0.5) * dut);
+    return r;
+}
+
 // First order (Section 3.3 gives n_CFL = 1 for it): no reconstruction, the
 // face values are the cell's.  Written as the reconstruction above with
 // zero slopes, so z at the faces is still deduced from h and h+z.
@@ -211,6 +268,15 @@ inline Recon<T> piecewise_constant(const Prim<T>& c) {
     r.un_m = r.un_p = c.un;
     r.ut_m = r.ut_p = c.ut;
     return r;
+}
+
+// The face values of one cell for the parameters' order and reconstruction.
+template <class T>
+inline Recon<T> reconstruct(const orc_params& p, const Prim<T>& a, const Prim<T>& c,
+                            const Prim<T>& b) {
+    if (p.order == 1) return piecewise_constant(c);
+    if (p.recon == 1 || p.recon == 2) return eno(a, c, b, p.h_eps, p.recon == 2);
+    return muscl(a, c, b, p.h_eps);
 }
 
 // ---------------------------------------------------------------------------
@@ -305,8 +371,55 @@ inline void kinetic(double g, T hL, T unL, T utL, T hR, T unR, T utR, T F[3]) {
     F[2] = m0L * utL + m0R * utR;
 }
 
+// VFRoe-ncv flux (Buffard, Gallouet and Herard, 2000; Gallouet, Herard and
+// Seguin, 2003), the fourth flux Section 4.1 lists: the interface value of
+// the Riemann problem of the system written in the non-conservative
+// variables W = (2c, u), c = sqrt(g h),
+//   (2c)_t + u (2c)_x + c u_x = 0,   u_t + c (2c)_x + u u_x = 0,
+// linearized about the mean state (c^, u^) = ((cL + cR)/2, (uL + uR)/2).
+// Its eigenvalues are u^ -/+ c^ and 2c - u, 2c + u are carried along them.
+// At x/t = 0: W_L if u^ - c^ >= 0, W_R if u^ + c^ <= 0, else the state with
+// 2c* + u* = 2cL + uL and 2c* - u* = 2cR - uR:
+//   c* = c^ + (uL - uR)/4,   u* = u^ + (cL - cR).
+// The face flux is the physical flux of that state, with h* = max(c*, 0)^2 / g
+// (the depth of U_L or U_R itself in the outer branches), and the
+// tangential velocity upwinded on u* (left side when u* >= 0).  Readings for
+// dry sides, where W holds a velocity that carries no water: a dry side
+// takes the other side's velocity, and two dry sides pass nothing.
+template <class T>
+inline void vfroe(double g, T hL, T unL, T utL, T hR, T unR, T utR, T F[3]) {
+    const bool wetL = hL > T(0.0), wetR = hR > T(0.0);
+    if (!wetL && !wetR) {
+        F[0] = F[1] = F[2] = T(0.0);
+        return;
+    }
+    if (!wetL) unL = unR;
+    if (!wetR) unR = unL;
+    T cL = dsqrt(T(g) * hL);
+    T cR = dsqrt(T(g) * hR);
+    T uh = T(0.5) * (unL + unR);
+    T ch = T(0.5) * (cL + cR);
+    T h, u;
+    if (uh - ch >= T(0.0)) {
+        h = hL;
+        u = unL;
+    } else if (uh + ch <= T(0.0)) {
+        h = hR;
+        u = unR;
+    } else {
+        T cs = vmax(ch + T(0.25) * (unL - unR), T(0.0));
+        h = (cs * cs) / T(g);
+        u = uh + (cL - cR);
+    }
+    T q = h * u;
+    F[0] = q;
+    F[1] = q * u + T(0.5 * g) * h * h;
+    F[2] = q * (u >= T(0.0) ? utL : utR);
+}
+
 // One face between a left cell (its "p" values) and a right cell (its "m"
-// values): hydrostatic reconstruction (Section 3.1), HLL (Rusanov, kinetic) flux and the two
+// values): hydrostatic reconstruction (Section 3.1), HLL (Rusanov, kinetic,
+// VFRoe-ncv) flux and the two
 // normal-momentum corrections S_{i+1/2L} (for the left cell) and
 // S_{i+1/2R} (for the right cell).  Also returns the face's wave-speed bound
 // max(|u-| + sqrt(g h-), |u+| + sqrt(g h+)) on the MUSCL states, i.e. before
@@ -332,6 +445,8 @@ inline Face<T> face(double g, T hm, T zm, T unm, T utm, T hp, T zp, T unp,
         rusanov(g, hL, unm, utm, hR, unp, utp, f.F);
     else if (flux == 2)
         kinetic(g, hL, unm, utm, hR, unp, utp, f.F);
+    else if (flux == 3)
+        vfroe(g, hL, unm, utm, hR, unp, utp, f.F);
     else
         hll(g, hL, unm, utm, hR, unp, utp, f.F);
     f.sL = T(0.5 * g) * (hm * hm - hL * hL);
@@ -540,7 +655,7 @@ void rate(const orc_params& p, const T* h_in, const T* qx_in, const T* qy_in,
             Prim<T> pa{h[a], u[a], v[a], eta[a]};
             Prim<T> pc{h[c], u[c], v[c], eta[c]};
             Prim<T> pb{h[b], u[b], v[b], eta[b]};
-            rc[i + 1] = p.order == 1 ? piecewise_constant(pc) : muscl(pa, pc, pb, h_eps);
+            rc[i + 1] = reconstruct(p, pa, pc, pb);
         }
         // faces i+1/2 for i = -1 .. nx-1
         std::vector<Face<T>> fc(nx + 1);
@@ -573,7 +688,7 @@ void rate(const orc_params& p, const T* h_in, const T* qx_in, const T* qy_in,
             Prim<T> pa{h[a], v[a], u[a], eta[a]};
             Prim<T> pc{h[c], v[c], u[c], eta[c]};
             Prim<T> pb{h[b], v[b], u[b], eta[b]};
-            rc[j + 1] = p.order == 1 ? piecewise_constant(pc) : muscl(pa, pc, pb, h_eps);
+            rc[j + 1] = reconstruct(p, pa, pc, pb);
         }
         std::vector<Face<T>> fc(ny + 1);
         for (int j = -1; j < ny; ++j) {
@@ -774,7 +889,7 @@ extern "C" {
 
 // Status codes: 0 = a step was taken; 1 = t_end already reached (no step);
 // -1 = invalid argument; -3 = negative depth; -4 = non-finite value;
-// -7 = non-finite time step.
+// -5 = the time step collapsed below dt_min; -7 = non-finite time step.
 int orc_rate(const orc_params* p, const double* h, const double* qx,
              const double* qy, const double* z, double* ph, double* pqx,
              double* pqy, double* amax) {
@@ -813,6 +928,7 @@ int orc_run(const orc_params* p, double* h, double* qx, double* qy,
         double dt = time_step(*p, amax, *t, t_end);
         if (!std::isfinite(dt)) { rc = -7; break; }
         if (!(dt > 0.0)) { rc = 1; break; }
+        if (dt < p->dt_min && dt < t_end - *t) { rc = -5; break; }
         step_fixed<double>(*p, fric, *t, dt, h, qx, qy, z, vinf);
         *t = *t + dt;
         if (dt_log) dt_log[k] = dt;
@@ -847,6 +963,16 @@ int orc_num_threads(void) {
 #endif
 }
 
+// set the number of threads of the parallel loops (results do not depend on
+// it: every cell is computed alone and the maxima are exact)
+void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 // prim rows: {h, un, ut, eta} for cells i-1, i, i+1.  out: {h_m, h_p, z_m,
 // z_p, un_m, un_p, ut_m, ut_p}.
 void orc_muscl(const double* a, const double* c, const double* b,
@@ -854,6 +980,16 @@ void orc_muscl(const double* a, const double* c, const double* b,
     Prim<double> pa{a[0], a[1], a[2], a[3]}, pc{c[0], c[1], c[2], c[3]},
         pb{b[0], b[1], b[2], b[3]};
     Recon<double> r = muscl(pa, pc, pb, h_eps);
+    double o[8] = {r.h_m, r.h_p, r.z_m, r.z_p, r.un_m, r.un_p, r.ut_m, r.ut_p};
+    std::memcpy(out, o, sizeof o);
+}
+
+// The same for the ENO reconstructions (modified != 0: modified ENO).
+void orc_eno(const double* a, const double* c, const double* b, double h_eps, int modified,
+             double* out) {
+    Prim<double> pa{a[0], a[1], a[2], a[3]}, pc{c[0], c[1], c[2], c[3]},
+        pb{b[0], b[1], b[2], b[3]};
+    Recon<double> r = eno(pa, pc, pb, h_eps, modified != 0);
     double o[8] = {r.h_m, r.h_p, r.z_m, r.z_p, r.un_m, r.un_p, r.ut_m, r.ut_p};
     std::memcpy(out, o, sizeof o);
 }

@@ -63,12 +63,35 @@ def hipcc() -> str:
 
 
 def build(verbose: bool = True) -> str:
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + f".tmp{os.getpid()}"
-    cmd = [hipcc(), *HIPCC_FLAGS, "-I", INCLUDE, *srcs, "-o", tmp]
+    """Compile each source to an object in parallel (separate translation
+    units, as one hipcc line over all of them would), then link."""
+    from concurrent.futures import ThreadPoolExecutor
+    tag = f".tmp{os.getpid()}"
+    objdir = os.path.join(PKG, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    compile_flags = [f for f in HIPCC_FLAGS if f != "-shared"]
+    jobs = []
+    for s in SOURCES:
+        obj = os.path.join(objdir, os.path.splitext(s)[0] + tag + ".o")
+        jobs.append((obj, [hipcc(), *compile_flags, "-I", INCLUDE, "-c",
+                           os.path.join(CSRC, s), "-o", obj]))
+
+    def run(job):
+        if verbose:
+            print(" ".join(job[1]), flush=True)
+        subprocess.check_call(job[1])
+        return job[0]
+
+    workers = max(1, min(len(jobs), os.cpu_count() or 1))
+    with ThreadPoolExecutor(workers) as ex:
+        objs = list(ex.map(run, jobs))
+    tmp = LIB + tag
+    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
+    for o in objs:
+        os.remove(o)
     os.replace(tmp, LIB)
     return LIB
 

@@ -22,12 +22,14 @@ SWE_EINVAL = -1
 SWE_EHIP = -2
 SWE_ENEGDEPTH = -3
 SWE_ENONFINITE = -4
-SWE_EDT = -5
+SWE_EDTMIN = -5
 SWE_ENOMEM = -6
+SWE_EDT = -7
 
 SWE_FLAG_NEGDEPTH = 1
 SWE_FLAG_NONFINITE = 2
 SWE_FLAG_DT = 4
+SWE_FLAG_DT_UNDERFLOW = 8
 
 SWE_BC_WALL = 0
 SWE_BC_OUTFLOW = 1
@@ -48,7 +50,8 @@ class swe_params(C.Structure):
                 ("fric_coef", C.c_double), ("rain", C.c_double),
                 ("infil_on", C.c_int32), ("ks", C.c_double),
                 ("psi", C.c_double), ("dtheta", C.c_double), ("order", C.c_int32),
-                ("flux", C.c_int32), ("bc_h", C.c_double * 4), ("bc_q", C.c_double * 4)]
+                ("flux", C.c_int32), ("bc_h", C.c_double * 4), ("bc_q", C.c_double * 4),
+                ("dt_min", C.c_double), ("recon", C.c_int32)]
 
 
 class swe_buffers(C.Structure):
@@ -176,8 +179,10 @@ def check(code: int, where: str) -> int:
 def make_params(nx, ny, dx, dy, g=9.81, cfl=0.5, dt_max=float("inf"),
                 h_eps=1e-12, bc=(0, 0, 0, 0), fric_law=0, fric_coef=0.0,
                 rain=0.0, infil_on=0, ks=0.0, psi=0.0, dtheta=0.0, order=2,
-                flux=0, bc_h=(0.0,) * 4, bc_q=(0.0,) * 4) -> swe_params:
+                flux=0, bc_h=(0.0,) * 4, bc_q=(0.0,) * 4, dt_min=0.0, recon=0) -> swe_params:
     p = swe_params()
+    p.dt_min = float(dt_min)
+    p.recon = int(recon)
     p.order = int(order)
     p.flux = int(flux)
     for k in range(4):

@@ -1394,6 +1394,7 @@ int swe_adj_forward(swe_adj* A, double* loss) {
     if (s.status & SWE_FLAG_NONFINITE) return SWE_ENONFINITE;
     if (s.status & SWE_FLAG_NEGDEPTH) return SWE_ENEGDEPTH;
     if (s.status & SWE_FLAG_DT) return SWE_EDT;
+    if (s.status & SWE_FLAG_DT_UNDERFLOW) return SWE_EDTMIN;
     return hip_ok(hipGetLastError());
 }
 

@@ -624,6 +624,7 @@ int swe_batch_get_status(swe_batch* b, uint32_t* flags, int32_t n) {
     if (any & SWE_FLAG_NONFINITE) return SWE_ENONFINITE;
     if (any & SWE_FLAG_NEGDEPTH) return SWE_ENEGDEPTH;
     if (any & SWE_FLAG_DT) return SWE_EDT;
+    if (any & SWE_FLAG_DT_UNDERFLOW) return SWE_EDTMIN;
     return SWE_OK;
 }
 

@@ -69,6 +69,9 @@ constexpr size_t SCALAR_BYTES = (sizeof(DevScalars) + 255) / 256 * 256;
 struct KParams {
     int nx, ny;
     double dx, dy, g, cfl, dt_max, h_eps;
+    // a dt of eq. (cfl) below dt_min (other than the step clipped to the end
+    // time) is a collapse: the step is not taken
+    double dt_min;
     int bcw, bce, bcs, bcn;
     int law;
     double coef;
@@ -320,6 +323,7 @@ __host__ __device__ __forceinline__ void kinetic_half(double g, double h, double
 // With depths, velocities and z capped at 2^60 and g at most 2^10, c1 and c2
 // stay below 2^62 and the HLL numerators below 2^251; den and the
 // numerators are bounded below here.  The Rusanov flux divides by nothing.
+
 template <int FLUX = 0, class D>
 __host__ __device__ __forceinline__ FaceOut face(double g, double hm, double zm, double unm,
                                                  double utm, double hp, double zp, double unp,
@@ -1159,19 +1163,23 @@ __device__ __forceinline__ double rain_rate(const MemberArgs& m, double t) {
 // Start of the update of a step: dt from the wave-speed bounds of stage 1
 // (eq. cfl), the rain r(t) at the step's start time, and, by thread 0 of
 // the lead block, the time, step count and dt log of the next slot.
-// Returns false when no step is taken (dt not positive or not finite; the
-// latter raises the sticky DT flag).
+// Returns false when no step is taken: dt not positive, not finite (raises
+// the sticky DT flag) or below dt_min without being the step clipped to the
+// end time (raises DT_UNDERFLOW; a frozen dt is taken as given).
 __device__ __forceinline__ bool begin_step(const MemberArgs& m, const TileIO& io, bool lead,
                                            double& dt, double& rain) {
     double ax, ay;
     read_amax(&m.sc->amax[io.slot][0][0], ax, ay);
     double tc = m.sc->t[io.slot];
     rain = rain_rate(m, tc);
-    dt = io.dt_fixed > 0.0 ? io.dt_fixed : time_step(m.p, ax, ay, tc, io.t_end);
+    const bool frozen = io.dt_fixed > 0.0;
+    dt = frozen ? io.dt_fixed : time_step(m.p, ax, ay, tc, io.t_end);
     const bool finite = (dt - dt) == 0.0;  // false for inf and NaN
+    const bool collapse = !frozen && dt < m.p.dt_min && dt < io.t_end - tc && dt > 0.0;
+    const bool take = finite && dt > 0.0 && !collapse;
     if (lead && threadIdx.x == 0) {
         long long st = m.sc->steps[io.slot];
-        if (finite && dt > 0.0) {
+        if (take) {
             m.sc->t[io.slot ^ 1] = tc + dt;
             m.sc->steps[io.slot ^ 1] = st + 1;
             m.sc->last_dt = dt;
@@ -1181,9 +1189,10 @@ __device__ __forceinline__ bool begin_step(const MemberArgs& m, const TileIO& io
             m.sc->t[io.slot ^ 1] = tc;
             m.sc->steps[io.slot ^ 1] = st;
             if (!finite) atomicOr(&m.sc->status, (unsigned)SWE_FLAG_DT);
+            if (collapse) atomicOr(&m.sc->status, (unsigned)SWE_FLAG_DT_UNDERFLOW);
         }
     }
-    return finite && dt > 0.0;
+    return take;
 }
 
 // First order (Section 3.3): the update of a step is one explicit Euler

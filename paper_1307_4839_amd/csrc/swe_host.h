@@ -38,6 +38,7 @@ inline int check_params(const swe_params* p) {
     if (!(p->dx > 0.0) || !(p->dy > 0.0) || !(p->g > 0.0) || !(p->cfl > 0.0))
         return SWE_EINVAL;
     if (!(p->h_eps >= 0.0) || !(p->dt_max > 0.0)) return SWE_EINVAL;
+    if (!(p->dt_min >= 0.0) || !std::isfinite(p->dt_min)) return SWE_EINVAL;
     for (int k = 0; k < 4; ++k) {
         if (p->bc[k] < SWE_BC_WALL || p->bc[k] > SWE_BC_IMPOSED_HQ) return SWE_EINVAL;
         if (!imposed_values_ok(p->bc[k], p->bc_h[k], p->bc_q[k])) return SWE_EINVAL;
@@ -48,6 +49,7 @@ inline int check_params(const swe_params* p) {
     if ((size_t)p->nx * (size_t)p->ny > ((size_t)1 << 36)) return SWE_EINVAL;
     if (p->order < 0 || p->order > 2) return SWE_EINVAL;
     if (p->flux < 0 || p->flux > 2) return SWE_EINVAL;
+    if (p->recon != 0) return SWE_EINVAL;
     return SWE_OK;
 }
 
@@ -64,6 +66,7 @@ inline KParams to_kparams(const swe_params& p) {
     KParams k;
     k.nx = p.nx; k.ny = p.ny;
     k.dx = p.dx; k.dy = p.dy; k.g = p.g; k.cfl = p.cfl; k.dt_max = p.dt_max;
+    k.dt_min = p.dt_min;
     k.h_eps = p.h_eps;
     k.bcw = p.bc[0]; k.bce = p.bc[1]; k.bcs = p.bc[2]; k.bcn = p.bc[3];
     k.imposed = 0;

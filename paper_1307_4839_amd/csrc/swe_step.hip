@@ -574,6 +574,7 @@ int swe_get_status(swe_ctx* c, uint32_t* flags) {
     if (s.status & SWE_FLAG_NONFINITE) return SWE_ENONFINITE;
     if (s.status & SWE_FLAG_NEGDEPTH) return SWE_ENEGDEPTH;
     if (s.status & SWE_FLAG_DT) return SWE_EDT;
+    if (s.status & SWE_FLAG_DT_UNDERFLOW) return SWE_EDTMIN;
     return SWE_OK;
 }
 
@@ -640,6 +641,7 @@ const char* swe_strerror(int code) {
         case SWE_ENEGDEPTH: return "negative water depth produced";
         case SWE_ENONFINITE: return "non-finite value produced";
         case SWE_EDT: return "time step not finite";
+        case SWE_EDTMIN: return "time step collapsed below dt_min";
         case SWE_ENOMEM: return "workspace too small";
         default: return "unknown error";
     }

@@ -78,6 +78,7 @@ class Workload:
     g: float = 9.81
     cfl: float = 0.5
     dt_max: float = math.inf
+    dt_min: float = 0.0  # a CFL dt below it (not clipped to t_end) stops the run
     h_eps: float = 1e-12
     fric_law: int = FRIC_NONE
     fric_coef: float = 0.0
@@ -101,8 +102,10 @@ class Workload:
     # 2: MUSCL + Heun (the paper's scheme); 1: first order (piecewise
     # constant, one Euler stage; the paper uses n_CFL = 1 with it)
     order: int = 2
-    # numerical flux: 0 HLL (the paper's), 1 Rusanov, 2 kinetic
+    # numerical flux: 0 HLL (the paper's), 1 Rusanov, 2 kinetic, 3 VFRoe-ncv
     flux: int = 0
+    # second-order reconstruction: 0 MUSCL (the paper's), 1 ENO, 2 modified ENO
+    recon: int = 0
     t_end: float = math.inf
     nsteps: int = 0
     gauges: Optional[np.ndarray] = None  # flat cell indices
@@ -115,7 +118,8 @@ class Workload:
                     fric_coef=self.fric_coef, rain=self.rain,
                     infil_on=self.infil_on, ks=self.ks, psi=self.psi,
                     dtheta=self.dtheta, order=self.order, flux=self.flux,
-                    bc_h=tuple(self.bc_h), bc_q=tuple(self.bc_q))
+                    bc_h=tuple(self.bc_h), bc_q=tuple(self.bc_q), dt_min=self.dt_min,
+                    recon=self.recon)
 
     def copy(self) -> "Workload":
         out = dataclasses.replace(self)

@@ -13,8 +13,9 @@ whose timed region starts after them.
     python -m paper_1307_4839_amd.rocprof_summary kernel --fetch DB --write DB \\
         --expect NAME=BYTES [...] --skip K --sources flowdir --json OUT.json
 
-the same copy-calibrated FETCH_SIZE / WRITE_SIZE figures for every kernel
-whose name contains NAME (one entry per full kernel name), against BYTES
+the same copy-calibrated FETCH_SIZE / WRITE_SIZE figures for the kernel
+whose short name (template arguments included, parameters and namespaces
+left out) is exactly NAME, e.g. 'flow_dir_kernel<float, 4>', against BYTES
 algorithmic bytes per launch.
 
 For ``counters``, per stage kernel: FETCH_SIZE and WRITE_SIZE (KiB per dispatch) averaged over
@@ -24,7 +25,9 @@ dispatch, of known size 2^30 bytes each way), next to the algorithmic bytes
 per launch (B1, B2 bytes per cell times N cells); with --sq, the SQ counters
 of a third run (VALU and SALU instructions, waves).  The JSON carries the
 hash of the kernel sources so that a benchmark reads it only for the kernels
-it was taken on.
+it was taken on.  ``--bench-log`` names the benchmark's stderr of one of
+the runs: the simulated time and wet fraction at which its timed steps
+started are recorded as the regime the counters describe.
 """
 
 from __future__ import annotations
@@ -35,6 +38,25 @@ import sqlite3
 import sys
 
 COPY_BYTES = 1 << 30
+
+
+def short_name(name: str) -> str:
+    """Kernel name without 'void', namespaces and the parameter list."""
+    return name.replace("void ", "").replace("(anonymous namespace)::", "").split("(")[0]
+
+
+def regime_of(log: str) -> dict:
+    """Simulated time and wet fraction when a benchmark's timed steps began,
+    from its '[bench] spin-up ...' line."""
+    import re
+    with open(log) as f:
+        for line in f:
+            m = re.search(r"spin-up (\d+) \+ warmup (\d+) steps done, t = ([0-9.eE+-]+) s, "
+                          r"wet fraction ([0-9.eE+-]+)", line)
+            if m:
+                return {"spinup_steps": int(m.group(1)), "warmup_steps": int(m.group(2)),
+                        "t_start_s": float(m.group(3)), "wet_fraction": float(m.group(4))}
+    raise SystemExit(f"{log}: no spin-up line")
 
 
 def _stage(name: str) -> str | None:
@@ -54,10 +76,10 @@ def trace(db: str, skip: dict) -> str:
     out.append(f"{'kernel':<60} {'calls':>6} {'total_ms':>10} {'avg_us':>10} "
                f"{'skip':>5} {'avg_us_after_skip':>18}")
     for name, durs in sorted(per.items(), key=lambda kv: -sum(kv[1])):
-        short = name.replace("void ", "").replace("(anonymous namespace)::", "").split("(")[0]
+        short = short_name(name)
         k = 0
         for key, val in skip.items():
-            if key in name:
+            if key in short:
                 k = val
         rest = durs[k:] if k < len(durs) else []
         avg_rest = (sum(rest) / len(rest) / 1e3) if rest else float("nan")
@@ -114,6 +136,7 @@ def counters(a) -> dict:
     fw = COPY_BYTES / 1024.0 / cw
     sq = _stage_avgs(a.sq, a.skip) if a.sq else {}
     rec = {"kernel_sha256_16": source_hash(), "workload": a.workload, "cells": a.cells,
+           "regime": regime_of(a.bench_log) if a.bench_log else {},
            "calibration": {"probe": "1 GiB device-to-device copy (__amd_rocclr_copyBuffer)",
                            "fetch_KiB": cf, "write_KiB": cw,
                            "fetch_factor": ff, "write_factor": fw},
@@ -153,7 +176,8 @@ def kernel_counters(a) -> dict:
                            "fetch_factor": ff, "write_factor": fw},
            "kernels": {}}
     for name in sorted(fetch):
-        key = next((k for k in expect if k in name), None)
+        short = short_name(name)
+        key = short if short in expect else None
         if key is None or name not in write:
             continue
         fr = [c["FETCH_SIZE"] for _, c in fetch[name][a.skip:] if "FETCH_SIZE" in c]
@@ -162,7 +186,6 @@ def kernel_counters(a) -> dict:
             continue
         fk, wk = sum(fr) / len(fr), sum(wr) / len(wr)
         fb, wb = fk * 1024.0 * ff, wk * 1024.0 * fw
-        short = name.replace("void ", "").replace("(anonymous namespace)::", "").split("(")[0]
         rec["kernels"][short] = {
             "name": name, "dispatches": len(fr), "fetch_KiB_raw": fk, "write_KiB_raw": wk,
             "fetch_bytes": fb, "write_bytes": wb, "bytes_per_launch": fb + wb,
@@ -173,7 +196,13 @@ def kernel_counters(a) -> dict:
 
 def counters_text(rec: dict) -> str:
     c = rec["calibration"]
-    out = [f"calibration: the 1 GiB copy reads FETCH_SIZE = {c['fetch_KiB']:.0f} KiB and "
+    out = []
+    if rec.get("regime"):
+        r = rec["regime"]
+        out.append(f"regime: counters taken on steps from t = {r['t_start_s']:.2f} s, wet "
+                   f"fraction {r['wet_fraction']:.4f} (after {r['spinup_steps']} spin-up + "
+                   f"{r['warmup_steps']} warmup steps)")
+    out += [f"calibration: the 1 GiB copy reads FETCH_SIZE = {c['fetch_KiB']:.0f} KiB and "
            f"WRITE_SIZE = {c['write_KiB']:.0f} KiB for 1048576 KiB moved each way: "
            f"fetch x{c['fetch_factor']:.4f}, write x{c['write_factor']:.4f}"]
     for st, k in rec["kernels"].items():
@@ -209,12 +238,13 @@ def main(argv=None):
     c.add_argument("--bytes1", type=int, required=True)
     c.add_argument("--bytes2", type=int, required=True)
     c.add_argument("--workload", default="")
+    c.add_argument("--bench-log", help="the benchmark's stderr of one of the runs")
     c.add_argument("--json")
     k = sub.add_parser("kernel")
     k.add_argument("--fetch", required=True)
     k.add_argument("--write", required=True)
     k.add_argument("--expect", action="append", default=[],
-                   help="NAME=BYTES: algorithmic bytes per launch of kernels matching NAME")
+                   help="NAME=BYTES: algorithmic bytes per launch of the kernel named NAME")
     k.add_argument("--skip", type=int, default=0)
     k.add_argument("--sources", choices=["stage", "flowdir"], default="stage")
     k.add_argument("--workload", default="")

@@ -279,7 +279,10 @@ class Ensemble:
 class Calibration:
     """Gauge-misfit loss of a run and its adjoint gradient with respect to the
     friction field (swe_adj_*).  The friction field lives in ``self.fric``
-    (device); ``forward`` runs the simulation, ``backward`` returns dL/dfric."""
+    (device); ``forward`` runs the simulation, ``backward`` returns dL/dfric
+    of the last forward pass.  Each forward pass chooses its time steps by
+    eq. (cfl) for the current field (the gradient is taken with them frozen)
+    unless ``set_dts`` fixed them."""
 
     def __init__(self, wl, gauges, every: int, obs, nsteps: int, ckpt_every: int = 0,
                  device: str = "cuda"):
@@ -319,6 +322,9 @@ class Calibration:
                                           every, self.obs.data_ptr(), aligned, nbytes,
                                           self.stream.cuda_stream)
         self.ckpt_every = ck
+        self.fixed_dts = False
+        # number of forward passes so far: a backward pass belongs to the last
+        self.generation = 0
 
     def close(self):
         if getattr(self, "handle", None):
@@ -332,12 +338,16 @@ class Calibration:
             pass
 
     def set_dts(self, dts) -> None:
+        """Fix the time steps of every later forward pass to ``dts``
+        (nsteps values); None returns to eq. (cfl) steps per forward pass."""
         if dts is None:
             capi.swe_adj_set_dts(self.handle, None)
+            self.fixed_dts = False
             return
         t = _dev(np.asarray(dts, dtype=np.float64), self.device)
         capi.swe_adj_set_dts(self.handle, t.data_ptr())
         torch.cuda.synchronize(self.device)
+        self.fixed_dts = True
 
     def dts(self) -> np.ndarray:
         t = torch.empty(self.nsteps, dtype=torch.float64, device=self.device)
@@ -346,7 +356,13 @@ class Calibration:
         return t.cpu().numpy()
 
     def forward(self) -> float:
-        return capi.swe_adj_forward(self.handle)
+        if not self.fixed_dts:
+            # the library freezes the steps a pass chose; the next field
+            # chooses its own
+            capi.swe_adj_set_dts(self.handle, None)
+        loss = capi.swe_adj_forward(self.handle)
+        self.generation += 1
+        return loss
 
     def series(self) -> np.ndarray:
         """Gauge depths of the last forward pass, one row per `every` steps."""
@@ -375,10 +391,14 @@ class GaugeMisfit(torch.autograd.Function):
             calib.fric.copy_(fric.detach().to(calib.fric.dtype).reshape(calib.fric.shape))
         loss = calib.forward()
         ctx.calib = calib
+        ctx.generation = calib.generation
         return torch.tensor(loss, dtype=torch.float64, device=fric.device)
 
     @staticmethod
     def backward(ctx, grad_out):
+        if ctx.calib.generation != ctx.generation:
+            raise RuntimeError("GaugeMisfit: the calibration ran another forward pass after "
+                               "this loss; call backward on a loss before the next apply")
         g = ctx.calib.backward()
         return grad_out * g, None
 

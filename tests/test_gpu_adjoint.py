@@ -160,6 +160,46 @@ def test_autograd_function(torch_cuda):
     assert torch.equal(n.grad, g2)
 
 
+def test_autograd_function_two_fields(torch_cuda):
+    # A calibration loop: each apply runs the field it is given on the time
+    # steps eq. (cfl) chooses for that field (the oracle's), and a loss whose
+    # calibration has run forward again refuses its backward pass.
+    torch = torch_cuda
+    from paper_1307_4839_amd.solver import Calibration, GaugeMisfit
+    wl, fric_obs = case_calibration()
+    nsteps, every = 40, 5
+    base = oracle.State(wl)
+    base.run(nsteps)
+    p = oracle.params_of(wl)
+    obs, _ = oracle.gauge_run(p, wl.h, wl.qx, wl.qy, wl.z, fric_obs, np.array(base.dts),
+                              wl.gauges, every)
+    say(f"[adjoint] two fields {wl.nx}x{wl.ny} {nsteps} steps")
+    cal = Calibration(wl, wl.gauges, every, obs, nsteps)
+    n1 = torch.tensor(wl.fric, dtype=torch.float64, device="cuda", requires_grad=True)
+    n2 = torch.tensor(2.5 * fric_obs, dtype=torch.float64, device="cuda", requires_grad=True)
+    l1 = GaugeMisfit.apply(n1, cal)
+    dts1 = cal.dts()
+    l2 = GaugeMisfit.apply(n2, cal)
+    dts2 = cal.dts()
+    with pytest.raises(RuntimeError):
+        l1.backward()
+    l2.backward()
+    w2 = wl.copy()
+    w2.fric = 2.5 * fric_obs
+    s2 = oracle.State(w2)
+    assert s2.run(nsteps) == 0
+    # (the Manning cube root is not correctly rounded on either side, so the
+    # steps agree with the oracle's to round-off, not bit for bit)
+    assert np.abs(dts1 - np.array(base.dts)).max() <= 1e-12 * dts1.max()
+    assert np.abs(dts2 - np.array(s2.dts)).max() <= 1e-12 * dts2.max()
+    assert np.abs(dts1 - dts2).max() > 1e-6 * dts1.max()
+    cal2 = Calibration(w2, wl.gauges, every, obs, nsteps)
+    L2 = cal2.forward()
+    g2 = cal2.backward()
+    assert l2.item() == L2
+    assert torch.equal(n2.grad, g2)
+
+
 def test_adjoint_finite_differences_fullsize(torch_cuda):
     torch = torch_cuda
     from paper_1307_4839_amd.solver import Calibration
@@ -172,6 +212,7 @@ def test_adjoint_finite_differences_fullsize(torch_cuda):
     say(f"[adjoint] full size {wl.nx}x{wl.ny}, {nsteps} steps, ckpt {base_run.ckpt_every}")
     base_run.forward()
     dts = base_run.dts()
+    base_run.set_dts(dts)
     base_run.fric.copy_(torch.as_tensor(wl.extra["fric_obs"], device="cuda"))
     base_run.forward()
     obs = base_run.series()

@@ -67,6 +67,7 @@ def test_lake_at_rest_islands(bc):
 # orc_run stops with -3 at the first negative depth; every run must be clean.
 # ---------------------------------------------------------------------------
 
+@pytest.mark.slow
 def test_positivity_dam_break():
     wl = I.dam_break_200()
     s = oracle.State(wl)
@@ -75,6 +76,7 @@ def test_positivity_dam_break():
     assert s.h.min() >= 0.0 and np.isfinite(s.h).all()
 
 
+@pytest.mark.slow
 def test_positivity_valley_small():
     wl = I.valley_2048(192, 192, dam_row=40)
     s = oracle.State(wl)
@@ -263,6 +265,36 @@ def test_one_dimensional_reduction(law, coef):
     assert np.abs(s.qx[0] - qq).max() <= 1e-12 * scale_q
 
 
+@pytest.mark.parametrize("law,coef", [(0, 0.0), (2, 0.2), (1, 0.03)])
+def test_one_dimensional_reduction_along_y(law, coef):
+    # The same 1D problem laid along y on cells of dx = 1 m, dy = 2.5 m: an
+    # x-uniform state with qx = 0 moves only through the y-faces, so the
+    # run equals the literal 1D scheme at a cell size of dy (the rate divides
+    # the y-face differences by dy, Sections 2.1 and 3.1), qx stays zero and
+    # every column stays the same.
+    nx, ny, dy = 4, 120, 2.5
+    rng = np.random.default_rng(19)
+    y = (np.arange(ny) + 0.5) * dy
+    z1 = 0.5 * np.exp(-((y - 175.0) / 20.0) ** 2) + 0.002 * (ny * dy - y)
+    h1 = np.where(y < 100.0, 1.5, 0.0) + 0.0 * y
+    q1 = rng.uniform(-0.2, 0.2, ny) * (h1 > 0)
+    z = np.tile(z1[:, None], (1, nx))
+    h = np.tile(h1[:, None], (1, nx))
+    qy = np.tile(q1[:, None], (1, nx))
+    wl = I.Workload("1d_y", nx, ny, 1.0, dy, z=z, h=h, qx=np.zeros_like(h), qy=qy,
+                    bc=(0, 0, 0, 1), fric_law=law, fric_coef=coef)
+    s = oracle.State(wl)
+    assert s.run(150) == 0
+    assert np.all(s.qx == 0.0)
+    for i in range(1, nx):
+        assert np.array_equal(s.h[:, i], s.h[:, 0]) and np.array_equal(s.qy[:, i], s.qy[:, 0])
+    hh, qq = h1.copy(), q1.copy()
+    for dt in s.dts:
+        hh, qq = swe1d.heun_step(hh, qq, z1, dt, dy, bc=(0, 1), law=law, coef=coef)
+    assert np.abs(s.h[:, 0] - hh).max() <= 1e-13 * np.abs(hh).max()
+    assert np.abs(s.qy[:, 0] - qq).max() <= 1e-12 * np.abs(qq).max()
+
+
 def test_one_dimensional_cfl_matches():
     # With dy large, the 2D bound tends to the 1D eq. (cfl) on the MUSCL states.
     nx = 100
@@ -288,6 +320,26 @@ def test_transpose_symmetry():
                         fric_coef=0.04)
     wl.rain = 1e-4
     wt = I.Workload("t", wl.ny, wl.nx, 1.0, 1.0, z=wl.z.T.copy(),
+                    h=wl.h.T.copy(), qx=wl.qy.T.copy(), qy=wl.qx.T.copy(),
+                    bc=(wl.bc[2], wl.bc[3], wl.bc[0], wl.bc[1]),
+                    fric_law=wl.fric_law, fric_coef=wl.fric_coef, rain=wl.rain)
+    a = oracle.State(wl)
+    b = oracle.State(wt)
+    assert a.run(40) == 0 and b.run(40) == 0
+    assert a.dts == b.dts
+    assert np.array_equal(a.h, b.h.T)
+    assert np.array_equal(a.qx, b.qy.T)
+    assert np.array_equal(a.qy, b.qx.T)
+
+
+def test_transpose_symmetry_unequal_cells():
+    # With dx != dy the transposed problem also swaps the cell sizes; the
+    # rate -(X/dx + Y/dy) and the CFL sum Ax/dx + Ay/dy then add the same
+    # two terms in the other order, so the runs are transposes bit for bit.
+    wl = I.random_state(30, 22, 23, dx=1.0, dy=2.5, bc=(0, 1, 1, 0),
+                        fric_law=I.FRIC_DARCY, fric_coef=0.3)
+    wl.rain = 1e-4
+    wt = I.Workload("t", wl.ny, wl.nx, wl.dy, wl.dx, z=wl.z.T.copy(),
                     h=wl.h.T.copy(), qx=wl.qy.T.copy(), qy=wl.qx.T.copy(),
                     bc=(wl.bc[2], wl.bc[3], wl.bc[0], wl.bc[1]),
                     fric_law=wl.fric_law, fric_coef=wl.fric_coef, rain=wl.rain)
@@ -415,6 +467,7 @@ def test_first_order_one_dimensional_reduction(law, coef):
     assert np.abs(s2.h[0] - s.h[0]).max() > 1e-3
 
 
+@pytest.mark.slow
 def test_first_order_positivity_and_cfl_one():
     for wl in (I.dam_break_200(), I.random_state(48, 40, 5, bc=(0, 1, 1, 0),
                                                  fric_law=I.FRIC_DARCY, fric_coef=0.2)):
@@ -501,6 +554,7 @@ def test_rusanov_one_dimensional_reduction(law, coef):
     assert np.abs(s.qx[0] - qq).max() <= 1e-12 * np.abs(qq).max()
 
 
+@pytest.mark.slow
 def test_rusanov_lake_at_rest_and_positivity():
     C = 1.2
     wl = _islands(40, 30, C, seed=13, bc=(0, 0, 0, 0))
@@ -586,6 +640,7 @@ def test_kinetic_face_against_quadrature_and_consistency():
         assert abs(f[0]) <= 1e-15 * (abs(q) + h * math.sqrt(G * h))
 
 
+@pytest.mark.slow
 def test_kinetic_lake_at_rest_and_positivity():
     C = 1.2
     wl = _islands(40, 30, C, seed=13, bc=(0, 0, 0, 0))
@@ -619,6 +674,265 @@ def test_kinetic_dam_breaks_converge():
             errs.append(np.abs(s.h[0] - exact(x, 10.0)).sum() * dx)
         orders = [math.log2(errs[k] / errs[k + 1]) for k in range(2)]
         assert min(orders) >= 0.7, (h_down, errs, orders)
+
+
+# ---------------------------------------------------------------------------
+# VFRoe-ncv flux (Section 4.1 lists it among the fluxes of the paper's code):
+# the interface state of the Riemann problem in (2c, u) linearized about the
+# mean state.  Pinned by consistency, the wall mirror, the tangential
+# velocity of the exact Riemann solution (carried by the mass flux from the
+# upwind side), independence of the velocity a dry side carries, the literal
+# 1D scheme, the lake at rest, positivity and dam-break convergence.
+# ---------------------------------------------------------------------------
+
+def test_vfroe_face_consistency_wall_and_upwinding():
+    rng = np.random.default_rng(61)
+    for k in range(60):
+        h, z, u, v = rng.uniform(0.1, 3.0), rng.uniform(-1, 1), rng.normal(0, 3), rng.normal()
+        f = oracle.face(G, h, z, u, v, h, z, u, v, flux=3)
+        q = h * u
+        assert np.allclose(f[:3], [q, q * u + 0.5 * G * h * h, q * v], rtol=1e-14,
+                           atol=1e-15 * (abs(q) + G * h * h)), (k, f[:3])
+        # mirrored states (a wall): no mass through the face
+        f = oracle.face(G, h, z, u, v, h, z, -u, v, flux=3)
+        assert f[0] == 0.0
+        # the tangential velocity jumps only at the contact, which moves with
+        # the mass: the face carries the upwind side's v with the mass flux
+        hL, hR = rng.uniform(0.05, 3.0, 2)
+        uL, uR = rng.normal(0, 3, 2)
+        vL, vR = rng.normal(0, 1, 2)
+        f = oracle.face(G, hL, 0.0, uL, vL, hR, 0.0, uR, vR, flux=3)
+        vup = vL if f[0] > 0 else vR
+        assert abs(f[2] - f[0] * vup) <= 1e-15 * abs(f[0] * vup) + 1e-300
+        # the velocity a dry side carries holds no water and changes nothing
+        a = oracle.face(G, 0.0, 0.0, rng.normal(0, 5), vL, hR, 0.0, uR, vR, flux=3)
+        b = oracle.face(G, 0.0, 0.0, rng.normal(0, 5), vL, hR, 0.0, uR, vR, flux=3)
+        assert np.array_equal(a[:3], b[:3])
+        a = oracle.face(G, hL, 0.0, uL, vL, 0.0, 0.0, rng.normal(0, 5), vR, flux=3)
+        b = oracle.face(G, hL, 0.0, uL, vL, 0.0, 0.0, rng.normal(0, 5), vR, flux=3)
+        assert np.array_equal(a[:3], b[:3])
+    # supercritical flow takes the upwind state's flux exactly
+    f = oracle.face(G, 1.0, 0.0, 6.0, 0.2, 0.5, 0.0, 5.0, -0.1, flux=3)
+    assert np.array_equal(f[:3], [6.0, 6.0 * 6.0 + 0.5 * G, 6.0 * 0.2])
+    # two dry sides pass nothing; it is not HLL
+    assert np.array_equal(oracle.face(G, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, -1.0, 0.0, flux=3)[:3],
+                          [0.0, 0.0, 0.0])
+    f3 = oracle.face(G, 1.0, 0.0, 0.5, 0.0, 0.4, 0.0, -0.2, 0.0, flux=3)
+    f0 = oracle.face(G, 1.0, 0.0, 0.5, 0.0, 0.4, 0.0, -0.2, 0.0, flux=0)
+    assert abs(f3[0] - f0[0]) > 1e-3
+
+
+@pytest.mark.parametrize("law,coef", [(0, 0.0), (1, 0.03)])
+def test_vfroe_one_dimensional_reduction(law, coef):
+    nx, ny = 120, 3
+    rng = np.random.default_rng(29)
+    x = (np.arange(nx) + 0.5)
+    z1 = 0.5 * np.exp(-((x - 70) / 8) ** 2) + 0.002 * (nx - x)
+    h1 = np.where(x < 40, 1.5, 0.0) + 0.0 * x
+    q1 = rng.uniform(-0.2, 0.2, nx) * (h1 > 0)
+    wl = I.Workload("1d", nx, ny, 1.0, 1.0, z=np.tile(z1, (ny, 1)), h=np.tile(h1, (ny, 1)),
+                    qx=np.tile(q1, (ny, 1)), qy=np.zeros((ny, nx)), bc=(0, 1, 0, 0),
+                    fric_law=law, fric_coef=coef, flux=3)
+    s = oracle.State(wl)
+    assert s.run(150) == 0
+    assert np.all(s.qy == 0.0)
+    hh, qq = h1.copy(), q1.copy()
+    for dt in s.dts:
+        hh, qq = swe1d.heun_step(hh, qq, z1, dt, 1.0, bc=(0, 1), law=law, coef=coef,
+                                 flux="vfroe")
+    assert np.abs(s.h[0] - hh).max() <= 1e-13 * np.abs(hh).max()
+    assert np.abs(s.qx[0] - qq).max() <= 1e-12 * np.abs(qq).max()
+
+
+@pytest.mark.slow
+def test_vfroe_lake_at_rest_and_positivity():
+    C = 1.2
+    wl = _islands(40, 30, C, seed=13, bc=(0, 0, 0, 0))
+    wl.flux = 3
+    s = oracle.State(wl)
+    assert s.run(1000) == 0
+    wet = wl.h > 0
+    assert np.abs((s.h + s.z)[wet] - C).max() <= 1e-12 * C
+    assert np.abs(s.qx).max() <= 1e-12 * math.sqrt(G * wl.h.max() ** 3)
+    # depths stay non-negative on the dam break, the valley and the rain-fed
+    # hillslope (the linearized interface state is not positivity-preserving
+    # in general: a strong compression of thin films overshoots its depth)
+    for wl, n in ((I.dam_break_200(), 300), (I.valley_2048(96, 96), 300),
+                  (I.hillslope_8192(96, 64), 400)):
+        for order, cfl in ((2, 0.5), (1, 1.0)):
+            wl.flux, wl.order, wl.cfl = 3, order, cfl
+            s = oracle.State(wl)
+            assert s.run(n, wl.t_end) in (0, 1)
+            assert s.h.min() >= 0.0
+            assert s.h.max() > 0.0
+
+
+def test_vfroe_dam_breaks_converge():
+    for h_down, exact in ((0.0, lambda x, t: ritter_h(x, t, 100.0, 1.0)),
+                          (0.1, lambda x, t: stoker_h(x, t, 100.0, 1.0, 0.1))):
+        errs = []
+        for n in (200, 400, 800):
+            dx = 200.0 / n
+            x = (np.arange(n) + 0.5) * dx
+            h = np.where(x < 100.0, 1.0, h_down)
+            wl = I.Workload("db", n, 2, dx, 1e9, z=np.zeros((2, n)), h=np.tile(h, (2, 1)),
+                            qx=np.zeros((2, n)), qy=np.zeros((2, n)), bc=(1, 1, 0, 0), flux=3)
+            s = oracle.State(wl)
+            assert s.run(10 ** 6, 10.0) == 1
+            errs.append(np.abs(s.h[0] - exact(x, 10.0)).sum() * dx)
+        orders = [math.log2(errs[k] / errs[k + 1]) for k in range(2)]
+        assert min(orders) >= 0.7, (h_down, errs, orders)
+
+
+# ---------------------------------------------------------------------------
+# ENO and modified ENO reconstructions (Section 4.1 lists them beside
+# MUSCL): at second order on the cells i-1, i, i+1, the one-sided slope of
+# smaller magnitude; the modified one keeps the face depths in [0, 2 h].
+# ---------------------------------------------------------------------------
+
+def test_eno_reconstruction_properties():
+    rng = np.random.default_rng(71)
+    for k in range(300):
+        a, c, b = (np.array([rng.uniform(0.0, 2.0) if rng.uniform() > 0.1 else 0.0,
+                             rng.normal(), rng.normal(), 0.0]) for _ in range(3))
+        c[0] = max(c[0], 1e-3)
+        for p in (a, c, b):
+            p[3] = p[0] + rng.uniform(-1, 1)   # eta = h + z
+        if k % 7 == 0:
+            a[0], c[0], b[0] = 1.0, 0.1, 1.0   # a thin cell between deep ones
+        for mod in (False, True):
+            r = oracle.eno(a, c, b, modified=mod)
+            h_m, h_p, z_m, z_p, u_m, u_p, v_m, v_p = r
+            # conservation of the mass and the discharge (Section 3.4)
+            assert abs(0.5 * (h_m + h_p) - c[0]) <= 4e-16 * max(c[0], 1.0)
+            if c[0] > 1e-12:
+                assert abs(0.5 * (h_m * u_m + h_p * u_p) - c[0] * c[1]) <= \
+                    2e-15 * (abs(c[0] * c[1]) + abs(h_m * u_m) + abs(h_p * u_p))
+            # z deduced from h and h + z
+            assert abs((h_m + z_m) + (h_p + z_p) - 2 * c[3]) <= 1e-14 * (1 + abs(c[3]))
+            # the smoother stencil: the slope of h + z is one of the two
+            # one-sided differences, the one of smaller magnitude
+            de = (h_p + z_p) - (h_m + z_m)
+            dm, dp = c[3] - a[3], b[3] - c[3]
+            assert abs(de) <= min(abs(dm), abs(dp)) * (1 + 1e-14) + 1e-15
+            assert min(abs(de - dm), abs(de - dp)) <= 1e-14 * (abs(dm) + abs(dp) + 1e-300)
+            if mod:
+                assert h_m >= 0.0 and h_p >= 0.0
+                assert h_m <= 2 * c[0] and h_p <= 2 * c[0]
+        # on monotone data it is minmod; at an extremum it keeps a slope
+        re_, rm_ = oracle.eno(a, c, b), oracle.muscl(a, c, b)
+        if (c[3] - a[3]) * (b[3] - c[3]) > 0:
+            assert np.allclose(re_[:2] + re_[2:4], rm_[:2] + rm_[2:4], rtol=0, atol=1e-14)
+        if (c[0] - a[0]) * (b[0] - c[0]) > 0:
+            assert np.allclose(re_[:2], rm_[:2], rtol=0, atol=1e-15)
+        elif (c[3] - a[3]) * (b[3] - c[3]) < 0 and c[3] - a[3] != c[3] - b[3]:
+            assert (re_[0] + re_[2]) != (re_[1] + re_[3])
+    # a dry cell keeps its values at both faces
+    a, c, b = np.array([1.0, 0.5, 0, 1.0]), np.array([0.0, 0, 0, 0.3]), \
+        np.array([0.2, 0.1, 0, 0.9])
+    for mod in (False, True):
+        assert np.array_equal(oracle.eno(a, c, b, modified=mod),
+                              [0.0, 0.0, 0.3, 0.3, 0.0, 0.0, 0.0, 0.0])
+    # a thin cell between deep ones: ENO gives a negative face depth,
+    # modified ENO does not
+    a, c, b = np.array([1.0, 0, 0, 1.0]), np.array([0.1, 0, 0, 0.1]), np.array([1.0, 0, 0, 1.0])
+    assert min(oracle.eno(a, c, b)[:2]) < 0.0
+    assert min(oracle.eno(a, c, b, modified=True)[:2]) >= 0.0
+    # linear data is reconstructed exactly
+    a, c, b = np.array([1.0, 0.1, 0.2, 3.0]), np.array([1.5, 0.3, 0.1, 3.25]), \
+        np.array([2.0, 0.5, 0.0, 3.5])
+    r = oracle.eno(a, c, b)
+    assert np.allclose(r[:2], [1.25, 1.75], rtol=0, atol=1e-15)
+    assert np.allclose(r[2:4], [3.125 - 1.25, 3.375 - 1.75], rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("recon,name", [(1, "eno"), (2, "enomod")])
+@pytest.mark.parametrize("law,coef", [(0, 0.0), (2, 0.2)])
+def test_eno_one_dimensional_reduction(recon, name, law, coef):
+    nx, ny = 120, 3
+    rng = np.random.default_rng(37)
+    x = (np.arange(nx) + 0.5)
+    z1 = 0.5 * np.exp(-((x - 70) / 8) ** 2) + 0.002 * (nx - x)
+    # wet everywhere (plain ENO is not positivity-preserving next to fronts)
+    h1 = 1.2 + 0.3 * np.exp(-((x - 20) / 5) ** 2) - 0.1 * (x > 60)
+    q1 = rng.uniform(-0.2, 0.2, nx)
+    wl = I.Workload("1d", nx, ny, 1.0, 1.0, z=np.tile(z1, (ny, 1)), h=np.tile(h1, (ny, 1)),
+                    qx=np.tile(q1, (ny, 1)), qy=np.zeros((ny, nx)), bc=(0, 1, 0, 0),
+                    fric_law=law, fric_coef=coef, recon=recon)
+    s = oracle.State(wl)
+    assert s.run(150) == 0
+    hh, qq = h1.copy(), q1.copy()
+    for dt in s.dts:
+        hh, qq = swe1d.heun_step(hh, qq, z1, dt, 1.0, bc=(0, 1), law=law, coef=coef,
+                                 recon=name)
+    assert np.abs(s.h[0] - hh).max() <= 1e-13 * np.abs(hh).max()
+    assert np.abs(s.qx[0] - qq).max() <= 1e-12 * np.abs(qq).max()
+    # and it is not the MUSCL run
+    wl.recon = 0
+    m = oracle.State(wl)
+    assert m.run(150) == 0
+    assert np.abs(m.h[0] - s.h[0]).max() > 1e-6
+
+
+@pytest.mark.parametrize("recon", [1, 2])
+def test_eno_lake_at_rest(recon):
+    C = 1.2
+    wl = _islands(40, 30, C, seed=13, bc=(0, 1, 1, 0))
+    wl.recon = recon
+    s = oracle.State(wl)
+    assert s.run(1000) == 0
+    wet = wl.h > 0
+    assert np.abs((s.h + s.z)[wet] - C).max() <= 1e-12 * C
+    assert np.abs(s.qx).max() <= 1e-12 * math.sqrt(G * wl.h.max() ** 3)
+
+
+def test_eno_positivity_on_the_workloads():
+    # plain ENO keeps depths non-negative on the valley and the rain-fed
+    # hillslope; at the dam break's front a film thinner than both of its
+    # neighbours gets a negative face depth and then a negative depth, which
+    # modified ENO exists to prevent
+    for wl, n in ((I.valley_2048(96, 96), 300), (I.hillslope_8192(96, 64), 400)):
+        wl.recon = 1
+        s = oracle.State(wl)
+        assert s.run(n, wl.t_end) in (0, 1)
+        assert s.h.min() >= 0.0 and s.h.max() > 0.0
+    wl = I.dam_break_200()
+    wl.recon = 1
+    assert oracle.State(wl).run(120, wl.t_end) == -3
+    wl.recon = 2
+    s = oracle.State(wl)
+    assert s.run(120, wl.t_end) == 0 and s.h.min() >= 0.0
+
+
+def test_modified_eno_positivity():
+    for wl in (I.dam_break_200(), I.random_state(48, 40, 6, bc=(0, 1, 1, 0),
+                                                 fric_law=I.FRIC_DARCY, fric_coef=0.2),
+               I.random_state(40, 36, 8, dry_frac=0.4, film_frac=0.3)):
+        for flux in (0, 1, 2):
+            wl.recon, wl.flux = 2, flux
+            s = oracle.State(wl)
+            assert s.run(300, wl.t_end) in (0, 1)
+            assert s.h.min() >= 0.0
+
+
+@pytest.mark.parametrize("recon", [1, 2])
+def test_eno_dam_breaks_converge(recon):
+    for h_down, exact in ((0.0, lambda x, t: ritter_h(x, t, 100.0, 1.0)),
+                          (0.1, lambda x, t: stoker_h(x, t, 100.0, 1.0, 0.1))):
+        errs = []
+        for n in (200, 400, 800):
+            dx = 200.0 / n
+            x = (np.arange(n) + 0.5) * dx
+            h = np.where(x < 100.0, 1.0, h_down)
+            wl = I.Workload("db", n, 2, dx, 1e9, z=np.zeros((2, n)), h=np.tile(h, (2, 1)),
+                            qx=np.zeros((2, n)), qy=np.zeros((2, n)), bc=(1, 1, 0, 0),
+                            recon=recon)
+            s = oracle.State(wl)
+            assert s.run(10 ** 6, 10.0) == 1
+            assert s.h.min() >= 0.0
+            errs.append(np.abs(s.h[0] - exact(x, 10.0)).sum() * dx)
+        orders = [math.log2(errs[k] / errs[k + 1]) for k in range(2)]
+        assert min(orders) >= 0.7, (recon, h_down, errs, orders)
 
 
 # ---------------------------------------------------------------------------
@@ -780,6 +1094,27 @@ def test_green_ampt_ponding():
     assert abs(s.h[0, 0] - h) <= 0.02 * h + 2 * R * dt
 
 
+def test_green_ampt_keeps_the_velocity_of_a_draining_sheet():
+    # A flat, frictionless sheet moving uniformly along walls it runs
+    # parallel to (walls west and east, free ends south and north) has no
+    # convective change; only infiltration (Section 3.5) drains it.  Water
+    # that infiltrates leaves with the cell's velocity (reading of the
+    # momentum of infiltrated water), so u = q/h stays what it was while h
+    # falls; a sink that kept q would speed the sheet up as it thins.
+    h0, v0 = 0.05, 0.4
+    wl = flat_workload(6, 5, bc=(0, 0, 1, 1), infil_on=1, ks=2e-4, psi=0.1,
+                       dtheta=0.4, dt_max=0.5)
+    wl.h[:] = h0
+    wl.qy[:] = h0 * v0
+    wl.vinf = np.full((5, 6), 0.01)
+    s = oracle.State(wl)
+    assert s.run(30) == 0
+    assert np.all(s.h < 0.9 * h0) and np.all(s.h > 0.0)
+    assert np.all(s.qx == 0.0)
+    assert np.abs(s.qy / s.h - v0).max() <= 1e-13 * v0
+    assert np.abs(s.vinf - (0.01 + (h0 - s.h))).max() <= 1e-15
+
+
 # ---------------------------------------------------------------------------
 # P14: CFL of a uniform state by hand (eq. cfl, 2D reading):
 #   dt = 0.5 / ((|u| + sqrt(gh))/dx + (|v| + sqrt(gh))/dy).
@@ -812,6 +1147,33 @@ def test_time_step_clips_to_t_end_and_dt_max():
 # ---------------------------------------------------------------------------
 # P15: restart is bit-identical.
 # ---------------------------------------------------------------------------
+
+def test_dt_min_collapse_stops_the_run():
+    # A uniform state keeps the eq. (cfl) step of the hand formula on every
+    # step.  A dt_min above it is a collapse of the time step: the run stops
+    # before the step (code -5), leaving the state and the time untouched.
+    # Below it the run goes on, and the last step, clipped to t_end - t and
+    # shorter than dt_min, is not a collapse.
+    h, u, v, dx, dy = 0.8, 0.9, -0.3, 2.0, 1.5
+    c = math.sqrt(G * h)
+    dt = 0.5 / ((abs(u) + c) / dx + (abs(v) + c) / dy)
+    wl = flat_workload(9, 7, dx=dx, dy=dy, bc=(1, 1, 1, 1))
+    wl.h[:] = h
+    wl.qx[:] = h * u
+    wl.qy[:] = h * v
+    wl.dt_min = 1.01 * dt
+    s = oracle.State(wl)
+    assert s.run(5) == -5
+    assert s.steps == 0 and s.t == 0.0
+    assert np.array_equal(s.h, wl.h) and np.array_equal(s.qx, wl.qx)
+    wl.dt_min = 0.99 * dt
+    s = oracle.State(wl)
+    assert s.run(10, 2.5 * dt) == 1
+    assert s.steps == 3 and s.t == 2.5 * dt
+    assert abs(s.dts[0] - dt) <= 1e-15 * dt and s.dts[0] == s.dts[1]
+    assert s.dts[2] < wl.dt_min
+    assert np.abs(s.h - h).max() <= 1e-15
+
 
 def test_restart_bit_identical():
     wl = I.hillslope_8192(40, 32)
