@@ -369,6 +369,33 @@ int swe_set_gauges(swe_ctx* ctx, const int32_t* cells, int32_t ngauges, int32_t 
  * array out when out is not NULL.  Synchronizes. */
 int swe_get_gauges(swe_ctx* ctx, double* out, int64_t max_copy, int64_t* nsamples);
 
+/* ---------------------------------------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops and harnesses that forbid hipMalloc.
+ *
+ * swe_run_noalloc is swe_create + swe_set_time(t0) + swe_step(nsteps, t_end)
+ * in one call, with the library's own scratch array as the workspace (a
+ * file-scope device array of 6 SWE_NOALLOC_MAX_CELLS doubles plus a scalar
+ * block, about 48 MiB, which every device the library runs on holds until
+ * the process ends).  It allocates nothing and creates no stream, event or
+ * graph: it validates, then enqueues the init, stage and copy kernels of
+ * the steps on `stream` (NULL = default stream) and returns without waiting.
+ * The steps, kernels and results are those of swe_step on the same inputs
+ * (bit for bit), with the default tiling, no gauges, no dt log and no
+ * hyetograph.  p and b as for swe_create (b's device buffers are the inputs
+ * and outputs: on completion the state is in b->h/qx/qy and V_inf in
+ * b->vinf); t0 finite; nsteps >= 0.  info is caller-owned device memory of 4
+ * doubles that receives, in stream order, the time reached, the last dt,
+ * the number of steps taken and the sticky SWE_FLAG_* bits (as doubles).
+ * Returns SWE_ENOMEM if nx ny > SWE_NOALLOC_MAX_CELLS, SWE_EINVAL for
+ * invalid arguments (nothing is enqueued then), SWE_EHIP if a launch fails.
+ * Every call on a device shares that device's scratch array, which keeps
+ * the last call's contents (the call clears what must start at zero): calls
+ * that overlap on one device (other streams, other host threads) race. */
+#define SWE_NOALLOC_MAX_CELLS (1 << 20)
+int swe_run_noalloc(const swe_params* p, const swe_buffers* b, double t0, int32_t nsteps,
+                    double t_end, void* stream, double* info);
+
 /* Human-readable text for an error code. */
 const char* swe_strerror(int code);
 

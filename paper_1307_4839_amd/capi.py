@@ -77,6 +77,8 @@ EXPORTS = {
     "swe_create": (C.c_int, [C.POINTER(swe_params), C.POINTER(swe_buffers),
                              C.c_void_p, C.c_size_t, C.c_void_p, C.POINTER(C.c_void_p)]),
     "swe_destroy": (C.c_int, [C.c_void_p]),
+    "swe_run_noalloc": (C.c_int, [C.POINTER(swe_params), C.POINTER(swe_buffers), C.c_double,
+                                  C.c_int32, C.c_double, C.c_void_p, C.c_void_p]),
     "swe_set_tiling": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
     "swe_get_tiling": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "swe_set_time": (C.c_int, [C.c_void_p, C.c_double]),
@@ -305,6 +307,17 @@ def swe_batch_set_boundary_values(b: int, member: int, side: int, h_b: float,
 
 def swe_step(ctx: int, nsteps: int, t_end: float = float("inf")) -> None:
     check(lib().swe_step(C.c_void_p(ctx), nsteps, t_end), "swe_step")
+
+
+SWE_NOALLOC_MAX_CELLS = 1 << 20
+
+
+def swe_run_noalloc(p: swe_params, b: swe_buffers, t0: float, nsteps: int, t_end: float,
+                    stream: Optional[int], info: int) -> int:
+    """Returns the status code (the caller checks it; no exception, so that
+    a test can see SWE_ENOMEM)."""
+    return lib().swe_run_noalloc(C.byref(p), C.byref(b), t0, nsteps, t_end,
+                                 C.c_void_p(stream or 0), C.c_void_p(info))
 
 
 def swe_get_time(ctx: int):

@@ -28,6 +28,7 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "swe.h"
@@ -549,6 +550,115 @@ int swe_step(swe_ctx* c, int32_t nsteps, double t_end) {
         hipLaunchKernelGGL(swe_copy_kernel, dim3(1024), dim3(256), 0, c->stream,
                            (const double*)c->m.qy[1], c->m.qy[0], n);
     }
+    return hip_ok(hipGetLastError());
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Runs without allocation (swe_run_noalloc)
+// ---------------------------------------------------------------------------
+
+namespace {
+
+// A scalar block, a second state and the stage rate for grids of up to
+// SWE_NOALLOC_MAX_CELLS cells: the workspace of swe_run_noalloc.  Every
+// device the library runs on holds its own copy until the process ends.
+constexpr size_t NOALLOC_PLANE = ((size_t)SWE_NOALLOC_MAX_CELLS * sizeof(double) + 255) / 256 * 256;
+constexpr size_t NOALLOC_BYTES = SCALAR_BYTES + 6 * NOALLOC_PLANE;
+__device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+// Device address of `scratch` on each device, taken once per device with the
+// device current (host code must not use the symbol's name as an address).
+constexpr int NOALLOC_DEVICES = 64;
+void* g_scratch[NOALLOC_DEVICES];
+std::mutex g_scratch_mu;
+
+int scratch_address(void** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= NOALLOC_DEVICES) return SWE_EHIP;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr)
+            return SWE_EHIP;
+        g_scratch[dev] = ptr;
+    }
+    *out = g_scratch[dev];
+    return SWE_OK;
+}
+
+// t, last dt, steps and status flags of the run into the caller's array
+__global__ void noalloc_info_kernel(const DevScalars* sc, int slot, double* info) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        info[0] = sc->t[slot];
+        info[1] = sc->last_dt;
+        info[2] = (double)sc->steps[slot];
+        info[3] = (double)sc->status;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int swe_run_noalloc(const swe_params* p, const swe_buffers* b, double t0, int32_t nsteps,
+                    double t_end, void* stream, double* info) {
+    int rc = check_params(p);
+    if (rc) return rc;
+    if (!b || !info || !b->h || !b->qx || !b->qy || !b->z) return SWE_EINVAL;
+    if (p->infil_on && !b->vinf) return SWE_EINVAL;
+    if (nsteps < 0 || !std::isfinite(t0) || std::isnan(t_end)) return SWE_EINVAL;
+    const size_t n = ncells(p);
+    if (n > (size_t)SWE_NOALLOC_MAX_CELLS) return SWE_ENOMEM;
+    void* base = nullptr;
+    rc = scratch_address(&base);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    MemberArgs m;
+    std::memset(&m, 0, sizeof m);
+    m.p = to_kparams(*p);
+    m.z = b->z;
+    m.fric = b->fric;
+    m.vinf = p->infil_on ? b->vinf : nullptr;
+    attach_fields(m, *b);
+    char* w = (char*)base;
+    m.sc = (DevScalars*)w;
+    w += SCALAR_BYTES;
+    m.h[0] = b->h; m.qx[0] = b->qx; m.qy[0] = b->qy;
+    m.h[1] = (double*)w; w += NOALLOC_PLANE;
+    m.qx[1] = (double*)w; w += NOALLOC_PLANE;
+    m.qy[1] = (double*)w; w += NOALLOC_PLANE;
+    m.ph = (double*)w; w += NOALLOC_PLANE;
+    m.pqx = (double*)w; w += NOALLOC_PLANE;
+    m.pqy = (double*)w;
+    // the scalar block keeps the last call's contents: start from zero
+    // accumulators and flags, time t0 and no hyetograph (a kernel, not a
+    // memset)
+    hipLaunchKernelGGL(swe_init_scalars_kernel, dim3(1), dim3(64), 0, s, m.sc, t0);
+    const int tx = default_tx(p->nx, p->ny), ty = auto_rows(p->nx, p->ny, tx);
+    const dim3 grid(strips_of(p->nx, tx), (p->ny + ty - 1) / ty);
+    int slot = 0, phase = 0;
+    for (int32_t k = 0; k < nsteps; ++k) {
+        TileIO io = host_step_io(m, phase, slot, t_end);
+        launch_stage<1>(tx, grid, s, m, io, ty);
+        if (m.p.order == 1)
+            launch_euler(s, m, io);
+        else
+            launch_stage<2>(tx, grid, s, m, io, ty);
+        slot ^= 1;
+        phase ^= 1;
+    }
+    if (phase == 1) {
+        hipLaunchKernelGGL(swe_copy_kernel, dim3(1024), dim3(256), 0, s, (const double*)m.h[1],
+                           m.h[0], n);
+        hipLaunchKernelGGL(swe_copy_kernel, dim3(1024), dim3(256), 0, s, (const double*)m.qx[1],
+                           m.qx[0], n);
+        hipLaunchKernelGGL(swe_copy_kernel, dim3(1024), dim3(256), 0, s, (const double*)m.qy[1],
+                           m.qy[0], n);
+    }
+    hipLaunchKernelGGL(noalloc_info_kernel, dim3(1), dim3(64), 0, s, (const DevScalars*)m.sc,
+                       slot, info);
     return hip_ok(hipGetLastError());
 }
 
