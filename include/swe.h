@@ -103,10 +103,15 @@ typedef struct swe_params {
                             paper's), 1 Rusanov (local Lax-Friedrichs),
                             2 kinetic (Perthame-Simeoni, particle velocities
                             uniform on [u - s, u + s], s = sqrt(3gh/2); the
-                            time step then uses |u| + s as the speed).
-                            The adjoint takes the second-order scheme
-                            (any flux); the members of an ensemble share
-                            order and flux. */
+                            time step then uses |u| + s as the speed),
+                            3 VFRoe-ncv (Section 4.1: the interface state of
+                            the Riemann problem in (2 sqrt(gh), u)
+                            linearized about the mean state; a dry side
+                            takes the other side's velocity; not
+                            positivity-preserving in general).  The adjoint
+                            takes the second-order MUSCL scheme with fluxes
+                            0-2; the members of an ensemble share order and
+                            flux (0-2, MUSCL at second order). */
     double bc_h[4];      /* imposed depth [m] per side (west, east, south,
                             north), finite and > 0 where bc is IMPOSED_H or
                             IMPOSED_HQ; ignored elsewhere */
@@ -121,9 +126,16 @@ typedef struct swe_params {
                             raised and later steps are not taken either
                             while it holds.  The last step of a run, clipped
                             to t_end - t, is exempt (dt == t_end - t). */
-    int32_t recon;       /* second-order reconstruction: 0 MUSCL with
-                            minmod (the paper's, Section 3.4); other values
-                            are refused */
+    int32_t recon;       /* second-order reconstruction (Section 4.1 lists
+                            MUSCL, ENO and modified ENO): 0 MUSCL with
+                            minmod (the paper's, Section 3.4); 1 ENO: the
+                            slope of h, h+z and the velocities is the
+                            one-sided difference of smaller magnitude (the
+                            left one on ties), which keeps slopes at extrema
+                            and may give negative face depths; 2 modified
+                            ENO: ENO with the depth slope limited to
+                            |D| <= 2 h_i (face depths in [0, 2 h_i]).  Used
+                            at second order only. */
 } swe_params;
 
 /* Optional per-cell fields below are read only, [ny][nx] FP64 device

@@ -1244,6 +1244,8 @@ int swe_adj_create(const swe_params* p, const swe_buffers* b, int32_t nsteps,
         return SWE_EINVAL;
     // the second-order scheme (any of the three fluxes)
     if (p->infil_on || p->fric_law == SWE_FRIC_NONE || p->order == 1) return SWE_EINVAL;
+    // the reverse sweeps exist for MUSCL and the HLL, Rusanov and kinetic fluxes
+    if (p->flux == 3 || p->recon != 0) return SWE_EINVAL;
     // walls and free outflow only: the reverse pass has no imposed ghosts
     for (int s = 0; s < 4; ++s)
         if (p->bc[s] >= SWE_BC_IMPOSED_H) return SWE_EINVAL;

@@ -400,6 +400,9 @@ int swe_batch_create(const swe_params* p, const swe_buffers* bufs, int32_t count
         // the members share the scheme (order and flux): one kernel per stage
         if ((p[k].order == 1) != (p[0].order == 1) || p[k].flux != p[0].flux)
             return SWE_EINVAL;
+        // the ensemble kernels take MUSCL and the HLL, Rusanov and kinetic
+        // fluxes (VFRoe-ncv and the ENO reconstructions: single contexts)
+        if (p[k].flux == 3 || (p[k].order != 1 && p[k].recon != 0)) return SWE_EINVAL;
         if (p[k].infil_on && !b.vinf) return SWE_EINVAL;
     }
     swe_batch* b = new (std::nothrow) swe_batch;

@@ -86,7 +86,9 @@ struct KParams {
     int fast_div;
     // 2: MUSCL + Heun; 1: first order (no reconstruction, one Euler stage)
     int order;
-    // 0: HLL; 1: Rusanov; 2: kinetic
+    // second-order reconstruction: 0 MUSCL, 1 ENO, 2 modified ENO
+    int recon;
+    // 0: HLL; 1: Rusanov; 2: kinetic; 3: VFRoe-ncv
     int flux;
     // some side has an imposed depth or discharge; its values per side
     // (west, east, south, north)
@@ -264,9 +266,60 @@ __host__ __device__ __forceinline__ Rec muscl(const Prim& a, const Prim& c, cons
     return muscl(a, c, b, h_eps, d.rcp(c.h), d);
 }
 
-// Face values of a cell: MUSCL at second order; at first order (Section
-// 3.3) the cell's own values, i.e. the reconstruction above with zero
-// slopes (z still deduced from h and h+z).
+// ENO at second order (Section 4.1 names ENO and modified ENO beside MUSCL;
+// the paper's second-order stencils are the cells i-1, i, i+1): the slope of
+// h, h+z and the velocities is the one-sided undivided difference of smaller
+// magnitude (the left one on ties).  A cell at or below the dry threshold
+// keeps its values at both faces.  MOD (modified ENO): the depth's slope is
+// limited to |D| <= 2 h, so both face depths stay in [0, 2 h].  Unlike
+// minmod's, the face depths may be anywhere (negative with plain ENO), so
+// the two quotients bound their numerators.
+__host__ __device__ __forceinline__ double eno_slope(double a, double b) {
+    return fabs(a) <= fabs(b) ? a : b;
+}
+
+template <bool MOD, class D>
+__host__ __device__ __forceinline__ Rec eno(const Prim& a, const Prim& c, const Prim& b,
+                                            double h_eps, const Recip& rc, D& d) {
+    Rec r;
+    if (!(c.h > h_eps)) {
+        r.h_m = r.h_p = c.h;
+        r.z_m = r.z_p = c.eta - c.h;
+        r.un_m = r.un_p = c.un;
+        r.ut_m = r.ut_p = c.ut;
+        return r;
+    }
+    double dh = eno_slope(c.h - a.h, b.h - c.h);
+    if (MOD) {
+        const double cap = 2.0 * c.h;
+        dh = fmin(fmax(dh, -cap), cap);
+    }
+    r.h_m = c.h - 0.5 * dh;
+    r.h_p = c.h + 0.5 * dh;
+    double de = eno_slope(c.eta - a.eta, b.eta - c.eta);
+    double eta_m = c.eta - 0.5 * de;
+    double eta_p = c.eta + 0.5 * de;
+    r.z_m = eta_m - r.h_m;
+    r.z_p = eta_p - r.h_p;
+    double dun = eno_slope(c.un - a.un, b.un - c.un);
+    double dut = eno_slope(c.ut - a.ut, b.ut - c.ut);
+    d.cap(r.h_m);
+    d.cap(r.h_p);
+    d.low2(r.h_m, r.h_p);
+    d.settle();
+    double wp = d.div(r.h_p, rc);
+    double wm = d.div(r.h_m, rc);
+    r.un_m = c.un - wp * (0.5 * dun);
+    r.un_p = c.un + wm * (0.5 * dun);
+    r.ut_m = c.ut - wp * (0.5 * dut);
+    r.ut_p = c.ut + wm * (0.5 * dut);
+    return r;
+}
+
+// Face values of a cell: ORDER 2 MUSCL, 3 ENO, 4 modified ENO (all second
+// order); at first order (ORDER 1, Section 3.3) the cell's own values, i.e.
+// the reconstruction above with zero slopes (z still deduced from h and
+// h+z).
 template <int ORDER, class D>
 __host__ __device__ __forceinline__ Rec reconstruct(const Prim& a, const Prim& c, const Prim& b,
                                                     double h_eps, const Recip& rc, D& d) {
@@ -277,6 +330,8 @@ __host__ __device__ __forceinline__ Rec reconstruct(const Prim& a, const Prim& c
         r.un_m = r.un_p = c.un;
         r.ut_m = r.ut_p = c.ut;
         return r;
+    } else if constexpr (ORDER == 3 || ORDER == 4) {
+        return eno<ORDER == 4>(a, c, b, h_eps, rc, d);
     } else {
         return muscl(a, c, b, h_eps, rc, d);
     }
@@ -323,7 +378,13 @@ __host__ __device__ __forceinline__ void kinetic_half(double g, double h, double
 // With depths, velocities and z capped at 2^60 and g at most 2^10, c1 and c2
 // stay below 2^62 and the HLL numerators below 2^251; den and the
 // numerators are bounded below here.  The Rusanov flux divides by nothing.
-
+// FLUX 3: the VFRoe-ncv flux, the interface value of the Riemann problem in
+// (2c, u) linearized about the mean state (U_L if uh - ch >= 0, U_R if
+// uh + ch <= 0, else c* = ch + (uL - uR)/4, u* = uh + (cL - cR) and
+// h* = max(c*, 0)^2 / g), the tangential velocity upwinded on u*; a dry side
+// takes the other side's velocity and two dry sides pass nothing.  Its one
+// quotient, c*^2 / g, is the division operator (g is not bounded below by
+// the fast window).
 template <int FLUX = 0, class D>
 __host__ __device__ __forceinline__ FaceOut face(double g, double hm, double zm, double unm,
                                                  double utm, double hp, double zp, double unp,
@@ -350,6 +411,29 @@ __host__ __device__ __forceinline__ FaceOut face(double g, double hm, double zm,
         F0 = m0L + m0R;
         F1 = m1L + m1R;
         F2 = m0L * utm + m0R * utp;
+    } else if constexpr (FLUX == 3) {
+        const bool wL = hL > 0.0, wR = hR > 0.0;
+        const double uL = wL ? unm : unp;
+        const double uR = wR ? unp : unm;
+        const double uh = 0.5 * (uL + uR);
+        const double ch = 0.5 * (cL + cR);
+        double hs, us;
+        if (uh - ch >= 0.0) {
+            hs = hL;
+            us = uL;
+        } else if (uh + ch <= 0.0) {
+            hs = hR;
+            us = uR;
+        } else {
+            const double cs = fmax(ch + 0.25 * (uL - uR), 0.0);
+            hs = (cs * cs) / g;
+            us = uh + (cL - cR);
+        }
+        const double qs = hs * us;
+        const bool any = wL || wR;
+        F0 = any ? qs : 0.0;
+        F1 = any ? qs * us + hg * hs * hs : 0.0;
+        F2 = any ? qs * (us >= 0.0 ? utm : utp) : 0.0;
     } else if constexpr (FLUX == 1) {
         // (F(U_L) + F(U_R))/2 - c/2 (U_R - U_L), c the largest local speed
         double c = vmax(fabs(unm) + cL, fabs(unp) + cR);

@@ -48,8 +48,8 @@ inline int check_params(const swe_params* p) {
     if (!(p->rain >= 0.0) || !std::isfinite(p->rain)) return SWE_EINVAL;
     if ((size_t)p->nx * (size_t)p->ny > ((size_t)1 << 36)) return SWE_EINVAL;
     if (p->order < 0 || p->order > 2) return SWE_EINVAL;
-    if (p->flux < 0 || p->flux > 2) return SWE_EINVAL;
-    if (p->recon != 0) return SWE_EINVAL;
+    if (p->flux < 0 || p->flux > 3) return SWE_EINVAL;
+    if (p->recon < 0 || p->recon > 2) return SWE_EINVAL;
     return SWE_OK;
 }
 
@@ -78,6 +78,7 @@ inline KParams to_kparams(const swe_params& p) {
     k.law = p.fric_law; k.coef = p.fric_coef; k.rain = p.rain;
     k.infil = p.infil_on; k.ks = p.ks; k.psi = p.psi; k.dtheta = p.dtheta;
     k.order = p.order == 1 ? 1 : 2;
+    k.recon = p.order == 1 ? 0 : p.recon;
     k.flux = p.flux;
     double ix = 0.0, iy = 0.0;
     k.dxy_pow2 = exact_pow2(p.dx, ix) && exact_pow2(p.dy, iy);
@@ -90,6 +91,10 @@ inline KParams to_kparams(const swe_params& p) {
 }
 
 inline bool valid_tx(int tx) { return tx == 64 || tx == 128 || tx == 256; }
+
+// ORDER template argument of the tile routine for a simulation: 1 first
+// order, 2 MUSCL, 3 ENO, 4 modified ENO
+inline int order_code(const KParams& p) { return p.order == 1 ? 1 : 2 + p.recon; }
 
 // Default strip width: one-wave strips (no LDS, no barrier) below 8M cells,
 // where they give enough blocks to fill the GPU; 256-column strips above

@@ -131,12 +131,27 @@ void launch_stage_tf(int tx, dim3 grid, hipStream_t s, const MemberArgs& m, cons
 template <int STAGE, bool FIELDS, int ORDER>
 void launch_stage_t(int tx, dim3 grid, hipStream_t s, const MemberArgs& m, const TileIO& io,
                     int ty) {
-    if (m.p.flux == 2)
+    if (m.p.flux == 3)
+        launch_stage_tf<STAGE, FIELDS, ORDER, 3>(tx, grid, s, m, io, ty);
+    else if (m.p.flux == 2)
         launch_stage_tf<STAGE, FIELDS, ORDER, 2>(tx, grid, s, m, io, ty);
     else if (m.p.flux == 1)
         launch_stage_tf<STAGE, FIELDS, ORDER, 1>(tx, grid, s, m, io, ty);
     else
         launch_stage_tf<STAGE, FIELDS, ORDER, 0>(tx, grid, s, m, io, ty);
+}
+
+template <int STAGE, bool FIELDS>
+void launch_stage_o(int tx, dim3 grid, hipStream_t s, const MemberArgs& m, const TileIO& io,
+                    int ty) {
+    switch (order_code(m.p)) {
+        case 1:
+            if constexpr (STAGE == 1) launch_stage_t<1, FIELDS, 1>(tx, grid, s, m, io, ty);
+            break;
+        case 3: launch_stage_t<STAGE, FIELDS, 3>(tx, grid, s, m, io, ty); break;
+        case 4: launch_stage_t<STAGE, FIELDS, 4>(tx, grid, s, m, io, ty); break;
+        default: launch_stage_t<STAGE, FIELDS, 2>(tx, grid, s, m, io, ty); break;
+    }
 }
 
 // Stage 1 never reads the rain and soil fields: its FIELDS variant only
@@ -145,22 +160,11 @@ void launch_stage_t(int tx, dim3 grid, hipStream_t s, const MemberArgs& m, const
 template <int STAGE>
 void launch_stage(int tx, dim3 grid, hipStream_t s, const MemberArgs& m, const TileIO& io,
                   int ty) {
-    if constexpr (STAGE == 1) {
-        if (m.p.imposed) {
-            if (m.p.order == 1)
-                launch_stage_t<1, true, 1>(tx, grid, s, m, io, ty);
-            else
-                launch_stage_t<1, true, 2>(tx, grid, s, m, io, ty);
-        } else if (m.p.order == 1)
-            launch_stage_t<1, false, 1>(tx, grid, s, m, io, ty);
-        else
-            launch_stage_t<1, false, 2>(tx, grid, s, m, io, ty);
-    } else {
-        if (has_fields(m) || m.p.imposed)
-            launch_stage_t<2, true, 2>(tx, grid, s, m, io, ty);
-        else
-            launch_stage_t<2, false, 2>(tx, grid, s, m, io, ty);
-    }
+    const bool fields = STAGE == 1 ? m.p.imposed != 0 : (has_fields(m) || m.p.imposed);
+    if (fields)
+        launch_stage_o<STAGE, true>(tx, grid, s, m, io, ty);
+    else
+        launch_stage_o<STAGE, false>(tx, grid, s, m, io, ty);
 }
 
 void launch_euler(hipStream_t s, const MemberArgs& m, const TileIO& io) {

@@ -386,6 +386,16 @@ def random_state(nx: int, ny: int, seed: int, dry_frac: float = 0.3,
     return wl
 
 
+def flowdir_dem(nx: int = 14786, ny: int = 10086, seed: int = 1307) -> np.ndarray:
+    """A float32 DEM of the paper's flow-direction size (Section 5.2 gives
+    only its dimensions): a ramp of 50 m across x plus uniform noise of 1 m,
+    [ny][nx]."""
+    rng = np.random.default_rng(seed)
+    z = rng.random((ny, nx), dtype=np.float32)
+    z += np.linspace(0.0, 50.0, nx, dtype=np.float32)[None, :]
+    return z
+
+
 WORKLOADS = {
     "dam_break_200": dam_break_200,
     "valley_2048": valley_2048,

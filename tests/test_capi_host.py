@@ -141,14 +141,18 @@ def test_first_order_limits_without_gpu():
     assert e.value.code == capi.SWE_EINVAL
 
 
-@pytest.mark.parametrize("flux", [1, 2])
+@pytest.mark.parametrize("flux", [1, 2, 3])
 def test_flux_variant_limits_without_gpu(flux):
-    # flux outside {0, 1, 2} is invalid; the members of an ensemble share
-    # one flux
+    # flux outside {0, 1, 2, 3} and a reconstruction outside {0, 1, 2} are
+    # invalid; the members of an ensemble share one flux
     from paper_1307_4839_amd import capi
-    for bad in (-1, 3):
+    for bad in (-1, 4):
         with pytest.raises(capi.SweError):
             capi.swe_workspace_bytes(capi.make_params(8, 8, 1.0, 1.0, flux=bad))
+        with pytest.raises(capi.SweError):
+            capi.swe_workspace_bytes(capi.make_params(8, 8, 1.0, 1.0, recon=bad - 1))
+    for recon in (1, 2):
+        capi.swe_workspace_bytes(capi.make_params(8, 8, 1.0, 1.0, recon=recon))
     capi.swe_workspace_bytes(capi.make_params(8, 8, 1.0, 1.0, flux=flux))
     p1 = capi.make_params(16, 16, 1.0, 1.0, fric_law=capi.SWE_FRIC_MANNING, fric_coef=0.03,
                           flux=flux)

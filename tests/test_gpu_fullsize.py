@@ -45,7 +45,7 @@ def window_step(wl, st, j, i, dt):
                    fric_law=wl.fric_law, fric_coef=wl.fric_coef,
                    fric=None if wl.fric is None else np.ascontiguousarray(wl.fric[j0:j1, i0:i1]),
                    rain=wl.rain, infil_on=wl.infil_on, ks=wl.ks, psi=wl.psi,
-                   dtheta=wl.dtheta, order=wl.order, flux=wl.flux,
+                   dtheta=wl.dtheta, order=wl.order, flux=wl.flux, recon=wl.recon,
                    vinf=None if "vinf" not in st else np.ascontiguousarray(st["vinf"][j0:j1, i0:i1]))
     s = oracle.State(w)
     s.step_fixed(dt)
@@ -105,15 +105,17 @@ def test_fullsize_hillslope_8192():
     check_fullsize(wl, 300, 200, seed=1)
 
 
-@pytest.mark.parametrize("order,flux", [(1, 0), (2, 1), (2, 2)])
-def test_fullsize_hillslope_8192_scheme_variants(order, flux):
+@pytest.mark.parametrize("order,flux,recon", [(1, 0, 0), (2, 1, 0), (2, 2, 0), (2, 3, 0),
+                                              (2, 0, 1), (2, 0, 2)])
+def test_fullsize_hillslope_8192_scheme_variants(order, flux, recon):
     # the variants bench.py times on the same workload: first order with HLL
-    # (n_CFL = 1), and the Rusanov and kinetic fluxes at second order
+    # (n_CFL = 1), the Rusanov, kinetic and VFRoe-ncv fluxes at second order,
+    # and the ENO and modified ENO reconstructions
     wl = I.hillslope_8192()
-    wl.order, wl.flux = order, flux
+    wl.order, wl.flux, wl.recon = order, flux, recon
     if order == 1:
         wl.cfl = 1.0
-    check_fullsize(wl, 300, 100, seed=10 + 3 * order + flux)
+    check_fullsize(wl, 300, 100, seed=10 + 3 * order + flux + 7 * recon)
 
 
 def test_fullsize_valley_2048():
