@@ -231,8 +231,11 @@ int swe_set_dt_log(swe_ctx* ctx, double* dev_log, int64_t capacity);
 /* Enqueue `nsteps` time steps (Algorithm 1: two stages, then Heun, then rain
  * and infiltration).  dt = min(dt_max, cfl / (Ax/dx + Ay/dy), t_end - t)
  * where Ax, Ay bound |u| + sqrt(g h) over the reconstructed face states
- * (eq. cfl).  Steps once t >= t_end are no-ops.  Asynchronous: the host
- * never waits.  Runs of 16 steps replay a captured HIP graph (re-captured
+ * (eq. cfl).  Steps once t >= t_end are no-ops.  Asynchronous (the host
+ * never waits) unless t_end is finite and nsteps > 256: the steps are then
+ * enqueued 256 at a time and the call waits for each batch to read the time,
+ * returning once t_end is reached instead of enqueueing steps that would all
+ * be no-ops.  Runs of 16 steps replay a captured HIP graph (re-captured
  * when t_end, the rain, the tiling or the dt log change).  On return
  * (stream order) the state is in the caller's h/qx/qy buffers. */
 int swe_step(swe_ctx* ctx, int32_t nsteps, double t_end);

@@ -22,9 +22,9 @@
  * device memory; code is [ny][nx] uint8 in device memory.  Both buffers
  * are owned by the caller and must not overlap.  The call is asynchronous:
  * it enqueues one kernel on hip_stream (NULL = the default stream) and
- * returns.  Any alignment is accepted; rows whose length nx is a multiple
- * of 4 with z 16-byte and code 4-byte aligned take a path that moves four
- * cells per lane.
+ * returns.  Any length and alignment is accepted: each lane moves four
+ * cells of a row with the widest loads (16, 8 or 4 bytes) and code stores
+ * (32, 16 or 8 bits) that the alignment of their address allows.
  */
 #ifndef SWE_FLOWDIR_H
 #define SWE_FLOWDIR_H
@@ -53,8 +53,11 @@ int swe_flow_dir_f64(const double* z, int32_t nx, int32_t ny, uint8_t* code,
 
 /* Rows per workgroup that swe_flow_dir_f32 (elem_bytes 4) or
  * swe_flow_dir_f64 (elem_bytes 8) uses for rows == 0, before any raise for
- * the grid limit.  Host only; SWE_EINVAL for other elem_bytes, negative
- * sizes or a null rows. */
+ * the grid limit: about 4096 (float) or 16384 (double) workgroups, moved
+ * within a factor 2 when that avoids a nearly empty last round of
+ * workgroups on the current device (its compute units and the kernel's
+ * occupancy; without a device, the unmoved value).  Host only; SWE_EINVAL
+ * for other elem_bytes, negative sizes or a null rows. */
 int swe_flow_dir_rows(int32_t nx, int32_t ny, int32_t elem_bytes, int32_t* rows);
 
 #ifdef __cplusplus

@@ -1353,6 +1353,7 @@ int swe_adj_get_series(swe_adj* A, double* out) {
 }
 
 int swe_adj_forward(swe_adj* A, double* loss) {
+    Range range("swe_adj_forward");
     if (!A) return SWE_EINVAL;
     const size_t n = A->n;
     // state ping-pong in the segment buffer's first two slots
@@ -1401,6 +1402,7 @@ int swe_adj_forward(swe_adj* A, double* loss) {
 }
 
 int swe_adj_backward(swe_adj* A, double* grad) {
+    Range range("swe_adj_backward");
     if (!A || !grad) return SWE_EINVAL;
     const size_t n = A->n;
     std::vector<double> dts(A->nsteps);

@@ -593,6 +593,7 @@ int swe_batch_set_dt_log(swe_batch* b, int32_t member, double* dev_log, int64_t 
 }
 
 int swe_batch_step(swe_batch* b, int32_t nsteps, double t_end) {
+    Range range("swe_batch_step");
     if (!b || nsteps < 0 || std::isnan(t_end)) return SWE_EINVAL;
     if (nsteps == 0) return SWE_OK;
     return run_steps(b, nsteps, t_end, true);

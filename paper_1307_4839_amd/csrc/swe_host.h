@@ -11,6 +11,8 @@
 #include <cstdint>
 #include <cstring>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "swe.h"
 #include "swe_device.h"
 
@@ -120,6 +122,16 @@ inline int auto_rows(int nx, int ny, int tx) {
 }
 
 inline int hip_ok(hipError_t e) { return e == hipSuccess ? SWE_OK : SWE_EHIP; }
+
+// A roctx range over the host work of an entry point (the enqueueing of a
+// step sequence, a forward or reverse adjoint pass), seen by rocprofv3
+// --marker-trace beside the kernels it launched.
+struct Range {
+    explicit Range(const char* name) { roctxRangePushA(name); }
+    ~Range() { roctxRangePop(); }
+    Range(const Range&) = delete;
+    Range& operator=(const Range&) = delete;
+};
 
 // Host mirror of step_io(): the buffers of one step.
 inline TileIO host_step_io(const MemberArgs& m, int phase, int slot, double t_end) {

@@ -526,9 +526,15 @@ int swe_get_gauges(swe_ctx* c, double* out, int64_t max_copy, int64_t* nsamples)
     return SWE_OK;
 }
 
-int swe_step(swe_ctx* c, int32_t nsteps, double t_end) {
-    if (!c || nsteps < 0 || std::isnan(t_end)) return SWE_EINVAL;
-    if (nsteps == 0) return SWE_OK;
+}  // extern "C"
+
+namespace {
+
+// Steps enqueued between two reads of the time when a long run may end
+// early (even, a multiple of GRAPH_STEPS).
+constexpr int32_t STOP_CHUNK = 256;
+
+int step_run(swe_ctx* c, int32_t nsteps, double t_end) {
     const bool profiling = c->prof_ev != nullptr;
     int32_t k = 0;
     // whole graphs first (not while profiling: events go between kernels)
@@ -555,6 +561,34 @@ int swe_step(swe_ctx* c, int32_t nsteps, double t_end) {
                            (const double*)c->m.qy[1], c->m.qy[0], n);
     }
     return hip_ok(hipGetLastError());
+}
+
+}  // namespace
+
+extern "C" {
+
+int swe_step(swe_ctx* c, int32_t nsteps, double t_end) {
+    if (!c || nsteps < 0 || std::isnan(t_end)) return SWE_EINVAL;
+    if (nsteps == 0) return SWE_OK;
+    Range range("swe_step");
+    if (!std::isfinite(t_end) || nsteps <= STOP_CHUNK) return step_run(c, nsteps, t_end);
+    // a finite end time: enqueue chunks and stop once it is reached, instead
+    // of enqueueing steps that would all be no-ops
+    for (int32_t left = nsteps; left > 0;) {
+        const int32_t k = left < STOP_CHUNK ? left : STOP_CHUNK;
+        int rc = step_run(c, k, t_end);
+        if (rc) return rc;
+        left -= k;
+        if (left > 0) {
+            double t = 0.0;
+            if (hipMemcpyAsync(&t, &c->m.sc->t[c->slot], sizeof t, hipMemcpyDeviceToHost,
+                               c->stream) != hipSuccess ||
+                hipStreamSynchronize(c->stream) != hipSuccess)
+                return SWE_EHIP;
+            if (t >= t_end) break;
+        }
+    }
+    return SWE_OK;
 }
 
 }  // extern "C"

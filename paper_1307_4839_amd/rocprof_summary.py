@@ -15,8 +15,10 @@ whose timed region starts after them.
 
 the same copy-calibrated FETCH_SIZE / WRITE_SIZE figures for the kernel
 whose short name (template arguments included, parameters and namespaces
-left out) is exactly NAME, e.g. 'flow_dir_kernel<float, 4>', against BYTES
-algorithmic bytes per launch.
+left out) is exactly NAME, e.g. 'flow_dir_kernel<float>', against BYTES
+algorithmic bytes per launch; NAME#G restricts it to the dispatches whose
+grid has G work-items along x (one launch shape of a kernel that runs on
+several grids).  ``trace --by-grid`` splits the trace the same way.
 
 For ``counters``, per stage kernel: FETCH_SIZE and WRITE_SIZE (KiB per dispatch) averaged over
 the dispatches after the first K, scaled by what the same counters read for
@@ -66,17 +68,25 @@ def _stage(name: str) -> str | None:
     return None
 
 
-def trace(db: str, skip: dict) -> str:
+def _grids(con) -> dict:
+    """{dispatch id: grid size along x}."""
+    return dict(con.execute("select dispatch_id, grid_size_x from rocpd_kernel_dispatch"))
+
+
+def trace(db: str, skip: dict, by_grid: bool = False) -> str:
     con = sqlite3.connect(db)
-    rows = con.execute("select name, start, duration from kernels order by start").fetchall()
+    rows = con.execute("select name, start, duration, dispatch_id from kernels "
+                       "order by start").fetchall()
+    grids = _grids(con) if by_grid else {}
     per = {}
-    for name, start, dur in rows:
-        per.setdefault(name, []).append(dur)
+    for name, start, dur, did in rows:
+        short = short_name(name) + (f"#{grids.get(did, 0)}" if by_grid else "")
+        per.setdefault(short, []).append(dur)
     out = []
     out.append(f"{'kernel':<60} {'calls':>6} {'total_ms':>10} {'avg_us':>10} "
                f"{'skip':>5} {'avg_us_after_skip':>18}")
     for name, durs in sorted(per.items(), key=lambda kv: -sum(kv[1])):
-        short = short_name(name)
+        short = name
         k = 0
         for key, val in skip.items():
             if key in short:
@@ -88,13 +98,17 @@ def trace(db: str, skip: dict) -> str:
     return "\n".join(out)
 
 
-def _counters(db: str):
-    """{kernel name: [(dispatch id, {counter: value}), ...]} in dispatch order."""
+def _counters(db: str, by_grid: bool = False):
+    """{kernel name: [(dispatch id, {counter: value}), ...]} in dispatch order
+    (with by_grid the key is 'name#grid size along x')."""
     con = sqlite3.connect(db)
     rows = con.execute("select name, dispatch_id, counter_name, sum(counter_value) "
                        "from pmc_events group by dispatch_id, counter_name").fetchall()
+    grids = _grids(con) if by_grid else {}
     per = {}
     for name, did, cn, v in rows:
+        if by_grid:
+            name = f"{name}#{grids.get(did, 0)}"
         per.setdefault(name, {}).setdefault(did, {})[cn] = v
     return {n: sorted(d.items()) for n, d in per.items()}
 
@@ -169,7 +183,8 @@ def kernel_counters(a) -> dict:
     for e in a.expect:
         k, v = e.rsplit("=", 1)
         expect[k] = int(v)
-    fetch, write = _counters(a.fetch), _counters(a.write)
+    by_grid = any("#" in k for k in expect)
+    fetch, write = _counters(a.fetch, by_grid), _counters(a.write, by_grid)
     rec = {"kernel_sha256_16": build.source_hash(paths), "workload": a.workload,
            "calibration": {"probe": "1 GiB device-to-device copy (__amd_rocclr_copyBuffer)",
                            "fetch_KiB": cf, "write_KiB": cw,
@@ -177,6 +192,9 @@ def kernel_counters(a) -> dict:
            "kernels": {}}
     for name in sorted(fetch):
         short = short_name(name)
+        if by_grid:
+            base, grid = name.rsplit("#", 1)
+            short = short_name(base) + "#" + grid
         key = short if short in expect else None
         if key is None or name not in write:
             continue
@@ -229,6 +247,8 @@ def main(argv=None):
     t.add_argument("db")
     t.add_argument("--skip", action="append", default=[],
                    help="NAME=K: ignore the first K dispatches of kernels matching NAME")
+    t.add_argument("--by-grid", action="store_true",
+                   help="one line per kernel and grid size along x")
     c = sub.add_parser("counters")
     c.add_argument("--fetch", required=True)
     c.add_argument("--write", required=True)
@@ -255,7 +275,7 @@ def main(argv=None):
         for s in a.skip:
             k, v = s.rsplit("=", 1)
             skip[k] = int(v)
-        print(trace(a.db, skip))
+        print(trace(a.db, skip, a.by_grid))
         return 0
     rec = kernel_counters(a) if a.cmd == "kernel" else counters(a)
     if a.json:

@@ -137,6 +137,43 @@ def test_adjoint_against_oracle_tangent(torch_cuda, make):
         assert abs(gd - dL) <= 1e-10 * max(abs(dL), 1e-300), (k, gd, dL)
 
 
+def test_adjoint_against_oracle_tangent_middle_size(torch_cuda):
+    # 256 x 256 cells, 400 steps, checkpoints every 20 steps: the exact pin
+    # (the oracle's forward-mode tangent with the same frozen time steps)
+    # at a size where many tiles, checkpoint segments and wet/dry fronts
+    # take part
+    from paper_1307_4839_amd.solver import Calibration
+    # (Darcy-Weisbach friction: its forward steps agree with the oracle bit
+    # for bit, so 400 steps add no round-off drift between the two sides)
+    wl = I.calibration_1024(256, 256, dam_row=40, ngauges=24, sigma_cells=8)
+    wl.fric_law = I.FRIC_DARCY
+    wl.fric = 0.3 + 0.1 * wl.fric / 0.03
+    fric_obs = 0.3 + 0.1 * wl.extra["fric_obs"] / 0.03
+    nsteps, every = 400, 10
+    say(f"[adjoint] middle size {wl.nx}x{wl.ny} {nsteps} steps: oracle")
+    base = oracle.State(wl)
+    assert base.run(nsteps) == 0
+    dts = np.array(base.dts)
+    p = oracle.params_of(wl)
+    obs, _ = oracle.gauge_run(p, wl.h, wl.qx, wl.qy, wl.z, fric_obs, dts, wl.gauges, every)
+    cal = Calibration(wl, wl.gauges, every, obs, nsteps, ckpt_every=20)
+    cal.set_dts(dts)
+    L = cal.forward()
+    g = cal.backward().cpu().numpy()
+    cal.close()
+    rng = np.random.default_rng(5)
+    for k in range(2):
+        d = rng.standard_normal((wl.ny, wl.nx)) * 1e-3
+        L0, dL = oracle.tangent_run(p, wl.h, wl.qx, wl.qy, wl.z, wl.fric, d, dts, wl.gauges,
+                                    every, obs)
+        if k == 0:
+            say(f"    loss gpu {L!r} oracle {L0!r}")
+            assert abs(L - L0) <= 1e-12 * abs(L0)
+        gd = float((g * d).sum())
+        say(f"    <g,d> = {gd!r}  oracle tangent = {dL!r}")
+        assert abs(gd - dL) <= 1e-10 * max(abs(dL), 1e-300), (k, gd, dL)
+
+
 def test_autograd_function(torch_cuda):
     torch = torch_cuda
     from paper_1307_4839_amd.solver import Calibration, GaugeMisfit

@@ -1,9 +1,11 @@
 """GPU parity of the flow-direction kernel (Section 5.2) with the oracle.
 
 Codes come from comparisons only, so the bar is bit-exact equality of every
-code, on ragged and aligned shapes (both kernel paths: four cells per lane
-and one), several rows-per-workgroup values, ties, nodata and NaN cells,
-unaligned buffers, and the full 8192 x 8192 terrain of the benchmark.
+code, on ragged and aligned shapes (row lengths of every residue mod 4, so
+rows start on 16-, 8- and 4-byte boundaries and end in partial lanes),
+several rows-per-workgroup values, ties, nodata and NaN cells, unaligned
+buffers, the full 8192 x 8192 terrain of the benchmark and the paper's
+14786 x 10086 size.
 """
 
 import sys
@@ -61,7 +63,7 @@ def run(torch, z, rows=0, offset=0):
 
 
 SHAPES = [(1, 1), (1, 7), (7, 1), (2, 2), (3, 5), (37, 29), (64, 1024), (70, 1028),
-          (33, 1030), (129, 2052), (5, 4096)]
+          (33, 1030), (129, 2052), (5, 4096), (21, 1031), (19, 1033), (40, 2050)]
 
 
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
@@ -77,13 +79,14 @@ def test_random_dem(torch_cuda, shape, dtype):
 
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
 def test_unaligned_buffers(torch_cuda, dtype):
-    # nx a multiple of 4 but buffers off their vector alignment: the
-    # one-cell-per-lane path
-    z = dem((45, 1032), seed=5, dtype=dtype)
-    ref = F.flow_directions(z)
-    for offset in (1, 2, 3):
-        say(f"[flowdir] unaligned offset {offset} dtype {np.dtype(dtype).name}")
-        assert np.array_equal(run(torch_cuda, z, rows=0, offset=offset), ref)
+    # buffers off their vector alignment, with row lengths of each residue
+    # mod 4: narrower loads and stores
+    for shape in ((45, 1032), (31, 1030), (29, 1029)):
+        z = dem(shape, seed=5 + shape[1], dtype=dtype)
+        ref = F.flow_directions(z)
+        for offset in (1, 2, 3):
+            say(f"[flowdir] {shape} unaligned offset {offset} dtype {np.dtype(dtype).name}")
+            assert np.array_equal(run(torch_cuda, z, rows=0, offset=offset), ref)
 
 
 def test_closed_forms_on_gpu(torch_cuda):
@@ -121,3 +124,19 @@ def test_fullsize_hillslope_terrain(torch_cuda, dtype):
     got = run(torch_cuda, z)
     assert np.array_equal(got, ref)
     assert got.max() <= 8
+
+
+def test_paper_size_float32(torch_cuda):
+    # the paper's DEM size (14786 x 10086, float32; a row length of 2 mod 4,
+    # so odd rows start on 8-byte boundaries): the benchmark's seeded ramp
+    # with noise, every code
+    torch = torch_cuda
+    z = I.flowdir_dem()
+    zt = torch.as_tensor(z).cuda()
+    say("[flowdir] 14786 x 10086 float32: oracle")
+    ref = F.flow_directions(z)
+    say("[flowdir] kernel")
+    from paper_1307_4839_amd.solver import flow_directions
+    out = flow_directions(zt)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), ref)
