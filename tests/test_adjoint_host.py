@@ -34,7 +34,9 @@ def emu(tmp_path_factory):
     out = str(tmp_path_factory.mktemp("emu") / "libadjemu.so")
     subprocess.check_call([hipcc, "--offload-arch=gfx950", "-O1", "-std=c++17", "-fPIC",
                            "-shared", "-ffp-contract=off", "-I", os.path.join(ROOT, "include"),
-                           os.path.join(HERE, "adjoint_host_emu.hip"), "-o", out],
+                           os.path.join(HERE, "adjoint_host_emu.hip"), "-o", out,
+                           "-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx",
+                           "-Wl,-rpath,/opt/rocm/lib"],
                           stderr=subprocess.DEVNULL)
     return C.CDLL(out)
 
