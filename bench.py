@@ -207,26 +207,59 @@ def adjoint_leg(steps, every):
     cal.forward()
     obs = cal.series()
     cal.close()
-    cal = Calibration(wl, wl.gauges, every, obs, steps)
-    cal.set_dts(dts)
-    cal.forward()  # warm
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    loss = cal.forward()
-    t1 = time.perf_counter()
-    grad = cal.backward()
-    t2 = time.perf_counter()
-    gnorm = float(torch.linalg.vector_norm(grad).item())
-    cal.close()
-    ms_f, ms_b = (t1 - t0) * 1e3, (t2 - t1) * 1e3
+    def timed(ckpt):
+        cal = Calibration(wl, wl.gauges, every, obs, steps, ckpt_every=ckpt)
+        cal.set_dts(dts)
+        cal.forward()  # warm
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        loss = cal.forward()
+        t1 = time.perf_counter()
+        grad = cal.backward()
+        t2 = time.perf_counter()
+        gnorm = float(torch.linalg.vector_norm(grad).item())
+        nbytes = cal.workspace.numel()
+        cal.close()
+        del cal, grad
+        torch.cuda.empty_cache()
+        return loss, gnorm, (t1 - t0) * 1e3, (t2 - t1) * 1e3, nbytes
+
+    ck = int(round(math.sqrt(steps)))
+    loss, gnorm, ms_f, ms_b, nb = timed(ck)
     print(f"[bench] adjoint: plain forward {ms_plain:.1f} ms, adjoint forward {ms_f:.1f} ms, "
-          f"reverse {ms_b:.1f} ms, loss {loss:.6e}", file=sys.stderr, flush=True)
-    return {"workload": f"calibration valley {wl.nx}x{wl.ny}, Manning field, {steps} steps, "
-                        f"{ng} gauges every {every} steps, checkpoints every "
-                        f"{int(round(math.sqrt(steps)))} steps",
-            "plain_forward_ms": ms_plain, "adjoint_forward_ms": ms_f,
-            "adjoint_reverse_ms": ms_b, "cost_ratio_vs_plain": (ms_f + ms_b) / ms_plain,
-            "loss": loss, "grad_norm": gnorm}
+          f"reverse {ms_b:.1f} ms, loss {loss:.6e} (checkpoints every {ck} steps, "
+          f"{nb / 2**30:.1f} GiB)", file=sys.stderr, flush=True)
+    out = {"workload": f"calibration valley {wl.nx}x{wl.ny}, Manning field, {steps} steps, "
+                       f"{ng} gauges every {every} steps, checkpoints every {ck} steps",
+           "plain_forward_ms": ms_plain, "adjoint_forward_ms": ms_f,
+           "adjoint_reverse_ms": ms_b, "cost_ratio_vs_plain": (ms_f + ms_b) / ms_plain,
+           "workspace_GiB": nb / 2**30, "loss": loss, "grad_norm": gnorm}
+    # one segment: the forward pass keeps every state and both rates and the
+    # reverse recomputes nothing (memory for time, when the GPU has room)
+    need = 9 * 8 * wl.nx * wl.ny * (steps + 2)
+    free, _ = torch.cuda.mem_get_info()
+    if free > need + (8 << 30):
+        loss1, gnorm1, ms_f1, ms_b1, nb1 = timed(steps)
+        print(f"[bench] adjoint, one segment: forward {ms_f1:.1f} ms, reverse {ms_b1:.1f} ms "
+              f"({nb1 / 2**30:.1f} GiB), same loss {loss1 == loss}", file=sys.stderr, flush=True)
+        out["one_segment"] = {"adjoint_forward_ms": ms_f1, "adjoint_reverse_ms": ms_b1,
+                              "cost_ratio_vs_plain": (ms_f1 + ms_b1) / ms_plain,
+                              "workspace_GiB": nb1 / 2**30, "same_loss": loss1 == loss,
+                              "same_grad_norm": gnorm1 == gnorm}
+    else:
+        out["one_segment"] = f"skipped: {need / 2**30:.0f} GiB needed, {free / 2**30:.0f} free"
+    return out
+
+
+def _flowdir_traffic(cnt, elem, algorithmic):
+    """Copy-calibrated HBM bytes per launch of the flow-direction kernel on
+    ``elem`` data from the committed counters, matched by element type and
+    algorithmic bytes (one entry per launch shape), or None."""
+    for key, k in (cnt or {}).get("kernels", {}).items():
+        if key.split("#")[0] == f"flow_dir_kernel<{elem}>" and \
+                k["algorithmic_bytes_per_launch"] == algorithmic:
+            return round(k["bytes_per_launch"])
+    return None
 
 
 def flow_dir_leg(wl, reps):
@@ -239,8 +272,7 @@ def flow_dir_leg(wl, reps):
     from paper_1307_4839_amd.solver import flow_directions
     out = {}
     cells = wl.nx * wl.ny
-    cnt = load_counters(FLOWDIR_COUNTERS_FILE, FLOWDIR_SOURCES) \
-        if (wl.nx, wl.ny) == (8192, 8192) else None
+    cnt = load_counters(FLOWDIR_COUNTERS_FILE, FLOWDIR_SOURCES)
     for name, dt, nbytes in (("f32", torch.float32, 4), ("f64", torch.float64, 8)):
         z = torch.as_tensor(wl.z).to(device="cuda:0", dtype=dt).contiguous()
         code = torch.empty((wl.ny, wl.nx), dtype=torch.uint8, device="cuda:0")
@@ -256,10 +288,8 @@ def flow_dir_leg(wl, reps):
         torch.cuda.synchronize()
         avg = e0.elapsed_time(e1) / reps
         gbps = (nbytes + 1) * cells / (avg / 1e3) / 1e9
-        traffic = None
-        kname = f"flow_dir_kernel<{'float' if name == 'f32' else 'double'}, 4>"
-        if cnt and kname in cnt["kernels"]:
-            traffic = round(cnt["kernels"][kname]["bytes_per_launch"])
+        traffic = _flowdir_traffic(cnt, "float" if name == "f32" else "double",
+                                   (nbytes + 1) * cells)
         out[name] = {"bound": "hbm", "avg_ms": avg, "bytes_per_cell": nbytes + 1,
                      "achieved": round(gbps, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(gbps / HBM_PEAK_GBS, 4), "traffic": traffic,
@@ -295,6 +325,7 @@ def flow_dir_leg(wl, reps):
                              "bytes_per_cell": 5, "achieved": round(gbps, 1),
                              "peak": HBM_PEAK_GBS, "unit": "GB/s",
                              "frac": round(gbps / HBM_PEAK_GBS, 4),
+                             "traffic": _flowdir_traffic(cnt, "float", 5 * nx * ny),
                              "algorithmic_bytes_per_launch": 5 * nx * ny,
                              "paper_s_context": {"SkelGIS": 31.0, "SkeTo": 101.0}}
     print(f"[bench] flow directions f32 at the paper's {nx}x{ny}: {avg * 1e3:.1f} us/launch "

@@ -339,6 +339,11 @@ int swe_batch_get_status(swe_batch* b, uint32_t* flags, int32_t n);
  * ------------------------------------------------------------------------- */
 typedef struct swe_adj swe_adj;
 
+/* The workspace holds the checkpoints (every ckpt_every-th state) and one
+ * segment of ckpt_every states with their two stage rates.  The forward
+ * pass leaves the last segment there, so the reverse pass recomputes every
+ * segment but that one: with ckpt_every >= nsteps (one segment, about
+ * 9 nx ny nsteps doubles) it recomputes nothing. */
 int swe_adj_workspace_bytes(const swe_params* p, int32_t nsteps, int32_t ckpt_every,
                             int32_t ngauges, int32_t every, size_t* bytes);
 int swe_adj_create(const swe_params* p, const swe_buffers* b, int32_t nsteps,

@@ -1059,6 +1059,8 @@ struct swe_adj {
     double* seg;           // device, (ckpt + 1) x 3N
     double* segphi;        // Phi(U^k) of the recomputed segment steps, ckpt x 3N
     double* segphi2;       // Phi(U*) of the same steps, ckpt x 3N
+    bool last_kept;        // the forward pass left the last segment's states and
+                           // rates in seg / segphi / segphi2
     double* ust;           // U* (3N)
     double* phi;           // Phi (3N)
     double* phi0;          // Phi(U^k) kept for the reverse of stage 1 (3N)
@@ -1072,13 +1074,36 @@ struct swe_adj {
 
 namespace {
 
-size_t adj_bytes(const swe_params* p, int nsteps, int ckpt, int ngauges, int every) {
-    size_t n = ncells(p), an = align256(n * sizeof(double));
-    size_t nck = (nsteps + ckpt - 1) / ckpt;
+// Byte offsets of the workspace's parts, from one place for both the size
+// a caller allocates and the carve-up of swe_adj_create.  A checkpoint
+// spacing beyond the step count means one segment: the whole run.
+struct AdjLayout {
+    int ckpt;
+    size_t scalars, loss, dts, series, ckpts, seg, segphi, segphi2, tail, total;
+};
+
+AdjLayout adj_layout(const swe_params* p, int nsteps, int ckpt, int ngauges, int every) {
+    AdjLayout L;
+    L.ckpt = ckpt < nsteps ? ckpt : nsteps;
+    size_t an = align256(ncells(p) * sizeof(double));
+    size_t nck = (nsteps + L.ckpt - 1) / L.ckpt;
     size_t rows = every > 0 ? nsteps / every : 0;
-    return SCALAR_BYTES + 256 + align256(nsteps * sizeof(double)) +
-           align256(rows * (size_t)ngauges * sizeof(double)) + 3 * an * nck +
-           3 * an * (ckpt + 1) + 2 * 3 * an * ckpt + 3 * an * 7;
+    size_t o = 0;
+    L.scalars = o; o += SCALAR_BYTES;
+    L.loss = o; o += 256;
+    L.dts = o; o += align256(nsteps * sizeof(double));
+    L.series = o; o += align256(rows * (size_t)ngauges * sizeof(double));
+    L.ckpts = o; o += 3 * an * nck;
+    L.seg = o; o += 3 * an * (L.ckpt + 1);
+    L.segphi = o; o += 3 * an * L.ckpt;
+    L.segphi2 = o; o += 3 * an * L.ckpt;
+    L.tail = o; o += 3 * an * 7;  // ust, phi, phi0, lamA, lamB, lam, mu
+    L.total = o;
+    return L;
+}
+
+size_t adj_bytes(const swe_params* p, int nsteps, int ckpt, int ngauges, int every) {
+    return adj_layout(p, nsteps, ckpt, ngauges, every).total;
 }
 
 inline double* plane(double* base, size_t n, int k) { return base + (size_t)k * n; }
@@ -1254,8 +1279,8 @@ int swe_adj_create(const swe_params* p, const swe_buffers* b, int32_t nsteps,
     if (nsteps < 1 || ckpt_every < 1 || ngauges < 1 || every < 1 || !gauges || !obs)
         return SWE_EINVAL;
     if (((uintptr_t)workspace & 255) != 0) return SWE_EINVAL;
-    size_t need = adj_bytes(p, nsteps, ckpt_every, ngauges, every);
-    if (workspace_bytes < need) return SWE_ENOMEM;
+    const AdjLayout L = adj_layout(p, nsteps, ckpt_every, ngauges, every);
+    if (workspace_bytes < L.total) return SWE_ENOMEM;
     {
         // every gauge must be a cell of the grid
         std::vector<int32_t> g(ngauges);
@@ -1273,28 +1298,28 @@ int swe_adj_create(const swe_params* p, const swe_buffers* b, int32_t nsteps,
     A->nsteps = nsteps;
     A->every = every;
     A->ngauges = ngauges;
-    A->ckpt = ckpt_every;
+    A->ckpt = L.ckpt;
     A->nrows = nsteps / every;
     A->gauges = gauges;
     A->obs = obs;
     A->h0 = b->h; A->qx0 = b->qx; A->qy0 = b->qy;
     size_t n = ncells(p), an = align256(n * sizeof(double));
     A->n = n;
-    char* w = (char*)workspace;
+    char* const base = (char*)workspace;
     MemberArgs& m = A->m;
     m.p = to_kparams(*p);
     m.z = b->z;
     m.fric = b->fric;
     m.vinf = nullptr;
-    m.sc = (DevScalars*)w; w += SCALAR_BYTES;
-    A->loss_dev = (double*)w; w += 256;
-    A->dts = (double*)w; w += align256(nsteps * sizeof(double));
-    A->series = (double*)w; w += align256((size_t)A->nrows * ngauges * sizeof(double));
-    size_t nck = (nsteps + ckpt_every - 1) / ckpt_every;
-    A->ckpts = (double*)w; w += 3 * an * nck;
-    A->seg = (double*)w; w += 3 * an * (ckpt_every + 1);
-    A->segphi = (double*)w; w += 3 * an * ckpt_every;
-    A->segphi2 = (double*)w; w += 3 * an * ckpt_every;
+    m.sc = (DevScalars*)(base + L.scalars);
+    A->loss_dev = (double*)(base + L.loss);
+    A->dts = (double*)(base + L.dts);
+    A->series = (double*)(base + L.series);
+    A->ckpts = (double*)(base + L.ckpts);
+    A->seg = (double*)(base + L.seg);
+    A->segphi = (double*)(base + L.segphi);
+    A->segphi2 = (double*)(base + L.segphi2);
+    char* w = base + L.tail;
     A->ust = (double*)w; w += 3 * an;
     A->phi = (double*)w; w += 3 * an;
     A->phi0 = (double*)w; w += 3 * an;
@@ -1302,6 +1327,10 @@ int swe_adj_create(const swe_params* p, const swe_buffers* b, int32_t nsteps,
     A->lamB = (double*)w; w += 3 * an;
     A->lam = (double*)w; w += 3 * an;
     A->mu = (double*)w; w += 3 * an;
+    if ((size_t)(w - base) != L.total) {  // the carve-up is the layout
+        delete A;
+        return SWE_EINVAL;
+    }
     A->aa.p = m.p;
     A->aa.z = b->z;
     A->aa.fric = b->fric;
@@ -1325,6 +1354,7 @@ int swe_adj_destroy(swe_adj* A) {
 
 int swe_adj_set_dts(swe_adj* A, const double* dts) {
     if (!A) return SWE_EINVAL;
+    A->last_kept = false;  // the kept segment belongs to the old steps
     if (!dts) {
         A->dts_frozen = false;
         return SWE_OK;
@@ -1372,17 +1402,37 @@ int swe_adj_forward(swe_adj* A, double* loss) {
     }
     double* cur = S0;
     double* nxt = S1;
+    // the last segment's steps write their states and both rates where the
+    // backward pass's recompute of that segment would, which it then skips
+    // (with one segment, ckpt_every >= nsteps, the reverse recomputes nothing)
+    const int last = ((A->nsteps - 1) / A->ckpt) * A->ckpt;
+    A->last_kept = false;
     for (int k = 0; k < A->nsteps; ++k) {
         if (k % A->ckpt == 0)
             (void)hipMemcpyAsync(A->ckpts + (size_t)(k / A->ckpt) * 3 * n, cur, 3 * n * sizeof(double),
                            hipMemcpyDeviceToDevice, A->stream);
+        double *phi = nullptr, *phi2 = nullptr;
+        if (k >= last) {
+            if (k == last && cur != S0) {
+                (void)hipMemcpyAsync(S0, cur, 3 * n * sizeof(double), hipMemcpyDeviceToDevice,
+                                     A->stream);
+                cur = S0;
+            }
+            nxt = cur + 3 * n;
+            phi = A->segphi + (size_t)(k - last) * 3 * n;
+            phi2 = A->segphi2 + (size_t)(k - last) * 3 * n;
+        }
         fwd_step(A, cur, cur + n, cur + 2 * n, nxt, nxt + n, nxt + 2 * n,
-                 A->dts_frozen ? host_dts[k] : 0.0, k);
+                 A->dts_frozen ? host_dts[k] : 0.0, k, phi, phi2);
         if ((k + 1) % A->every == 0 && (k + 1) / A->every <= A->nrows)
             hipLaunchKernelGGL(gauge_kernel, dim3((A->ngauges + 63) / 64), dim3(64), 0,
                                A->stream, (const double*)nxt, A->gauges, A->ngauges,
                                A->series + (size_t)((k + 1) / A->every - 1) * A->ngauges);
-        double* t = cur; cur = nxt; nxt = t;
+        if (k >= last) {
+            cur = nxt;
+        } else {
+            double* t = cur; cur = nxt; nxt = t;
+        }
     }
     hipLaunchKernelGGL(loss_kernel, dim3(1), dim3(64), 0, A->stream, (const double*)A->series,
                        A->obs, (size_t)A->nrows * A->ngauges, A->loss_dev);
@@ -1394,6 +1444,7 @@ int swe_adj_forward(swe_adj* A, double* loss) {
     if (hipMemcpy(&s, A->m.sc, sizeof s, hipMemcpyDeviceToHost) != hipSuccess) return SWE_EHIP;
     if (loss) *loss = l;
     A->dts_frozen = true;  // the backward pass replays exactly these steps
+    A->last_kept = true;
     if (s.status & SWE_FLAG_NONFINITE) return SWE_ENONFINITE;
     if (s.status & SWE_FLAG_NEGDEPTH) return SWE_ENEGDEPTH;
     if (s.status & SWE_FLAG_DT) return SWE_EDT;
@@ -1416,10 +1467,15 @@ int swe_adj_backward(swe_adj* A, double* grad) {
     for (int sg = nseg - 1; sg >= 0; --sg) {
         const int s = sg * A->ckpt;
         const int e = s + A->ckpt < A->nsteps ? s + A->ckpt : A->nsteps;
-        // recompute U^s .. U^{e-1} into the segment buffer
-        (void)hipMemcpyAsync(A->seg, A->ckpts + (size_t)sg * 3 * n, 3 * n * sizeof(double),
-                       hipMemcpyDeviceToDevice, A->stream);
-        for (int k = s; k < e - 1; ++k) {
+        // the forward pass left the last segment in place, rates included
+        const bool full = sg == nseg - 1 && A->last_kept;
+        // else recompute U^s .. U^{e-1} into the segment buffer
+        if (!full) {
+            (void)hipMemcpyAsync(A->seg, A->ckpts + (size_t)sg * 3 * n, 3 * n * sizeof(double),
+                                 hipMemcpyDeviceToDevice, A->stream);
+            A->last_kept = false;
+        }
+        for (int k = s; !full && k < e - 1; ++k) {
             double* in = A->seg + (size_t)(k - s) * 3 * n;
             double* o = in + 3 * n;
             fwd_step(A, in, in + n, in + 2 * n, o, o + n, o + 2 * n, dts[k], k,
@@ -1434,7 +1490,9 @@ int swe_adj_backward(swe_adj* A, double* grad) {
                                    A->ngauges, A->lam);
             }
             const double* Uk = A->seg + (size_t)(k - s) * 3 * n;
-            const bool kept = k < e - 1;  // the recompute stopped before the last step
+            // the recompute stops before the segment's last step; the
+            // forward pass did not
+            const bool kept = full || k < e - 1;
             adj_step(A, Uk, dts[k], grad, kept ? A->segphi + (size_t)(k - s) * 3 * n : nullptr,
                      kept ? A->segphi2 + (size_t)(k - s) * 3 * n : nullptr);
             // lam <- lamA (the buffers trade places)

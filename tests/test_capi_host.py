@@ -120,6 +120,22 @@ def test_adjoint_rejects_rain_and_soil_fields_without_gpu():
         assert e.value.code == capi.SWE_EINVAL
 
 
+def test_adjoint_workspace_with_spacing_beyond_the_run_without_gpu():
+    # a checkpoint spacing of at least the step count is one segment: the
+    # workspace is that of a spacing equal to the step count, and it grows
+    # with the spacing below it (one state and two rates per step kept)
+    from paper_1307_4839_amd import capi
+    p = capi.make_params(40, 24, 1.0, 1.0, fric_law=capi.SWE_FRIC_MANNING, fric_coef=0.03)
+    one = capi.swe_adj_workspace_bytes(p, 60, 60, 3, 5)
+    for ckpt in (61, 1000, 1 << 30):
+        assert capi.swe_adj_workspace_bytes(p, 60, ckpt, 3, 5) == one
+    sizes = [capi.swe_adj_workspace_bytes(p, 60, c, 3, 5) for c in (8, 15, 30, 60)]
+    assert sizes == sorted(sizes) and len(set(sizes)) == 4
+    plane = -(-40 * 24 * 8 // 256) * 256
+    assert capi.swe_adj_workspace_bytes(p, 60, 60, 3, 5) - \
+        capi.swe_adj_workspace_bytes(p, 60, 59, 3, 5) == 3 * plane * (3 - 1)
+
+
 def test_first_order_limits_without_gpu():
     # the adjoint runs the second-order scheme only and the members of an
     # ensemble share it; an order outside {0, 1, 2} is invalid (all checked

@@ -174,6 +174,38 @@ def test_adjoint_against_oracle_tangent_middle_size(torch_cuda):
         assert abs(gd - dL) <= 1e-10 * max(abs(dL), 1e-300), (k, gd, dL)
 
 
+def test_gradient_independent_of_checkpoint_spacing(torch_cuda):
+    # checkpoints every 7 steps (the forward pass keeps the last segment,
+    # the reverse recomputes the others), every step, and one segment (the
+    # forward pass keeps everything, nothing is recomputed): the same
+    # deterministic kernels on the same states, so the same bits; a second
+    # reverse pass after one forward pass gives them again
+    torch = torch_cuda
+    from paper_1307_4839_amd.solver import Calibration
+    wl, fric_obs = case_calibration()
+    nsteps, every = 60, 5
+    base = oracle.State(wl)
+    assert base.run(nsteps) == 0
+    dts = np.array(base.dts)
+    p = oracle.params_of(wl)
+    obs, _ = oracle.gauge_run(p, wl.h, wl.qx, wl.qy, wl.z, fric_obs, dts, wl.gauges, every)
+    out = []
+    for ck in (7, 1, 60, 1000):
+        say(f"[adjoint] checkpoints every {ck} of {nsteps}")
+        cal = Calibration(wl, wl.gauges, every, obs, nsteps, ckpt_every=ck)
+        cal.set_dts(dts)
+        L = cal.forward()
+        g1 = cal.backward().cpu().numpy()
+        g2 = cal.backward().cpu().numpy()
+        assert np.array_equal(g1, g2)
+        out.append((L, g1))
+        cal.close()
+        torch.cuda.empty_cache()
+    for L, g in out[1:]:
+        assert L == out[0][0]
+        assert np.array_equal(g, out[0][1])
+
+
 def test_autograd_function(torch_cuda):
     torch = torch_cuda
     from paper_1307_4839_amd.solver import Calibration, GaugeMisfit
