@@ -1007,12 +1007,14 @@ __device__ __forceinline__ int march(const MemberArgs& m, const TileIO& io, int 
     // else quotients sharing the reciprocals of dx and dy
     const Recip Rdx = d.rcp(p.dx), Rdy = d.rcp(p.dy);
 
-    // --- prologue: rows y0-2 .. y0+1, face y0-1/2; prefetch row y0+2 -------
+    // --- prologue: rows y0-2 .. y0+1, face y0-1/2; stage 1 prefetches row
+    // y0+2 ------------------------------------------------------------------
     Fetch<STAGE> fA = fetch<STAGE>(m, io, y0 - 2, cs);
     Fetch<STAGE> fB = fetch<STAGE>(m, io, y0 - 1, cs);
     Fetch<STAGE> fC = fetch<STAGE>(m, io, y0, cs);
     Fetch<STAGE> fD = fetch<STAGE>(m, io, y0 + 1, cs);
-    Fetch<STAGE> fnext = fetch<STAGE>(m, io, y0 + 2, cs);
+    Fetch<STAGE> fnext;
+    if (STAGE == 1) fnext = fetch<STAGE>(m, io, y0 + 2, cs);
     RawCell rA = cell(fA);
     RawCell rB = cell(fB);
     RawCell rC = cell(fC);
@@ -1029,12 +1031,12 @@ __device__ __forceinline__ int march(const MemberArgs& m, const TileIO& io, int 
     note_cell(d, rD, p1);
     // stage input discharges of rows j and j+1 (stage 2 needs them for U**)
     double q0x = rC.qx, q0y = rC.qy, q1x = rD.qx, q1y = rD.qy;
-    // U^n of rows j and j+1 (stage 2: Heun's average)
-    double n0h = fC.h, n0x = fC.qx, n0y = fC.qy, n1h = fD.h, n1x = fD.qx, n1y = fD.qy;
-    double c0 = fC.coef, c1 = fD.coef;
 
     Rec rprev = reconstruct<ORDER>(to_y(pA), to_y(pB), to_y(p0), p.h_eps, d.rcp(pB.h), d);
     Rec rcur = reconstruct<ORDER>(to_y(pB), to_y(p0), to_y(p1), p.h_eps, R0, d);
+    // stage 2: the centred source of the y-reconstruction, taken when the
+    // reconstruction is made, so that only its face j+1/2 side stays live
+    double fcy_cur = STAGE == 2 ? centred(p.g, rcur) : 0.0;
     double gm0, gm1, gm2;  // face below the current row, as seen from above
     double gm_speed = 0.0;
     {
@@ -1062,30 +1064,46 @@ __device__ __forceinline__ int march(const MemberArgs& m, const TileIO& io, int 
     }
 
     for (int j = y0; j < y1; ++j) {
-        // the loads of row j+2 were issued one iteration ahead; issue j+3
-        Fetch<STAGE> f2 = fnext;
-        if (j + 1 < y1) fnext = fetch<STAGE>(m, io, j + 3, cs);
-        // stage 2: V_inf of the output row, loaded while the row is computed
-        double vi = 0.0;
-        if (STAGE == 2 && p.infil && out_col) vi = m.vinf[(size_t)j * p.nx + c];
+        // Stage 1: the loads of row j+2 were issued one iteration ahead;
+        // issue j+3.  Stage 2 issues those of row j+2 here and uses them
+        // after the x direction of row j, which hides their latency and keeps
+        // the two directions' temporaries from being live together (three
+        // waves per SIMD instead of two).
+        Fetch<STAGE> f2;
+        if (STAGE == 2) {
+            f2 = fetch<STAGE>(m, io, j + 2, cs);
+        } else {
+            f2 = fnext;
+            if (j + 1 < y1) fnext = fetch<STAGE>(m, io, j + 3, cs);
+        }
 
         // ---- y direction, all in registers ----
-        RawCell r2 = cell(f2);
-        Recip R2 = d.rcp(r2.h);
-        Prim p2 = prim_x(r2, p.h_eps, R2, d);
-        note_cell(d, r2, p2);
-        d.settle();
-        Rec rnext = reconstruct<ORDER>(to_y(p0), to_y(p1), to_y(p2), p.h_eps, R1, d);
-        FaceOut gp = face<FLUX>(p.g, rcur.h_p, rcur.z_p, rcur.un_p, rcur.ut_p, rnext.h_m, rnext.z_m,
-                          rnext.un_m, rnext.ut_m, d);
-        double gp_speed = 0.0;
-        if (STAGE == 1)
-            gp_speed = face_speed<FLUX>(p.g, rcur.h_p, rcur.un_p, rnext.h_m, rnext.un_m, d);
-        d.settle();
-        double fcy = centred(p.g, rcur);
-        double Y0 = gp.f0 - gm0;
-        double Y1 = gp.fl1 - gm1 - fcy;  // normal momentum (qy)
-        double Y2 = gp.f2 - gm2;         // tangential momentum (qx)
+        RawCell r2;
+        Recip R2;
+        Prim p2;
+        Rec rnext;
+        FaceOut gp;
+        double gp_speed = 0.0, fcy_next = 0.0;
+        double Y0, Y1, Y2;
+        auto y_direction = [&]() {
+            r2 = cell(f2);
+            R2 = d.rcp(r2.h);
+            p2 = prim_x(r2, p.h_eps, R2, d);
+            note_cell(d, r2, p2);
+            d.settle();
+            rnext = reconstruct<ORDER>(to_y(p0), to_y(p1), to_y(p2), p.h_eps, R1, d);
+            if (STAGE == 2) fcy_next = centred(p.g, rnext);
+            gp = face<FLUX>(p.g, rcur.h_p, rcur.z_p, rcur.un_p, rcur.ut_p, rnext.h_m, rnext.z_m,
+                            rnext.un_m, rnext.ut_m, d);
+            if (STAGE == 1)
+                gp_speed = face_speed<FLUX>(p.g, rcur.h_p, rcur.un_p, rnext.h_m, rnext.un_m, d);
+            d.settle();
+            const double fcy = STAGE == 2 ? fcy_cur : centred(p.g, rcur);
+            Y0 = gp.f0 - gm0;
+            Y1 = gp.fl1 - gm1 - fcy;  // normal momentum (qy)
+            Y2 = gp.f2 - gm2;         // tangential momentum (qx)
+        };
+        if (STAGE == 1) y_direction();
 
         // ---- x direction, neighbours through DPP or LDS ----
         const int b = j & 1;
@@ -1122,13 +1140,8 @@ __device__ __forceinline__ int march(const MemberArgs& m, const TileIO& io, int 
         double fp_speed = 0.0;
         if (STAGE == 1) fp_speed = face_speed<FLUX>(p.g, rx.h_p, rx.un_p, hm_r, unm_r, d);
         d.settle();
-        double fm0, fm1, fm2;
-        if (WAVE) {
-            if (FAST && __builtin_amdgcn_ballot_w64(!d.ok()) != 0) return j;
-            fm0 = from_left(fp.f0);
-            fm1 = from_left(fp.fr1);
-            fm2 = from_left(fp.f2);
-        } else {
+        const double fcx = centred(p.g, rx);
+        if (!WAVE) {
             L.f0[t] = fp.f0;
             L.f1[t] = fp.fr1;
             L.f2[t] = fp.f2;
@@ -1136,6 +1149,29 @@ __device__ __forceinline__ int march(const MemberArgs& m, const TileIO& io, int 
             L.u[b ^ 1][t] = p1.un;
             L.v[b ^ 1][t] = p1.ut;
             L.e[b ^ 1][t] = p1.eta;
+        }
+        // stage 2: the y direction, before the row's operand-bounds vote so
+        // that the vote covers it
+        if (STAGE == 2) y_direction();
+        // stage 2: V_inf, U^n (Heun's average) and the friction coefficient
+        // of the output row, read again (cached since the row was fetched)
+        // rather than kept in registers since then
+        double vi = 0.0, n0h = 0.0, n0x = 0.0, n0y = 0.0, c0 = 0.0;
+        if (STAGE == 2 && out_col) {
+            const size_t ix = (size_t)j * p.nx + c;
+            if (p.infil) vi = m.vinf[ix];
+            n0h = io.h[ix];
+            n0x = io.qx[ix];
+            n0y = io.qy[ix];
+            c0 = m.fric ? m.fric[ix] : p.coef;
+        }
+        double fm0, fm1, fm2;
+        if (WAVE) {
+            if (FAST && __builtin_amdgcn_ballot_w64(!d.ok()) != 0) return j;
+            fm0 = from_left(fp.f0);
+            fm1 = from_left(fp.fr1);
+            fm2 = from_left(fp.f2);
+        } else {
             if (FAST && !d.ok()) L.bad[j & 1] = 1;
             __syncthreads();
             if (FAST && __builtin_amdgcn_readfirstlane(L.bad[j & 1]) != 0) return j;
@@ -1149,7 +1185,6 @@ __device__ __forceinline__ int march(const MemberArgs& m, const TileIO& io, int 
             if (col_in) ay = fmax(ay, gp_speed);
             if (xface_ok) ax = fmax(ax, fp_speed);
         }
-        double fcx = centred(p.g, rx);
         double X0 = fp.f0 - fm0;
         double X1 = fp.fl1 - fm1 - fcx;  // normal momentum (qx)
         double X2 = fp.f2 - fm2;         // tangential momentum (qy)
@@ -1217,11 +1252,8 @@ __device__ __forceinline__ int march(const MemberArgs& m, const TileIO& io, int 
         R1 = R2;
         q0x = q1x; q0y = q1y;
         q1x = r2.qx; q1y = r2.qy;
-        n0h = n1h; n0x = n1x; n0y = n1y;
-        n1h = f2.h; n1x = f2.qx; n1y = f2.qy;
-        c0 = c1;
-        c1 = f2.coef;
         rcur = rnext;
+        fcy_cur = fcy_next;
         gm0 = gp.f0;
         gm1 = gp.fr1;
         gm2 = gp.f2;
