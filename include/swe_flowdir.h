@@ -22,9 +22,12 @@
  * device memory; code is [ny][nx] uint8 in device memory.  Both buffers
  * are owned by the caller and must not overlap.  The call is asynchronous:
  * it enqueues one kernel on hip_stream (NULL = the default stream) and
- * returns.  Any length and alignment is accepted: each lane moves four
- * cells of a row with the widest loads (16, 8 or 4 bytes) and code stores
- * (32, 16 or 8 bits) that the alignment of their address allows.
+ * returns.  Any row length is accepted, and any placement of the buffers
+ * provided z is aligned to its element size (4 or 8 bytes): each lane
+ * reads its four cells of a row with the widest loads their alignment
+ * allows (16, 8 or 4 bytes) and stores their codes as one aligned 32-bit
+ * word (joined across two lanes when the row's codes do not start on a
+ * 4-byte boundary).
  */
 #ifndef SWE_FLOWDIR_H
 #define SWE_FLOWDIR_H
@@ -42,8 +45,8 @@ extern "C" {
  * where needed to keep the launch grid within its limits).
  * Returns SWE_OK (also for nx == 0 or ny == 0, with nothing launched),
  * SWE_EINVAL for nx or ny negative, more than 2^36 cells, rows negative or
- * above 65536, or a null pointer with cells to process, and SWE_EHIP if
- * the launch fails. */
+ * above 65536, a null pointer with cells to process or a z not aligned to
+ * its element size, and SWE_EHIP if the launch fails. */
 int swe_flow_dir_f32(const float* z, int32_t nx, int32_t ny, uint8_t* code,
                      int32_t rows, void* hip_stream);
 
@@ -53,11 +56,9 @@ int swe_flow_dir_f64(const double* z, int32_t nx, int32_t ny, uint8_t* code,
 
 /* Rows per workgroup that swe_flow_dir_f32 (elem_bytes 4) or
  * swe_flow_dir_f64 (elem_bytes 8) uses for rows == 0, before any raise for
- * the grid limit: about 4096 (float) or 16384 (double) workgroups, moved
- * within a factor 2 when that avoids a nearly empty last round of
- * workgroups on the current device (its compute units and the kernel's
- * occupancy; without a device, the unmoved value).  Host only; SWE_EINVAL
- * for other elem_bytes, negative sizes or a null rows. */
+ * the grid limit: about 6144 (float) or 16384 (double) workgroups of 1024
+ * columns, within [4, 64].  Host only, no device call; SWE_EINVAL for other
+ * elem_bytes, negative sizes or a null rows. */
 int swe_flow_dir_rows(int32_t nx, int32_t ny, int32_t elem_bytes, int32_t* rows);
 
 #ifdef __cplusplus

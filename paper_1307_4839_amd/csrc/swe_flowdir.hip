@@ -10,10 +10,13 @@
 // cells start at a column that is a multiple of 4, so the alignment of
 // their address depends on the row only (the same for every lane of the
 // row): each row is loaded with the widest loads its alignment allows
-// (16, 8 or 4 bytes) and its codes stored as whole 32-, 16- or 8-bit words,
-// so rows whose length is not a multiple of 4 keep the wide path.  The last
-// lane of a row may hold fewer than four cells.  Codes are written with
-// non-temporal stores (they are not read again by the kernel).
+// (16, 8 or 4 bytes), and its codes are stored as aligned 32-bit words: on a
+// row whose codes do not start on a 4-byte boundary, each lane joins its
+// last codes with the next lane's first ones (a lane shift), so rows whose
+// length is not a multiple of 4 keep whole-word stores.  The last lane of a
+// row may hold fewer than four cells.  Codes of rows that start on a cache
+// line are written with non-temporal stores (they are not read again by the
+// kernel), the others through the cache (see store_codes).
 //
 // Cells outside the grid read as elevation 0, which the strictly-positive
 // test never selects, so the boundary needs no special case.
@@ -116,17 +119,69 @@ __device__ __forceinline__ uint32_t cell_code(const Row<T>& lo, const Row<T>& mi
     return code;
 }
 
-// The four codes of a lane (packed little-endian) to out, with the widest
-// stores its alignment allows; only the first `n` when the row ends sooner.
-__device__ __forceinline__ void store_codes(uint8_t* out, uint32_t packed, int al, int n) {
-    if (n == 4 && al == 4) {
-        __builtin_nontemporal_store(packed, reinterpret_cast<uint32_t*>(out));
-    } else if (n == 4 && al == 2) {
-        __builtin_nontemporal_store((uint16_t)(packed & 0xffffu), reinterpret_cast<uint16_t*>(out));
-        __builtin_nontemporal_store((uint16_t)(packed >> 16), reinterpret_cast<uint16_t*>(out) + 1);
-    } else {
-        for (int c = 0; c < n; ++c)
-            __builtin_nontemporal_store((uint8_t)(packed >> (8 * c)), out + c);
+// Value of lane t+1 of the wave (lane 63 gets its own), by a full-wave DPP
+// shift.
+__device__ __forceinline__ uint32_t from_next_lane(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x130, 0xf, 0xf, false);
+}
+
+// Bytes [b0, b1) of a lane's packed codes to out + b0, with the widest
+// aligned stores that fit (at most three stores).
+__device__ __forceinline__ void store_bytes(uint8_t* out, uint32_t packed, int b0, int b1) {
+    int b = b0;
+    while (b < b1) {
+        const uintptr_t a = reinterpret_cast<uintptr_t>(out + b);
+        if (b1 - b >= 2 && (a & 1) == 0) {
+            *reinterpret_cast<uint16_t*>(out + b) = (uint16_t)(packed >> (8 * b));
+            b += 2;
+        } else {
+            out[b] = (uint8_t)(packed >> (8 * b));
+            b += 1;
+        }
+    }
+}
+
+// The `n` codes of a lane (packed little-endian, n = 4 but for the last
+// lane of a row) to out.  A row whose codes start on a 4-byte boundary is
+// one 32-bit store per lane.  On a row whose codes start s = 1..3 bytes
+// before a boundary, every lane stores one aligned 32-bit word made of its
+// last 4 - s codes and the first s codes of the next lane (taken by a lane
+// shift), and only the wave's first lane, its last lane and the end of the
+// row store single bytes or halves.  `line`: the row's codes start on a
+// 128-byte cache line, so every wave writes whole lines, and the stores
+// are non-temporal (the codes are not read again); other rows store through
+// the cache, where the lines that two waves share are merged before they
+// are written to memory (non-temporal stores of such rows wrote about 1.19
+// times the code bytes, these 1.05).  `lane` is the lane in the wave; all
+// lanes of a wave that are left of an active lane are active with n = 4.
+__device__ __forceinline__ void store_codes(uint8_t* out, uint32_t packed, int s, int n,
+                                            int n_next, int lane, bool line) {
+    if (s == 0) {
+        if (n < 4) {
+            store_bytes(out, packed, 0, n);
+        } else if (line) {
+            __builtin_nontemporal_store(packed, reinterpret_cast<uint32_t*>(out));
+        } else {
+            // keeps the compiler from hoisting this store and the
+            // non-temporal one above into one store without the hint
+            asm volatile("" ::: "memory");
+            *reinterpret_cast<uint32_t*>(out) = packed;
+        }
+        return;
+    }
+    // the next lane's codes (every lane of the wave takes part in the shift)
+    const uint32_t next = from_next_lane(packed);
+    // the word at out + s: this lane's codes s..3 and the next lane's 0..s-1
+    const bool join = lane < 63 && n == 4 && n_next >= s;
+    // codes 0..s-1 go into the previous lane's word unless this lane is the
+    // wave's first or the previous lane did not join (this lane then holds
+    // fewer than s codes)
+    const bool lead = lane == 0 || n < s;
+    if (lead) store_bytes(out, packed, 0, min(s, n));
+    if (join) {
+        *reinterpret_cast<uint32_t*>(out + s) = (packed >> (8 * s)) | (next << (32 - 8 * s));
+    } else if (n > s) {
+        store_bytes(out, packed, s, n);
     }
 }
 
@@ -134,13 +189,16 @@ template <typename T>
 __global__ __launch_bounds__(FD_THREADS) void flow_dir_kernel(const T* __restrict__ z,
                                                               uint8_t* __restrict__ code,
                                                               int nx, int ny, int rows,
-                                                              int strips, int zal, int cal) {
+                                                              int strips, int zal, int cal0) {
     const int b = blockIdx.x;
     const int strip = b % strips;
     const int seg = b / strips;
     const int col0 = (strip * FD_THREADS + (int)threadIdx.x) * 4;
     const bool active = col0 < nx;
-    const int ncell = min(4, nx - col0);
+    const int ncell = active ? min(4, nx - col0) : 0;
+    // codes held by the next lane of the row (0 past its end)
+    const int ncell_next = col0 + 4 < nx ? min(4, nx - col0 - 4) : 0;
+    const int lane = (int)threadIdx.x & 63;
     const int y0 = seg * rows;
     const int y1 = min(ny, y0 + rows);
 
@@ -156,13 +214,21 @@ __global__ __launch_bounds__(FD_THREADS) void flow_dir_kernel(const T* __restric
 #pragma unroll
         for (int u = 0; u < FD_BATCH; ++u) {
             const int j = j0 + u;
-            if (active && j < y1) {
+            // rows past the segment's end are the same for every lane: the
+            // whole wave skips them, so the lane shift of store_codes sees
+            // every lane of the wave
+            if (j < y1) {
                 const long long e = (long long)j * nx + col0;
                 uint32_t packed = 0;
 #pragma unroll
                 for (int c = 1; c <= 4; ++c)
                     packed |= cell_code<T>(w[u], w[u + 1], w[u + 2], c) << (8 * (c - 1));
-                store_codes(code + e, packed, min(cal, elem_align(e)), ncell);
+                // bytes from the codes' start to the next 4-byte boundary
+                // (the same for every lane of the row), and whether the
+                // row's codes start on a cache line
+                const int s = (int)((4 - ((cal0 + e) & 3)) & 3);
+                const bool line = ((cal0 + (long long)j * nx) & 127) == 0;
+                store_codes(code + e, packed, s, ncell, ncell_next, lane, line);
             }
         }
         w[0] = w[FD_BATCH];
@@ -170,51 +236,17 @@ __global__ __launch_bounds__(FD_THREADS) void flow_dir_kernel(const T* __restric
     }
 }
 
-// About 4096 workgroups of 1024 columns for float32 and 16384 for float64
-// (measured optimum on 8192 x 8192: 16 and 4 rows).
+// Rows per workgroup: about 6144 workgroups of 1024 columns for float32 and
+// 16384 for float64, within [4, 64] (measured on 8192 x 8192, 14786 x 10086
+// and nearby widths: 8 to 16 rows and 24 rows for float32, 4 rows for
+// float64, are the fastest or within 2% of it).
 int default_rows(long long nx, long long ny, int elem_bytes) {
-    const int shift = elem_bytes == 8 ? 24 : 22;
-    long long cells = nx * ny;
-    long long r = (cells + (1LL << shift) - 1) >> shift;
+    const long long cells = nx * ny;
+    const long long per = elem_bytes == 8 ? (16384LL << 10) : (6144LL << 10);
+    long long r = (cells + per / 2) / per;
     if (r < 4) r = 4;
     if (r > 64) r = 64;
     return (int)r;
-}
-
-// Workgroups of flow_dir_kernel<T> the current device holds at once (compute
-// units x resident workgroups per unit), or 0 when that cannot be queried.
-template <typename T>
-int resident_blocks() {
-    int dev = -1, cus = 0, per = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0) return 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-        return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, flow_dir_kernel<T>, FD_THREADS, 0) !=
-        hipSuccess)
-        return 0;
-    return cus * per;
-}
-
-// The default rows per workgroup adjusted to the device: a launch runs in
-// rounds of `resident` workgroups, each taking about rows + 2 row loads, so
-// a last round that is nearly empty costs almost a full one.  Among rows
-// within a factor 2 of the default, take the one with the fewest
-// rounds x (rows + 2) when that saves more than 15%.
-int balanced_rows(long long nx, long long ny, int r0, int resident) {
-    if (resident <= 0) return r0;
-    const long long strips = (nx + FD_THREADS * 4 - 1) / (FD_THREADS * 4);
-    auto cost = [&](long long r) {
-        const long long blocks = strips * ((ny + r - 1) / r);
-        return ((blocks + resident - 1) / resident) * (r + 2);
-    };
-    long long best = r0, cbest = cost(r0);
-    const long long lo = r0 / 2 < 4 ? 4 : r0 / 2, hi = 2 * r0 > 64 ? 64 : 2 * r0;
-    for (long long r = lo; r <= hi; ++r)
-        if (cost(r) < cbest) {
-            cbest = cost(r);
-            best = r;
-        }
-    return 100 * cbest < 85 * cost(r0) ? (int)best : r0;
 }
 
 bool check_args(const void* z, int32_t nx, int32_t ny, const void* code, int32_t rows) {
@@ -224,35 +256,26 @@ bool check_args(const void* z, int32_t nx, int32_t ny, const void* code, int32_t
     return true;
 }
 
-// Alignment in elements of a pointer to `bytes`-byte elements: the largest
-// of 4, 2, 1 elements, spanning at most 16 bytes, that divides the address.
-int ptr_align(const void* p, int bytes) {
-    const uintptr_t a = reinterpret_cast<uintptr_t>(p);
-    for (int k = 4; k > 1; k /= 2)
-        if ((uintptr_t)k * bytes <= 16 && a % ((uintptr_t)k * bytes) == 0) return k;
-    return 1;
-}
-
 template <typename T>
 int flow_dir_launch(const T* z, int32_t nx, int32_t ny, uint8_t* code, int32_t rows,
                     void* stream) {
     if (!check_args(z, nx, ny, code, rows)) return SWE_EINVAL;
     if (nx == 0 || ny == 0) return SWE_OK;
-    // alignments of the buffers themselves, in elements; a row's own
-    // alignment is the smaller of this and that of its offset
-    const int zal = ptr_align(z, (int)sizeof(T));
-    const int cal = ptr_align(code, 1);
+    const uintptr_t za = reinterpret_cast<uintptr_t>(z);
+    if (za % sizeof(T) != 0) return SWE_EINVAL;  // z must be aligned to its element
+    // z's own alignment in elements (at most 16 bytes; a row's is the
+    // smaller of this and that of its offset) and the codes' address mod 128
+    const int zal = za % 16 == 0 ? 16 / (int)sizeof(T) : za % 8 == 0 ? 8 / (int)sizeof(T) : 1;
+    const int cal0 = (int)(reinterpret_cast<uintptr_t>(code) & 127);
     const int width = FD_THREADS * 4;
     const long long strips = (nx + width - 1) / width;
-    long long r = rows > 0 ? rows
-                           : balanced_rows(nx, ny, default_rows(nx, ny, (int)sizeof(T)),
-                                           resident_blocks<T>());
+    long long r = rows > 0 ? rows : default_rows(nx, ny, (int)sizeof(T));
     // one-dimensional grid of strips x segments
     while (strips * ((ny + r - 1) / r) > 0x7fffffffLL) r *= 2;
     const long long blocks = strips * ((ny + r - 1) / r);
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipLaunchKernelGGL((flow_dir_kernel<T>), dim3((unsigned)blocks), dim3(FD_THREADS), 0, s, z,
-                       code, (int)nx, (int)ny, (int)r, (int)strips, zal, cal);
+                       code, (int)nx, (int)ny, (int)r, (int)strips, zal, cal0);
     return hipGetLastError() == hipSuccess ? SWE_OK : SWE_EHIP;
 }
 
@@ -270,8 +293,6 @@ extern "C" int swe_flow_dir_f64(const double* z, int32_t nx, int32_t ny, uint8_t
 
 extern "C" int swe_flow_dir_rows(int32_t nx, int32_t ny, int32_t elem_bytes, int32_t* rows) {
     if (!rows || nx < 0 || ny < 0 || (elem_bytes != 4 && elem_bytes != 8)) return SWE_EINVAL;
-    const int r0 = default_rows(nx, ny, elem_bytes);
-    *rows = balanced_rows(nx, ny, r0,
-                          elem_bytes == 4 ? resident_blocks<float>() : resident_blocks<double>());
+    *rows = default_rows(nx, ny, elem_bytes);
     return SWE_OK;
 }

@@ -49,7 +49,13 @@ def test_flow_dir_validation_without_gpu():
             with pytest.raises(capi.SweError) as e:
                 fn(*args)
             assert e.value.code == capi.SWE_EINVAL
-    assert capi.swe_flow_dir_rows(8192, 8192, 4) == 16
+    # a DEM not aligned to its element size (the address is never read)
+    for fn, addr in ((capi.swe_flow_dir_f32, 4098), (capi.swe_flow_dir_f64, 4100)):
+        with pytest.raises(capi.SweError) as e:
+            fn(addr, 4, 4, 16, 0, 0)
+        assert e.value.code == capi.SWE_EINVAL
+    assert capi.swe_flow_dir_rows(8192, 8192, 4) == 11
+    assert capi.swe_flow_dir_rows(14786, 10086, 4) == 24
     assert capi.swe_flow_dir_rows(8192, 8192, 8) == 4
     assert capi.swe_flow_dir_rows(3, 3, 4) == 4
     assert capi.swe_flow_dir_rows(1 << 16, 1 << 16, 4) == 64

@@ -52,14 +52,21 @@ def run(torch, z, rows=0, offset=0):
                          else torch.float64, device="cuda")
         zb[offset:].copy_(torch.as_tensor(z.ravel()))
         zt = zb[offset:].view(ny, nx)
-        ob = torch.full((ny * nx + offset,), 255, dtype=torch.uint8, device="cuda")
-        out = ob[offset:].view(ny, nx)
+        # guard bytes before and after the codes: the kernel must not touch them
+        ob = torch.full((ny * nx + offset + GUARD,), 255, dtype=torch.uint8, device="cuda")
+        out = ob[offset:offset + ny * nx].view(ny, nx)
     else:
         zt = torch.as_tensor(z).cuda()
         out = torch.full((ny, nx), 255, dtype=torch.uint8, device="cuda")
     flow_directions(zt, out=out, rows=rows)
     torch.cuda.synchronize()
+    if offset:
+        whole = ob.cpu().numpy()
+        assert (whole[:offset] == 255).all() and (whole[offset + ny * nx:] == 255).all()
     return out.cpu().numpy()
+
+
+GUARD = 16
 
 
 SHAPES = [(1, 1), (1, 7), (7, 1), (2, 2), (3, 5), (37, 29), (64, 1024), (70, 1028),
