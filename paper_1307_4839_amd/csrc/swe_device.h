@@ -920,11 +920,20 @@ __device__ __forceinline__ double from_right(double v) {
     return __hiloint2double(hi, lo);
 }
 
-template <int TXT> struct TileLds {
+// Stage 2: U^n of rows j, j+1 and j+2 of each lane's column (slot = row mod
+// 3), kept from the row's fetch for Heun's average of row j; each lane reads
+// and writes its own column only.  Stage 1 has none.
+template <int TXT, int STAGE> struct UnRing {
+    double v[3][3][TXT];
+};
+template <int TXT> struct UnRing<TXT, 1> {};
+
+template <int TXT, int STAGE> struct TileLds {
     double h[2][TXT], u[2][TXT], v[2][TXT], e[2][TXT];  // primitives of row j (j & 1)
     double hm[TXT], zm[TXT], unm[TXT], utm[TXT];  // x-reconstruction, face i-1/2 side
     double f0[TXT], f1[TXT], f2[TXT];             // x-fluxes
     int bad[2];                                   // operand bounds broken in row j (j & 1)
+    UnRing<TXT, STAGE> un;
 };
 
 // March rows y0 .. y1-1 of a tile with division policy D (see Division).
@@ -971,7 +980,7 @@ __device__ __forceinline__ void finish_cell(const MemberArgs& m, const TileIO& i
 template <int STAGE, int TXT, class D, bool FIELDS, int ORDER, int FLUX, bool PHI2>
 __device__ __forceinline__ int march(const MemberArgs& m, const TileIO& io, int strip, int y0,
                                      int y1, double dt, double rain, double& ax, double& ay,
-                                     TileLds<TXT>& L) {
+                                     TileLds<TXT, STAGE>& L) {
     constexpr int OUTW = TXT - 2 * HALO;
     constexpr bool FAST = !std::is_same<D, ExactDiv>::value;
     const KParams& p = m.p;
@@ -1031,6 +1040,12 @@ __device__ __forceinline__ int march(const MemberArgs& m, const TileIO& io, int 
     note_cell(d, rD, p1);
     // stage input discharges of rows j and j+1 (stage 2 needs them for U**)
     double q0x = rC.qx, q0y = rC.qy, q1x = rD.qx, q1y = rD.qy;
+    if constexpr (STAGE == 2) {
+        // U^n of rows y0 and y0+1 for Heun's average
+        const int s0 = y0 % 3, s1 = (y0 + 1) % 3;
+        L.un.v[s0][0][t] = fC.h; L.un.v[s0][1][t] = fC.qx; L.un.v[s0][2][t] = fC.qy;
+        L.un.v[s1][0][t] = fD.h; L.un.v[s1][1][t] = fD.qx; L.un.v[s1][2][t] = fD.qy;
+    }
 
     Rec rprev = reconstruct<ORDER>(to_y(pA), to_y(pB), to_y(p0), p.h_eps, d.rcp(pB.h), d);
     Rec rcur = reconstruct<ORDER>(to_y(pB), to_y(p0), to_y(p1), p.h_eps, R0, d);
@@ -1086,6 +1101,11 @@ __device__ __forceinline__ int march(const MemberArgs& m, const TileIO& io, int 
         double gp_speed = 0.0, fcy_next = 0.0;
         double Y0, Y1, Y2;
         auto y_direction = [&]() {
+            if constexpr (STAGE == 2) {
+                // U^n of row j+2, for its Heun average two rows later
+                const int s2 = (j + 2) % 3;
+                L.un.v[s2][0][t] = f2.h; L.un.v[s2][1][t] = f2.qx; L.un.v[s2][2][t] = f2.qy;
+            }
             r2 = cell(f2);
             R2 = d.rcp(r2.h);
             p2 = prim_x(r2, p.h_eps, R2, d);
@@ -1153,17 +1173,20 @@ __device__ __forceinline__ int march(const MemberArgs& m, const TileIO& io, int 
         // stage 2: the y direction, before the row's operand-bounds vote so
         // that the vote covers it
         if (STAGE == 2) y_direction();
-        // stage 2: V_inf, U^n (Heun's average) and the friction coefficient
-        // of the output row, read again (cached since the row was fetched)
-        // rather than kept in registers since then
+        // stage 2: V_inf and the friction coefficient of the output row
+        // (read again if it is a field), and its U^n for Heun's average from
+        // the ring, rather than kept in registers since the row was fetched
         double vi = 0.0, n0h = 0.0, n0x = 0.0, n0y = 0.0, c0 = 0.0;
-        if (STAGE == 2 && out_col) {
-            const size_t ix = (size_t)j * p.nx + c;
-            if (p.infil) vi = m.vinf[ix];
-            n0h = io.h[ix];
-            n0x = io.qx[ix];
-            n0y = io.qy[ix];
-            c0 = m.fric ? m.fric[ix] : p.coef;
+        if constexpr (STAGE == 2) {
+            const int s0 = j % 3;
+            n0h = L.un.v[s0][0][t];
+            n0x = L.un.v[s0][1][t];
+            n0y = L.un.v[s0][2][t];
+            if (out_col) {
+                const size_t ix = (size_t)j * p.nx + c;
+                if (p.infil) vi = m.vinf[ix];
+                c0 = m.fric ? m.fric[ix] : p.coef;
+            }
         }
         double fm0, fm1, fm2;
         if (WAVE) {
@@ -1370,7 +1393,7 @@ __device__ __forceinline__ void stage_tile(const MemberArgs& m, const TileIO& io
     const int c = strip * OUTW - HALO + t;
     const bool out_col = (t >= HALO) && (t < TXT - HALO) && (c < p.nx);
 
-    __shared__ TileLds<TXT> L;
+    __shared__ TileLds<TXT, STAGE> L;
 
     double dt = 0.0, rain = 0.0;
     if (STAGE == 2) {

@@ -8,7 +8,7 @@ K dispatches of that kernel (``--skip``), e.g. the warmup steps of a benchmark
 whose timed region starts after them.
 
     python -m paper_1307_4839_amd.rocprof_summary counters --fetch DB --write DB \\
-        [--sq DB] --skip K --cells N --bytes1 B1 --bytes2 B2 --json OUT.json
+        [--sq DB ...] --skip K --cells N --bytes1 B1 --bytes2 B2 --json OUT.json
 
     python -m paper_1307_4839_amd.rocprof_summary kernel --fetch DB --write DB \\
         --expect NAME=BYTES [...] --skip K --sources flowdir --json OUT.json
@@ -25,7 +25,7 @@ the dispatches after the first K, scaled by what the same counters read for
 the plain device copy in the same runs (the largest __amd_rocclr_copyBuffer
 dispatch, of known size 2^30 bytes each way), next to the algorithmic bytes
 per launch (B1, B2 bytes per cell times N cells); with --sq, the SQ counters
-of a third run (VALU and SALU instructions, waves).  The JSON carries the
+of further runs (VALU and SALU instructions, waves, the VALU mix).  The JSON carries the
 hash of the kernel sources so that a benchmark reads it only for the kernels
 it was taken on.  ``--bench-log`` names the benchmark's stderr of one of
 the runs: the simulated time and wet fraction at which its timed steps
@@ -148,7 +148,12 @@ def counters(a) -> dict:
     cw = _copy_counter(a.write, "WRITE_SIZE")
     ff = COPY_BYTES / 1024.0 / cf
     fw = COPY_BYTES / 1024.0 / cw
-    sq = _stage_avgs(a.sq, a.skip) if a.sq else {}
+    # SQ counters of one or more runs (each run holds what one pass can
+    # collect), merged per stage kernel
+    sq = {}
+    for db in a.sq or []:
+        for st, vals in _stage_avgs(db, a.skip).items():
+            sq.setdefault(st, {}).update(vals)
     rec = {"kernel_sha256_16": source_hash(), "workload": a.workload, "cells": a.cells,
            "regime": regime_of(a.bench_log) if a.bench_log else {},
            "calibration": {"probe": "1 GiB device-to-device copy (__amd_rocclr_copyBuffer)",
@@ -235,8 +240,14 @@ def counters_text(rec: dict) -> str:
             line = "   SQ: " + "  ".join(f"{kk}={v:.4g}" for kk, v in sorted(sq.items()))
             out.append(line)
             if "SQ_INSTS_VALU" in sq and rec["cells"]:
+                per = 64.0 / rec["cells"]
                 out.append(f"   VALU wave-instructions x 64 lanes per cell: "
-                           f"{sq['SQ_INSTS_VALU'] * 64 / rec['cells']:.1f}")
+                           f"{sq['SQ_INSTS_VALU'] * per:.1f}")
+                kinds = [(kk[len("SQ_INSTS_VALU_"):], v) for kk, v in sorted(sq.items())
+                         if kk.startswith("SQ_INSTS_VALU_")]
+                if kinds:
+                    out.append("   of which, per cell: " + "  ".join(
+                        f"{kk} {v * per:.1f}" for kk, v in kinds))
     return "\n".join(out)
 
 
@@ -252,7 +263,8 @@ def main(argv=None):
     c = sub.add_parser("counters")
     c.add_argument("--fetch", required=True)
     c.add_argument("--write", required=True)
-    c.add_argument("--sq")
+    c.add_argument("--sq", action="append", default=[],
+                   help="a run with SQ counters (repeatable: one per counter pass)")
     c.add_argument("--skip", type=int, default=0)
     c.add_argument("--cells", type=int, required=True)
     c.add_argument("--bytes1", type=int, required=True)
