@@ -386,6 +386,28 @@ def random_state(nx: int, ny: int, seed: int, dry_frac: float = 0.3,
     return wl
 
 
+def thacker_planar(n: int = 100, L: float = 4.0, a: float = 1.0, h0: float = 0.1,
+                   eta: float = 0.5) -> Workload:
+    """Thacker's planar surface in a paraboloid (Thacker 1981), at t = 0: a
+    basin z = h0 (r^2 / a^2 - 1) centred in an L x L walled square of n x n
+    cells, frictionless, holding water under a plane surface that rotates
+    with period 2 pi / omega, omega = sqrt(2 g h0) / a, and a uniform
+    velocity (u, v) = eta omega (-sin, cos)(omega t).  The shoreline stays
+    inside r < a (1 + eta), away from the walls.  Values at cell centres."""
+    d = L / n
+    c = _centres(n, d) - 0.5 * L
+    X, Y = np.meshgrid(c, c)
+    z = h0 * ((X * X + Y * Y) / (a * a) - 1.0)
+    omega = math.sqrt(2.0 * 9.81 * h0) / a
+    surf = eta * h0 / (a * a) * (2.0 * X - eta)
+    h = np.maximum(surf - z, 0.0)
+    return Workload(f"thacker_{n}", n, n, d, d, z=np.ascontiguousarray(z),
+                    h=np.ascontiguousarray(h), qx=np.zeros((n, n)),
+                    qy=np.ascontiguousarray(h * (eta * omega)),
+                    bc=(WALL, WALL, WALL, WALL), t_end=2.0 * math.pi / omega,
+                    nsteps=10 ** 7)
+
+
 def flowdir_dem(nx: int = 14786, ny: int = 10086, seed: int = 1307) -> np.ndarray:
     """A float32 DEM of the paper's flow-direction size (Section 5.2 gives
     only its dimensions): a ramp of 50 m across x plus uniform noise of 1 m,

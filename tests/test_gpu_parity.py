@@ -130,6 +130,16 @@ def test_hillslope_small_rain_infiltration(torch_cuda):
     assert (s.h > 0).any()
 
 
+@pytest.mark.parametrize("n", [100, 131])
+def test_thacker_planar_one_period(torch_cuda, n):
+    # a rotating plane surface in a paraboloid with its moving shoreline
+    # (frictionless, walls far away): one full period, 131 cells a side
+    # leaving ragged tiles; the results must be bitwise the oracle's
+    wl = I.thacker_planar(n)
+    s, st = compare_run(wl, wl.nsteps, t_end=wl.t_end, tol=0.0)
+    assert s.t == wl.t_end
+
+
 def test_calibration_small_friction_field(torch_cuda):
     wl = I.calibration_1024(260, 300, dam_row=40, ngauges=8, sigma_cells=6)
     compare_run(wl, 200)

@@ -417,6 +417,49 @@ def test_stoker_convergence():
 
 
 # ---------------------------------------------------------------------------
+# P10: Thacker's planar surface in a paraboloid (Thacker 1981), the textbook
+# 2D solution of the frictionless system with a moving shoreline: a plane
+# free surface rotating in the basin z = h0 (r^2/a^2 - 1) with period
+# 2 pi / omega, omega = sqrt(2 g h0) / a, and a uniform velocity
+# eta omega (-sin, cos)(omega t).  It fixes the 2D method of lines (R1) on
+# wet/dry fronts that move in both directions, where the 1D pins cannot.
+# ---------------------------------------------------------------------------
+
+def thacker_exact(n, t, L=4.0, a=1.0, h0=0.1, eta=0.5):
+    d = L / n
+    c = (np.arange(n) + 0.5) * d - L / 2
+    X, Y = np.meshgrid(c, c)
+    om = math.sqrt(2 * G * h0) / a
+    z = h0 * ((X ** 2 + Y ** 2) / a ** 2 - 1)
+    surf = eta * h0 / a ** 2 * (2 * X * math.cos(om * t) + 2 * Y * math.sin(om * t) - eta)
+    return np.maximum(surf - z, 0.0), -eta * om * math.sin(om * t), eta * om * math.cos(om * t)
+
+
+def test_thacker_planar_convergence():
+    errs = []
+    for n in (50, 100, 200):
+        wl = I.thacker_planar(n)
+        s = oracle.State(wl)
+        rc = s.run(wl.nsteps, wl.t_end)
+        assert rc == 1 and s.t == wl.t_end
+        assert s.h.min() >= 0.0
+        he, ue, ve = thacker_exact(n, wl.t_end)
+        d = wl.dx
+        errs.append(np.abs(s.h - he).sum() * d * d)
+        # the velocity is uniform where the water is deep: after one period
+        # it is back to (0, eta omega)
+        deep = s.h > 0.02
+        u = s.qx[deep] / s.h[deep]
+        v = s.qy[deep] / s.h[deep]
+        assert abs(np.median(u) - ue) < 0.05 * abs(ve) and abs(np.median(v) - ve) < 0.05 * abs(ve)
+    orders = [math.log2(errs[k] / errs[k + 1]) for k in range(2)]
+    # one period at 200^2: L1 depth error under 1% of the water volume
+    # (about 0.157 m^3); first order at the moving shoreline at least
+    assert errs[-1] < 1.5e-3, errs
+    assert min(orders) >= 1.0, (errs, orders)
+
+
+# ---------------------------------------------------------------------------
 # First order (Section 3.3: no reconstruction, n_CFL = 1; one Euler stage):
 # well-balanced, positive, equal to the literal 1D first-order scheme,
 # convergent on the Ritter dam break, and its CFL is eq. (cfl) on the cell
