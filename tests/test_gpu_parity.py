@@ -1,6 +1,6 @@
 """GPU parity: the HIP library against the CPU oracle, through the C ABI.
 
-Bar (the benchmark spec): per field, max|gpu - oracle| / max|oracle| <= 1e-12 and
+Bar: per field, max|gpu - oracle| / max|oracle| <= 1e-12 and
 every step's dt within 1e-12 relative.  The kernels evaluate the formulas in
 the oracle's order without contraction, so most cases agree bit for bit;
 the bar stays the stated tolerance because the Manning cube root is not
