@@ -124,7 +124,7 @@ def cpu_baseline(wl, rows, spinup, seconds):
 
 
 def ensemble_leg(members, steps, trial_steps):
-    """The ensemble in one persistent launch per stage (autotuned tile shape,
+    """The ensemble in one launch per stage (autotuned tile shape,
     graph-replayed steps) vs the same scenarios run one after another with
     the single-simulation context on the same GPU."""
     import torch

@@ -277,8 +277,8 @@ int swe_profile_end(swe_ctx* ctx, double* ms_rate, double* ms_update,
  * buffers b[k] (same conventions as swe_create), its own time, time step
  * (its own CFL bound), status flags and rain; all members share the
  * scheme (order and flux: SWE_EINVAL otherwise).  One step of the ensemble is
- * one persistent launch per stage over a work list of (member, strip, row
- * range) tiles; runs of 16 steps replay a captured HIP graph.  Every member
+ * one launch per stage over a work list of (member, strip, row range) tiles,
+ * one block per tile; runs of 16 steps replay a captured HIP graph.  Every member
  * evolves exactly (bit for bit) as it would in its own context.
  * ------------------------------------------------------------------------- */
 typedef struct swe_batch swe_batch;

@@ -5,10 +5,12 @@
 // routine of swe_device.h; the members share the scheme, order and flux, so
 // that one kernel serves each stage), with its own grid, parameters, time,
 // time step (its own CFL bound, Section 3.3), status flags and buffers.  A
-// step of the whole ensemble is ONE persistent launch per stage: a grid
-// sized to the resident capacity of the GPU walks a work list of (member,
-// strip, row range) tiles, largest members first.  Runs of 16 steps replay a captured
-// HIP graph.  The tile shape (strip width x rows) is chosen by a measuring
+// step of the whole ensemble is ONE launch per stage over a work list of
+// (member, strip, row range) tiles, largest members first: one block per
+// tile, dispatched in list order.  (A persistent grid sized to the GPU's
+// resident capacity, each block walking the list, held 173 VGPRs in stage 2
+// and 2 waves per SIMD; one tile per block holds 162 and 3.)  Runs of 16
+// steps replay a captured HIP graph.  The tile shape (strip width x rows) is chosen by a measuring
 // autotuner that times the candidates on the live state and restores it
 // bit for bit afterwards; results never depend on the tile shape.
 
@@ -39,15 +41,15 @@ __global__ __launch_bounds__(TXT) void batch_stage_kernel(const MemberArgs* __re
                                                           const int4* __restrict__ tiles,
                                                           int ntiles, int phase, int slot,
                                                           double t_end) {
-    for (int k = blockIdx.x; k < ntiles; k += gridDim.x) {
-        const int4 tl = tiles[k];  // member, strip, first row, end row
-        // read in place (uniform loads): a private copy of the record would
-        // live in scratch memory, since its buffer pairs are indexed by phase
-        const MemberArgs& m = ms[tl.x];
-        const TileIO io = step_io(m, phase, slot, t_end);
-        stage_tile<STAGE, TXT, FIELDS, ORDER, FLUX>(m, io, tl.y, tl.z, tl.w,
-                                                    tl.y == 0 && tl.z == 0, k);
-    }
+    const int k = blockIdx.x;
+    if (k >= ntiles) return;
+    const int4 tl = tiles[k];  // member, strip, first row, end row
+    // read in place (uniform loads): a private copy of the record would live
+    // in scratch memory, since its buffer pairs are indexed by phase
+    const MemberArgs& m = ms[tl.x];
+    const TileIO io = step_io(m, phase, slot, t_end);
+    stage_tile<STAGE, TXT, FIELDS, ORDER, FLUX>(m, io, tl.y, tl.z, tl.w,
+                                                tl.y == 0 && tl.z == 0, k);
 }
 
 // Update of the first-order scheme (Section 3.3: one explicit Euler stage,
@@ -60,7 +62,9 @@ __global__ __launch_bounds__(TXT) void batch_euler_kernel(const MemberArgs* __re
                                                           int ntiles, int phase, int slot,
                                                           double t_end) {
     constexpr int OUTW = TXT - 2 * HALO;
-    for (int k = blockIdx.x; k < ntiles; k += gridDim.x) {
+    {
+        const int k = blockIdx.x;
+        if (k >= ntiles) return;
         const int4 tl = tiles[k];
         const MemberArgs& m = ms[tl.x];
         const KParams& p = m.p;
@@ -69,7 +73,7 @@ __global__ __launch_bounds__(TXT) void batch_euler_kernel(const MemberArgs* __re
         // every lane takes part (the hyetograph lookup uses wave ballots)
         const bool go = begin_step(m, io, tl.y == 0 && tl.z == 0, dt, rain);
         const int c = tl.y * OUTW + (int)threadIdx.x;
-        if ((int)threadIdx.x >= OUTW || c >= p.nx) continue;
+        if ((int)threadIdx.x >= OUTW || c >= p.nx) return;
         for (int j = tl.z; j < tl.w; ++j) {
             const size_t i = (size_t)j * p.nx + c;
             if (!go) {
@@ -187,14 +191,6 @@ void launch_batch(const Variant& v, int tx, int grid, hipStream_t s, const Membe
                        slot, t_end);
 }
 
-template <int STAGE>
-int resident_blocks(int tx, const Variant& v) {
-    int nb = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pick<STAGE>(tx, v), tx, 0);
-    if (e != hipSuccess) return 1;
-    return nb < 1 ? 1 : nb;
-}
-
 }  // namespace
 
 struct swe_batch {
@@ -208,8 +204,6 @@ struct swe_batch {
     size_t tiles_cap;
     int ntiles;
     int tx, ty;
-    int cus;
-    int grid1, grid2;             // persistent grid of each stage for this tiling
     hipStream_t stream;
     int slot;
     size_t max_cells;
@@ -254,14 +248,6 @@ Variant variant(const swe_batch* b, int stage) {
                    b->flux};
 }
 
-int persistent_grid(const swe_batch* b, int stage) {
-    const int nb = stage == 1 ? resident_blocks<1>(b->tx, variant(b, 1))
-                              : resident_blocks<2>(b->tx, variant(b, 2));
-    long long g = (long long)nb * b->cus;
-    if (g > b->ntiles) g = b->ntiles;
-    return g < 1 ? 1 : (int)g;
-}
-
 // Work list for a tile shape: members from largest to smallest, each
 // member's tiles in strip-major order.
 int build_tiles(swe_batch* b, int tx, int ty) {
@@ -287,16 +273,14 @@ int build_tiles(swe_batch* b, int tx, int ty) {
     b->ntiles = (int)t.size();
     b->tx = tx;
     b->ty = ty;
-    b->grid1 = persistent_grid(b, 1);
-    b->grid2 = persistent_grid(b, 2);
     b->epoch++;
     return SWE_OK;
 }
 
 void enqueue_step(swe_batch* b, int phase, double t_end) {
-    launch_batch<1>(variant(b, 1), b->tx, b->grid1, b->stream, b->md, b->tiles, b->ntiles,
+    launch_batch<1>(variant(b, 1), b->tx, b->ntiles, b->stream, b->md, b->tiles, b->ntiles,
                     phase, b->slot, t_end);
-    launch_batch<2>(variant(b, 2), b->tx, b->grid2, b->stream, b->md, b->tiles, b->ntiles,
+    launch_batch<2>(variant(b, 2), b->tx, b->ntiles, b->stream, b->md, b->tiles, b->ntiles,
                     phase, b->slot, t_end);
     b->slot ^= 1;
 }
@@ -459,10 +443,6 @@ int swe_batch_create(const swe_params* p, const swe_buffers* bufs, int32_t count
         bk.sc = (DevScalars*)w; w += SCALAR_BYTES;
         hipLaunchKernelGGL(swe_init_scalars_kernel, dim3(1), dim3(64), 0, b->stream, m.sc, 0.0);
     }
-    int dev = 0;
-    (void)hipGetDevice(&dev);
-    b->cus = 256;
-    (void)hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (hipMemcpyAsync(b->bd, b->bh.data(), sizeof(Backup) * count, hipMemcpyHostToDevice,
                        b->stream) != hipSuccess) {
         delete b;

@@ -189,7 +189,7 @@ class Solver:
 
 class Ensemble:
     """Independent simulations of uneven sizes stepped together on one GPU
-    (one persistent launch per stage for the whole ensemble)."""
+    (one launch per stage for the whole ensemble, one block per tile)."""
 
     def __init__(self, workloads, device: str = "cuda"):
         if not torch.cuda.is_available():
