@@ -449,11 +449,16 @@ int swe_batch_create(const swe_params* p, const swe_buffers* bufs, int32_t count
         return SWE_EHIP;
     }
     rc = upload_members(b);
-    // default tile shape: strips of 256 columns; rows for the largest member
+    // default tile shape (before any autotuning): the single context's
+    // strip width for the largest member (one-wave strips below 8M cells),
+    // 32 rows for one-wave strips (where the autotuner lands on mixed
+    // ensembles), else half the single context's rows for that member
     int big = 0;
     for (int k = 1; k < count; ++k)
         if (ncells(&p[k]) > ncells(&p[big])) big = k;
-    if (!rc) rc = build_tiles(b, 256, std::max(MIN_TY, auto_rows(p[big].nx, p[big].ny, 256) / 2));
+    const int tx0 = default_tx(p[big].nx, p[big].ny);
+    const int ty0 = tx0 == 64 ? 32 : std::max(MIN_TY, auto_rows(p[big].nx, p[big].ny, tx0) / 2);
+    if (!rc) rc = build_tiles(b, tx0, ty0);
     if (rc) {
         delete b;
         return rc;
