@@ -81,8 +81,12 @@ extern "C" {
 #define SWE_FRIC_MANNING 1 /* coefficient n:  S_f = n^2 |u| u / h^(4/3) */
 #define SWE_FRIC_DARCY 2   /* coefficient f:  S_f = f/(8g) |u| u / h    */
 
+/* Largest row length (cells along x): a cell's byte offset within its row
+ * stays below 2^31. */
+#define SWE_MAX_NX (1 << 28)
+
 typedef struct swe_params {
-    int32_t nx, ny;      /* cells, >= 2 each */
+    int32_t nx, ny;      /* cells, >= 2 each; nx <= SWE_MAX_NX, nx ny <= 2^36 */
     double dx, dy;       /* cell sizes [m], > 0 */
     double g;            /* gravity [m/s^2] (9.81) */
     double cfl;          /* n_CFL (0.5 at second order, eq. cfl) */

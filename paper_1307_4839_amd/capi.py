@@ -39,6 +39,7 @@ SWE_BC_IMPOSED_HQ = 4
 SWE_FRIC_NONE = 0
 SWE_FRIC_MANNING = 1
 SWE_FRIC_DARCY = 2
+SWE_MAX_NX = 1 << 28  # longest row (cells along x)
 
 
 class swe_params(C.Structure):

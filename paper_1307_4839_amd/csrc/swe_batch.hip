@@ -89,7 +89,7 @@ __global__ __launch_bounds__(TXT) void batch_euler_kernel(const MemberArgs* __re
             const double coef = m.fric ? m.fric[i] : p.coef;
             friction(p, coef, h0, qx0, qy0, h1, qx1, qy1, dt);
             const double vi = p.infil ? m.vinf[i] : 0.0;
-            finish_cell<FIELDS>(m, io, i, dt, rain, h1, qx1, qy1, vi);
+            finish_cell<FIELDS>(m, io, i, 0u, dt, rain, h1, qx1, qy1, vi);
         }
     }
 }

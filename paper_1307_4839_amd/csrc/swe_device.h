@@ -792,25 +792,38 @@ __device__ __forceinline__ RawCell imposed_ghost(const KParams& p, int side, Raw
     return o;
 }
 
-// Issue the loads of cell (row r, mapped column cs).
+// The element at byte offset `off` of a row that starts at `row`.  In the
+// tile kernels the row is the same for every lane of the block (scalar
+// registers) and `off` is the lane's column times the element size, the
+// same vector register for every array: each access is one load or store
+// with a scalar base and a 32-bit vector offset, with no 64-bit address
+// arithmetic per array.  Columns are below 2^28 (check_params), so the
+// offset fits in 32 bits.
+template <class T>
+__device__ __forceinline__ T& at(T* row, uint32_t off) {
+    using B = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+    return *reinterpret_cast<T*>(reinterpret_cast<B*>(row) + off);
+}
+
+// Issue the loads of cell (row r, mapped column at byte offset o).
 template <int STAGE>
 __device__ __forceinline__ Fetch<STAGE> fetch(const MemberArgs& m, const TileIO& io, int r,
-                                              int cs) {
+                                              uint32_t o) {
     Fetch<STAGE> f;
     int rs = map_index(r, m.p.ny, m.p.bcs, m.p.bcn, f.sy);
     f.ys = (r < 0 && r >= -HALO && m.p.bcs >= SWE_BC_IMPOSED_H)                ? 2
            : (r >= m.p.ny && r < m.p.ny + HALO && m.p.bcn >= SWE_BC_IMPOSED_H) ? 3
                                                                                : -1;
-    size_t idx = (size_t)rs * m.p.nx + cs;
-    f.h = io.h[idx];
-    f.qx = io.qx[idx];
-    f.qy = io.qy[idx];
-    f.z = m.z[idx];
+    const size_t ro = (size_t)rs * m.p.nx;
+    f.h = at(io.h + ro, o);
+    f.qx = at(io.qx + ro, o);
+    f.qy = at(io.qy + ro, o);
+    f.z = at(m.z + ro, o);
     if (STAGE == 2) {
-        f.ph = io.ph[idx];
-        f.pqx = io.pqx[idx];
-        f.pqy = io.pqy[idx];
-        f.coef = m.fric ? m.fric[idx] : m.p.coef;
+        f.ph = at(io.ph + ro, o);
+        f.pqx = at(io.pqx + ro, o);
+        f.pqy = at(io.pqy + ro, o);
+        f.coef = m.fric ? at(m.fric + ro, o) : m.p.coef;
     } else {
         f.ph = f.pqx = f.pqy = f.coef = 0.0;
     }
@@ -936,6 +949,36 @@ template <int TXT, int STAGE> struct TileLds {
     UnRing<TXT, STAGE> un;
 };
 
+// End of a step for a cell: rain R = r(t) w and Green-Ampt with the
+// cell's soil (the optional fields are compiled in only for launches that
+// have some), then U^{n+1} and V_inf written and the sticky flags raised.
+// The cell is element ro of each array plus the byte offset o (see at()).
+template <bool FIELDS>
+__device__ __forceinline__ void finish_cell(const MemberArgs& m, const TileIO& io, size_t ro,
+                                            uint32_t o, double dt, double rain, double hn,
+                                            double qxn, double qyn, double vi) {
+    const KParams& p = m.p;
+    double rate = rain, gks = p.ks, gpsi = p.psi, gdth = p.dtheta;
+    if constexpr (FIELDS) {
+        if (m.rain_w) rate = rain * at(m.rain_w + ro, o);
+        if (p.infil) {
+            if (m.ks_f) gks = at(m.ks_f + ro, o);
+            if (m.psi_f) gpsi = at(m.psi_f + ro, o);
+            if (m.dth_f) gdth = at(m.dth_f + ro, o);
+        }
+    }
+    rain_infiltration(p, dt, rate, gks, gpsi, gdth, hn, qxn, qyn, vi);
+    if (p.infil) at(m.vinf + ro, o) = vi;
+    at(io.ho + ro, o) = hn;
+    at(io.qxo + ro, o) = qxn;
+    at(io.qyo + ro, o) = qyn;
+    bool fin = (hn - hn) == 0.0 && (qxn - qxn) == 0.0 && (qyn - qyn) == 0.0;
+    if (!fin)
+        atomicOr(&m.sc->status, (unsigned)SWE_FLAG_NONFINITE);
+    else if (hn < 0.0)
+        atomicOr(&m.sc->status, (unsigned)SWE_FLAG_NEGDEPTH);
+}
+
 // March rows y0 .. y1-1 of a tile with division policy D (see Division).
 // A tile one wave wide (TXT = 64) exchanges x-neighbours with DPP lane
 // shifts and takes its decisions by a wave vote: no LDS, no barrier.  Wider
@@ -948,34 +991,6 @@ template <int TXT, int STAGE> struct TileLds {
 // the caller to march on from row j with ExactDiv.  Thread 0 lowers the flag
 // of row j+1 after the first barrier of row j, when every lane has read it
 // for row j-1.  Returns y1 when the tile is done.
-// End of a step for cell idx: rain R = r(t) w and Green-Ampt with the
-// cell's soil (the optional fields are compiled in only for launches that
-// have some), then U^{n+1} and V_inf written and the sticky flags raised.
-template <bool FIELDS>
-__device__ __forceinline__ void finish_cell(const MemberArgs& m, const TileIO& io, size_t idx,
-                                            double dt, double rain, double hn, double qxn,
-                                            double qyn, double vi) {
-    const KParams& p = m.p;
-    double rate = rain, gks = p.ks, gpsi = p.psi, gdth = p.dtheta;
-    if constexpr (FIELDS) {
-        if (m.rain_w) rate = rain * m.rain_w[idx];
-        if (p.infil) {
-            if (m.ks_f) gks = m.ks_f[idx];
-            if (m.psi_f) gpsi = m.psi_f[idx];
-            if (m.dth_f) gdth = m.dth_f[idx];
-        }
-    }
-    rain_infiltration(p, dt, rate, gks, gpsi, gdth, hn, qxn, qyn, vi);
-    if (p.infil) m.vinf[idx] = vi;
-    io.ho[idx] = hn;
-    io.qxo[idx] = qxn;
-    io.qyo[idx] = qyn;
-    bool fin = (hn - hn) == 0.0 && (qxn - qxn) == 0.0 && (qyn - qyn) == 0.0;
-    if (!fin)
-        atomicOr(&m.sc->status, (unsigned)SWE_FLAG_NONFINITE);
-    else if (hn < 0.0)
-        atomicOr(&m.sc->status, (unsigned)SWE_FLAG_NEGDEPTH);
-}
 
 template <int STAGE, int TXT, class D, bool FIELDS, int ORDER, int FLUX, bool PHI2>
 __device__ __forceinline__ int march(const MemberArgs& m, const TileIO& io, int strip, int y0,
@@ -988,6 +1003,8 @@ __device__ __forceinline__ int march(const MemberArgs& m, const TileIO& io, int 
     const int x0 = strip * OUTW;
     const int c = x0 - HALO + t;
     const bool out_col = (t >= HALO) && (t < TXT - HALO) && (c < p.nx);
+    // byte offset of the output column (used by out_col lanes only)
+    uint32_t oc = (uint32_t)c * (uint32_t)sizeof(double);
     const bool col_in = (c >= 0) && (c < p.nx);
     // a face c+1/2 computed by thread t has valid neighbour data when
     // 1 <= t <= TXT-3; it is a real face when -1 <= c <= nx-1
@@ -997,6 +1014,8 @@ __device__ __forceinline__ int march(const MemberArgs& m, const TileIO& io, int 
 
     double sx;
     const int cs = map_index(c, p.nx, p.bcw, p.bce, sx);
+    // byte offset of the mapped column (map_index keeps it inside the grid)
+    uint32_t os = (uint32_t)cs * (uint32_t)sizeof(double);
     // x-ghost column of an imposed west (0) or east (1) side
     const int xside = !(FIELDS && p.imposed)                               ? -1
                       : (c < 0 && p.bcw >= SWE_BC_IMPOSED_H)               ? 0
@@ -1018,12 +1037,12 @@ __device__ __forceinline__ int march(const MemberArgs& m, const TileIO& io, int 
 
     // --- prologue: rows y0-2 .. y0+1, face y0-1/2; stage 1 prefetches row
     // y0+2 ------------------------------------------------------------------
-    Fetch<STAGE> fA = fetch<STAGE>(m, io, y0 - 2, cs);
-    Fetch<STAGE> fB = fetch<STAGE>(m, io, y0 - 1, cs);
-    Fetch<STAGE> fC = fetch<STAGE>(m, io, y0, cs);
-    Fetch<STAGE> fD = fetch<STAGE>(m, io, y0 + 1, cs);
+    Fetch<STAGE> fA = fetch<STAGE>(m, io, y0 - 2, os);
+    Fetch<STAGE> fB = fetch<STAGE>(m, io, y0 - 1, os);
+    Fetch<STAGE> fC = fetch<STAGE>(m, io, y0, os);
+    Fetch<STAGE> fD = fetch<STAGE>(m, io, y0 + 1, os);
     Fetch<STAGE> fnext;
-    if (STAGE == 1) fnext = fetch<STAGE>(m, io, y0 + 2, cs);
+    if (STAGE == 1) fnext = fetch<STAGE>(m, io, y0 + 2, os);
     RawCell rA = cell(fA);
     RawCell rB = cell(fB);
     RawCell rC = cell(fC);
@@ -1079,6 +1098,11 @@ __device__ __forceinline__ int march(const MemberArgs& m, const TileIO& io, int 
     }
 
     for (int j = y0; j < y1; ++j) {
+        // The column offsets are opaque to the compiler from here: it cannot
+        // fold them into each array's base before the loop (one 64-bit
+        // address per array, live across the loop), so every access takes
+        // its row in scalar registers and the offset as it is.
+        asm volatile("" : "+v"(os), "+v"(oc));
         // Stage 1: the loads of row j+2 were issued one iteration ahead;
         // issue j+3.  Stage 2 issues those of row j+2 here and uses them
         // after the x direction of row j, which hides their latency and keeps
@@ -1086,10 +1110,10 @@ __device__ __forceinline__ int march(const MemberArgs& m, const TileIO& io, int 
         // waves per SIMD instead of two).
         Fetch<STAGE> f2;
         if (STAGE == 2) {
-            f2 = fetch<STAGE>(m, io, j + 2, cs);
+            f2 = fetch<STAGE>(m, io, j + 2, os);
         } else {
             f2 = fnext;
-            if (j + 1 < y1) fnext = fetch<STAGE>(m, io, j + 3, cs);
+            if (j + 1 < y1) fnext = fetch<STAGE>(m, io, j + 3, os);
         }
 
         // ---- y direction, all in registers ----
@@ -1183,9 +1207,8 @@ __device__ __forceinline__ int march(const MemberArgs& m, const TileIO& io, int 
             n0x = L.un.v[s0][1][t];
             n0y = L.un.v[s0][2][t];
             if (out_col) {
-                const size_t ix = (size_t)j * p.nx + c;
-                if (p.infil) vi = m.vinf[ix];
-                c0 = m.fric ? m.fric[ix] : p.coef;
+                if (p.infil) vi = at(m.vinf + (size_t)j * p.nx, oc);
+                c0 = m.fric ? at(m.fric + (size_t)j * p.nx, oc) : p.coef;
             }
         }
         double fm0, fm1, fm2;
@@ -1249,22 +1272,22 @@ __device__ __forceinline__ int march(const MemberArgs& m, const TileIO& io, int 
             } else {
                 tail(d);
             }
-            size_t idx = (size_t)j * p.nx + c;
+            const size_t ro = (size_t)j * p.nx;
             if (STAGE == 1) {
-                io.ph[idx] = rh;
-                io.pqx[idx] = rqx;
-                io.pqy[idx] = rqy;
+                at(io.ph + ro, oc) = rh;
+                at(io.pqx + ro, oc) = rqx;
+                at(io.pqy + ro, oc) = rqy;
             } else {
                 if constexpr (PHI2) {
-                    io.ph2[idx] = rh;
-                    io.pqx2[idx] = rqx;
-                    io.pqy2[idx] = rqy;
+                    at(io.ph2 + ro, oc) = rh;
+                    at(io.pqx2 + ro, oc) = rqx;
+                    at(io.pqy2 + ro, oc) = rqy;
                 }
                 // Heun: U^{n+1} = (U^n + U**)/2
                 double hn = 0.5 * (n0h + h2);
                 double qxn = 0.5 * (n0x + qx2);
                 double qyn = 0.5 * (n0y + qy2);
-                finish_cell<FIELDS>(m, io, idx, dt, rain, hn, qxn, qyn, vi);
+                finish_cell<FIELDS>(m, io, ro, oc, dt, rain, hn, qxn, qyn, vi);
             }
         }
 
@@ -1360,7 +1383,7 @@ __device__ __forceinline__ void euler_cells(const MemberArgs& m, const TileIO& i
         const double coef = m.fric ? m.fric[i] : p.coef;
         friction(p, coef, h0, qx0, qy0, h1, qx1, qy1, dt);
         const double vi = p.infil ? m.vinf[i] : 0.0;
-        finish_cell<FIELDS>(m, io, i, dt, rain, h1, qx1, qy1, vi);
+        finish_cell<FIELDS>(m, io, i, 0u, dt, rain, h1, qx1, qy1, vi);
     }
 }
 

@@ -37,6 +37,8 @@ inline bool imposed_values_ok(int type, double h_b, double q_b) {
 inline int check_params(const swe_params* p) {
     if (!p) return SWE_EINVAL;
     if (p->nx < 2 || p->ny < 2) return SWE_EINVAL;
+    // the tile kernels address a cell as its row plus a 32-bit byte offset
+    if (p->nx > SWE_MAX_NX) return SWE_EINVAL;
     if (!(p->dx > 0.0) || !(p->dy > 0.0) || !(p->g > 0.0) || !(p->cfl > 0.0))
         return SWE_EINVAL;
     if (!(p->h_eps >= 0.0) || !(p->dt_max > 0.0)) return SWE_EINVAL;

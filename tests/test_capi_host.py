@@ -74,10 +74,15 @@ def test_parameter_validation_without_gpu():
                 capi.make_params(10, 10, 1.0, 1.0, bc=(0, 0, 0, 7)),
                 capi.make_params(10, 10, 1.0, 1.0, fric_law=5),
                 capi.make_params(10, 10, 1.0, 1.0, infil_on=1, dtheta=0.0),
-                capi.make_params(10, 10, 1.0, 1.0, dt_max=0.0)):
+                capi.make_params(10, 10, 1.0, 1.0, dt_max=0.0),
+                # rows longer than 2^28 cells (a cell's byte offset within
+                # its row must stay below 2^31)
+                capi.make_params(capi.SWE_MAX_NX + 1, 2, 1.0, 1.0)):
         with pytest.raises(capi.SweError) as e:
             capi.swe_workspace_bytes(bad)
         assert e.value.code == capi.SWE_EINVAL
+    # the longest row allowed
+    assert capi.swe_workspace_bytes(capi.make_params(capi.SWE_MAX_NX, 2, 1.0, 1.0)) >= 6 * (1 << 29) * 8
 
 
 def test_strerror_texts():
