@@ -631,6 +631,15 @@ __global__ __launch_bounds__(TXT) void adj_vjp_kernel(AdjArgs a, const double* _
     const int cs = map_index(c, nx, p.bcw, p.bce, sx);
     const bool col_real = c >= 0 && c < nx;
     const bool out = t >= H && t < TXT - H && col_real;
+    // byte offsets within a row (see at()): the mapped column, the seeds'
+    // column (0 off the grid, where the seed is 0) and the output column
+    uint32_t os = (uint32_t)cs * (uint32_t)sizeof(double);
+    uint32_t om = (uint32_t)(col_real ? c : 0) * (uint32_t)sizeof(double);
+    uint32_t oc = (uint32_t)c * (uint32_t)sizeof(double);
+    // v / dx and v / dy: products when both are powers of two (equal to the
+    // quotients bit for bit)
+    auto over_dx = [&](double v) { return p.dxy_pow2 ? v * p.inv_dx : v / p.dx; };
+    auto over_dy = [&](double v) { return p.dxy_pow2 ? v * p.inv_dy : v / p.dy; };
 
     // lanes whose ghost columns fold into this column: west (w1, w2) and
     // east (e1, e2); a lane with none reads itself with weight 0
@@ -648,12 +657,17 @@ __global__ __launch_bounds__(TXT) void adj_vjp_kernel(AdjArgs a, const double* _
     // applied) and its seed (0 off the grid)
     auto load = [&](int r, RawCell& cell, double& sy, double m[3]) {
         const int rs = map_index(r, ny, p.bcs, p.bcn, sy);
-        cell = load_raw(h, qx, qy, a.z, nx, rs, cs, sx, sy);
-        const bool real = r >= 0 && r < ny && col_real;
-        const size_t idx = (size_t)(real ? r : 0) * nx + (real ? c : 0);
-        m[0] = real ? mu_h[idx] : 0.0;
-        m[1] = real ? mu_qx[idx] : 0.0;
-        m[2] = real ? mu_qy[idx] : 0.0;
+        const size_t ro = (size_t)rs * nx;
+        cell.h = at(h + ro, os);
+        cell.qx = sx * at(qx + ro, os);
+        cell.qy = sy * at(qy + ro, os);
+        cell.z = at(a.z + ro, os);
+        const bool row_real = r >= 0 && r < ny;
+        const bool real = row_real && col_real;
+        const size_t rm = (size_t)(row_real ? r : 0) * nx;
+        m[0] = real ? at(mu_h + rm, om) : 0.0;
+        m[1] = real ? at(mu_qx + rm, om) : 0.0;
+        m[2] = real ? at(mu_qy + rm, om) : 0.0;
     };
     auto shl = [](const Prim& v) {
         Prim o;
@@ -674,7 +688,7 @@ __global__ __launch_bounds__(TXT) void adj_vjp_kernel(AdjArgs a, const double* _
         const Prim Pl = shl(P), Pr = shr(P);
         const Rec R = muscl(Pl, P, Pr, p.h_eps);
         // X_i enters Phi_i as -X_i / dx
-        const double b0 = -m[0] / p.dx, b1 = -m[1] / p.dx, b2 = -m[2] / p.dx;
+        const double b0 = over_dx(-m[0]), b1 = over_dx(-m[1]), b2 = over_dx(-m[2]);
         const double l0 = from_left(b0), l1 = from_left(b1), l2 = from_left(b2);
         // face c, between column c-1 (lane t-1, its p side) and c
         const FaceBar fb = face_rev<FLUX>(p.g, from_left(R.h_p), from_left(R.z_p),
@@ -731,11 +745,14 @@ __global__ __launch_bounds__(TXT) void adj_vjp_kernel(AdjArgs a, const double* _
 
     const int n_end = y1 == ny ? y1 + 4 : y1 + 2;
     for (int n = y0 - 3; n <= n_end; ++n) {
+        // the offsets are opaque from here, so that each access takes its
+        // row in scalar registers rather than a base folded before the loop
+        asm volatile("" : "+v"(os), "+v"(om), "+v"(oc));
         RawCell r0;
         double s0, m0[3];
         load(n, r0, s0, m0);
         const Prim P0 = to_y(prim_x(r0, p.h_eps));
-        const double bY0[3] = {-m0[0] / p.dy, -m0[2] / p.dy, -m0[1] / p.dy};
+        const double bY0[3] = {over_dy(-m0[0]), over_dy(-m0[2]), over_dy(-m0[1])};
 
         // x part of row n
         if (n >= y0 && n < y1) {
@@ -797,10 +814,10 @@ __global__ __launch_bounds__(TXT) void adj_vjp_kernel(AdjArgs a, const double* _
                         tot[q] += Gs[0][q][t] + (p.bcs != SWE_BC_WALL ? Gs[1][q][t] : 0.0);
                     if (jd == 1 && p.bcs == SWE_BC_WALL) tot[q] += Gs[1][q][t];
                 }
-                const size_t idx = (size_t)jd * nx + c;
-                lh[idx] += tot[0];
-                lqx[idx] += tot[1];
-                lqy[idx] += tot[2];
+                const size_t ro = (size_t)jd * nx;
+                at(lh + ro, oc) += tot[0];
+                at(lqx + ro, oc) += tot[1];
+                at(lqy + ro, oc) += tot[2];
             }
             // ghost rows above fold into rows ny-1 and ny-2 (written before)
             if (out && (jd == ny || jd == ny + 1)) {
@@ -808,10 +825,10 @@ __global__ __launch_bounds__(TXT) void adj_vjp_kernel(AdjArgs a, const double* _
                 if (jd == ny) dst = ny - 1;
                 if (jd == ny + 1) dst = p.bcn == SWE_BC_WALL ? ny - 2 : ny - 1;
                 if (dst >= y0 && dst < y1) {
-                    const size_t idx = (size_t)dst * nx + c;
-                    lh[idx] += yb[0];
-                    lqx[idx] += yb[1];
-                    lqy[idx] += yb[2];
+                    const size_t ro = (size_t)dst * nx;
+                    at(lh + ro, oc) += yb[0];
+                    at(lqx + ro, oc) += yb[1];
+                    at(lqy + ro, oc) += yb[2];
                 }
             }
         }
