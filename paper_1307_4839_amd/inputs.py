@@ -408,6 +408,26 @@ def thacker_planar(n: int = 100, L: float = 4.0, a: float = 1.0, h0: float = 0.1
                     nsteps=10 ** 7)
 
 
+def longest_rows(nx: int = 1 << 28, ny: int = 2) -> Workload:
+    """Rows of the greatest length the library takes (2^28 cells along x,
+    two rows): a sawtooth bed (0.1 mm per cell over 4096-cell teeth) under 1 m
+    of water, 0.5 m more on every other 4096-cell run, at rest; walls west,
+    south and north, free outflow east.  The time step is capped at 0.01 s
+    (the CFL bound of this state is 0.065 s), so a step's dt is known
+    without a pass over all cells.  No random draws."""
+    i = np.arange(nx, dtype=np.int64)
+    z_row = (i & 4095).astype(np.float64) * 1e-4
+    h_row = 1.0 + 0.5 * ((i >> 12) & 1).astype(np.float64)
+    del i
+    z = np.empty((ny, nx))
+    z[:] = z_row
+    h = np.empty((ny, nx))
+    h[:] = h_row
+    return Workload("longest_rows", nx, ny, 1.0, 1.0, z=z, h=h,
+                    qx=np.zeros((ny, nx)), qy=np.zeros((ny, nx)),
+                    bc=(WALL, OUTFLOW, WALL, WALL), dt_max=0.01, nsteps=1)
+
+
 def flowdir_dem(nx: int = 14786, ny: int = 10086, seed: int = 1307) -> np.ndarray:
     """A float32 DEM of the paper's flow-direction size (Section 5.2 gives
     only its dimensions): a ramp of 50 m across x plus uniform noise of 1 m,

@@ -131,3 +131,52 @@ def test_fullsize_calibration_1024():
 def test_fullsize_valley_5120():
     wl = I.valley_5120()
     check_fullsize(wl, 2000, 200, seed=4)
+
+
+def test_longest_rows():
+    # Rows of SWE_MAX_NX cells: a cell's byte offset within its row reaches
+    # 2^31 - 8, the top of the range of the kernels' 32-bit lane offsets.
+    # One step from the initial state with dt capped by dt_max, so the
+    # oracle needs no pass over all 2^29 cells; windows sampled along the
+    # whole row: both ends, strip edges of the tiling, the last strip.
+    import torch
+    from paper_1307_4839_amd import capi
+    from paper_1307_4839_amd.solver import Solver
+    say("[fullsize] longest rows: generating 2^28 x 2 inputs")
+    wl = I.longest_rows()
+    nx, ny = wl.nx, wl.ny
+    assert nx == capi.SWE_MAX_NX
+    g = Solver(wl)
+    tx = g.tiling()[0]
+    say(f"[fullsize] longest rows: one GPU step, {tx}-column strips")
+    g.step(1)
+    t, dt_gpu, steps = g.time()
+    rc, flags = g.status()
+    assert rc == 0 and flags == 0 and steps == 1
+    assert dt_gpu == wl.dt_max
+    outw = tx - 4
+    last = (nx - 1) // outw * outw  # first column of the last strip
+    rng = np.random.default_rng(11)
+    cols = [0, 1, 2, outw - 1, outw, 4095, 4096, 8191, 8192, nx // 2, last - 1, last, last + 1,
+            nx - 4097, nx - 4096, nx - 3, nx - 2, nx - 1]
+    cols += [int(c) for c in rng.integers(0, nx, 40)]
+    cols += [int(c) for c in rng.integers(nx - (1 << 20), nx, 20)]
+    pre = {"h": wl.h, "qx": wl.qx, "qy": wl.qy}
+    say(f"[fullsize] longest rows: {ny * len(cols)} sampled windows")
+    refs, gpus = [], []
+    for j in range(ny):
+        for i in cols:
+            refs.append(window_step(wl, pre, j, i, wl.dt_max))
+            gpus.append({k: getattr(g, k)[j, i].item() for k in ("h", "qx", "qy")})
+    bad = 0
+    for k in ("h", "qx", "qy"):
+        scale = max(max(abs(r[k]) for r in refs), 1e-300)
+        for n, (r, v) in enumerate(zip(refs, gpus)):
+            if abs(v[k] - r[k]) > 1e-14 * scale:
+                bad += 1
+                say(f"   mismatch {k} at sample {n}: gpu {v[k]!r} oracle {r[k]!r}")
+    # the sampled cells are not all still: the step moved water
+    assert max(abs(r["qx"]) for r in refs) > 0
+    assert bad == 0
+    del g
+    torch.cuda.empty_cache()
