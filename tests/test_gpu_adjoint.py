@@ -55,6 +55,20 @@ def case_random_bcs():
     return wl, 0.04 * (1.0 + 0.2 * xo)
 
 
+def case_unequal_cells():
+    # cells of 1.5 m x 0.75 m: neither size a power of two (the seeds of the
+    # reverse are divided by dx and dy, not multiplied by their inverses),
+    # and dx != dy (each direction of the reverse uses its own size)
+    rng = np.random.default_rng(13)
+    wl = I.random_state(40, 36, seed=13, dx=1.5, dy=0.75, bc=(0, 1, 1, 0),
+                        fric_law=I.FRIC_MANNING, fric_coef=0.04)
+    xi = I.smooth_field(rng, wl.nx, wl.ny, 4.0)
+    wl.fric = 0.04 * (1.0 + 0.2 * xi)
+    xo = I.smooth_field(rng, wl.nx, wl.ny, 4.0)
+    wl.gauges = np.sort(rng.choice(wl.nx * wl.ny, 10, replace=False)).astype(np.int32)
+    return wl, 0.04 * (1.0 + 0.2 * xo)
+
+
 def case_darcy():
     wl = I.calibration_1024(64, 72, dam_row=15, ngauges=8, sigma_cells=3)
     wl.fric_law = I.FRIC_DARCY
@@ -106,7 +120,7 @@ SMALL = [_small(2, 2, (0, 0, 0, 0), 41), _small(3, 5, (1, 1, 1, 1), 42),
          _small(130, 9, (0, 1, 0, 1), 45)]
 
 
-@pytest.mark.parametrize("make", [case_calibration, case_random_bcs, case_darcy,
+@pytest.mark.parametrize("make", [case_calibration, case_random_bcs, case_unequal_cells, case_darcy,
                                   case_rusanov_calibration, case_rusanov_random_bcs,
                                   case_kinetic_calibration, case_kinetic_random_bcs] + SMALL)
 def test_adjoint_against_oracle_tangent(torch_cuda, make):
