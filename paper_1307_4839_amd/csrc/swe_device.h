@@ -968,10 +968,12 @@ __device__ __forceinline__ void finish_cell(const MemberArgs& m, const TileIO& i
         }
     }
     rain_infiltration(p, dt, rate, gks, gpsi, gdth, hn, qxn, qyn, vi);
-    if (p.infil) at(m.vinf + ro, o) = vi;
-    at(io.ho + ro, o) = hn;
-    at(io.qxo + ro, o) = qxn;
-    at(io.qyo + ro, o) = qyn;
+    // stored with the non-temporal hint: nothing reads them again before
+    // the next step, and the caches are left to the rows a tile re-reads
+    if (p.infil) __builtin_nontemporal_store(vi, &at(m.vinf + ro, o));
+    __builtin_nontemporal_store(hn, &at(io.ho + ro, o));
+    __builtin_nontemporal_store(qxn, &at(io.qxo + ro, o));
+    __builtin_nontemporal_store(qyn, &at(io.qyo + ro, o));
     bool fin = (hn - hn) == 0.0 && (qxn - qxn) == 0.0 && (qyn - qyn) == 0.0;
     if (!fin)
         atomicOr(&m.sc->status, (unsigned)SWE_FLAG_NONFINITE);
@@ -1274,9 +1276,10 @@ __device__ __forceinline__ int march(const MemberArgs& m, const TileIO& io, int 
             }
             const size_t ro = (size_t)j * p.nx;
             if (STAGE == 1) {
-                at(io.ph + ro, oc) = rh;
-                at(io.pqx + ro, oc) = rqx;
-                at(io.pqy + ro, oc) = rqy;
+                // the rate is read once, by stage 2: non-temporal hint
+                __builtin_nontemporal_store(rh, &at(io.ph + ro, oc));
+                __builtin_nontemporal_store(rqx, &at(io.pqx + ro, oc));
+                __builtin_nontemporal_store(rqy, &at(io.pqy + ro, oc));
             } else {
                 if constexpr (PHI2) {
                     at(io.ph2 + ro, oc) = rh;
